@@ -1,0 +1,593 @@
+// C ABI of libflod: argument validation, workspace management and stage orchestration on
+// the caller's stream. Every arithmetic step runs in the kernels of this library.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "flod_internal.h"
+
+using namespace flod;
+
+namespace {
+
+struct Buf {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+
+enum BufId {
+  B_XYAB, B_COP, B_BLUE, B_DEPTH, B_RECT, B_TILES, B_BLOCKVIS, B_PREFIX,
+  B_DKEY0, B_DKEY1, B_DVAL0, B_DVAL1, B_TBSUM, B_TPREFIX,
+  B_TKEY0, B_TKEY1, B_TVAL0, B_TVAL1, B_HIST, B_SCAN, B_TOT, B_RANGES, B_COUNTERS,
+  B_G2D, B_COUNT
+};
+
+struct Saved {
+  bool valid = false;
+  bool is_level = false;
+  flod_level level{};
+  int sh_degree = 0;
+  DevCamera cam{};
+  float bg[3] = {0, 0, 0};
+  const float *final_T = nullptr;
+  const int32_t *n_contrib = nullptr;
+  int sorted_vals = 0;   // which of B_TVAL0/B_TVAL1 holds the sorted values
+  int sorted_keys = 0;
+  int depth_buf = 0;
+};
+
+}  // namespace
+
+struct flod_ctx {
+  int device = 0;
+  flod_alloc_fn alloc = nullptr;
+  flod_free_fn release = nullptr;
+  void *user = nullptr;
+  Buf buf[B_COUNT];
+  hipStream_t last_stream = nullptr;
+  size_t required = 0;
+  unsigned long long *host_counters = nullptr;   // pinned: [visible u32 | K u32], [K u64]
+  Saved saved;
+  flod_stats stats{};
+  // timing
+  bool timing = false;
+  hipEvent_t ev[FLOD_NUM_STAGES][2];
+  bool ev_pending[FLOD_NUM_STAGES];
+  double ms[FLOD_NUM_STAGES];
+  int64_t calls[FLOD_NUM_STAGES];
+  bool events_made = false;
+};
+
+namespace {
+
+size_t ws_bytes(const flod_ctx *c) {
+  size_t t = 0;
+  for (int i = 0; i < B_COUNT; ++i) t += c->buf[i].cap;
+  return t;
+}
+
+void release_buf(flod_ctx *c, Buf &b, hipStream_t s) {
+  if (!b.p) return;
+  if (c->release)
+    c->release(c->user, b.p, b.cap, (void *)s);
+  else
+    (void)hipFreeAsync(b.p, s);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+// Grow-only buffers: reallocate with 25% headroom when too small.
+flod_status ensure(flod_ctx *c, BufId id, size_t bytes, hipStream_t s, size_t *extra_needed) {
+  Buf &b = c->buf[id];
+  if (bytes == 0) bytes = 256;
+  if (b.cap >= bytes) return FLOD_OK;
+  size_t want = bytes + bytes / 4;
+  want = (want + 255) & ~(size_t)255;
+  release_buf(c, b, s);
+  void *p = nullptr;
+  if (c->alloc) {
+    p = c->alloc(c->user, want, (void *)s);
+  } else {
+    if (hipMallocAsync(&p, want, s) != hipSuccess) p = nullptr;
+  }
+  if (!p) {
+    *extra_needed += want;
+    return FLOD_ERR_WORKSPACE;
+  }
+  b.p = p;
+  b.cap = want;
+  return FLOD_OK;
+}
+
+template <class T> T *P(flod_ctx *c, BufId id) { return reinterpret_cast<T *>(c->buf[id].p); }
+
+flod_status dev(hipError_t e) { return e == hipSuccess ? FLOD_OK : FLOD_ERR_DEVICE; }
+
+void timing_flush(flod_ctx *c) {
+  if (!c->events_made) return;
+  for (int k = 0; k < FLOD_NUM_STAGES; ++k) {
+    if (!c->ev_pending[k]) continue;
+    float ms = 0.f;
+    if (hipEventSynchronize(c->ev[k][1]) == hipSuccess && hipEventElapsedTime(&ms, c->ev[k][0], c->ev[k][1]) == hipSuccess) {
+      c->ms[k] += ms;
+      c->calls[k] += 1;
+    }
+    c->ev_pending[k] = false;
+  }
+}
+
+struct StageTimer {
+  flod_ctx *c;
+  hipStream_t s;
+  int stage = -1;
+  StageTimer(flod_ctx *c_, hipStream_t s_) : c(c_), s(s_) {}
+  void begin(int k) {
+    if (!c->timing) return;
+    stage = k;
+    (void)hipEventRecord(c->ev[k][0], s);
+  }
+  void end() {
+    if (!c->timing || stage < 0) return;
+    (void)hipEventRecord(c->ev[stage][1], s);
+    c->ev_pending[stage] = true;
+    stage = -1;
+  }
+};
+
+int ceil_log2(int64_t v) {
+  int b = 0;
+  while (b < 62 && ((int64_t)1 << b) < v) ++b;
+  return b;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+flod_status check_level(const flod_level *lv) {
+  if (!lv || lv->n < 0) return FLOD_ERR_INVALID_ARG;
+  if (lv->n == 0) return FLOD_OK;
+  if (!lv->means || !lv->log_scales || !lv->quats || !lv->opacity_logits || !lv->sh) return FLOD_ERR_INVALID_ARG;
+  if (!aligned(lv->quats, 16) || !aligned(lv->sh, 16) || !aligned(lv->means, 4) || !aligned(lv->log_scales, 4) ||
+      !aligned(lv->opacity_logits, 4))
+    return FLOD_ERR_INVALID_ARG;
+  if (!(lv->s_min >= 0.0f) || !isfinite(lv->s_min)) return FLOD_ERR_INVALID_ARG;
+  return FLOD_OK;
+}
+
+flod_status check_camera(const flod_camera *cam) {
+  if (!cam) return FLOD_ERR_INVALID_ARG;
+  if (cam->width <= 0 || cam->height <= 0 || cam->width > 16384 || cam->height > 16384) return FLOD_ERR_INVALID_ARG;
+  if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f) || !isfinite(cam->fx) || !isfinite(cam->fy)) return FLOD_ERR_INVALID_ARG;
+  return FLOD_OK;
+}
+
+DevCamera dev_camera(const flod_camera *cam) {
+  DevCamera d;
+  memcpy(d.R, cam->R, sizeof(d.R));
+  memcpy(d.t, cam->t, sizeof(d.t));
+  memcpy(d.campos, cam->campos, sizeof(d.campos));
+  d.fx = cam->fx; d.fy = cam->fy; d.cx = cam->cx; d.cy = cam->cy;
+  d.W = cam->width; d.H = cam->height;
+  d.tiles_x = (cam->width + kTile - 1) / kTile;
+  d.tiles_y = (cam->height + kTile - 1) / kTile;
+  return d;
+}
+
+float sq32(float d) { return isinf(d) ? INFINITY : (float)((double)d * (double)d); }
+
+// The forward pipeline over the candidate set described by p.
+flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const float bg[3],
+                          flod_frame *out, hipStream_t s) {
+  c->required = 0;
+  c->last_stream = s;
+  c->saved.valid = false;
+  timing_flush(c);
+  StageTimer tm(c, s);
+  const int64_t N = p.n_total;
+  const DevCamera &cam = p.cam;
+  const int n_tiles = cam.tiles_x * cam.tiles_y;
+  const int nb = (int)((N + kBlock - 1) / kBlock);
+  const int nbs = (int)((N + kSortTile - 1) / kSortTile);
+  size_t extra = 0;
+  flod_status st = FLOD_OK;
+  auto need = [&](BufId id, size_t bytes) {
+    flod_status r = ensure(c, id, bytes, s, &extra);
+    if (r != FLOD_OK) st = r;
+  };
+  need(B_XYAB, 16 * (size_t)N);
+  need(B_COP, 16 * (size_t)N);
+  need(B_BLUE, 4 * (size_t)N);
+  need(B_DEPTH, 4 * (size_t)N);
+  need(B_RECT, 8 * (size_t)N);
+  need(B_TILES, 4 * (size_t)N);
+  need(B_BLOCKVIS, 4 * (size_t)nb);
+  need(B_PREFIX, 8 * (size_t)nb);
+  need(B_DKEY0, 4 * (size_t)N);
+  need(B_DKEY1, 4 * (size_t)N);
+  need(B_DVAL0, 4 * (size_t)N);
+  need(B_DVAL1, 4 * (size_t)N);
+  need(B_TBSUM, 4 * (size_t)nb);
+  need(B_TPREFIX, 8 * (size_t)nb);
+  need(B_HIST, 4 * (size_t)kRadix * nbs);
+  need(B_SCAN, 4 * (size_t)kRadix * nbs);
+  need(B_TOT, 4 * (size_t)kRadix);
+  need(B_RANGES, 8 * (size_t)n_tiles);
+  need(B_COUNTERS, 8 * (size_t)kCntSlots);
+  if (st != FLOD_OK) {
+    c->required = ws_bytes(c) + extra;
+    return st;
+  }
+  uint32_t *counters = P<uint32_t>(c, B_COUNTERS);
+  int64_t n_vis = 0;
+  unsigned long long K = 0;
+  int dres = 0;
+  if (N > 0) {
+    PreOut o;
+    o.xyab = P<float4>(c, B_XYAB);
+    o.cop = P<float4>(c, B_COP);
+    o.blue = P<float>(c, B_BLUE);
+    o.depth = P<uint32_t>(c, B_DEPTH);
+    o.rect = P<uint2>(c, B_RECT);
+    o.tiles = P<uint32_t>(c, B_TILES);
+    o.block_vis = P<uint32_t>(c, B_BLOCKVIS);
+    o.n_selected = reinterpret_cast<unsigned long long *>(n_selected);
+    tm.begin(FLOD_STAGE_PREPROCESS);
+    if (launch_preprocess(p, o, s) != hipSuccess) return FLOD_ERR_DEVICE;
+    tm.end();
+    tm.begin(FLOD_STAGE_COMPACT);
+    if (launch_scan_blocks(o.block_vis, nullptr, kBlock, P<unsigned long long>(c, B_PREFIX), counters + kCntVisible,
+                           nullptr, nb, s) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    if (launch_compact(o.tiles, o.depth, N, P<unsigned long long>(c, B_PREFIX), P<uint32_t>(c, B_DKEY0),
+                       P<uint32_t>(c, B_DVAL0), s) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    tm.end();
+    tm.begin(FLOD_STAGE_DEPTH_SORT);
+    uint32_t *dk[2] = {P<uint32_t>(c, B_DKEY0), P<uint32_t>(c, B_DKEY1)};
+    uint32_t *dv[2] = {P<uint32_t>(c, B_DVAL0), P<uint32_t>(c, B_DVAL1)};
+    if (launch_radix_sort(dk, dv, counters + kCntVisible, N, 32, P<uint32_t>(c, B_HIST), P<uint32_t>(c, B_SCAN),
+                          P<uint32_t>(c, B_TOT), &dres, s) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    tm.end();
+    tm.begin(FLOD_STAGE_OFFSETS);
+    if (launch_tile_counts(dv[dres], counters + kCntVisible, N, o.tiles, P<uint32_t>(c, B_TBSUM), s) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    if (launch_scan_blocks(P<uint32_t>(c, B_TBSUM), counters + kCntVisible, kBlock,
+                           P<unsigned long long>(c, B_TPREFIX), counters + kCntInstances,
+                           reinterpret_cast<unsigned long long *>(counters + kCntTotal64), nb, s) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    // the one host synchronisation: instance count to size the sort
+    if (hipMemcpyAsync(c->host_counters, counters, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return FLOD_ERR_DEVICE;
+    tm.end();
+    const uint32_t *hc = reinterpret_cast<const uint32_t *>(c->host_counters);
+    n_vis = hc[kCntVisible];
+    K = c->host_counters[1];
+  }
+  c->stats.n_candidates = N;
+  c->stats.n_visible = n_vis;
+  c->stats.n_instances = (int64_t)K;
+  c->stats.tiles_x = cam.tiles_x;
+  c->stats.tiles_y = cam.tiles_y;
+  c->stats.width = cam.W;
+  c->stats.height = cam.H;
+  if (K >= 0xFFFFFFFFull) return FLOD_ERR_OVERFLOW;
+  const int64_t Kn = (int64_t)K;
+  const int nbk = (int)((Kn + kSortTile - 1) / kSortTile);
+  need(B_TKEY0, 4 * (size_t)Kn);
+  need(B_TKEY1, 4 * (size_t)Kn);
+  need(B_TVAL0, 4 * (size_t)Kn);
+  need(B_TVAL1, 4 * (size_t)Kn);
+  if (nbk > nbs) {
+    need(B_HIST, 4 * (size_t)kRadix * nbk);
+    need(B_SCAN, 4 * (size_t)kRadix * nbk);
+  }
+  if (st != FLOD_OK) {
+    c->required = ws_bytes(c) + extra;
+    return st;
+  }
+  uint32_t *tk[2] = {P<uint32_t>(c, B_TKEY0), P<uint32_t>(c, B_TKEY1)};
+  uint32_t *tv[2] = {P<uint32_t>(c, B_TVAL0), P<uint32_t>(c, B_TVAL1)};
+  int tres = 0;
+  if (Kn > 0) {
+    uint32_t *dv = dres ? P<uint32_t>(c, B_DVAL1) : P<uint32_t>(c, B_DVAL0);
+    tm.begin(FLOD_STAGE_EMIT);
+    if (launch_emit(dv, counters + kCntVisible, n_vis, P<uint32_t>(c, B_TILES), P<uint2>(c, B_RECT),
+                    P<unsigned long long>(c, B_TPREFIX), cam.tiles_x, tk[0], tv[0], s) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    tm.end();
+    tm.begin(FLOD_STAGE_TILE_SORT);
+    const int bits = ceil_log2(n_tiles);
+    if (bits > 0) {
+      if (launch_radix_sort(tk, tv, counters + kCntInstances, Kn, bits, P<uint32_t>(c, B_HIST),
+                            P<uint32_t>(c, B_SCAN), P<uint32_t>(c, B_TOT), &tres, s) != hipSuccess)
+        return FLOD_ERR_DEVICE;
+    }
+    tm.end();
+  }
+  tm.begin(FLOD_STAGE_RANGES);
+  if (launch_ranges(tk[tres], Kn, n_tiles, P<uint2>(c, B_RANGES), s) != hipSuccess) return FLOD_ERR_DEVICE;
+  tm.end();
+  tm.begin(FLOD_STAGE_BLEND);
+  if (launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP), P<float>(c, B_BLUE),
+                   cam, bg, out->image, out->final_T, out->n_contrib, s) != hipSuccess)
+    return FLOD_ERR_DEVICE;
+  tm.end();
+  Saved &sv = c->saved;
+  sv.valid = true;
+  sv.cam = cam;
+  sv.bg[0] = bg[0]; sv.bg[1] = bg[1]; sv.bg[2] = bg[2];
+  sv.final_T = out->final_T;
+  sv.n_contrib = out->n_contrib;
+  sv.sorted_vals = tres;
+  sv.sorted_keys = tres;
+  sv.depth_buf = dres;
+  sv.sh_degree = p.sh_degree;
+  return FLOD_OK;
+}
+
+PreParams base_params(const DevCamera &cam, int sh_degree) {
+  PreParams p;
+  memset(&p, 0, sizeof(p));
+  p.cam = cam;
+  p.sh_degree = sh_degree;
+  p.logit_min = (float)(-log(254.0));
+  return p;
+}
+
+bool frame_ok(const flod_frame *out) { return out && out->image && out->final_T && out->n_contrib; }
+
+}  // namespace
+
+extern "C" {
+
+flod_status flod_ctx_create(flod_ctx **ctx, int device, flod_alloc_fn alloc, flod_free_fn release, void *user) {
+  if (!ctx || (alloc == nullptr) != (release == nullptr)) return FLOD_ERR_INVALID_ARG;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return FLOD_ERR_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return FLOD_ERR_DEVICE;
+  flod_ctx *c = new (std::nothrow) flod_ctx();
+  if (!c) return FLOD_ERR_WORKSPACE;
+  c->device = device;
+  c->alloc = alloc;
+  c->release = release;
+  c->user = user;
+  if (hipHostMalloc((void **)&c->host_counters, 64, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return FLOD_ERR_DEVICE;
+  }
+  memset(c->ms, 0, sizeof(c->ms));
+  memset(c->calls, 0, sizeof(c->calls));
+  memset(c->ev_pending, 0, sizeof(c->ev_pending));
+  *ctx = c;
+  return FLOD_OK;
+}
+
+void flod_ctx_destroy(flod_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = ctx->last_stream;
+  (void)hipStreamSynchronize(s);
+  for (int i = 0; i < B_COUNT; ++i) release_buf(ctx, ctx->buf[i], s);
+  (void)hipStreamSynchronize(s);
+  if (ctx->events_made)
+    for (int k = 0; k < FLOD_NUM_STAGES; ++k) {
+      (void)hipEventDestroy(ctx->ev[k][0]);
+      (void)hipEventDestroy(ctx->ev[k][1]);
+    }
+  if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+  delete ctx;
+}
+
+size_t flod_ctx_workspace_bytes(const flod_ctx *ctx) { return ctx ? ws_bytes(ctx) : 0; }
+
+size_t flod_ctx_required_bytes(const flod_ctx *ctx) { return ctx ? ctx->required : 0; }
+
+flod_status flod_ctx_trim(flod_ctx *ctx, void *stream) {
+  if (!ctx) return FLOD_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < B_COUNT; ++i) release_buf(ctx, ctx->buf[i], s);
+  ctx->saved.valid = false;
+  return FLOD_OK;
+}
+
+flod_status flod_render_level(flod_ctx *ctx, const flod_level *level, int sh_degree, const flod_camera *cam,
+                              const float bg[3], flod_frame *out, void *stream) {
+  if (!ctx || !bg || !frame_ok(out) || sh_degree < 0 || sh_degree > 3) return FLOD_ERR_INVALID_ARG;
+  flod_status st = check_level(level);
+  if (st != FLOD_OK) return st;
+  if ((st = check_camera(cam)) != FLOD_OK) return st;
+  if (level->n > 0xFFFFFFF0ll) return FLOD_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  PreParams p = base_params(dev_camera(cam), sh_degree);
+  p.n_levels = 1;
+  p.select = 0;
+  DevLevel &L = p.lv[0];
+  L.means = level->means; L.log_scales = level->log_scales; L.quats = level->quats;
+  L.logits = level->opacity_logits; L.sh = level->sh;
+  L.offset = 0; L.n = level->n; L.s_min = level->s_min;
+  L.lo2 = 0.0f; L.hi2 = INFINITY;
+  p.n_total = level->n;
+  st = render_common(ctx, p, nullptr, bg, out, (hipStream_t)stream);
+  if (st == FLOD_OK) {
+    ctx->saved.is_level = true;
+    ctx->saved.level = *level;
+  }
+  return st;
+}
+
+flod_status flod_render_selective(flod_ctx *ctx, const flod_level *levels, int n_levels, int l_start, int l_end,
+                                  const float *d_proj, const float centre[3], int sh_degree, const flod_camera *cam,
+                                  const float bg[3], flod_frame *out, int64_t *n_selected, void *stream) {
+  if (!ctx || !levels || !d_proj || !centre || !bg || !frame_ok(out) || sh_degree < 0 || sh_degree > 3)
+    return FLOD_ERR_INVALID_ARG;
+  if (n_levels < 1 || n_levels > FLOD_MAX_LEVELS || l_start < 1 || l_end < l_start || l_end > n_levels)
+    return FLOD_ERR_INVALID_ARG;
+  flod_status st = check_camera(cam);
+  if (st != FLOD_OK) return st;
+  for (int l = l_start; l <= l_end; ++l)
+    if ((st = check_level(&levels[l - 1])) != FLOD_OK) return st;
+  for (int l = 0; l < n_levels; ++l)
+    if (!(d_proj[l] >= 0.0f)) return FLOD_ERR_INVALID_ARG;
+  if (!isfinite(centre[0]) || !isfinite(centre[1]) || !isfinite(centre[2])) return FLOD_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  PreParams p = base_params(dev_camera(cam), sh_degree);
+  p.select = 1;
+  p.centre[0] = centre[0]; p.centre[1] = centre[1]; p.centre[2] = centre[2];
+  int64_t off = 0;
+  int k = 0;
+  for (int l = l_start; l <= l_end; ++l, ++k) {
+    const flod_level &lv = levels[l - 1];
+    DevLevel &L = p.lv[k];
+    L.means = lv.means; L.log_scales = lv.log_scales; L.quats = lv.quats;
+    L.logits = lv.opacity_logits; L.sh = lv.sh;
+    L.offset = off; L.n = lv.n; L.s_min = lv.s_min;
+    // eq. 6 with d_proj^(l_end) = 0 and d_proj^(l_start - 1) = infinity
+    const float hi = (l == l_start) ? INFINITY : d_proj[l - 2];
+    const float lo = (l == l_end) ? 0.0f : d_proj[l - 1];
+    L.lo2 = sq32(lo);
+    L.hi2 = sq32(hi);
+    off += lv.n;
+  }
+  p.n_levels = k;
+  p.n_total = off;
+  if (off > 0xFFFFFFF0ll) return FLOD_ERR_INVALID_ARG;
+  // the kernel's level index is relative to l_start
+  int64_t *nsel = n_selected;
+  if (nsel) {
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(nsel), 0u, 2 * (int64_t)n_levels, (hipStream_t)stream);
+    if (e != hipSuccess) return FLOD_ERR_DEVICE;
+    nsel += (l_start - 1);
+  }
+  st = render_common(ctx, p, nsel, bg, out, (hipStream_t)stream);
+  if (st == FLOD_OK) ctx->saved.is_level = false;
+  return st;
+}
+
+flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_grads *grads, void *stream) {
+  if (!ctx || !dL_dimage || !grads) return FLOD_ERR_INVALID_ARG;
+  const Saved &sv = ctx->saved;
+  if (!sv.valid || !sv.is_level) return FLOD_ERR_UNSUPPORTED;
+  const int64_t N = sv.level.n;
+  if (N > 0 && (!grads->d_means || !grads->d_log_scales || !grads->d_quats || !grads->d_opacity_logits ||
+                !grads->d_sh || !aligned(grads->d_quats, 16) || !aligned(grads->d_sh, 16)))
+    return FLOD_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  ctx->last_stream = s;
+  ctx->required = 0;
+  timing_flush(ctx);
+  StageTimer tm(ctx, s);
+  if (N == 0) return FLOD_OK;
+  size_t extra = 0;
+  if (ensure(ctx, B_G2D, 9 * 4 * (size_t)N, s, &extra) != FLOD_OK) {
+    ctx->required = ws_bytes(ctx) + extra;
+    return FLOD_ERR_WORKSPACE;
+  }
+  float *g2d = P<float>(ctx, B_G2D);
+  tm.begin(FLOD_STAGE_BLEND_BWD);
+  if (launch_fill_u32(reinterpret_cast<uint32_t *>(g2d), 0u, 9 * N, s) != hipSuccess) return FLOD_ERR_DEVICE;
+  const uint32_t *vals = sv.sorted_vals ? P<uint32_t>(ctx, B_TVAL1) : P<uint32_t>(ctx, B_TVAL0);
+  if (launch_blend_bwd(P<uint2>(ctx, B_RANGES), vals, P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
+                       P<float>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d, N,
+                       s) != hipSuccess)
+    return FLOD_ERR_DEVICE;
+  tm.end();
+  tm.begin(FLOD_STAGE_PREPROCESS_BWD);
+  PreParams p = base_params(sv.cam, sv.sh_degree);
+  p.n_levels = 1;
+  DevLevel &L = p.lv[0];
+  L.means = sv.level.means; L.log_scales = sv.level.log_scales; L.quats = sv.level.quats;
+  L.logits = sv.level.opacity_logits; L.sh = sv.level.sh;
+  L.offset = 0; L.n = N; L.s_min = sv.level.s_min;
+  p.n_total = N;
+  if (launch_preprocess_bwd(p, P<uint32_t>(ctx, B_TILES), g2d, N, *grads, s) != hipSuccess) return FLOD_ERR_DEVICE;
+  tm.end();
+  return FLOD_OK;
+}
+
+flod_status flod_ctx_stats(const flod_ctx *ctx, flod_stats *out) {
+  if (!ctx || !out) return FLOD_ERR_INVALID_ARG;
+  *out = ctx->stats;
+  return FLOD_OK;
+}
+
+flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out) {
+  if (!ctx || !out) return FLOD_ERR_INVALID_ARG;
+  flod_ctx *c = const_cast<flod_ctx *>(ctx);
+  const Saved &sv = ctx->saved;
+  memset(out, 0, sizeof(*out));
+  if (!sv.valid) return FLOD_ERR_UNSUPPORTED;
+  out->tile_ids = sv.sorted_keys ? P<uint32_t>(c, B_TKEY1) : P<uint32_t>(c, B_TKEY0);
+  out->values = sv.sorted_vals ? P<uint32_t>(c, B_TVAL1) : P<uint32_t>(c, B_TVAL0);
+  out->ranges = P<uint32_t>(c, B_RANGES);
+  out->depth_bits = P<uint32_t>(c, B_DEPTH);
+  out->rect = P<uint32_t>(c, B_RECT);
+  out->tiles_touched = P<uint32_t>(c, B_TILES);
+  out->xy_conic = P<float>(c, B_XYAB);
+  out->conic_c_opacity_rg = P<float>(c, B_COP);
+  out->blue = P<float>(c, B_BLUE);
+  return FLOD_OK;
+}
+
+flod_status flod_ctx_set_timing(flod_ctx *ctx, int enable) {
+  if (!ctx) return FLOD_ERR_INVALID_ARG;
+  if (enable && !ctx->events_made) {
+    if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+    for (int k = 0; k < FLOD_NUM_STAGES; ++k) {
+      if (hipEventCreate(&ctx->ev[k][0]) != hipSuccess || hipEventCreate(&ctx->ev[k][1]) != hipSuccess)
+        return FLOD_ERR_DEVICE;
+    }
+    ctx->events_made = true;
+  }
+  ctx->timing = enable != 0;
+  return FLOD_OK;
+}
+
+flod_status flod_ctx_stage_times(flod_ctx *ctx, double *ms, int64_t *calls, int reset) {
+  if (!ctx) return FLOD_ERR_INVALID_ARG;
+  timing_flush(ctx);
+  for (int k = 0; k < FLOD_NUM_STAGES; ++k) {
+    if (ms) ms[k] = ctx->ms[k];
+    if (calls) calls[k] = ctx->calls[k];
+    if (reset) { ctx->ms[k] = 0.0; ctx->calls[k] = 0; }
+  }
+  return FLOD_OK;
+}
+
+const char *flod_stage_name(int stage) {
+  static const char *names[FLOD_NUM_STAGES] = {"preprocess", "compact", "depth_sort", "offsets", "emit",
+                                               "tile_sort", "ranges", "blend", "blend_bwd", "preprocess_bwd"};
+  return (stage >= 0 && stage < FLOD_NUM_STAGES) ? names[stage] : "unknown";
+}
+
+float flod_smin(int l, int l_max, float lambda, float rho) {
+  if (l >= l_max) return 0.0f;
+  return (float)((double)lambda * pow((double)rho, (double)(1 - l)));
+}
+
+float flod_dproj(float s_min, float f, float gamma) {
+  return (float)((double)s_min / (double)gamma * (double)f);
+}
+
+const char *flod_status_str(flod_status status) {
+  switch (status) {
+    case FLOD_OK: return "ok";
+    case FLOD_ERR_INVALID_ARG: return "invalid argument";
+    case FLOD_ERR_WORKSPACE: return "workspace allocation refused";
+    case FLOD_ERR_OVERFLOW: return "instance count overflow (more than 2^32-1 tile instances)";
+    case FLOD_ERR_DEVICE: return "HIP device error";
+    case FLOD_ERR_UNSUPPORTED: return "unsupported operation";
+  }
+  return "unknown status";
+}
+
+flod_status flod_copy_to_host(void *dst_host, const void *src_device, size_t bytes) {
+  if (bytes == 0) return FLOD_OK;
+  if (!dst_host || !src_device) return FLOD_ERR_INVALID_ARG;
+  return dev(hipMemcpy(dst_host, src_device, bytes, hipMemcpyDeviceToHost));
+}
+
+}  // extern "C"

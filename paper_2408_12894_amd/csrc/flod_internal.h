@@ -1,0 +1,106 @@
+// Internal declarations shared by the kernels and the host orchestration of libflod.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/flod.h"
+
+namespace flod {
+
+constexpr int kTile = FLOD_TILE;          // 16x16 pixel tiles
+constexpr int kBlock = 256;               // threads per workgroup (4 wave64)
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;   // 256 buckets per radix pass
+constexpr int kSortItems = 16;            // keys per thread in a radix pass
+constexpr int kSortTile = kBlock * kSortItems;   // 4096 keys per workgroup
+
+// Rasterizer conventions (3DGS framework): near plane, EWA dilation, eigenvalue floor,
+// 3-sigma radius, Jacobian clamp at 1.3x the half field of view, alpha clamp, alpha floor,
+// transmittance floor, support cut q <= 9.
+constexpr float kNearZ = 0.2f;
+constexpr float kDilate = 0.3f;
+constexpr float kEigFloor = 0.1f;
+constexpr float kFovClamp = 1.3f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;
+constexpr float kQCut = 9.0f;
+
+struct DevCamera {
+  float R[9], t[3], campos[3];
+  float fx, fy, cx, cy;
+  int W, H, tiles_x, tiles_y;
+};
+
+struct DevLevel {
+  const float *means, *log_scales, *quats, *logits, *sh;
+  int64_t offset, n;
+  float s_min;
+  float lo2, hi2;     // eq. 6 band, squared; used only when selecting
+};
+
+struct PreParams {
+  DevLevel lv[FLOD_MAX_LEVELS];
+  int n_levels;
+  int select;
+  int sh_degree;
+  float logit_min;    // opacity cull: logit < logit_min  <=>  opacity < 1/255
+  float centre[3];
+  DevCamera cam;
+  int64_t n_total;
+};
+
+// Per-candidate outputs of the preprocess (structure of arrays).
+struct PreOut {
+  float4 *xyab;       // mu'x, mu'y, conic a, conic b
+  float4 *cop;        // conic c, opacity, red, green
+  float *blue;
+  uint32_t *depth;    // FP32 bits of the view-space depth
+  uint2 *rect;        // (x0 | y0 << 16, x1 | y1 << 16)
+  uint32_t *tiles;    // tiles touched, 0 when culled or not selected
+  uint32_t *block_vis;  // per-workgroup count of visible candidates
+  unsigned long long *n_selected;   // per-level selected counts (may be null)
+};
+
+// Counters in device memory (one small array per context).
+enum : int {
+  kCntVisible = 0,      // u32 count of visible candidates
+  kCntInstances = 1,    // u32 count of instances (valid when the u64 total fits)
+  kCntTotal64 = 2,      // u64 scratch for totals (two u32 slots: 2, 3)
+  kCntSlots = 8
+};
+
+// ---- launches (each file defines its own) ----
+hipError_t launch_preprocess(const PreParams &p, const PreOut &o, hipStream_t s);
+hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int items_per_block,
+                              unsigned long long *prefix, uint32_t *total32,
+                              unsigned long long *total64, int max_blocks, hipStream_t s);
+hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
+                          const unsigned long long *prefix, uint32_t *keys, uint32_t *vals,
+                          hipStream_t s);
+hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr,
+                             int64_t n_max, int bits, uint32_t *hist, uint32_t *scan,
+                             uint32_t *tot, int *result_buf, hipStream_t s);
+hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_max,
+                              const uint32_t *tiles, uint32_t *block_sum, hipStream_t s);
+hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_vis,
+                       const uint32_t *tiles, const uint2 *rect,
+                       const unsigned long long *prefix, int tiles_x, uint32_t *tile_ids,
+                       uint32_t *values, hipStream_t s);
+hipError_t launch_ranges(const uint32_t *tile_ids, int64_t K, int n_tiles, uint2 *ranges,
+                         hipStream_t s);
+hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
+                        const float4 *cop, const float *blue, const DevCamera &cam,
+                        const float bg[3], float *image, float *final_T, int32_t *n_contrib,
+                        hipStream_t s);
+hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
+                            const float4 *cop, const float *blue, const DevCamera &cam,
+                            const float bg[3], const float *final_T, const int32_t *n_contrib,
+                            const float *dL_dimage, float *g2d, int64_t g2d_stride,
+                            hipStream_t s);
+hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, const float *g2d,
+                                 int64_t g2d_stride, const flod_grads &g, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+}  // namespace flod

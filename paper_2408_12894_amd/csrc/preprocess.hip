@@ -1,0 +1,109 @@
+// Preprocess: selection (eq. 6), activation (eq. 4), projection (eq. 1 and EWA), culling,
+// tile rectangle, depth key and SH colour, one thread per candidate Gaussian.
+//
+// Memory: one pass over the attributes (12 + 12 + 16 + 4 + 192 bytes per Gaussian, the SH
+// row read as 12 dwordx4 loads), 52 bytes written per Gaussian. Rejected candidates stop
+// after reading the mean (selection) or the mean and logit (near-plane / opacity culls).
+#include "project.h"
+
+namespace flod {
+
+__global__ __launch_bounds__(kBlock) void k_preprocess(PreParams p, PreOut o) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool vis = false;
+  bool selected = false;
+  int lvl = 0;
+  if (i < p.n_total) {
+    lvl = level_of(p, i);
+    const DevLevel L = level_at(p, lvl);
+    const int64_t j = i - L.offset;
+    const float m0 = L.means[j * 3 + 0], m1 = L.means[j * 3 + 1], m2 = L.means[j * 3 + 2];
+    selected = true;
+    if (p.select) {
+      float d2 = dist2(m0, m1, m2, p.centre);
+      selected = (L.lo2 <= d2) && (d2 < L.hi2);
+    }
+    uint32_t tiles = 0;
+    if (selected) {
+      Proj pr;
+      view_transform(p.cam, m0, m1, m2, pr);
+      const float logit = L.logits[j];
+      if (pr.tz > kNearZ && !(logit < p.logit_min)) {
+        float ls[3] = {L.log_scales[j * 3 + 0], L.log_scales[j * 3 + 1], L.log_scales[j * 3 + 2]};
+        const float4 q4 = reinterpret_cast<const float4 *>(L.quats)[j];
+        float q[4] = {q4.x, q4.y, q4.z, q4.w};
+        bool ok = project_cov(p.cam, ls, q, L.s_min, pr);
+        if (ok && pr.det > 0.0f) {
+          float m = 0.5f * (pr.a + pr.c);
+          float disc = m * m - pr.det;
+          float lam = m + sqrtf(fmaxf(kEigFloor, disc));
+          float r = ceilf(3.0f * sqrtf(lam));
+          float x0 = floorf((pr.mx - r) * 0.0625f);
+          float x1 = floorf((pr.mx + r) * 0.0625f);
+          float y0 = floorf((pr.my - r) * 0.0625f);
+          float y1 = floorf((pr.my + r) * 0.0625f);
+          x0 = fmaxf(x0, 0.0f);
+          y0 = fmaxf(y0, 0.0f);
+          x1 = fminf(x1, (float)(p.cam.tiles_x - 1));
+          y1 = fminf(y1, (float)(p.cam.tiles_y - 1));
+          if (x0 <= x1 && y0 <= y1) {
+            vis = true;
+            const uint32_t ix0 = (uint32_t)x0, iy0 = (uint32_t)y0, ix1 = (uint32_t)x1, iy1 = (uint32_t)y1;
+            tiles = (ix1 - ix0 + 1) * (iy1 - iy0 + 1);
+            // colour from SH (not on the key path: contraction allowed via fmaf)
+            float dx = m0 - p.cam.campos[0], dy = m1 - p.cam.campos[1], dz = m2 - p.cam.campos[2];
+            float inv = 1.0f / sqrtf((dx * dx + dy * dy) + dz * dz);
+            float Y[16];
+            sh_basis(p.sh_degree, dx * inv, dy * inv, dz * inv, Y);
+            const float4 *shv = reinterpret_cast<const float4 *>(L.sh + j * (FLOD_SH_COEFFS * 3));
+            const int nk = (p.sh_degree + 1) * (p.sh_degree + 1);
+            const int nv4 = (nk * 3 + 3) / 4;
+            float sh[48];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+              if (k < nv4) {
+                float4 v = shv[k];
+                sh[4 * k + 0] = v.x; sh[4 * k + 1] = v.y; sh[4 * k + 2] = v.z; sh[4 * k + 3] = v.w;
+              }
+            }
+            float col[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+              float acc = 0.0f;
+#pragma unroll
+              for (int k = 0; k < 16; ++k)
+                if (k < nk) acc = fmaf(sh[k * 3 + ch], Y[k], acc);
+              col[ch] = fmaxf(acc + 0.5f, 0.0f);
+            }
+            const float opac = 1.0f / (1.0f + __expf(-logit));
+            o.xyab[i] = make_float4(pr.mx, pr.my, pr.ca, pr.cb);
+            o.cop[i] = make_float4(pr.cc, opac, col[0], col[1]);
+            o.blue[i] = col[2];
+            o.depth[i] = __float_as_uint(pr.tz);
+            o.rect[i] = make_uint2(ix0 | (iy0 << 16), ix1 | (iy1 << 16));
+          }
+        }
+      }
+    }
+    o.tiles[i] = tiles;
+  }
+  // per-level selected counts, aggregated per wave
+  if (o.n_selected) {
+    const int lane = threadIdx.x & 63;
+    for (int k = 0; k < p.n_levels; ++k) {
+      unsigned long long m = __ballot(selected && lvl == k);
+      if (lane == 0 && m) atomicAdd(&o.n_selected[k], (unsigned long long)__popcll(m));
+    }
+  }
+  int cnt = __syncthreads_count(vis);
+  if (threadIdx.x == 0) o.block_vis[blockIdx.x] = (uint32_t)cnt;
+}
+
+hipError_t launch_preprocess(const PreParams &p, const PreOut &o, hipStream_t s) {
+  if (p.n_total <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((p.n_total + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_preprocess, dim3(grid), dim3(kBlock), 0, s, p, o);
+  return hipGetLastError();
+}
+
+}  // namespace flod

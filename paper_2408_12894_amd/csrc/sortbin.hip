@@ -1,0 +1,338 @@
+// Binning: visible-set compaction, depth sort, instance emission, stable tile sort, ranges.
+//
+// Order of the instance list: ascending (tile, depth bits, Gaussian index). It is built as
+//   1. compact the visible candidates in index order,
+//   2. stable LSD radix sort of (depth bits, index) over the visible Gaussians (N keys),
+//   3. emit each Gaussian's tiles in that depth order (row-major inside its rectangle),
+//   4. stable LSD radix sort of the K instances by tile id only.
+// Stability makes step 4 keep the (depth, index) order inside each tile, so only the tile
+// digits of the K-long list are sorted: ceil(log2(tiles) / 8) passes instead of a full
+// 64-bit key sort.
+//
+// The radix pass is a reduce-then-scan design (no inter-workgroup spinning, which would
+// need cross-XCD coherent flags): per-workgroup digit histograms, a per-digit scan over
+// workgroups, then a scatter in which each workgroup ranks its 4096 keys stably in LDS
+// (wave64 ballots over the digit bits), reorders them by digit in LDS and writes each
+// digit run contiguously.
+#include "flod_internal.h"
+
+namespace flod {
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan over a kBlock-thread workgroup; *total receives the sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total) {
+  __shared__ uint32_t s_w[kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = wave_incl_scan(v);
+  if (lane == 63) s_w[w] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    uint32_t t = s_w[k];
+    base += (k < w) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Scan of per-workgroup counts (one workgroup): 64-bit exclusive prefixes and the total.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_scan_blocks(const uint32_t *in, const uint32_t *n_items,
+                                                        int items_per_block, unsigned long long *prefix,
+                                                        uint32_t *total32, unsigned long long *total64,
+                                                        int max_blocks) {
+  int nb = max_blocks;
+  if (n_items) nb = (int)(((unsigned long long)*n_items + items_per_block - 1) / items_per_block);
+  unsigned long long run = 0;
+  for (int base = 0; base < nb; base += kBlock) {
+    const int k = base + threadIdx.x;
+    uint32_t v = (k < nb) ? in[k] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(v, &tot);
+    if (k < nb) prefix[k] = run + ex;
+    run += tot;
+  }
+  if (threadIdx.x == 0) {
+    if (total64) *total64 = run;
+    if (total32) *total32 = run > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)run;
+  }
+}
+
+hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int items_per_block,
+                              unsigned long long *prefix, uint32_t *total32, unsigned long long *total64,
+                              int max_blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, s, in, n_items, items_per_block, prefix,
+                     total32, total64, max_blocks);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Compaction of visible candidates into (depth bits, index) pairs, in index order.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
+                                                    const unsigned long long *prefix, uint32_t *keys,
+                                                    uint32_t *vals) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool v = (i < n) && tiles[i] != 0u;
+  uint32_t tot;
+  uint32_t ex = block_excl_scan(v ? 1u : 0u, &tot);
+  if (v) {
+    const uint64_t pos = prefix[blockIdx.x] + ex;
+    keys[pos] = depth[i];
+    vals[pos] = (uint32_t)i;
+  }
+}
+
+hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
+                          const unsigned long long *prefix, uint32_t *keys, uint32_t *vals, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tiles, depth,
+                     n, prefix, keys, vals);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Radix pass: histogram, per-digit scan, stable scatter.
+// hist[d * nb_max + b] = count of digit d in workgroup b; scan = exclusive prefix over b.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const uint32_t *n_ptr, int shift,
+                                                    uint32_t *hist, int nb_max) {
+  __shared__ uint32_t h[kRadix];
+  const uint32_t n = *n_ptr;
+  const uint32_t nb = (n + kSortTile - 1) / kSortTile;
+  const uint32_t b = blockIdx.x;
+  if (b >= nb) return;
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t base = b * kSortTile;
+#pragma unroll 4
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint32_t idx = base + r * kBlock + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nb_max + b] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_rs_scan(const uint32_t *n_ptr, const uint32_t *hist, uint32_t *scan,
+                                                    uint32_t *tot, int nb_max) {
+  const uint32_t n = *n_ptr;
+  const int nb = (int)((n + kSortTile - 1) / kSortTile);
+  const int d = blockIdx.x;
+  const uint32_t *row = hist + (size_t)d * nb_max;
+  uint32_t *out = scan + (size_t)d * nb_max;
+  uint32_t run = 0;
+  for (int base = 0; base < nb; base += kBlock) {
+    const int k = base + threadIdx.x;
+    uint32_t v = (k < nb) ? row[k] : 0u;
+    uint32_t t;
+    uint32_t ex = block_excl_scan(v, &t);
+    if (k < nb) out[k] = run + ex;
+    run += t;
+  }
+  if (threadIdx.x == 0) tot[d] = run;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restrict__ keys_in,
+                                                       const uint32_t *__restrict__ vals_in,
+                                                       uint32_t *__restrict__ keys_out,
+                                                       uint32_t *__restrict__ vals_out, const uint32_t *n_ptr,
+                                                       int shift, const uint32_t *hist, const uint32_t *scan,
+                                                       const uint32_t *tot, int nb_max) {
+  __shared__ uint32_t s_keys[kSortTile];
+  __shared__ uint32_t s_vals[kSortTile];
+  __shared__ uint32_t s_goff[kRadix];
+  __shared__ uint32_t s_run[kRadix];
+  __shared__ uint32_t s_wcnt[kBlock / 64][kRadix];
+  const uint32_t n = *n_ptr;
+  const uint32_t nb = (n + kSortTile - 1) / kSortTile;
+  const uint32_t b = blockIdx.x;
+  if (b >= nb) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // digit bases over the whole array and this workgroup's local digit bases
+  uint32_t t_all;
+  uint32_t dbase = block_excl_scan(tot[tid], &t_all);
+  const uint32_t cnt = hist[(size_t)tid * nb_max + b];
+  uint32_t t_loc;
+  uint32_t lbase = block_excl_scan(cnt, &t_loc);
+  s_goff[tid] = dbase + scan[(size_t)tid * nb_max + b] - lbase;
+  s_run[tid] = lbase;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) s_wcnt[k][tid] = 0;
+  __syncthreads();
+  const uint32_t base = b * kSortTile;
+  const uint32_t count = min((uint32_t)kSortTile, n - base);
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint32_t li = r * kBlock + tid;
+    const bool valid = li < count;
+    const uint32_t key = valid ? keys_in[base + li] : 0u;
+    const uint32_t val = valid ? vals_in[base + li] : 0u;
+    const uint32_t d = (key >> shift) & (kRadix - 1);
+    // lanes of this wave holding the same digit
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < kRadixBits; ++bit) {
+      const bool set = (d >> bit) & 1u;
+      const unsigned long long bb = __ballot(set);
+      peers &= set ? bb : ~bb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = s_run[d] + rank;
+      for (int k = 0; k < w; ++k) pos += s_wcnt[k][d];
+      s_keys[pos] = key;
+      s_vals[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; ++k) {
+      add += s_wcnt[k][tid];
+      s_wcnt[k][tid] = 0;
+    }
+    s_run[tid] += add;
+    __syncthreads();
+  }
+  for (uint32_t li = tid; li < count; li += kBlock) {
+    const uint32_t key = s_keys[li];
+    const uint32_t d = (key >> shift) & (kRadix - 1);
+    const uint32_t pos = s_goff[d] + li;
+    keys_out[pos] = key;
+    vals_out[pos] = s_vals[li];
+  }
+}
+
+// Sort (keys, vals) by the low `bits` bits of the keys; stable. Ping-pongs between
+// buffers [0] and [1]; *result_buf receives the index holding the result.
+hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr, int64_t n_max,
+                             int bits, uint32_t *hist, uint32_t *scan, uint32_t *tot, int *result_buf,
+                             hipStream_t s) {
+  *result_buf = 0;
+  if (n_max <= 0) return hipSuccess;
+  const int nb_max = (int)((n_max + kSortTile - 1) / kSortTile);
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += kRadixBits) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(nb_max), dim3(kBlock), 0, s, keys[cur], n_ptr, shift, hist, nb_max);
+    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, s, n_ptr, hist, scan, tot, nb_max);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nb_max), dim3(kBlock), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
+                       vals[cur ^ 1], n_ptr, shift, hist, scan, tot, nb_max);
+    cur ^= 1;
+  }
+  *result_buf = cur;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Tiles touched in depth order: per-workgroup sums over the sorted visible Gaussians.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
+                                                        const uint32_t *tiles, uint32_t *block_sum) {
+  const uint32_t n = *n_ptr;
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (blockIdx.x * kBlock >= n) return;
+  const uint32_t c = (j < n) ? tiles[sorted_ids[j]] : 0u;
+  uint32_t tot;
+  block_excl_scan(c, &tot);
+  if (threadIdx.x == 0) block_sum[blockIdx.x] = tot;
+}
+
+hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_max,
+                              const uint32_t *tiles, uint32_t *block_sum, hipStream_t s) {
+  if (n_max <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)((n_max + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     sorted_ids, n_ptr, tiles, block_sum);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Instance emission: each wave walks its 64 Gaussians one at a time and writes each
+// rectangle's tiles with all 64 lanes (row-major), so large rectangles are spread over a
+// wave and every store is contiguous.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr,
+                                                 const uint32_t *tiles, const uint2 *rect,
+                                                 const unsigned long long *prefix, int tiles_x,
+                                                 uint32_t *__restrict__ tile_ids, uint32_t *__restrict__ values) {
+  const uint32_t n = *n_ptr;
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (blockIdx.x * kBlock >= n) return;
+  const bool valid = j < n;
+  const uint32_t g = valid ? sorted_ids[j] : 0u;
+  const uint32_t c = valid ? tiles[g] : 0u;
+  uint32_t tot;
+  const uint32_t ex = block_excl_scan(c, &tot);
+  const uint32_t off = (uint32_t)(prefix[blockIdx.x] + ex);
+  uint2 rc = valid ? rect[g] : make_uint2(0u, 0u);
+  const int lane = threadIdx.x & 63;
+  for (int src = 0; src < 64; ++src) {
+    const uint32_t cs = __shfl(c, src, 64);
+    if (cs == 0) continue;
+    const uint32_t os = __shfl(off, src, 64);
+    const uint32_t gs = __shfl(g, src, 64);
+    const uint32_t r0 = __shfl(rc.x, src, 64), r1 = __shfl(rc.y, src, 64);
+    const uint32_t x0 = r0 & 0xFFFFu, y0 = r0 >> 16, x1 = r1 & 0xFFFFu;
+    const uint32_t wdt = x1 - x0 + 1;
+    for (uint32_t m = lane; m < cs; m += 64) {
+      const uint32_t yy = y0 + m / wdt, xx = x0 + m % wdt;
+      tile_ids[os + m] = yy * (uint32_t)tiles_x + xx;
+      values[os + m] = gs;
+    }
+  }
+}
+
+hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_vis, const uint32_t *tiles,
+                       const uint2 *rect, const unsigned long long *prefix, int tiles_x, uint32_t *tile_ids,
+                       uint32_t *values, hipStream_t s) {
+  if (n_vis <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_vis + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, sorted_ids,
+                     n_ptr, tiles, rect, prefix, tiles_x, tile_ids, values);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Tile ranges from the sorted tile ids (ranges zeroed beforehand).
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *tile_ids, int64_t K, uint2 *ranges) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= K) return;
+  const uint32_t t = tile_ids[k];
+  if (k == 0 || tile_ids[k - 1] != t) ranges[t].x = (uint32_t)k;
+  if (k == K - 1 || tile_ids[k + 1] != t) ranges[t].y = (uint32_t)(k + 1);
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ranges(const uint32_t *tile_ids, int64_t K, int n_tiles, uint2 *ranges, hipStream_t s) {
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * (int64_t)n_tiles, s);
+  if (e != hipSuccess || K <= 0) return e;
+  hipLaunchKernelGGL(k_ranges, dim3((unsigned)((K + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tile_ids, K,
+                     ranges);
+  return hipGetLastError();
+}
+
+}  // namespace flod

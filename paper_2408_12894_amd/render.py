@@ -1,0 +1,276 @@
+"""Torch-facing API over libflod: device memory and streams come from PyTorch, every step of
+the rasterizer runs in the HIP kernels behind the C ABI (include/flod.h).
+
+    r = Renderer()
+    image, final_T, n_contrib = r.render_level(level, cam, bg)
+    image, ... = r.render_selective(levels, l_start, l_end, d_proj, centre, cam, bg)
+    image = rasterize(means, log_scales, quats, opacity_logits, sh, cam, s_min, bg)   # autograd
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+
+SH_COEFFS = 16
+
+
+@dataclass
+class GaussianLevel:
+    """One level G^(l) resident on the device (FP32, contiguous)."""
+    means: torch.Tensor            # [n,3]
+    log_scales: torch.Tensor       # [n,3]
+    quats: torch.Tensor            # [n,4]
+    opacity_logits: torch.Tensor   # [n]
+    sh: torch.Tensor               # [n,16,3]
+    s_min: float = 0.0
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @staticmethod
+    def from_arrays(means, log_scales, quats, opacity_logits, sh, s_min=0.0, device="cuda"):
+        def t(a):
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).to(device).contiguous()
+        return GaussianLevel(t(means), t(log_scales), t(quats), t(opacity_logits), t(sh), float(s_min))
+
+    @staticmethod
+    def from_scene(scene, device="cuda"):
+        return GaussianLevel.from_arrays(*scene.arrays(), s_min=scene.s_min, device=device)
+
+    def nbytes(self) -> int:
+        return sum(x.numel() * x.element_size() for x in
+                   (self.means, self.log_scales, self.quats, self.opacity_logits, self.sh))
+
+    def c_struct(self) -> _lib.Level:
+        for x in (self.means, self.log_scales, self.quats, self.opacity_logits, self.sh):
+            if x.dtype != torch.float32 or not x.is_contiguous() or not x.is_cuda:
+                raise ValueError("level tensors must be contiguous float32 CUDA tensors")
+        return _lib.Level(self.means.data_ptr(), self.log_scales.data_ptr(), self.quats.data_ptr(),
+                          self.opacity_logits.data_ptr(), self.sh.data_ptr(), self.n, float(self.s_min))
+
+
+def camera_struct(cam) -> _lib.Camera:
+    c = _lib.Camera()
+    c.R[:] = [float(v) for v in np.asarray(cam.R, np.float32).ravel()]
+    c.t[:] = [float(v) for v in np.asarray(cam.t, np.float32).ravel()]
+    c.campos[:] = [float(v) for v in np.asarray(cam.campos, np.float32).ravel()]
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def _floats(vals, n):
+    arr = (C.c_float * n)()
+    arr[:] = [float(v) for v in vals]
+    return arr
+
+
+def _stream_ptr(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Renderer:
+    """Owns one libflod context (workspace plus the state kept for the backward pass).
+
+    A Renderer is used by one host thread at a time; use one Renderer per concurrent stream.
+    alloc/release: optional workspace allocator callbacks (see flod_alloc_fn in flod.h).
+    """
+
+    def __init__(self, device: int | None = None, alloc=None, release=None):
+        self.L = _lib.load()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self._alloc_cb = _lib.ALLOC_FN(alloc) if alloc else _lib.ALLOC_FN(0)
+        self._free_cb = _lib.FREE_FN(release) if release else _lib.FREE_FN(0)
+        h = C.c_void_p()
+        _lib.check(self.L.flod_ctx_create(C.byref(h), self.device, self._alloc_cb, self._free_cb, None),
+                   "flod_ctx_create")
+        self.ctx = h
+        self.generation = 0
+        self._last_level_forward = None
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.flod_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ forward
+    def _frame(self, cam, device):
+        H, W = int(cam.height), int(cam.width)
+        image = torch.empty((3, H, W), dtype=torch.float32, device=device)
+        final_T = torch.empty((H, W), dtype=torch.float32, device=device)
+        n_contrib = torch.empty((H, W), dtype=torch.int32, device=device)
+        fr = _lib.Frame(image.data_ptr(), final_T.data_ptr(), n_contrib.data_ptr())
+        return image, final_T, n_contrib, fr
+
+    def render_level(self, level: GaussianLevel, cam, bg=(0.0, 0.0, 0.0), sh_degree: int = 3, stream=None):
+        """Single-level render. Returns (image [3,H,W], final_T [H,W], n_contrib [H,W])."""
+        image, final_T, n_contrib, fr = self._frame(cam, level.means.device)
+        lv = level.c_struct()
+        cs = camera_struct(cam)
+        st = self.L.flod_render_level(self.ctx, C.byref(lv), int(sh_degree), C.byref(cs), _floats(bg, 3),
+                                      C.byref(fr), C.c_void_p(_stream_ptr(stream)))
+        _lib.check(st, "flod_render_level")
+        self.generation += 1
+        self._last_level_forward = self.generation
+        return image, final_T, n_contrib
+
+    def render_selective(self, levels, l_start: int, l_end: int, d_proj, centre, cam, bg=(0.0, 0.0, 0.0),
+                         sh_degree: int = 3, stream=None, with_counts: bool = False):
+        """Selective render over levels l_start..l_end (1-based) with distance bands d_proj
+        (d_proj[l-1] = d_proj^(l)) around `centre`. Returns (image, final_T, n_contrib) and,
+        with with_counts, the per-level selected counts (int64 tensor on the device)."""
+        n_levels = len(levels)
+        arr = (_lib.Level * n_levels)()
+        for i, lv in enumerate(levels):
+            arr[i] = lv.c_struct()
+        dev = levels[l_start - 1].means.device
+        image, final_T, n_contrib, fr = self._frame(cam, dev)
+        counts = torch.empty(n_levels, dtype=torch.int64, device=dev) if with_counts else None
+        cs = camera_struct(cam)
+        st = self.L.flod_render_selective(self.ctx, arr, n_levels, int(l_start), int(l_end),
+                                          _floats(d_proj, n_levels), _floats(centre, 3), int(sh_degree),
+                                          C.byref(cs), _floats(bg, 3), C.byref(fr),
+                                          C.c_void_p(counts.data_ptr() if counts is not None else 0),
+                                          C.c_void_p(_stream_ptr(stream)))
+        _lib.check(st, "flod_render_selective")
+        self.generation += 1
+        self._last_level_forward = None
+        if with_counts:
+            return image, final_T, n_contrib, counts
+        return image, final_T, n_contrib
+
+    # ------------------------------------------------------------------ backward
+    def backward(self, level: GaussianLevel, dL_dimage: torch.Tensor, stream=None):
+        """Gradients of the last render_level with respect to the level's tensors."""
+        if self._last_level_forward != self.generation:
+            raise RuntimeError("backward needs the most recent call on this Renderer to be render_level")
+        dL = dL_dimage.contiguous().float()
+        n = level.n
+        dev = level.means.device
+        g = dict(means=torch.empty((n, 3), device=dev), log_scales=torch.empty((n, 3), device=dev),
+                 quats=torch.empty((n, 4), device=dev), opacity_logits=torch.empty((n,), device=dev),
+                 sh=torch.empty((n, SH_COEFFS, 3), device=dev))
+        gs = _lib.Grads(g["means"].data_ptr(), g["log_scales"].data_ptr(), g["quats"].data_ptr(),
+                        g["opacity_logits"].data_ptr(), g["sh"].data_ptr())
+        st = self.L.flod_render_backward(self.ctx, C.c_void_p(dL.data_ptr()), C.byref(gs),
+                                         C.c_void_p(_stream_ptr(stream)))
+        _lib.check(st, "flod_render_backward")
+        return g
+
+    # ------------------------------------------------------------------ introspection
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        _lib.check(self.L.flod_ctx_stats(self.ctx, C.byref(s)), "flod_ctx_stats")
+        return {f: getattr(s, f) for f, _ in _lib.Stats._fields_}
+
+    def workspace_bytes(self) -> int:
+        return int(self.L.flod_ctx_workspace_bytes(self.ctx))
+
+    def required_bytes(self) -> int:
+        return int(self.L.flod_ctx_required_bytes(self.ctx))
+
+    def trim(self, stream=None):
+        _lib.check(self.L.flod_ctx_trim(self.ctx, C.c_void_p(_stream_ptr(stream))), "flod_ctx_trim")
+
+    def set_timing(self, on: bool):
+        _lib.check(self.L.flod_ctx_set_timing(self.ctx, int(bool(on))), "flod_ctx_set_timing")
+
+    def stage_times(self, reset: bool = False) -> dict:
+        ms = (C.c_double * _lib.NUM_STAGES)()
+        calls = (C.c_int64 * _lib.NUM_STAGES)()
+        _lib.check(self.L.flod_ctx_stage_times(self.ctx, ms, calls, int(reset)), "flod_ctx_stage_times")
+        return {_lib.STAGES[k]: (float(ms[k]), int(calls[k])) for k in range(_lib.NUM_STAGES)}
+
+    def view(self) -> dict:
+        """Copy the last render's intermediate buffers to host numpy arrays."""
+        torch.cuda.synchronize()
+        v = _lib.View()
+        _lib.check(self.L.flod_ctx_view(self.ctx, C.byref(v)), "flod_ctx_view")
+        s = self.stats()
+        N, K = s["n_candidates"], s["n_instances"]
+        tiles = s["tiles_x"] * s["tiles_y"]
+
+        def get(ptr, count, dtype):
+            out = np.empty(count, dtype=dtype)
+            if count:
+                _lib.check(self.L.flod_copy_to_host(out.ctypes.data_as(C.c_void_p), C.c_void_p(ptr),
+                                                    out.nbytes), "flod_copy_to_host")
+            return out
+
+        return dict(tile_ids=get(v.tile_ids, K, np.uint32), values=get(v.values, K, np.uint32),
+                    ranges=get(v.ranges, 2 * tiles, np.uint32).reshape(tiles, 2),
+                    depth_bits=get(v.depth_bits, N, np.uint32),
+                    rect=get(v.rect, 2 * N, np.uint32).reshape(N, 2),
+                    tiles_touched=get(v.tiles_touched, N, np.uint32),
+                    xy_conic=get(v.xy_conic, 4 * N, np.float32).reshape(N, 4),
+                    cop=get(v.conic_c_opacity_rg, 4 * N, np.float32).reshape(N, 4),
+                    blue=get(v.blue, N, np.float32), stats=s)
+
+
+def smin_schedule(l: int, l_max: int, lam: float = 0.2, rho: float = 4.0) -> float:
+    """eq. 3 via the library's host helper."""
+    return float(_lib.load().flod_smin(int(l), int(l_max), float(lam), float(rho)))
+
+
+def dproj(s_min: float, f: float, gamma: float = 1.0) -> float:
+    """eq. 7 via the library's host helper."""
+    return float(_lib.load().flod_dproj(float(s_min), float(f), float(gamma)))
+
+
+# ---------------------------------------------------------------------------------------
+# Differentiable rasterization
+# ---------------------------------------------------------------------------------------
+
+class FLoDRasterize(torch.autograd.Function):
+    """image = rasterize(level tensors); backward through the hand-written HIP kernels."""
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, renderer, cam, s_min, bg, sh_degree):
+        level = GaussianLevel(means.detach().contiguous(), log_scales.detach().contiguous(),
+                              quats.detach().contiguous(), opacity_logits.detach().contiguous(),
+                              sh.detach().contiguous(), float(s_min))
+        image, final_T, n_contrib = renderer.render_level(level, cam, bg, sh_degree)
+        ctx.renderer = renderer
+        ctx.level = level
+        ctx.gen = renderer.generation
+        ctx.frame = (final_T, n_contrib)
+        return image
+
+    @staticmethod
+    def backward(ctx, grad_image):
+        r = ctx.renderer
+        if r.generation != ctx.gen:
+            raise RuntimeError("the Renderer rendered again between this forward and its backward; "
+                               "use one Renderer per differentiable render in flight")
+        g = r.backward(ctx.level, grad_image)
+        return g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None, None, None, None, None
+
+
+def rasterize(means, log_scales, quats, opacity_logits, sh, cam, s_min=0.0, bg=(0.0, 0.0, 0.0), sh_degree=3,
+              renderer: Renderer | None = None):
+    if renderer is None:
+        renderer = _default_renderer()
+    return FLoDRasterize.apply(means, log_scales, quats, opacity_logits, sh, renderer, cam, s_min, bg, sh_degree)
+
+
+_DEFAULT = {}
+
+
+def _default_renderer() -> Renderer:
+    dev = torch.cuda.current_device()
+    if dev not in _DEFAULT:
+        _DEFAULT[dev] = Renderer(dev)
+    return _DEFAULT[dev]

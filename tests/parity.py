@@ -1,0 +1,98 @@
+"""Helpers for GPU-versus-oracle parity tests (imported by tests only).
+
+Tolerances (floating point, the bar stated for this hot path):
+  image and final_T     1e-4 absolute on pixels the oracle does not flag (a flagged pixel has a
+                        support-cut, alpha-floor, alpha-clamp or transmittance decision within a
+                        relative 1e-4 of its threshold, where FP32 and FP64 may decide apart)
+  key path              bit-exact: visibility, depth bits, tile rectangle, tiles touched, mu',
+                        conic; sorted (tile, Gaussian) list and tile ranges
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+IMG_TOL = 1e-4
+FLAG_FRAC_MAX = 2e-2
+
+
+def unpack_rect(r):
+    r = np.asarray(r, np.uint32)
+    return np.stack([r[:, 0] & 0xFFFF, r[:, 0] >> 16, r[:, 1] & 0xFFFF, r[:, 1] >> 16], axis=1).astype(np.int32)
+
+
+def check_keys(view, k, idx=None):
+    """Per-candidate key fields and the sorted instance list against O1 (bit-exact).
+    idx: oracle indices of the GPU candidates (default: the identity)."""
+    vis = k["visible"].astype(bool)
+    if idx is not None:
+        vis = vis[idx]
+        sub = {n: k[n][idx] for n in ("depth_bits", "rect", "tiles", "mxy", "conic")}
+    else:
+        sub = k
+    g_vis = view["tiles_touched"] > 0
+    np.testing.assert_array_equal(g_vis, vis, err_msg="visibility")
+    np.testing.assert_array_equal(view["tiles_touched"][vis], sub["tiles"][vis], err_msg="tiles touched")
+    np.testing.assert_array_equal(view["depth_bits"][vis], sub["depth_bits"][vis], err_msg="depth bits")
+    np.testing.assert_array_equal(unpack_rect(view["rect"][vis]), sub["rect"][vis], err_msg="tile rect")
+    np.testing.assert_array_equal(view["xy_conic"][vis, :2].view(np.uint32), sub["mxy"][vis].view(np.uint32),
+                                  err_msg="mu' bits")
+    g_conic = np.stack([view["xy_conic"][vis, 2], view["xy_conic"][vis, 3], view["cop"][vis, 0]], 1)
+    np.testing.assert_array_equal(g_conic.view(np.uint32), sub["conic"][vis].view(np.uint32), err_msg="conic bits")
+
+
+def check_instances(view, k, index_offset=0):
+    tile, val, ranges = oracle.instances(k)
+    assert view["stats"]["n_instances"] == tile.shape[0], (view["stats"]["n_instances"], tile.shape[0])
+    np.testing.assert_array_equal(view["tile_ids"], tile, err_msg="sorted tile ids")
+    np.testing.assert_array_equal(view["values"].astype(np.int64) + index_offset, val.astype(np.int64),
+                                  err_msg="sorted values")
+    # ranges of empty tiles are [0, 0) on the GPU; compare lengths there
+    gl = view["ranges"][:, 1].astype(np.int64) - view["ranges"][:, 0]
+    ol = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    np.testing.assert_array_equal(gl, ol, err_msg="range lengths")
+    ne = ol > 0
+    np.testing.assert_array_equal(view["ranges"][ne], ranges[ne], err_msg="ranges")
+    return tile, val, ranges
+
+
+def check_image(image, final_T, n_contrib, ref, view, cam, index_offset=0, tol=IMG_TOL, frac_max=FLAG_FRAC_MAX):
+    """Compare GPU outputs with O2 at ref['pix']; returns (max error, flagged fraction)."""
+    pix = ref["pix"]
+    xs, ys = pix[:, 0], pix[:, 1]
+    img = np.asarray(image)
+    got = img[:, ys, xs].T.astype(np.float64)
+    gT = np.asarray(final_T)[ys, xs].astype(np.float64)
+    gn = np.asarray(n_contrib)[ys, xs].astype(np.int64)
+    ok = ref["flag"] == 0
+    frac = 1.0 - ok.mean()
+    assert frac <= frac_max, f"flagged fraction {frac}"
+    err = np.abs(got - ref["rgb"])[ok].max() if ok.any() else 0.0
+    errT = np.abs(gT - ref["T"])[ok].max() if ok.any() else 0.0
+    assert err <= tol, f"image max abs error {err}"
+    assert errT <= tol, f"final_T max abs error {errT}"
+    # the last blended Gaussian, read through the tile list position n_contrib
+    tiles_x = (cam.width + 15) // 16
+    tile = (ys // 16) * tiles_x + xs // 16
+    start = view["ranges"][tile, 0].astype(np.int64)
+    has = gn > 0
+    assert np.all((ref["last"] >= 0)[ok] == has[ok]), "pixels with / without a blended Gaussian"
+    sel = ok & has
+    last_gpu = view["values"][start[sel] + gn[sel] - 1].astype(np.int64) + index_offset
+    np.testing.assert_array_equal(last_gpu, ref["last"][sel], err_msg="last blended Gaussian")
+    return float(err), float(frac)
+
+
+def check_fp64_fields(view, p64, vis_ids, rtol_xy=1e-5, rtol_conic=2e-4):
+    """Continuous per-Gaussian fields against the FP64 projection (tolerance)."""
+    g = view["xy_conic"][vis_ids].astype(np.float64)
+    c = view["cop"][vis_ids].astype(np.float64)
+    np.testing.assert_allclose(g[:, 0], p64[:, 0], rtol=rtol_xy, atol=1e-3)
+    np.testing.assert_allclose(g[:, 1], p64[:, 1], rtol=rtol_xy, atol=1e-3)
+    scale = np.abs(p64[:, 2:5]).max(axis=1, keepdims=True)
+    conic = np.stack([g[:, 2], g[:, 3], c[:, 0]], 1)
+    assert np.all(np.abs(conic - p64[:, 2:5]) <= rtol_conic * scale + 1e-9), "conic"
+    np.testing.assert_allclose(c[:, 1], p64[:, 5], atol=2e-6)          # opacity
+    rgb = np.stack([c[:, 2], c[:, 3], view["blue"][vis_ids]], 1)
+    np.testing.assert_allclose(rgb, p64[:, 6:9], atol=2e-5)
