@@ -83,7 +83,7 @@ def lib():
         L.or_project64.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp]
         L.or_image.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.or_grad.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp, i64, vp, vp,
-                              vp, vp, vp, vp, vp]
+                              vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -229,7 +229,9 @@ def image(order, means, log_scales, quats, logits, smin, sh, deg, cam, bg, pix=N
     return out
 
 
-def grad(order, means, log_scales, quats, logits, smin, sh, deg, cam, bg, pix, dL_dpix) -> dict:
+def grad(order, means, log_scales, quats, logits, smin, sh, deg, cam, bg, pix, dL_dpix, with_scale=False) -> dict:
+    """O3. With with_scale, out['scale'][name] holds each entry's summation scale (the
+    magnitudes of the per-pixel terms it sums, through the absolute Jacobian)."""
     n, (m, ls, q, lg), sm = _arrays(means, log_scales, quats, logits, smin, np.float64)
     shc = np.ascontiguousarray(np.asarray(sh, np.float64))
     order = np.ascontiguousarray(np.asarray(order, np.int64))
@@ -239,10 +241,17 @@ def grad(order, means, log_scales, quats, logits, smin, sh, deg, cam, bg, pix, d
     bgv = np.ascontiguousarray(np.asarray(bg, np.float32))
     out = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
                opacity_logits=np.zeros(n), sh=np.zeros((n, 16, 3)))
+    sc = None
+    if with_scale:
+        sc = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
+                  opacity_logits=np.zeros(n), sh=np.zeros((n, 16, 3)))
+    sp = [None] * 5 if sc is None else [_p(sc[k]) for k in ("means", "log_scales", "quats", "opacity_logits", "sh")]
     c = _cam(cam)
     lib().or_grad(n, order.shape[0], _p(order), _p(m), _p(ls), _p(q), _p(lg), _p(sm), _p(shc), int(deg),
                   C.byref(c), _p(bgv), pix.shape[0], _p(pix), _p(dl), _p(out["means"]), _p(out["log_scales"]),
-                  _p(out["quats"]), _p(out["opacity_logits"]), _p(out["sh"]))
+                  _p(out["quats"]), _p(out["opacity_logits"]), _p(out["sh"]), *sp)
+    if sc is not None:
+        out["scale"] = sc
     return out
 
 

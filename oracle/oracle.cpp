@@ -495,22 +495,30 @@ void or_image(int64_t nv, const int64_t* order, const double* means, const doubl
 }
 
 // O3: FP64 gradient of L = sum_p sum_ch dL_dpix[p,ch] * I[p,ch] with respect to every
-// Gaussian's raw parameters (grads for ids outside `order` stay zero).
+// Gaussian's raw parameters (grads for ids outside `order` stay zero). When s_means is not
+// NULL, s_* receive the summation scale of each entry: the per-pixel 2D terms' magnitudes,
+// summed, and carried through the absolute value of the projection Jacobian. An FP32
+// evaluation of the same sums can only be trusted to a small multiple of eps times this.
 // g_means [n,3], g_ls [n,3], g_q [n,4], g_logit [n], g_sh [n,48]; all zeroed here.
 void or_grad(int64_t n, int64_t nv, const int64_t* order, const double* means, const double* ls, const double* q,
              const double* logits, const double* smin, const double* sh, int deg, const CamIn* camin,
              const float* bg, int64_t npix, const int32_t* pix_xy, const double* dL_dpix,
-             double* g_means, double* g_ls, double* g_q, double* g_logit, double* g_sh) {
+             double* g_means, double* g_ls, double* g_q, double* g_logit, double* g_sh, double* s_means,
+             double* s_ls, double* s_q, double* s_logit, double* s_sh) {
   Cam<double> cam = cam_as<double>(*camin);
   std::vector<Gauss64> G;
   project64_all(nv, order, means, ls, q, logits, smin, sh, deg, cam, G);
   double bgd[3] = {bg[0], bg[1], bg[2]};
   int nth = omp_get_max_threads();
-  // per-thread accumulators of dL/d(mx, my, ca, cb, cc, opac, r, g, b) in list order
+  // per-thread accumulators of dL/d(mx, my, ca, cb, cc, opac, r, g, b) in list order, and of
+  // the magnitudes of the per-pixel terms summed into them (the scale of the summation)
+  const bool want_scale = s_means != nullptr;
   std::vector<std::vector<double>> acc(nth, std::vector<double>((size_t)nv * 9, 0.0));
+  std::vector<std::vector<double>> accm(want_scale ? nth : 0, std::vector<double>((size_t)nv * 9, 0.0));
 #pragma omp parallel
   {
     std::vector<double>& A = acc[omp_get_thread_num()];
+    double* Am = want_scale ? accm[omp_get_thread_num()].data() : nullptr;
     std::vector<Contrib> rec;
 #pragma omp for schedule(dynamic, 16)
     for (int64_t p = 0; p < npix; ++p) {
@@ -526,9 +534,11 @@ void or_grad(int64_t n, int64_t nv, const int64_t* order, const double* means, c
         const Contrib& e = rec[r];
         const Gauss64& g = G[e.k];
         double* a = &A[(size_t)e.k * 9];
+        double* am = Am ? Am + (size_t)e.k * 9 : nullptr;
         double dalpha = 0.0;
         for (int ch = 0; ch < 3; ++ch) {
           a[6 + ch] += e.alpha * e.T * dC[ch];
+          if (am) am[6 + ch] += std::fabs(e.alpha * e.T * dC[ch]);
           dalpha += dC[ch] * (e.T * g.rgb[ch] - S[ch] / (1.0 - e.alpha));
           S[ch] += e.alpha * e.T * g.rgb[ch];
         }
@@ -536,11 +546,13 @@ void or_grad(int64_t n, int64_t nv, const int64_t* order, const double* means, c
         a[5] += dalpha * e.G;
         double dq = dalpha * (-0.5 * e.alpha);
         // q = ca dx^2 + 2 cb dx dy + cc dy^2, dx = px - mx
-        a[2] += dq * e.dx * e.dx;
-        a[3] += dq * 2.0 * e.dx * e.dy;
-        a[4] += dq * e.dy * e.dy;
-        a[0] += dq * (-2.0 * (g.ca * e.dx + g.cb * e.dy));
-        a[1] += dq * (-2.0 * (g.cb * e.dx + g.cc * e.dy));
+        double t[5] = {dq * (-2.0 * (g.ca * e.dx + g.cb * e.dy)), dq * (-2.0 * (g.cb * e.dx + g.cc * e.dy)),
+                       dq * e.dx * e.dx, dq * 2.0 * e.dx * e.dy, dq * e.dy * e.dy};
+        for (int j = 0; j < 5; ++j) a[j] += t[j];
+        if (am) {
+          am[5] += std::fabs(dalpha * e.G);
+          for (int j = 0; j < 5; ++j) am[j] += std::fabs(t[j]);
+        }
       }
     }
   }
@@ -549,12 +561,22 @@ void or_grad(int64_t n, int64_t nv, const int64_t* order, const double* means, c
   std::memset(g_q, 0, sizeof(double) * n * 4);
   std::memset(g_logit, 0, sizeof(double) * n);
   std::memset(g_sh, 0, sizeof(double) * n * 48);
+  if (want_scale) {
+    std::memset(s_means, 0, sizeof(double) * n * 3);
+    std::memset(s_ls, 0, sizeof(double) * n * 3);
+    std::memset(s_q, 0, sizeof(double) * n * 4);
+    std::memset(s_logit, 0, sizeof(double) * n);
+    std::memset(s_sh, 0, sizeof(double) * n * 48);
+  }
   Cam<Dual> camd = cam_as<Dual>(*camin);
 #pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < nv; ++k) {
-    double d2[9] = {0};
+    double d2[9] = {0}, m2[9] = {0};
     for (int t = 0; t < nth; ++t)
-      for (int j = 0; j < 9; ++j) d2[j] += acc[t][(size_t)k * 9 + j];
+      for (int j = 0; j < 9; ++j) {
+        d2[j] += acc[t][(size_t)k * 9 + j];
+        if (want_scale) m2[j] += accm[t][(size_t)k * 9 + j];
+      }
     bool any = false;
     for (int j = 0; j < 9; ++j) any = any || d2[j] != 0.0;
     if (!any) continue;
@@ -572,6 +594,14 @@ void or_grad(int64_t n, int64_t nv, const int64_t* order, const double* means, c
     for (int i = 0; i < 3; ++i) { g_means[g * 3 + i] = gr[i]; g_ls[g * 3 + i] = gr[3 + i]; }
     for (int i = 0; i < 4; ++i) g_q[g * 4 + i] = gr[6 + i];
     g_logit[g] = gr[10];
+    if (want_scale) {
+      double sc[ND] = {0};
+      for (int j = 0; j < 9; ++j)
+        for (int i = 0; i < ND; ++i) sc[i] += m2[j] * std::fabs(outs[j]->d[i]);
+      for (int i = 0; i < 3; ++i) { s_means[g * 3 + i] = sc[i]; s_ls[g * 3 + i] = sc[3 + i]; }
+      for (int i = 0; i < 4; ++i) s_q[g * 4 + i] = sc[6 + i];
+      s_logit[g] = sc[10];
+    }
     // colour is linear in the SH coefficients: d c_ch / d k_{j,ch} = Y_j(dir) unless clamped
     double dir[3] = {means[g * 3 + 0] - cam.campos[0], means[g * 3 + 1] - cam.campos[1],
                      means[g * 3 + 2] - cam.campos[2]};
@@ -581,7 +611,10 @@ void or_grad(int64_t n, int64_t nv, const int64_t* order, const double* means, c
     sh_basis<double>(deg, dir[0], dir[1], dir[2], Y);
     for (int ch = 0; ch < 3; ++ch) {
       if (p.clamped[ch]) continue;
-      for (int j = 0; j < (deg + 1) * (deg + 1); ++j) g_sh[g * 48 + j * 3 + ch] = d2[6 + ch] * Y[j];
+      for (int j = 0; j < (deg + 1) * (deg + 1); ++j) {
+        g_sh[g * 48 + j * 3 + ch] = d2[6 + ch] * Y[j];
+        if (want_scale) s_sh[g * 48 + j * 3 + ch] = m2[6 + ch] * std::fabs(Y[j]);
+      }
     }
   }
 }

@@ -1,150 +1,137 @@
 // Backward pass of the rasterizer (the rasterize-and-backpropagate step of Algorithm 1).
 //
-// Blend backward: one workgroup per tile, one pixel per thread, walking the tile list back
-// to front from the last blended entry. The per-pixel transmittance before entry i is
+// Blend backward: one wave per tile (4 pixels per lane), walking the tile list back to
+// front from the last blended entry. The per-pixel transmittance before entry i is
 // recovered from the saved final T as T_i = T_{i+1} / (1 - alpha_i) (alpha <= 0.99), and
 //   dC/dc_i     = alpha_i T_i
 //   dC/dalpha_i = T_i c_i - S_i / (1 - alpha_i),  S_i = sum_{j>i} alpha_j T_j c_j + T_final bg
-// then alpha -> (opacity, q) unless the 0.99 clamp is active, q -> (conic, mu').
-// Per entry the 9 gradient components are reduced across each wave with shuffles, the 4
-// waves' partial sums are combined in LDS and one FP32 atomic per component is issued per
-// (tile, Gaussian).
+//               = T_i (c_i - Shat_i),  Shat_i = S_i / T_{i+1}
+// where the normalised colour behind entry i follows the convex update
+//   Shat_{i-1} = alpha_i c_i + (1 - alpha_i) Shat_i,  Shat_last = bg,
+// which avoids the cancellation between T_i c_i and S_i / (1 - alpha_i) in FP32.
+// Then alpha -> (opacity, q) unless the 0.99 clamp is active, q -> (conic, mu').
+// Per entry the 9 gradient components are reduced across the wave with DPP and one FP32
+// atomic per component is issued per (tile, Gaussian).
 //
 // Preprocess backward: one thread per Gaussian, recomputing the forward projection and
 // applying the chain rule to the mean (through mu', the EWA Jacobian and the SH view
 // direction), log-scales (eq. 4: times exp(s_opt); s_min gets no gradient), quaternion
 // (through the normalisation), opacity logit (times o (1 - o)) and SH coefficients.
-#include "project.h"
+#include "blend_common.h"
 
 namespace flod {
 
-constexpr int kXcdsB = 8;
 constexpr int kG2d = 9;   // mu'x, mu'y, conic a, b, c, opacity, red, green, blue
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2 *__restrict__ ranges,
-                                                      const uint32_t *__restrict__ values,
-                                                      const float4 *__restrict__ xyab,
-                                                      const float4 *__restrict__ cop,
-                                                      const float *__restrict__ blue, int W, int H, int tiles_x,
-                                                      int n_tiles, float bg0, float bg1, float bg2,
-                                                      const float *__restrict__ final_T,
-                                                      const int32_t *__restrict__ n_contrib,
-                                                      const float *__restrict__ dimg, float *__restrict__ g2d,
-                                                      int64_t stride) {
-  __shared__ float4 s_a[kBlock];
-  __shared__ float4 s_b[kBlock];
-  __shared__ float s_c[kBlock];
-  __shared__ uint32_t s_id[kBlock];
-  __shared__ float s_red[kBlock / 64][kG2d][kBlock];
-  __shared__ int s_max[kBlock / 64];
-  const int chunk = (n_tiles + kXcdsB - 1) / kXcdsB;
-  const int tile = (blockIdx.x % kXcdsB) * chunk + blockIdx.x / kXcdsB;
+// One wave64 per tile, 4 pixels per lane (the forward's geometry). Per pixel the state is
+// T (transmittance after the current entry), V = dL/dC . Shat (the upstream gradient dotted
+// with the normalised colour behind the current entry) and dL/dC.
+// Per entry the lane sums its pixels' 9 gradient components in registers, the wave reduces
+// them with DPP and lane 63 issues one FP32 atomic per non-zero component.
+__global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(const uint2 *__restrict__ ranges,
+                                                             const uint32_t *__restrict__ values,
+                                                             const float4 *__restrict__ xyab,
+                                                             const float4 *__restrict__ cop,
+                                                             const float *__restrict__ blue, int W, int H,
+                                                             int tiles_x, int n_tiles, float bg0, float bg1,
+                                                             float bg2, const float *__restrict__ final_T,
+                                                             const int32_t *__restrict__ n_contrib,
+                                                             const float *__restrict__ dimg,
+                                                             float *__restrict__ g2d, int64_t stride) {
+  __shared__ float4 s_a[kBatch];
+  __shared__ float4 s_b[kBatch];
+  __shared__ float s_c[kBatch];
+  __shared__ uint32_t s_id[kBatch];
+  const int tile = xcd_tile(blockIdx.x, n_tiles);
   if (tile >= n_tiles) return;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int px = (tile % tiles_x) * kTile + (tid & (kTile - 1));
-  const int py = (tile / tiles_x) * kTile + (tid >> 4);
-  const bool inside = px < W && py < H;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const uint2 rg = ranges[tile];
-  const size_t pix = (size_t)py * W + px, plane = (size_t)W * H;
-  float T = 1.0f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
-  int last = 0;
-  if (inside) {
-    T = final_T[pix];
-    last = n_contrib[pix];
-    dC0 = dimg[pix];
-    dC1 = dimg[plane + pix];
-    dC2 = dimg[2 * plane + pix];
+  const int lane = threadIdx.x;
+  const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
+  const int px = x0 + (lane & (kTile - 1));
+  const float fx = (float)px + 0.5f;
+  const size_t plane = (size_t)W * H;
+  float fy[kPix], T[kPix], V[kPix], d0[kPix], d1[kPix], d2[kPix];
+  int last[kPix];
+  int mylast = 0;
+#pragma unroll
+  for (int k = 0; k < kPix; ++k) {
+    const int py = y0 + (lane >> 4) + kRowStep * k;
+    fy[k] = (float)py + 0.5f;
+    T[k] = 1.0f; V[k] = 0.0f; d0[k] = 0.0f; d1[k] = 0.0f; d2[k] = 0.0f;
+    last[k] = 0;
+    if (px < W && py < H) {
+      const size_t pix = (size_t)py * W + px;
+      T[k] = final_T[pix];
+      last[k] = n_contrib[pix];
+      d0[k] = dimg[pix];
+      d1[k] = dimg[plane + pix];
+      d2[k] = dimg[2 * plane + pix];
+      V[k] = d0[k] * bg0 + d1[k] * bg1 + d2[k] * bg2;
+      mylast = max(mylast, last[k]);
+    }
   }
-  float S0 = T * bg0, S1 = T * bg1, S2 = T * bg2;
-  // longest prefix any pixel of the tile used
-  int m = last;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
-  if (lane == 0) s_max[w] = m;
-  __syncthreads();
-  int maxlast = s_max[0];
-#pragma unroll
-  for (int k = 1; k < kBlock / 64; ++k) maxlast = max(maxlast, s_max[k]);
-  for (int end = maxlast; end > 0; end -= kBlock) {
-    const int start = max(0, end - kBlock);
+  for (int o = 32; o > 0; o >>= 1) mylast = max(mylast, __shfl_xor(mylast, o, 64));
+  const uint2 rg = ranges[tile];
+  for (int end = mylast; end > 0; end -= kBatch) {
+    const int start = max(0, end - kBatch);
     const int cnt = end - start;
     __syncthreads();
-    if (tid < cnt) {
-      const uint32_t g = values[rg.x + start + tid];
-      s_id[tid] = g;
-      s_a[tid] = xyab[g];
-      s_b[tid] = cop[g];
-      s_c[tid] = blue[g];
+    for (int e = lane; e < cnt; e += kBlendThreads) {
+      const uint32_t g = values[rg.x + start + e];
+      s_id[e] = g;
+      s_a[e] = xyab[g];
+      s_b[e] = cop[g];
+      s_c[e] = blue[g];
     }
     __syncthreads();
     for (int jl = cnt - 1; jl >= 0; --jl) {
       const int jpos = start + jl;
+      const float4 A = s_a[jl];
+      const float4 B = s_b[jl];
+      const float c2 = s_c[jl];
+      const float dx = fx - A.x;
       float gr[kG2d];
 #pragma unroll
       for (int c = 0; c < kG2d; ++c) gr[c] = 0.0f;
       bool contrib = false;
-      if (jpos < last) {
-        const float4 A = s_a[jl];
-        const float4 B = s_b[jl];
-        const float dx = fx - A.x, dy = fy - A.y;
+#pragma unroll
+      for (int k = 0; k < kPix; ++k) {
+        if (jpos >= last[k]) continue;
+        const float dy = fy[k] - A.y;
         const float q = conic_q(A.z, A.w, B.x, dx, dy);
-        if (q <= kQCut) {
-          const float G = __expf(-0.5f * q);
-          const float a0 = B.y * G;
-          const float alpha = fminf(kAlphaMax, a0);
-          if (alpha >= kAlphaMin) {
-            contrib = true;
-            const float om = 1.0f - alpha;
-            const float Ti = T / om;
-            const float c0 = B.z, c1 = B.w, c2 = s_c[jl];
-            const float wT = alpha * Ti;
-            gr[6] = wT * dC0;
-            gr[7] = wT * dC1;
-            gr[8] = wT * dC2;
-            const float dalpha = dC0 * (Ti * c0 - S0 / om) + dC1 * (Ti * c1 - S1 / om) + dC2 * (Ti * c2 - S2 / om);
-            S0 = fmaf(wT, c0, S0);
-            S1 = fmaf(wT, c1, S1);
-            S2 = fmaf(wT, c2, S2);
-            T = Ti;
-            if (a0 <= kAlphaMax) {
-              gr[5] = dalpha * G;
-              const float dq = -0.5f * alpha * dalpha;
-              gr[2] = dq * dx * dx;
-              gr[3] = dq * 2.0f * dx * dy;
-              gr[4] = dq * dy * dy;
-              gr[0] = dq * (-2.0f * (A.z * dx + A.w * dy));
-              gr[1] = dq * (-2.0f * (A.w * dx + B.x * dy));
-            }
-          }
+        if (q > kQCut) continue;
+        const float G = __expf(-0.5f * q);
+        const float a0 = B.y * G;
+        const float alpha = fminf(kAlphaMax, a0);
+        if (alpha < kAlphaMin) continue;
+        contrib = true;
+        const float inv = 1.0f / (1.0f - alpha);
+        const float Ti = T[k] * inv;
+        const float wT = alpha * Ti;
+        const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * c2;   // dL/dC . c
+        const float dalpha = Ti * (dcc - V[k]);
+        gr[6] = fmaf(wT, d0[k], gr[6]);
+        gr[7] = fmaf(wT, d1[k], gr[7]);
+        gr[8] = fmaf(wT, d2[k], gr[8]);
+        V[k] = fmaf(alpha, dcc - V[k], V[k]);   // alpha dcc + (1 - alpha) V
+        T[k] = Ti;
+        if (a0 <= kAlphaMax) {
+          gr[5] = fmaf(dalpha, G, gr[5]);
+          const float dq = -0.5f * alpha * dalpha;
+          gr[2] = fmaf(dq * dx, dx, gr[2]);
+          gr[3] = fmaf(dq * 2.0f * dx, dy, gr[3]);
+          gr[4] = fmaf(dq * dy, dy, gr[4]);
+          gr[0] = fmaf(dq, -2.0f * (A.z * dx + A.w * dy), gr[0]);
+          gr[1] = fmaf(dq, -2.0f * (A.w * dx + B.x * dy), gr[1]);
         }
       }
-      if (__ballot(contrib) != 0ull) {
+      if (__any(contrib)) {
+        const uint32_t g = s_id[jl];
 #pragma unroll
         for (int c = 0; c < kG2d; ++c) {
-          const float v = wave_sum(gr[c]);
-          if (lane == 0) s_red[w][c][jl] = v;
+          const float v = wave_sum_to_lane63(gr[c]);
+          if (lane == kBlendThreads - 1 && v != 0.0f) atomicAdd(&g2d[c * stride + g], v);
         }
-      } else if (lane == 0) {
-#pragma unroll
-        for (int c = 0; c < kG2d; ++c) s_red[w][c][jl] = 0.0f;
-      }
-    }
-    __syncthreads();
-    if (tid < cnt) {
-      const uint32_t g = s_id[tid];
-#pragma unroll
-      for (int c = 0; c < kG2d; ++c) {
-        float v = s_red[0][c][tid];
-#pragma unroll
-        for (int k = 1; k < kBlock / 64; ++k) v += s_red[k][c][tid];
-        if (v != 0.0f) atomicAdd(&g2d[c * stride + g], v);
       }
     }
   }
@@ -155,9 +142,10 @@ hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const f
                             const int32_t *n_contrib, const float *dL_dimage, float *g2d, int64_t g2d_stride,
                             hipStream_t s) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
-  const int grid = ((n_tiles + kXcdsB - 1) / kXcdsB) * kXcdsB;
-  hipLaunchKernelGGL(k_blend_bwd, dim3(grid), dim3(kBlock), 0, s, ranges, values, xyab, cop, blue, cam.W, cam.H,
-                     cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimage, g2d, g2d_stride);
+  const int grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
+  hipLaunchKernelGGL(k_blend_bwd, dim3(grid), dim3(kBlendThreads), 0, s, ranges, values, xyab, cop, blue, cam.W,
+                     cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimage, g2d,
+                     g2d_stride);
   return hipGetLastError();
 }
 

@@ -1,0 +1,36 @@
+// Shared by the forward and backward blend kernels: tile/lane geometry, the XCD-aware tile
+// order and wave64 reductions through DPP (no LDS crossbar traffic).
+#pragma once
+
+#include "project.h"
+
+namespace flod {
+
+constexpr int kXcds = 8;
+constexpr int kBlendThreads = 64;                          // one wave64 per 16x16 tile
+constexpr int kPix = (kTile * kTile) / kBlendThreads;      // 4 pixels per lane
+constexpr int kRowStep = kBlendThreads / kTile;            // lane rows 0..3, then +4, +8, +12
+constexpr int kBatch = 256;                                // list entries staged in LDS at once
+
+__device__ __forceinline__ int xcd_tile(int bid, int n_tiles) {
+  const int chunk = (n_tiles + kXcds - 1) / kXcds;
+  return (bid % kXcds) * chunk + bid / kXcds;
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_or_zero(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, true));
+}
+
+// Sum over the 64 lanes; the total is valid in lane 63.
+__device__ __forceinline__ float wave_sum_to_lane63(float x) {
+  x += dpp_or_zero<0xB1>(x);         // quad_perm [1,0,3,2]
+  x += dpp_or_zero<0x4E>(x);         // quad_perm [2,3,0,1]
+  x += dpp_or_zero<0x141>(x);        // row_half_mirror
+  x += dpp_or_zero<0x140>(x);        // row_mirror: every lane holds its row's sum
+  x += dpp_or_zero<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+  x += dpp_or_zero<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+}  // namespace flod

@@ -487,8 +487,8 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
     return FLOD_ERR_WORKSPACE;
   }
   float *g2d = P<float>(ctx, B_G2D);
-  tm.begin(FLOD_STAGE_BLEND_BWD);
   if (launch_fill_u32(reinterpret_cast<uint32_t *>(g2d), 0u, 9 * N, s) != hipSuccess) return FLOD_ERR_DEVICE;
+  tm.begin(FLOD_STAGE_BLEND_BWD);
   const uint32_t *vals = sv.sorted_vals ? P<uint32_t>(ctx, B_TVAL1) : P<uint32_t>(ctx, B_TVAL0);
   if (launch_blend_bwd(P<uint2>(ctx, B_RANGES), vals, P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
                        P<float>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d, N,

@@ -1,0 +1,149 @@
+"""GPU backward parity: hand-written HIP gradients against the oracle's FP64 analytic
+gradient (itself pinned by FP64 central differences in test_oracle_pins.py).
+
+Loss: L = sum_p sum_ch w[p,ch] * image[p,ch] with fixed random w (w = 0 on pixels the oracle
+flags, on both sides). Tolerance per entry:
+    |g_gpu - g_oracle| <= 1e-4 * max(1, |g_oracle|) + 3e-5 * scale
+where `scale` (from the oracle) is the sum of the magnitudes of the per-pixel terms that the
+entry adds up, carried through the absolute projection Jacobian. The first term is the
+1e-4 bar; the second is FP32 summation: each per-pixel term carries the rounding of a
+transmittance chain through up to a few hundred contributors (~500 eps = 3e-5), so an entry
+that is a small sum of large opposite-signed terms cannot be closer than that. A genuine
+error (a wrong sign, a missing term, a wrong clamp) is of the order of the terms themselves.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_12894_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-4
+SUM_TOL = 3e-5
+NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+@pytest.fixture(scope="module")
+def renderer():
+    from paper_2408_12894_amd import render
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return render.Renderer(0)
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def grad_parity(renderer, scene, cam, bg, deg=3, pix=None, seed=0):
+    from paper_2408_12894_amd import render
+    level = render.GaussianLevel.from_scene(scene)
+    image, final_T, n_contrib = renderer.render_level(level, cam, bg, deg)
+    k = oracle.keys(*scene.arrays()[:4], scene.s_min, cam)
+    order = oracle.depth_order(k)
+    if pix is None:
+        pix = oracle.all_pixels(cam.width, cam.height)
+    ref = oracle.image(order, *scene.arrays()[:4], scene.s_min, scene.sh, deg, cam, bg, pix)
+    rng = np.random.default_rng(seed)
+    w = rng.normal(size=(pix.shape[0], 3))
+    w[ref["flag"] == 1] = 0.0
+    dimg = np.zeros((3, cam.height, cam.width), np.float32)
+    dimg[:, pix[:, 1], pix[:, 0]] = w.T.astype(np.float32)
+    w64 = dimg[:, pix[:, 1], pix[:, 0]].T.astype(np.float64)      # exactly what the GPU sees
+    g = renderer.backward(level, torch.from_numpy(dimg).cuda())
+    torch.cuda.synchronize()
+    go = oracle.grad(order, *scene.arrays()[:4], scene.s_min, scene.sh, deg, cam, bg, pix, w64, with_scale=True)
+    worst = {}
+    for name in NAMES:
+        a = g[name].cpu().numpy().astype(np.float64).reshape(scene.n, -1)
+        b = go[name].reshape(scene.n, -1)
+        sc = go["scale"][name].reshape(scene.n, -1)
+        if name == "sh":
+            nk = (deg + 1) ** 2
+            a = a.reshape(scene.n, 16, 3)[:, :nk].reshape(scene.n, -1)
+            b = b.reshape(scene.n, 16, 3)[:, :nk].reshape(scene.n, -1)
+            sc = sc.reshape(scene.n, 16, 3)[:, :nk].reshape(scene.n, -1)
+            assert np.all(g["sh"].cpu().numpy()[:, nk:] == 0)
+        allowed = GRAD_TOL * np.maximum(1.0, np.abs(b)) + SUM_TOL * sc
+        ratio = np.abs(a - b) / allowed
+        worst[name] = float(ratio.max()) if ratio.size else 0.0
+        if ratio.size and ratio.max() > 1.0:
+            i = np.unravel_index(ratio.argmax(), ratio.shape)
+            raise AssertionError(f"{name}{i}: gpu {a[i]:.6g} oracle {b[i]:.6g} |diff| {abs(a[i] - b[i]):.3g} "
+                                 f"allowed {allowed[i]:.3g} (scale {sc[i]:.3g}); tensor max |g| "
+                                 f"{np.abs(b).max():.3g}; entries over {(ratio > 1).sum()} of {ratio.size}")
+    nz = sum(int((np.abs(go[n]) > 1e-6).sum()) for n in NAMES)
+    return worst, nz
+
+
+def test_fd_instance(renderer):
+    _say("64 Gaussians, 32x32 (the finite-difference instance)")
+    scene, cam, _ = synth.fd_case()
+    worst, nz = grad_parity(renderer, scene, cam, np.array([0.2, 0.1, 0.3], np.float32))
+    assert nz > 1000
+    print(worst)
+
+
+@pytest.mark.parametrize("deg", [0, 3])
+def test_small_scene(renderer, deg):
+    _say(f"2k Gaussians, 128x128, sh degree {deg}")
+    scene, cam, _ = synth.small_forward_case()
+    worst, nz = grad_parity(renderer, scene, cam, np.array([0.1, 0.2, 0.3], np.float32), deg=deg, seed=1)
+    print(worst)
+
+
+def test_ragged_with_scale_floor(renderer):
+    _say("3k Gaussians, 100x75, s_min = 0.02")
+    scene = synth.uniform_scene(3000, seed=60, s_mu=-4.0, s_sigma=0.6, s_min=0.02)
+    cam = synth.look_at_camera((0.6, 0.3, -3.5), (0, 0, 0), 100, 75)
+    grad_parity(renderer, scene, cam, np.zeros(3, np.float32), seed=2)
+
+
+def test_training_size_sampled(renderer):
+    """500k Gaussians at 1280x720 (the training-step configuration) with the loss restricted
+    to 1024 sampled pixels, so the oracle's FP64 gradient stays cheap."""
+    _say("500k Gaussians, 1280x720, 1024 sampled pixels")
+    scene, _, cam, bg = synth.training_case()
+    rng = np.random.default_rng(61)
+    pix = np.stack([rng.integers(0, 1280, 1024), rng.integers(0, 720, 1024)], 1).astype(np.int32)
+    pix = np.unique(pix, axis=0)
+    worst, nz = grad_parity(renderer, scene, cam, bg, pix=pix, seed=3)
+    print(worst, nz)
+
+
+def test_autograd_l1_step(renderer):
+    """rasterize() under an L1 loss: torch autograd reaches the HIP backward, and its
+    gradients equal Renderer.backward with dL/dimage = sign(I - I_target) / P."""
+    from paper_2408_12894_amd import render
+    _say("autograd L1 step")
+    scene, cam, _ = synth.small_forward_case()
+    target = scene.copy()
+    target.means = target.means + np.float32(0.01)
+    bg = (0.0, 0.0, 0.0)
+    tl = render.GaussianLevel.from_scene(target)
+    tgt, _, _ = renderer.render_level(tl, cam, bg)
+    lv = render.GaussianLevel.from_scene(scene)
+    params = [t.clone().requires_grad_(True) for t in (lv.means, lv.log_scales, lv.quats, lv.opacity_logits, lv.sh)]
+    img = render.rasterize(*params, cam, scene.s_min, bg, renderer=renderer)
+    loss = (img - tgt).abs().mean()
+    loss.backward()
+    dimg = torch.sign(img.detach() - tgt) / img.numel()
+    renderer.render_level(lv, cam, bg)
+    g = renderer.backward(lv, dimg)
+    for p, name in zip(params, NAMES):
+        torch.testing.assert_close(p.grad, g[name], rtol=1e-5, atol=1e-7)
+    assert float(params[0].grad.abs().sum()) > 0
+
+
+def test_backward_after_selective_is_unsupported(renderer):
+    from paper_2408_12894_amd import _lib, render
+    _say("backward after a selective render")
+    scene, cam, _ = synth.small_forward_case()
+    lv = render.GaussianLevel.from_scene(scene)
+    renderer.render_selective([lv], 1, 1, [0.0], cam.campos, cam)
+    renderer._last_level_forward = renderer.generation     # bypass the Python-side guard
+    with pytest.raises(_lib.FlodError) as e:
+        renderer.backward(lv, torch.zeros((3, cam.height, cam.width), device="cuda"))
+    assert e.value.status == _lib.FLOD_ERR_UNSUPPORTED
