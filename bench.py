@@ -1,23 +1,27 @@
 """Benchmark of the FLoD-3DGS rasterizer hot path on one MI355X.
 
-Step (the timed unit): one forward render + L1 loss + backward (gradients for means,
-log-scales, quaternions, opacity logits and SH) at 1920x1080 over 1,000,000 cluster-scene
-Gaussians (SH degree 3, FP32), cycling over 8 seeded orbit cameras; the L1 target of each
-camera is rendered once, before timing, from a perturbed copy of the scene.
+Step (the timed unit, `value`): one forward render + L1 loss + backward (gradients for
+means, log-scales, quaternions, opacity logits and SH) at 1920x1080 over 1,000,000
+cluster-scene Gaussians (SH degree 3, FP32), cycling over 8 seeded orbit cameras; each
+camera's L1 target is rendered once, before timing, from a perturbed copy of the scene.
+Inputs are resident in HBM before timing starts.
 
-Printed: ONE JSON line. `value` is fwd+bwd iterations per second; further fields report the
-forward-only FPS on the same frames, the multi-level stack at 1080p (max level alone and
-selective rendering over levels 1..5 with per-view distance bands), the 1280x720 / 500k
-training step, and the serving loop's p50/p99 latency under its HBM budget. `roofline` is
-the dominant kernel's achieved rate against the MI355X peak, from HIP events recorded on the
-render stream around that kernel inside the timed region; `cpu_baseline` is the CPU oracle
-on a bounded sample of the same workload.
+Printed: ONE JSON line. Besides the step it reports, each timed the same way (warm-up, then a
+timed loop bracketed by device synchronisation):
+  render_fps          forward only, same scene and cameras
+  stack_1080p         the 5-level stack (40k..2.5M, 4.39M resident): level 5 alone and
+                      selective rendering over levels 1..5 with per-view bands 16/8/4/2
+  train_720p          forward + L1 + backward at 1280x720 over 500k Gaussians (s_min 0.0125)
+  serving             512 Poisson requests (mean gap 2 ms) of mixed resolution and level
+                      selection over the resident stack, 4 slots, 32 GiB HBM budget
+  roofline            the dominant kernel of the step, from HIP events recorded on the render
+                      stream around that kernel inside the timed region
+  cpu_baseline        the CPU oracle on a bounded sample of the step's workload
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -30,6 +34,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X fp32 vector, TFLOP/s
 
+# Algorithmic FP32 operations per (pixel, list entry) pair of the blend kernels (an FMA
+# counts 2): every evaluated pair recomputes d, q = d^T conic d, exp, o*G and the clamp (15);
+# a blended pair adds 9 in the forward (T update, weight, 3 colour FMAs) and 46 in the
+# backward (transmittance recovery, dL/dalpha, 9 gradient components, the suffix update).
+FLOPS_EVAL = 15
+FLOPS_BLEND_FWD = 9
+FLOPS_BLEND_BWD = 46
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -37,10 +49,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--n", type=int, default=1_000_000, help="Gaussians in the 1080p scene")
-    ap.add_argument("--no-extras", action="store_true", help="only the fwd+bwd step (for profiling)")
+    ap.add_argument("--no-extras", action="store_true", help="only the fwd+bwd step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--fwd-only", action="store_true", help="time forward renders only (profiling)")
+    ap.add_argument("--serving-requests", type=int, default=512)
     return ap.parse_args()
 
 
@@ -48,12 +60,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stage_delta(before, after):
-    return {k: (after[k][0] - before[k][0], after[k][1] - before[k][1]) for k in after}
+def timed(fn, n, warm, sync):
+    for i in range(warm):
+        fn(i)
+    sync()
+    t0 = time.perf_counter()
+    for i in range(n):
+        fn(i)
+    sync()
+    return (time.perf_counter() - t0) / n
 
 
 def algorithmic_bytes(stage, N, n_vis, K, P, tiles):
-    """Bytes each stage must move at minimum (per launch of the stage)."""
+    """Bytes a stage must move (one launch), per its definition in the design doc."""
     return {
         "preprocess": (236 + 52) * N,
         "compact": 8 * N + 8 * n_vis,
@@ -63,7 +82,7 @@ def algorithmic_bytes(stage, N, n_vis, K, P, tiles):
         "tile_sort": 2 * (4 + 16) * K,
         "ranges": 4 * K + 8 * tiles,
         "blend": 40 * K + 20 * P,
-        "blend_bwd": 40 * K + 32 * P + 36 * K,
+        "blend_bwd": 40 * K + 20 * P + 12 * P + 36 * K,
         "preprocess_bwd": (236 + 52 + 36 + 236) * N,
     }[stage]
 
@@ -71,23 +90,24 @@ def algorithmic_bytes(stage, N, n_vis, K, P, tiles):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
-              "described in DESIGN.md and not run", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}); this build runs on a single "
+              "MI355X and its multi-GPU sharding is a design only", file=sys.stderr)
         sys.exit(2)
     import torch
 
-    from paper_2408_12894_amd import render, synth
+    from paper_2408_12894_amd import render, serving, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
+    sync = torch.cuda.synchronize
+    bg = (0.0, 0.0, 0.0)
+    out_extra = {}
 
     # ------------------------------------------------------------------ 1080p / 1M step
-    log(f"generating the 1080p scene ({args.n} Gaussians)")
+    log(f"1080p scene: {args.n} Gaussians")
     scene = synth.cluster_scene(args.n, seed=1, layout_seed=1)
     cams = synth.orbit_cameras(2, 8, 4.0, 1920, 1080)
-    bg = (0.0, 0.0, 0.0)
     target = scene.copy()
     rng = np.random.default_rng(3)
     target.means = (scene.means + rng.normal(0, 0.01, scene.means.shape)).astype(np.float32)
@@ -106,74 +126,127 @@ def main():
         loss = (img - targets[i % len(cams)]).abs().mean()
         loss.backward()
 
-    def fwd_step(i):
-        r.render_level(lv, cams[i % len(cams)], bg)
-
-    step = fwd_step if args.fwd_only else train_step
-    log("warmup")
+    log("fwd+bwd step")
     for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
+        train_step(i)
+    sync()
     r.set_timing(True)
     r.stage_times(reset=True)
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(i)
-    torch.cuda.synchronize()
+        train_step(i)
+    sync()
     t1 = time.perf_counter()
     stage = r.stage_times(reset=True)
     r.set_timing(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
     iters_s = 1e3 / ms_step
-    # counts for the roofline: average over the 8 cameras
-    Ks, vis = [], []
+
+    # workload counts per camera (K, visible, pairs walked and blended)
+    Ks, vis, walk, blended = [], [], [], []
+    nbl = torch.empty((1080, 1920), dtype=torch.int32, device=dev)
     for c in cams:
-        r.render_level(lv, c, bg)
+        _, _, nc = r.render_level(lv, c, bg, n_blended=nbl)
         s = r.stats()
         Ks.append(s["n_instances"])
         vis.append(s["n_visible"])
-    torch.cuda.synchronize()
-    K = float(np.mean(Ks))
-    n_vis = float(np.mean(vis))
-    N = scene.n
-    P = 1920 * 1080
-    tiles = 120 * 68
-    per_stage = {}
-    for k, (ms, calls) in stage.items():
-        if calls:
-            per_stage[k] = {"ms": ms / calls, "calls": calls}
+        walk.append(int(nc.sum(dtype=torch.int64)))
+        blended.append(int(nbl.sum(dtype=torch.int64)))
+    v0 = r.view()
+    lens = v0["ranges"][:, 1].astype(np.int64) - v0["ranges"][:, 0]
+    K, n_vis = float(np.mean(Ks)), float(np.mean(vis))
+    Pi_walk, Pi_blend = float(np.mean(walk)), float(np.mean(blended))
+    N, P, tiles = scene.n, 1920 * 1080, 120 * 68
+    per_stage = {k: {"ms": ms / c} for k, (ms, c) in stage.items() if c}
+    for k, v in per_stage.items():
+        v["GBs_algorithmic"] = algorithmic_bytes(k, N, n_vis, K, P, tiles) / (v["ms"] * 1e-3) / 1e9
     dom = max(per_stage, key=lambda k: per_stage[k]["ms"])
     dom_ms = per_stage[dom]["ms"]
     if dom in ("blend", "blend_bwd"):
-        # ALU-bound: report bytes-based rate too, but bound by fp32 VALU
-        byts = algorithmic_bytes(dom, N, n_vis, K, P, tiles)
-        roof = {"kernel": dom, "bound": "hbm", "achieved": byts / (dom_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s"}
+        per_pair = FLOPS_BLEND_BWD if dom == "blend_bwd" else FLOPS_BLEND_FWD
+        flops = FLOPS_EVAL * Pi_walk + per_pair * Pi_blend
+        ach = flops / (dom_ms * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None, "algorithmic_flops_per_launch": flops,
+                "pairs_walked": Pi_walk, "pairs_blended": Pi_blend}
     else:
         byts = algorithmic_bytes(dom, N, n_vis, K, P, tiles)
-        roof = {"kernel": dom, "bound": "hbm", "achieved": byts / (dom_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["algorithmic_bytes_per_launch"] = byts
+        ach = byts / (dom_ms * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": byts}
     roof["avg_launch_ms"] = dom_ms
-    for k in per_stage:
-        b = algorithmic_bytes(k, N, n_vis, K, P, tiles)
-        per_stage[k]["GBs"] = b / (per_stage[k]["ms"] * 1e-3) / 1e9
-    log(f"step {ms_step:.3f} ms ({iters_s:.1f} it/s), K={K:.0f}, visible={n_vis:.0f}")
-    # workload shape on camera 0: per-tile list lengths and blended-prefix lengths
-    _, _, nc0 = r.render_level(lv, cams[0], bg)
-    v0 = r.view()
-    lens = (v0["ranges"][:, 1].astype(np.int64) - v0["ranges"][:, 0])
-    ncv = nc0.cpu().numpy().astype(np.int64)
-    log(f"  tile list length: mean {lens.mean():.0f} p50 {np.median(lens):.0f} p99 {np.percentile(lens, 99):.0f} "
-        f"max {lens.max()}; sum n_contrib {ncv.sum():.3g} (mean {ncv.mean():.1f}, max {ncv.max()})")
+    log(f"step {ms_step:.3f} ms ({iters_s:.1f} it/s); K={K:.0f} visible={n_vis:.0f} "
+        f"pairs walked {Pi_walk:.3g} blended {Pi_blend:.3g}")
+    log(f"tile list length mean {lens.mean():.0f} p50 {np.median(lens):.0f} p99 {np.percentile(lens, 99):.0f} "
+        f"max {lens.max()}")
     for k, v in per_stage.items():
-        log(f"  {k:15s} {v['ms']:.3f} ms  {v['GBs']:.0f} GB/s (algorithmic)")
+        log(f"  {k:15s} {v['ms']:.3f} ms  {v['GBs_algorithmic']:.0f} GB/s algorithmic")
+
+    if not args.no_extras:
+        # -------------------------------------------------------------- forward FPS
+        t = timed(lambda i: r.render_level(lv, cams[i % 8], bg), 8 * 8, 8, sync)
+        out_extra["render_fps"] = 1.0 / t
+        log(f"render: {1e3 * t:.3f} ms/frame ({1 / t:.1f} FPS)")
+        del params, targets
+        # -------------------------------------------------------------- 720p training step
+        tr_scene, tr_target, tr_cam, _ = synth.training_case()
+        tr_lv = render.GaussianLevel.from_scene(tr_scene, dev)
+        tr_tgt = r.render_level(render.GaussianLevel.from_scene(tr_target, dev), tr_cam, bg)[0]
+        tr_params = [t.clone().requires_grad_(True) for t in
+                     (tr_lv.means, tr_lv.log_scales, tr_lv.quats, tr_lv.opacity_logits, tr_lv.sh)]
+
+        def tr_step(i):
+            for p in tr_params:
+                p.grad = None
+            img = render.rasterize(*tr_params, tr_cam, tr_scene.s_min, bg, renderer=r)
+            (img - tr_tgt).abs().mean().backward()
+
+        t = timed(tr_step, 30, 5, sync)
+        out_extra["train_720p"] = {"iters_s": 1.0 / t, "ms": 1e3 * t, "n_gaussians": tr_scene.n,
+                                   "K": r.stats()["n_instances"]}
+        log(f"train 720p/500k: {1e3 * t:.3f} ms ({1 / t:.1f} it/s)")
+        del tr_params, tr_lv, tr_tgt
+        # -------------------------------------------------------------- 5-level stack at 1080p
+        log("5-level stack (4.39M resident)")
+        stack_scenes = synth.level_stack()
+        stack = [render.GaussianLevel.from_scene(s, dev) for s in stack_scenes]
+        del stack_scenes
+        t_l5 = timed(lambda i: r.render_level(stack[4], cams[i % 8], bg), 16, 8, sync)
+        k_l5 = r.stats()["n_instances"]
+        t_sel = timed(lambda i: r.render_selective(stack, 1, 5, synth.LEVEL_BANDS, cams[i % 8].campos, cams[i % 8],
+                                                   bg), 16, 8, sync)
+        _, _, _, cnt = r.render_selective(stack, 1, 5, synth.LEVEL_BANDS, cams[0].campos, cams[0], bg,
+                                          with_counts=True)
+        sel_counts = cnt.cpu().tolist()
+        k_sel = r.stats()["n_instances"]
+        per_level = {}
+        for l in range(1, 6):
+            tl_ = timed(lambda i: r.render_level(stack[l - 1], cams[i % 8], bg), 8, 2, sync)
+            per_level[f"L{l}"] = {"fps": 1.0 / tl_, "K_cam0_last": r.stats()["n_instances"]}
+        out_extra["stack_1080p"] = {
+            "resident_gaussians": int(sum(x.n for x in stack)), "resident_bytes": int(sum(x.nbytes() for x in stack)),
+            "max_level_fps": 1.0 / t_l5, "selective_1_5_fps": 1.0 / t_sel,
+            "selective_vs_max_level": t_l5 / t_sel, "selected_per_level_cam0": sel_counts,
+            "K_max_level": k_l5, "K_selective": k_sel, "per_level": per_level}
+        log(f"stack: L5 {1 / t_l5:.1f} FPS, selective[1,5] {1 / t_sel:.1f} FPS, selected {sel_counts}")
+        # -------------------------------------------------------------- serving
+        if not args.no_serving:
+            trace = synth.serving_trace(seed=30, count=args.serving_requests)
+            warm = synth.serving_trace(seed=33, count=16)
+            serving.serve_trace(stack, warm, n_slots=4, budget_bytes=32 << 30)
+            recs, st = serving.serve_trace(stack, trace, n_slots=4, budget_bytes=32 << 30)
+            out_extra["serving"] = {k: (float(v) if isinstance(v, (float, np.floating)) else v) for k, v in st.items()}
+            log(f"serving: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms, {st['throughput_rps']:.0f} req/s, "
+                f"peak {st['peak_bytes'] / 2**30:.2f} GiB of {st['budget_bytes'] / 2**30:.0f}")
+            # the same trace served one request at a time through the plain path
+            recs1, st1 = serving.serve_trace(stack, trace[:128], n_slots=1, budget_bytes=32 << 30)
+            out_extra["serving"]["one_slot_first128"] = {"p50_ms": st1["p50_ms"], "p99_ms": st1["p99_ms"],
+                                                         "throughput_rps": st1["throughput_rps"]}
+        del stack
 
     out = {
         "metric": "fwd+bwd iters/s & render FPS at 1080p/1M Gaussians; serving p50/p99 latency",
-        "value": iters_s if not args.fwd_only else None,
+        "value": iters_s,
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -184,15 +257,41 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "1920x1080, 1M cluster-scene Gaussians (SH degree 3), forward + L1 + backward, "
-                               "8 orbit cameras", "n_gaussians": N, "width": 1920, "height": 1080,
-                   "instances_K": K, "visible": n_vis},
+        "config": {"workload": "fwd+bwd step, 1920x1080, 1M cluster-scene Gaussians, SH degree 3, 8 orbit cameras",
+                   "n_gaussians": N, "width": 1920, "height": 1080, "instances_K": K, "visible": n_vis},
         "roofline": roof,
         "stages_ms": {k: round(v["ms"], 4) for k, v in per_stage.items()},
     }
-    if args.fwd_only:
-        out["value"] = iters_s
-        out["unit"] = "frames/s"
+    out.update(out_extra)
+
+    # ------------------------------------------------------------------ CPU oracle baseline
+    if not args.no_cpu:
+        import oracle
+        threads = len(os.sched_getaffinity(0))
+        oracle.set_threads(threads)
+        cam = cams[0]
+        t0 = time.perf_counter()
+        k = oracle.keys(*scene.arrays()[:4], scene.s_min, cam)
+        oracle.instances(k)
+        order = oracle.depth_order(k)
+        t_keys = time.perf_counter() - t0
+        rng = np.random.default_rng(7)
+        npx = 512
+        pix = np.stack([rng.integers(0, 1920, npx), rng.integers(0, 1080, npx)], 1).astype(np.int32)
+        t0 = time.perf_counter()
+        ref = oracle.image(order, *scene.arrays()[:4], scene.s_min, scene.sh, 3, cam, bg, pix)
+        t_img = time.perf_counter() - t0
+        w = np.sign(rng.normal(size=(npx, 3))) / (3 * P)
+        t0 = time.perf_counter()
+        oracle.grad(order, *scene.arrays()[:4], scene.s_min, scene.sh, 3, cam, bg, pix, w)
+        t_grad = time.perf_counter() - t0
+        t_frame = t_keys + (t_img + t_grad) * P / npx
+        out["cpu_baseline"] = {"value": 1.0 / t_frame, "unit": "iters/s", "cores": oracle.get_threads(),
+                               "kind": "oracle",
+                               "sample": f"fwd+bwd step at 1920x1080/1M, camera 0: O1 keys and sorted instance list "
+                                         f"in full ({t_keys:.2f} s), O2 image and O3 gradient on {npx} of {P} pixels "
+                                         f"({t_img + t_grad:.2f} s), extrapolated per pixel to the frame"}
+        log(f"cpu oracle: {t_frame:.1f} s per step extrapolated ({oracle.get_threads()} threads)")
     print(json.dumps(out), flush=True)
 
 

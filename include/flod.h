@@ -80,6 +80,7 @@ typedef struct {
   float *image;        /* [3,H,W] planar RGB: composite + final_T * background, no clamp */
   float *final_T;      /* [H,W]   transmittance left after the last blended Gaussian     */
   int32_t *n_contrib;  /* [H,W]   tile-list position (1-based) of the last blended entry  */
+  int32_t *n_blended;  /* [H,W]   number of Gaussians blended into the pixel; may be NULL */
 } flod_frame;
 
 /* Gradients of the loss with respect to the level's inputs (device, caller-allocated,
@@ -167,6 +168,9 @@ typedef struct {
   const float *xy_conic;        /* [n_candidates,4] mu'x, mu'y, conic a, conic b            */
   const float *conic_c_opacity_rg; /* [n_candidates,4] conic c, opacity, red, green         */
   const float *blue;            /* [n_candidates] */
+  const float *grad2d;          /* [9, n_candidates] after flod_render_backward: dL/d(mu'x,
+                                   mu'y, conic a, b, c, opacity, red, green, blue), with b
+                                   the off-diagonal conic entry; NULL before a backward   */
 } flod_view;
 flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out);
 

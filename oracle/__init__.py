@@ -83,7 +83,7 @@ def lib():
         L.or_project64.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp]
         L.or_image.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.or_grad.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp, i64, vp, vp,
-                              vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+                              vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -246,11 +246,15 @@ def grad(order, means, log_scales, quats, logits, smin, sh, deg, cam, bg, pix, d
         sc = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
                   opacity_logits=np.zeros(n), sh=np.zeros((n, 16, 3)))
     sp = [None] * 5 if sc is None else [_p(sc[k]) for k in ("means", "log_scales", "quats", "opacity_logits", "sh")]
+    out["g2d"] = np.zeros((n, 9))
+    s2d = np.zeros((n, 9)) if with_scale else None
+    sp += [_p(out["g2d"]), None if s2d is None else _p(s2d)]
     c = _cam(cam)
     lib().or_grad(n, order.shape[0], _p(order), _p(m), _p(ls), _p(q), _p(lg), _p(sm), _p(shc), int(deg),
                   C.byref(c), _p(bgv), pix.shape[0], _p(pix), _p(dl), _p(out["means"]), _p(out["log_scales"]),
                   _p(out["quats"]), _p(out["opacity_logits"]), _p(out["sh"]), *sp)
     if sc is not None:
+        sc["g2d"] = s2d
         out["scale"] = sc
     return out
 

@@ -496,29 +496,31 @@ void or_image(int64_t nv, const int64_t* order, const double* means, const doubl
 
 // O3: FP64 gradient of L = sum_p sum_ch dL_dpix[p,ch] * I[p,ch] with respect to every
 // Gaussian's raw parameters (grads for ids outside `order` stay zero). When s_means is not
-// NULL, s_* receive the summation scale of each entry: the per-pixel 2D terms' magnitudes,
-// summed, and carried through the absolute value of the projection Jacobian. An FP32
+// NULL, s_* receive the summation scale of each entry: the per-pixel 2D terms' magnitudes
+// (with dL/dalpha taken at the size of the two parts it is the difference of), summed, and
+// carried through the absolute value of the projection Jacobian. An FP32
 // evaluation of the same sums can only be trusted to a small multiple of eps times this.
+// g2d / s2d (may be NULL): [n, 9] gradient with respect to (mu'x, mu'y, conic a, b, c,
+// opacity, r, g, b) and its summation scale, by Gaussian id.
 // g_means [n,3], g_ls [n,3], g_q [n,4], g_logit [n], g_sh [n,48]; all zeroed here.
 void or_grad(int64_t n, int64_t nv, const int64_t* order, const double* means, const double* ls, const double* q,
              const double* logits, const double* smin, const double* sh, int deg, const CamIn* camin,
              const float* bg, int64_t npix, const int32_t* pix_xy, const double* dL_dpix,
              double* g_means, double* g_ls, double* g_q, double* g_logit, double* g_sh, double* s_means,
-             double* s_ls, double* s_q, double* s_logit, double* s_sh) {
+             double* s_ls, double* s_q, double* s_logit, double* s_sh, double* g2d, double* s2d) {
   Cam<double> cam = cam_as<double>(*camin);
   std::vector<Gauss64> G;
   project64_all(nv, order, means, ls, q, logits, smin, sh, deg, cam, G);
   double bgd[3] = {bg[0], bg[1], bg[2]};
-  int nth = omp_get_max_threads();
-  // per-thread accumulators of dL/d(mx, my, ca, cb, cc, opac, r, g, b) in list order, and of
-  // the magnitudes of the per-pixel terms summed into them (the scale of the summation)
+  // accumulators of dL/d(mx, my, ca, cb, cc, opac, r, g, b) in list order, and of the
+  // magnitudes of the per-pixel terms summed into them (the scale of the summation)
   const bool want_scale = s_means != nullptr;
-  std::vector<std::vector<double>> acc(nth, std::vector<double>((size_t)nv * 9, 0.0));
-  std::vector<std::vector<double>> accm(want_scale ? nth : 0, std::vector<double>((size_t)nv * 9, 0.0));
+  std::vector<double> acc((size_t)nv * 9, 0.0);
+  std::vector<double> accm(want_scale ? (size_t)nv * 9 : 0, 0.0);
 #pragma omp parallel
   {
-    std::vector<double>& A = acc[omp_get_thread_num()];
-    double* Am = want_scale ? accm[omp_get_thread_num()].data() : nullptr;
+    double* A = acc.data();
+    double* Am = want_scale ? accm.data() : nullptr;
     std::vector<Contrib> rec;
 #pragma omp for schedule(dynamic, 16)
     for (int64_t p = 0; p < npix; ++p) {
@@ -533,25 +535,44 @@ void or_grad(int64_t n, int64_t nv, const int64_t* order, const double* means, c
       for (size_t r = rec.size(); r-- > 0;) {
         const Contrib& e = rec[r];
         const Gauss64& g = G[e.k];
-        double* a = &A[(size_t)e.k * 9];
+        double* a = A + (size_t)e.k * 9;
         double* am = Am ? Am + (size_t)e.k * 9 : nullptr;
-        double dalpha = 0.0;
+        double dalpha = 0.0, dalpha_mag = 0.0;
+        double t[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int ch = 0; ch < 3; ++ch) {
-          a[6 + ch] += e.alpha * e.T * dC[ch];
-          if (am) am[6 + ch] += std::fabs(e.alpha * e.T * dC[ch]);
+          t[6 + ch] = e.alpha * e.T * dC[ch];
           dalpha += dC[ch] * (e.T * g.rgb[ch] - S[ch] / (1.0 - e.alpha));
+          dalpha_mag += std::fabs(dC[ch]) * (e.T * std::fabs(g.rgb[ch]) + std::fabs(S[ch]) / (1.0 - e.alpha));
           S[ch] += e.alpha * e.T * g.rgb[ch];
         }
-        if (e.clamp) continue;   // alpha = 0.99 does not depend on o or q
-        a[5] += dalpha * e.G;
-        double dq = dalpha * (-0.5 * e.alpha);
-        // q = ca dx^2 + 2 cb dx dy + cc dy^2, dx = px - mx
-        double t[5] = {dq * (-2.0 * (g.ca * e.dx + g.cb * e.dy)), dq * (-2.0 * (g.cb * e.dx + g.cc * e.dy)),
-                       dq * e.dx * e.dx, dq * 2.0 * e.dx * e.dy, dq * e.dy * e.dy};
-        for (int j = 0; j < 5; ++j) a[j] += t[j];
-        if (am) {
-          am[5] += std::fabs(dalpha * e.G);
-          for (int j = 0; j < 5; ++j) am[j] += std::fabs(t[j]);
+        // magnitudes of the same terms with dL/dalpha replaced by the size of the two parts
+        // it is the difference of (the scale at which a float evaluation can resolve it)
+        double tm[9];
+        for (int j = 0; j < 9; ++j) tm[j] = std::fabs(t[j]);
+        if (!e.clamp) {   // alpha = 0.99 does not depend on o or q
+          t[5] = dalpha * e.G;
+          double dq = dalpha * (-0.5 * e.alpha);
+          // q = ca dx^2 + 2 cb dx dy + cc dy^2, dx = px - mx
+          t[0] = dq * (-2.0 * (g.ca * e.dx + g.cb * e.dy));
+          t[1] = dq * (-2.0 * (g.cb * e.dx + g.cc * e.dy));
+          t[2] = dq * e.dx * e.dx;
+          t[3] = dq * 2.0 * e.dx * e.dy;
+          t[4] = dq * e.dy * e.dy;
+          const double dqm = dalpha_mag * 0.5 * e.alpha;
+          tm[5] = dalpha_mag * e.G;
+          tm[0] = dqm * 2.0 * (std::fabs(g.ca * e.dx) + std::fabs(g.cb * e.dy));
+          tm[1] = dqm * 2.0 * (std::fabs(g.cb * e.dx) + std::fabs(g.cc * e.dy));
+          tm[2] = dqm * e.dx * e.dx;
+          tm[3] = dqm * 2.0 * std::fabs(e.dx * e.dy);
+          tm[4] = dqm * e.dy * e.dy;
+        }
+        for (int j = 0; j < 9; ++j) {
+#pragma omp atomic
+          a[j] += t[j];
+          if (am) {
+#pragma omp atomic
+            am[j] += tm[j];
+          }
         }
       }
     }
@@ -561,6 +582,8 @@ void or_grad(int64_t n, int64_t nv, const int64_t* order, const double* means, c
   std::memset(g_q, 0, sizeof(double) * n * 4);
   std::memset(g_logit, 0, sizeof(double) * n);
   std::memset(g_sh, 0, sizeof(double) * n * 48);
+  if (g2d) std::memset(g2d, 0, sizeof(double) * n * 9);
+  if (s2d) std::memset(s2d, 0, sizeof(double) * n * 9);
   if (want_scale) {
     std::memset(s_means, 0, sizeof(double) * n * 3);
     std::memset(s_ls, 0, sizeof(double) * n * 3);
@@ -572,15 +595,18 @@ void or_grad(int64_t n, int64_t nv, const int64_t* order, const double* means, c
 #pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < nv; ++k) {
     double d2[9] = {0}, m2[9] = {0};
-    for (int t = 0; t < nth; ++t)
-      for (int j = 0; j < 9; ++j) {
-        d2[j] += acc[t][(size_t)k * 9 + j];
-        if (want_scale) m2[j] += accm[t][(size_t)k * 9 + j];
-      }
+    for (int j = 0; j < 9; ++j) {
+      d2[j] = acc[(size_t)k * 9 + j];
+      if (want_scale) m2[j] = accm[(size_t)k * 9 + j];
+    }
+    int64_t g = order[k];
+    if (g2d)
+      for (int j = 0; j < 9; ++j) g2d[g * 9 + j] = d2[j];
+    if (s2d && want_scale)
+      for (int j = 0; j < 9; ++j) s2d[g * 9 + j] = m2[j];
     bool any = false;
     for (int j = 0; j < 9; ++j) any = any || d2[j] != 0.0;
     if (!any) continue;
-    int64_t g = order[k];
     Dual mu[3], s[3], qq[4], lg;
     for (int i = 0; i < 3; ++i) { mu[i] = Dual::var(means[g * 3 + i], i); s[i] = Dual::var(ls[g * 3 + i], 3 + i); }
     for (int i = 0; i < 4; ++i) qq[i] = Dual::var(q[g * 4 + i], 6 + i);

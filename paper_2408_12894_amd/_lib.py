@@ -46,7 +46,8 @@ class Camera(C.Structure):
 
 
 class Frame(C.Structure):
-    _fields_ = [("image", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p)]
+    _fields_ = [("image", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
+                ("n_blended", C.c_void_p)]
 
 
 class Grads(C.Structure):
@@ -62,7 +63,8 @@ class Stats(C.Structure):
 class View(C.Structure):
     _fields_ = [("tile_ids", C.c_void_p), ("values", C.c_void_p), ("ranges", C.c_void_p),
                 ("depth_bits", C.c_void_p), ("rect", C.c_void_p), ("tiles_touched", C.c_void_p),
-                ("xy_conic", C.c_void_p), ("conic_c_opacity_rg", C.c_void_p), ("blue", C.c_void_p)]
+                ("xy_conic", C.c_void_p), ("conic_c_opacity_rg", C.c_void_p), ("blue", C.c_void_p),
+                ("grad2d", C.c_void_p)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)

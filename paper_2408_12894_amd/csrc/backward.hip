@@ -2,7 +2,8 @@
 //
 // Blend backward: one wave per tile (4 pixels per lane), walking the tile list back to
 // front from the last blended entry. The per-pixel transmittance before entry i is
-// recovered from the saved final T as T_i = T_{i+1} / (1 - alpha_i) (alpha <= 0.99), and
+// recovered from the saved final T as T_i = T_{i+1} / (1 - alpha_i) (alpha <= 0.99, FP64
+// reciprocal: the chain runs through up to thousands of contributors), and
 //   dC/dc_i     = alpha_i T_i
 //   dC/dalpha_i = T_i c_i - S_i / (1 - alpha_i),  S_i = sum_{j>i} alpha_j T_j c_j + T_final bg
 //               = T_i (c_i - Shat_i),  Shat_i = S_i / T_{i+1}
@@ -23,9 +24,19 @@ namespace flod {
 
 constexpr int kG2d = 9;   // mu'x, mu'y, conic a, b, c, opacity, red, green, blue
 
+// 1/x in FP64 from the hardware estimate and two Newton steps (x in [0.01, 1]).
+__device__ __forceinline__ double recip64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // One wave64 per tile, 4 pixels per lane (the forward's geometry). Per pixel the state is
 // T (transmittance after the current entry), V = dL/dC . Shat (the upstream gradient dotted
-// with the normalised colour behind the current entry) and dL/dC.
+// with the normalised colour behind the current entry) and dL/dC; T and V are FP64 because
+// both run through chains of up to thousands of contributors.
 // Per entry the lane sums its pixels' 9 gradient components in registers, the wave reduces
 // them with DPP and lane 63 issues one FP32 atomic per non-zero component.
 __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(const uint2 *__restrict__ ranges,
@@ -49,23 +60,24 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(const uint2 *__rest
   const int px = x0 + (lane & (kTile - 1));
   const float fx = (float)px + 0.5f;
   const size_t plane = (size_t)W * H;
-  float fy[kPix], T[kPix], V[kPix], d0[kPix], d1[kPix], d2[kPix];
+  float fy[kPix], d0[kPix], d1[kPix], d2[kPix];
+  double T[kPix], V[kPix];
   int last[kPix];
   int mylast = 0;
 #pragma unroll
   for (int k = 0; k < kPix; ++k) {
     const int py = y0 + (lane >> 4) + kRowStep * k;
     fy[k] = (float)py + 0.5f;
-    T[k] = 1.0f; V[k] = 0.0f; d0[k] = 0.0f; d1[k] = 0.0f; d2[k] = 0.0f;
+    T[k] = 1.0; V[k] = 0.0; d0[k] = 0.0f; d1[k] = 0.0f; d2[k] = 0.0f;
     last[k] = 0;
     if (px < W && py < H) {
       const size_t pix = (size_t)py * W + px;
-      T[k] = final_T[pix];
+      T[k] = (double)final_T[pix];
       last[k] = n_contrib[pix];
       d0[k] = dimg[pix];
       d1[k] = dimg[plane + pix];
       d2[k] = dimg[2 * plane + pix];
-      V[k] = d0[k] * bg0 + d1[k] * bg1 + d2[k] * bg2;
+      V[k] = (double)(d0[k] * bg0 + d1[k] * bg1 + d2[k] * bg2);
       mylast = max(mylast, last[k]);
     }
   }
@@ -105,16 +117,16 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(const uint2 *__rest
         const float alpha = fminf(kAlphaMax, a0);
         if (alpha < kAlphaMin) continue;
         contrib = true;
-        const float inv = 1.0f / (1.0f - alpha);
-        const float Ti = T[k] * inv;
+        const double Ti64 = T[k] * recip64(1.0 - (double)alpha);
+        const float Ti = (float)Ti64;
         const float wT = alpha * Ti;
         const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * c2;   // dL/dC . c
-        const float dalpha = Ti * (dcc - V[k]);
+        const float dalpha = (float)(Ti64 * ((double)dcc - V[k]));
         gr[6] = fmaf(wT, d0[k], gr[6]);
         gr[7] = fmaf(wT, d1[k], gr[7]);
         gr[8] = fmaf(wT, d2[k], gr[8]);
-        V[k] = fmaf(alpha, dcc - V[k], V[k]);   // alpha dcc + (1 - alpha) V
-        T[k] = Ti;
+        V[k] = fma((double)alpha, (double)dcc - V[k], V[k]);   // alpha dcc + (1 - alpha) V
+        T[k] = Ti64;
         if (a0 <= kAlphaMax) {
           gr[5] = fmaf(dalpha, G, gr[5]);
           const float dq = -0.5f * alpha * dalpha;

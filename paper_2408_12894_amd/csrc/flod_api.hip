@@ -35,6 +35,7 @@ struct Saved {
   int sorted_vals = 0;   // which of B_TVAL0/B_TVAL1 holds the sorted values
   int sorted_keys = 0;
   int depth_buf = 0;
+  bool has_grad2d = false;
 };
 
 }  // namespace
@@ -181,6 +182,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   c->required = 0;
   c->last_stream = s;
   c->saved.valid = false;
+  c->saved.has_grad2d = false;
   timing_flush(c);
   StageTimer tm(c, s);
   const int64_t N = p.n_total;
@@ -311,7 +313,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   tm.end();
   tm.begin(FLOD_STAGE_BLEND);
   if (launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP), P<float>(c, B_BLUE),
-                   cam, bg, out->image, out->final_T, out->n_contrib, s) != hipSuccess)
+                   cam, bg, out->image, out->final_T, out->n_contrib, out->n_blended, s) != hipSuccess)
     return FLOD_ERR_DEVICE;
   tm.end();
   Saved &sv = c->saved;
@@ -505,6 +507,7 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   p.n_total = N;
   if (launch_preprocess_bwd(p, P<uint32_t>(ctx, B_TILES), g2d, N, *grads, s) != hipSuccess) return FLOD_ERR_DEVICE;
   tm.end();
+  ctx->saved.has_grad2d = true;
   return FLOD_OK;
 }
 
@@ -529,6 +532,7 @@ flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out) {
   out->xy_conic = P<float>(c, B_XYAB);
   out->conic_c_opacity_rg = P<float>(c, B_COP);
   out->blue = P<float>(c, B_BLUE);
+  out->grad2d = sv.has_grad2d ? P<float>(c, B_G2D) : nullptr;
   return FLOD_OK;
 }
 

@@ -107,17 +107,20 @@ class Renderer:
             pass
 
     # ------------------------------------------------------------------ forward
-    def _frame(self, cam, device):
+    def _frame(self, cam, device, n_blended=None):
         H, W = int(cam.height), int(cam.width)
         image = torch.empty((3, H, W), dtype=torch.float32, device=device)
         final_T = torch.empty((H, W), dtype=torch.float32, device=device)
         n_contrib = torch.empty((H, W), dtype=torch.int32, device=device)
-        fr = _lib.Frame(image.data_ptr(), final_T.data_ptr(), n_contrib.data_ptr())
+        fr = _lib.Frame(image.data_ptr(), final_T.data_ptr(), n_contrib.data_ptr(),
+                        n_blended.data_ptr() if n_blended is not None else None)
         return image, final_T, n_contrib, fr
 
-    def render_level(self, level: GaussianLevel, cam, bg=(0.0, 0.0, 0.0), sh_degree: int = 3, stream=None):
-        """Single-level render. Returns (image [3,H,W], final_T [H,W], n_contrib [H,W])."""
-        image, final_T, n_contrib, fr = self._frame(cam, level.means.device)
+    def render_level(self, level: GaussianLevel, cam, bg=(0.0, 0.0, 0.0), sh_degree: int = 3, stream=None,
+                     n_blended: torch.Tensor | None = None):
+        """Single-level render. Returns (image [3,H,W], final_T [H,W], n_contrib [H,W]); the
+        optional int32 [H,W] tensor n_blended receives the per-pixel blended count."""
+        image, final_T, n_contrib, fr = self._frame(cam, level.means.device, n_blended)
         lv = level.c_struct()
         cs = camera_struct(cam)
         st = self.L.flod_render_level(self.ctx, C.byref(lv), int(sh_degree), C.byref(cs), _floats(bg, 3),
@@ -217,7 +220,8 @@ class Renderer:
                     tiles_touched=get(v.tiles_touched, N, np.uint32),
                     xy_conic=get(v.xy_conic, 4 * N, np.float32).reshape(N, 4),
                     cop=get(v.conic_c_opacity_rg, 4 * N, np.float32).reshape(N, 4),
-                    blue=get(v.blue, N, np.float32), stats=s)
+                    blue=get(v.blue, N, np.float32), stats=s,
+                    grad2d=get(v.grad2d, 9 * N, np.float32).reshape(9, N) if v.grad2d else None)
 
 
 def smin_schedule(l: int, l_max: int, lam: float = 0.2, rho: float = 4.0) -> float:

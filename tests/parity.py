@@ -57,7 +57,8 @@ def check_instances(view, k, index_offset=0):
     return tile, val, ranges
 
 
-def check_image(image, final_T, n_contrib, ref, view, cam, index_offset=0, tol=IMG_TOL, frac_max=FLAG_FRAC_MAX):
+def check_image(image, final_T, n_contrib, ref, view, cam, index_offset=0, tol=IMG_TOL, frac_max=FLAG_FRAC_MAX,
+                n_blended=None):
     """Compare GPU outputs with O2 at ref['pix']; returns (max error, flagged fraction)."""
     pix = ref["pix"]
     xs, ys = pix[:, 0], pix[:, 1]
@@ -81,6 +82,9 @@ def check_image(image, final_T, n_contrib, ref, view, cam, index_offset=0, tol=I
     sel = ok & has
     last_gpu = view["values"][start[sel] + gn[sel] - 1].astype(np.int64) + index_offset
     np.testing.assert_array_equal(last_gpu, ref["last"][sel], err_msg="last blended Gaussian")
+    if n_blended is not None:
+        gb = np.asarray(n_blended)[ys, xs].astype(np.int64)
+        np.testing.assert_array_equal(gb[ok], ref["nblend"][ok].astype(np.int64), err_msg="blended count")
     return float(err), float(frac)
 
 

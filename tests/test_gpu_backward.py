@@ -56,6 +56,15 @@ def grad_parity(renderer, scene, cam, bg, deg=3, pix=None, seed=0):
     torch.cuda.synchronize()
     go = oracle.grad(order, *scene.arrays()[:4], scene.s_min, scene.sh, deg, cam, bg, pix, w64, with_scale=True)
     worst = {}
+    g2d = renderer.view()["grad2d"].T.astype(np.float64)        # [n, 9]
+    g2d_names = ("mu_x", "mu_y", "conic_a", "conic_b", "conic_c", "opacity", "red", "green", "blue")
+    allowed = GRAD_TOL * np.maximum(1.0, np.abs(go["g2d"])) + SUM_TOL * go["scale"]["g2d"]
+    ratio = np.abs(g2d - go["g2d"]) / allowed
+    worst["2d"] = float(ratio.max())
+    if ratio.max() > 1.0:
+        i = np.unravel_index(ratio.argmax(), ratio.shape)
+        raise AssertionError(f"2D gradient {g2d_names[i[1]]} of Gaussian {i[0]}: gpu {g2d[i]:.6g} oracle "
+                             f"{go['g2d'][i]:.6g} allowed {allowed[i]:.3g}; entries over {(ratio > 1).sum()}")
     for name in NAMES:
         a = g[name].cpu().numpy().astype(np.float64).reshape(scene.n, -1)
         b = go[name].reshape(scene.n, -1)

@@ -29,9 +29,11 @@ def _say(msg):
 def gpu_render(renderer, scene, cam, bg, deg=3):
     from paper_2408_12894_amd import render
     level = render.GaussianLevel.from_scene(scene)
-    image, final_T, n_contrib = renderer.render_level(level, cam, bg, deg)
+    nbl = torch.empty((cam.height, cam.width), dtype=torch.int32, device="cuda")
+    image, final_T, n_contrib = renderer.render_level(level, cam, bg, deg, n_blended=nbl)
     torch.cuda.synchronize()
     view = renderer.view()
+    view["n_blended"] = nbl.cpu().numpy()
     return image.cpu().numpy(), final_T.cpu().numpy(), n_contrib.cpu().numpy(), view
 
 
@@ -42,7 +44,7 @@ def full_parity(renderer, scene, cam, bg, deg=3, pix=None, frac_max=2e-2):
     check_instances(view, k)
     order = oracle.depth_order(k)
     ref = oracle.image(order, *scene.arrays()[:4], scene.s_min, scene.sh, deg, cam, bg, pix)
-    err, frac = check_image(image, T, nc, ref, view, cam, frac_max=frac_max)
+    err, frac = check_image(image, T, nc, ref, view, cam, frac_max=frac_max, n_blended=view["n_blended"])
     vis = np.nonzero(k["visible"])[0]
     if vis.size:
         p64 = oracle.project64(vis, *scene.arrays()[:4], scene.s_min, scene.sh, deg, cam)
