@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB mebibytes device-to-device 10 times (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -74,16 +76,16 @@ def timed(fn, n, warm, sync):
 def algorithmic_bytes(stage, N, n_vis, K, P, tiles):
     """Bytes a stage must move (one launch), per its definition in the design doc."""
     return {
-        "preprocess": (236 + 52) * N,
+        "preprocess": (236 + 56) * N,
         "compact": 8 * N + 8 * n_vis,
         "depth_sort": 4 * 2 * 8 * n_vis,
         "offsets": 8 * n_vis,
-        "emit": 16 * n_vis + 8 * K,
+        "emit": 28 * n_vis + 8 * K,
         "tile_sort": 2 * (4 + 16) * K,
         "ranges": 4 * K + 8 * tiles,
-        "blend": 40 * K + 20 * P,
-        "blend_bwd": 40 * K + 20 * P + 12 * P + 36 * K,
-        "preprocess_bwd": (236 + 52 + 36 + 236) * N,
+        "blend": 44 * K + 20 * P,
+        "blend_bwd": 44 * K + 20 * P + 12 * P + 36 * K,
+        "preprocess_bwd": (236 + 56 + 36 + 236) * N,
     }[stage]
 
 
@@ -99,6 +101,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration << 18            # float32 elements in MIB mebibytes
+        src = torch.ones(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 10}), flush=True)
+        return
     dev = torch.device("cuda:0")
     sync = torch.cuda.synchronize
     bg = (0.0, 0.0, 0.0)

@@ -165,9 +165,11 @@ typedef struct {
   const uint32_t *depth_bits;   /* [n_candidates] bits of the view-space depth (FP32)       */
   const uint32_t *rect;         /* [n_candidates,2] (x0 | y0<<16, x1 | y1<<16) inclusive    */
   const uint32_t *tiles_touched;/* [n_candidates] 0 = not rendered                          */
-  const float *xy_conic;        /* [n_candidates,4] mu'x, mu'y, conic a, conic b            */
+  const float *xy_conic;        /* [n_candidates,4] mu'x, mu'y (FP32 rounding of the FP64
+                                   projection), conic a, conic b                            */
   const float *conic_c_opacity_rg; /* [n_candidates,4] conic c, opacity, red, green         */
-  const float *blue;            /* [n_candidates] */
+  const float *blue;            /* [n_candidates,2] blue, and (bits) the residual of mu' as
+                                   two bf16: x in the low half, y in the high half          */
   const float *grad2d;          /* [9, n_candidates] after flod_render_backward: dL/d(mu'x,
                                    mu'y, conic a, b, c, opacity, red, green, blue), with b
                                    the off-diagonal conic entry; NULL before a backward   */

@@ -5,7 +5,8 @@ CPU-baseline leg. The product package never imports this module, and this module
 imports the product package (it only receives the same seeded numpy inputs).
 
 Parts (see oracle.cpp for the arithmetic):
-  keys()          O1 FP32 key mirror per Gaussian (culls, depth bits, radius, tile rect)
+  keys()          O1 key mirror per Gaussian (culls, depth bits, tile footprint and its
+                  bounding rectangle, stored FP32 mu' with its bf16 residual and conic)
   instances()     O1 instance list sorted by (tile, depth bits, index) and tile ranges
   depth_order()   surviving ids in (depth bits, index) order: the compositing order
   image()         O2 FP64 brute-force image at chosen pixels, with ambiguity flags
@@ -77,8 +78,8 @@ def lib():
         L.or_get_threads.restype = C.c_int
         L.or_sh_basis.argtypes = [C.c_int, vp, vp]
         L.or_select_level.argtypes = [i64, vp, vp, f32, f32, vp]
-        L.or_keys.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
-        L.or_instances.argtypes = [i64, vp, vp, vp, i32, i32, i64, vp, vp, vp]
+        L.or_keys.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.or_instances.argtypes = [i64, vp, vp, vp, vp, i32, i32, i64, vp, vp, vp]
         L.or_instances.restype = i64
         L.or_project64.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp]
         L.or_image.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -143,7 +144,7 @@ def select(levels_means, centre, l_start: int, l_end: int, d_proj) -> np.ndarray
 
 
 # ----------------------------------------------------------------------------------
-# O1: FP32 key mirror
+# O1: key mirror
 # ----------------------------------------------------------------------------------
 
 def _arrays(means, log_scales, quats, logits, smin, dt=np.float32):
@@ -159,11 +160,11 @@ def keys(means, log_scales, quats, logits, smin, cam, keep=None) -> dict:
     out = dict(visible=np.zeros(n, np.uint8), depth_bits=np.zeros(n, np.uint32),
                rect=np.zeros((n, 4), np.int32), tiles=np.zeros(n, np.uint32),
                radius=np.zeros(n, np.float32), mxy=np.zeros((n, 2), np.float32),
-               conic=np.zeros((n, 3), np.float32))
+               conic=np.zeros((n, 3), np.float32), mu_lo=np.zeros(n, np.uint32))
     c = _cam(cam)
     lib().or_keys(n, _p(m), _p(ls), _p(q), _p(lg), _p(sm), None if kp is None else _p(kp), C.byref(c),
                   _p(out["visible"]), _p(out["depth_bits"]), _p(out["rect"]), _p(out["tiles"]),
-                  _p(out["radius"]), _p(out["mxy"]), _p(out["conic"]))
+                  _p(out["radius"]), _p(out["mxy"]), _p(out["conic"]), _p(out["mu_lo"]))
     out["tiles_x"] = (int(cam.width) + TILE - 1) // TILE
     out["tiles_y"] = (int(cam.height) + TILE - 1) // TILE
     return out
@@ -177,8 +178,8 @@ def instances(k: dict):
     tile = np.zeros(max(K, 1), np.uint32)
     val = np.zeros(max(K, 1), np.uint32)
     ranges = np.zeros((n_tiles, 2), np.uint32)
-    got = lib().or_instances(n, _p(k["visible"]), _p(k["depth_bits"]), _p(k["rect"]), k["tiles_x"], n_tiles,
-                             K, _p(tile), _p(val), _p(ranges))
+    got = lib().or_instances(n, _p(k["visible"]), _p(k["depth_bits"]), _p(k["mxy"]), _p(k["conic"]),
+                             k["tiles_x"], k["tiles_y"], K, _p(tile), _p(val), _p(ranges))
     assert got == K
     return tile[:K], val[:K], ranges
 

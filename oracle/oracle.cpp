@@ -6,9 +6,11 @@
 //
 // Three parts, each a plain definition with no tiling, blocking or early-out beyond what
 // the definition itself states:
-//   O1  FP32 key mirror: per-Gaussian discrete decisions (selection, culls, depth bits,
-//       integer radius, tile rectangle) in IEEE single precision, no contraction,
-//       followed by std::sort of the (tile, depth bits, index) instance list.
+//   O1  key mirror: per-Gaussian discrete decisions (selection, culls, depth bits, tile
+//       footprint) and the stored FP32 projection (mu' and its bf16 residual,
+//       conic), from the FP64 projection of the FP32 inputs in a fixed operation order with
+//       no contraction and the scale's exp rounded once to FP32, followed by std::sort of
+//       the (tile, depth bits, index) instance list.
 //   O2  FP64 image: every pixel loops over all surviving Gaussians in O1 depth order
 //       and composites front to back in double precision.
 //   O3  FP64 gradient: per-pixel reverse compositing in double, then the per-Gaussian
@@ -193,7 +195,8 @@ template <class T> struct Proj {
 
 template <class T>
 void project(const T mu[3], const T ls[3], const T qv[4], const T& logit, const T& smin,
-             const double* sh, int deg, const Cam<T>& cam, bool with_colour, Proj<T>& p) {
+             const double* sh, int deg, const Cam<T>& cam, bool with_colour, Proj<T>& p,
+             bool scale_exp_fp32 = false) {
   const T* Rc = cam.R;
   // view transform t = R_c mu + t_c
   p.tx = ((Rc[0] * mu[0] + Rc[1] * mu[1]) + Rc[2] * mu[2]) + cam.t[0];
@@ -201,7 +204,12 @@ void project(const T mu[3], const T ls[3], const T qv[4], const T& logit, const 
   p.tz = ((Rc[6] * mu[0] + Rc[7] * mu[1]) + Rc[8] * mu[2]) + cam.t[2];
   // eq. 4: s = exp(s_opt) + s_min
   T s[3];
-  for (int i = 0; i < 3; ++i) s[i] = ex(ls[i]) + smin;
+  for (int i = 0; i < 3; ++i) {
+    if (scale_exp_fp32)   // exp evaluated in FP64 and rounded once to FP32 (the key mirror)
+      s[i] = T(double((float)std::exp(val(ls[i])))) + smin;
+    else
+      s[i] = ex(ls[i]) + smin;
+  }
   // unit quaternion (w, x, y, z)
   T n2 = ((qv[0] * qv[0] + qv[1] * qv[1]) + qv[2] * qv[2]) + qv[3] * qv[3];
   p.qzero = !(val(n2) > 0.0);
@@ -286,43 +294,106 @@ void project(const T mu[3], const T ls[3], const T qv[4], const T& logit, const 
 // O1 result for one Gaussian.
 struct KeyOut {
   uint8_t visible;
-  uint32_t depth_bits;
+  uint32_t depth_bits;   // bits of float(t_z)
   int32_t rect[4];       // xmin, ymin, xmax, ymax (inclusive tiles)
   uint32_t tiles;
   float radius;
-  float mx, my, ca, cb, cc;
+  float mx, my, ca, cb, cc;   // FP32 roundings of mu' and the conic
+  uint32_t mu_lo;        // bf16 residuals of mu': x in the low half, y in the high half
 };
 
-void key_one(const float* mu, const float* ls, const float* q, float logit, float smin,
-             const Cam<float>& cam, int tiles_x, int tiles_y, KeyOut& o) {
+// Tile footprint of a Gaussian from its stored FP32 mu' and conic: per tile row, the tiles
+// whose [16 tx, 16 tx + 16) meets the x-extent of the ellipse d^T conic d <= Q (Q = 9.009)
+// over the row's band of pixel centres. FP64, fixed operation order.
+struct Span { int ty, tx0, tx1; };
+const double kQSpan = 9.009;
+
+int footprint_spans(float mxf, float myf, float af, float bf, float cf, int tiles_x, int tiles_y, Span* out,
+                    int max_rows) {
+  const double mx = mxf, my = myf, a = af, b = bf, c = cf;
+  const double det = a * c - b * b;
+  if (!(det > 0.0) || !(a > 0.0)) return 0;
+  const double sxx = c / det, syy = a / det, sxy = -b / det;
+  const double hx = std::sqrt(kQSpan * sxx);
+  const double hy = std::sqrt(kQSpan * syy);
+  const double dyr = sxy * std::sqrt(kQSpan / sxx);
+  double y0 = std::floor((my - hy) * 0.0625);
+  double y1 = std::floor((my + hy) * 0.0625);
+  y0 = std::max(y0, 0.0);
+  y1 = std::min(y1, (double)(tiles_y - 1));
+  if (!(y0 <= y1)) return 0;
+  int n = 0;
+  for (int ty = (int)y0; ty <= (int)y1 && n < max_rows; ++ty) {
+    // band of pixel-centre offsets in this row, clipped to the ellipse's y-extent
+    const double dlo = std::max((16.0 * ty + 0.5) - my, -hy);
+    const double dhi = std::min((16.0 * ty + 15.5) - my, hy);
+    if (!(dlo <= dhi)) continue;
+    const double qa = kQSpan * a;
+    const double rlo = std::sqrt(std::max(0.0, qa - det * dlo * dlo));
+    const double rhi = std::sqrt(std::max(0.0, qa - det * dhi * dhi));
+    // x = (-b dy +/- sqrt(Q a - det dy^2)) / a; the extreme points sit at dy = +/- dyr
+    const double right = (dlo <= dyr && dyr <= dhi) ? hx : std::max((-b * dlo + rlo) / a, (-b * dhi + rhi) / a);
+    const double left = (dlo <= -dyr && -dyr <= dhi) ? -hx : std::min((-b * dlo - rlo) / a, (-b * dhi - rhi) / a);
+    double x0 = std::floor((mx + left) * 0.0625);
+    double x1 = std::floor((mx + right) * 0.0625);
+    x0 = std::max(x0, 0.0);
+    x1 = std::min(x1, (double)(tiles_x - 1));
+    if (!(x0 <= x1)) continue;
+    out[n++] = Span{ty, (int)x0, (int)x1};
+  }
+  return n;
+}
+
+// Round to nearest even to bf16, kept in the upper 16 bits (finite inputs).
+uint32_t bf16_rne(float v) {
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  uint32_t lsb = (u >> 16) & 1u;
+  return (u + 0x7FFFu + lsb) & 0xFFFF0000u;
+}
+
+void key_one(const float* muf, const float* lsf, const float* qf, float logit, float smin,
+             const Cam<double>& cam, int tiles_x, int tiles_y, KeyOut& o) {
   std::memset(&o, 0, sizeof(o));
-  Proj<float> p;
-  project<float>(mu, ls, q, logit, smin, nullptr, 0, cam, false, p);
+  double mu[3], ls[3], q[4];
+  for (int i = 0; i < 3; ++i) { mu[i] = muf[i]; ls[i] = lsf[i]; }
+  for (int i = 0; i < 4; ++i) q[i] = qf[i];
+  Proj<double> p;
+  project<double>(mu, ls, q, (double)logit, (double)smin, nullptr, 0, cam, false, p, true);
   // culls: near plane, opacity below 1/255 (logit compared in FP32), zero quaternion
   const float logit_min = (float)(-std::log(254.0));
-  if (!(p.tz > K<float>::near_z)) return;
+  if (!(p.tz > K<double>::near_z)) return;
   if (logit < logit_min) return;
   if (p.qzero) return;
-  if (!(p.det > 0.0f)) return;
-  float m = K<float>::half * (p.a + p.c);
-  float disc = m * m - p.det;
-  float lam = m + std::sqrt(std::max(K<float>::eig_floor, disc));
-  float r = std::ceil(K<float>::three * std::sqrt(lam));
-  float x0 = std::floor((p.mx - r) * K<float>::tile_inv);
-  float x1 = std::floor((p.mx + r) * K<float>::tile_inv);
-  float y0 = std::floor((p.my - r) * K<float>::tile_inv);
-  float y1 = std::floor((p.my + r) * K<float>::tile_inv);
-  x0 = std::max(x0, 0.0f);
-  y0 = std::max(y0, 0.0f);
-  x1 = std::min(x1, (float)(tiles_x - 1));
-  y1 = std::min(y1, (float)(tiles_y - 1));
-  if (!(x0 <= x1) || !(y0 <= y1)) return;
+  if (!(p.det > 0.0)) return;
+  double m = K<double>::half * (p.a + p.c);
+  double disc = m * m - p.det;
+  double lam = m + std::sqrt(std::max(K<double>::eig_floor, disc));
+  double r = std::ceil(K<double>::three * std::sqrt(lam));
+  o.mx = (float)p.mx; o.my = (float)p.my;
+  o.ca = (float)p.ca; o.cb = (float)p.cb; o.cc = (float)p.cc;
+  std::vector<Span> sp((size_t)tiles_y);
+  int ns = footprint_spans(o.mx, o.my, o.ca, o.cb, o.cc, tiles_x, tiles_y, sp.data(), tiles_y);
+  uint32_t count = 0;
+  int rx0 = 0xFFFF, rx1 = 0;
+  for (int k = 0; k < ns; ++k) {
+    count += (uint32_t)(sp[k].tx1 - sp[k].tx0 + 1);
+    rx0 = std::min(rx0, sp[k].tx0);
+    rx1 = std::max(rx1, sp[k].tx1);
+  }
+  if (count == 0) return;
+  // rectangle reported: tile rows of the footprint's y-extent, columns of the spans
+  const double sy = std::sqrt(kQSpan * ((double)o.ca / ((double)o.ca * o.cc - (double)o.cb * o.cb)));
+  double y0 = std::max(std::floor(((double)o.my - sy) * 0.0625), 0.0);
+  double y1 = std::min(std::floor(((double)o.my + sy) * 0.0625), (double)(tiles_y - 1));
   o.visible = 1;
-  std::memcpy(&o.depth_bits, &p.tz, 4);
-  o.rect[0] = (int32_t)x0; o.rect[1] = (int32_t)y0; o.rect[2] = (int32_t)x1; o.rect[3] = (int32_t)y1;
-  o.tiles = (uint32_t)((o.rect[2] - o.rect[0] + 1) * (o.rect[3] - o.rect[1] + 1));
-  o.radius = r;
-  o.mx = p.mx; o.my = p.my; o.ca = p.ca; o.cb = p.cb; o.cc = p.cc;
+  float tzf = (float)p.tz;
+  std::memcpy(&o.depth_bits, &tzf, 4);
+  o.rect[0] = rx0; o.rect[1] = (int32_t)y0; o.rect[2] = rx1; o.rect[3] = (int32_t)y1;
+  o.tiles = count;
+  o.radius = (float)r;
+  uint32_t lx = bf16_rne((float)(p.mx - (double)o.mx)), ly = bf16_rne((float)(p.my - (double)o.my));
+  o.mu_lo = (lx >> 16) | ly;
 }
 
 inline bool near_rel(double x, double thr) { return std::fabs(x - thr) <= 1e-4 * std::fabs(thr); }
@@ -411,8 +482,8 @@ void or_select_level(int64_t n, const float* means, const float* centre, float l
 void or_keys(int64_t n, const float* means, const float* ls, const float* q, const float* logits,
              const float* smin, const uint8_t* keep, const CamIn* camin,
              uint8_t* visible, uint32_t* depth_bits, int32_t* rect, uint32_t* tiles, float* radius,
-             float* mxy, float* conic) {
-  Cam<float> cam = cam_as<float>(*camin);
+             float* mxy, float* conic, uint32_t* mu_lo) {
+  Cam<double> cam = cam_as<double>(*camin);
   int tx = (cam.W + TILE - 1) / TILE, ty = (cam.H + TILE - 1) / TILE;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
@@ -429,21 +500,26 @@ void or_keys(int64_t n, const float* means, const float* ls, const float* q, con
     radius[i] = o.radius;
     mxy[i * 2 + 0] = o.mx; mxy[i * 2 + 1] = o.my;
     conic[i * 3 + 0] = o.ca; conic[i * 3 + 1] = o.cb; conic[i * 3 + 2] = o.cc;
+    mu_lo[i] = o.mu_lo;
   }
 }
 
-// O1: instance list sorted by (tile, depth bits, index); tile rect enumerated row-major.
-// Returns K; writes at most cap entries. ranges: [2 * n_tiles] (start, end).
-int64_t or_instances(int64_t n, const uint8_t* visible, const uint32_t* depth_bits, const int32_t* rect,
-                     int32_t tiles_x, int32_t n_tiles, int64_t cap, uint32_t* out_tile, uint32_t* out_val,
-                     uint32_t* ranges) {
+// O1: instance list sorted by (tile, depth bits, index); each visible Gaussian's footprint
+// enumerated row by row. Returns K; writes at most cap entries. ranges: [2 * n_tiles].
+int64_t or_instances(int64_t n, const uint8_t* visible, const uint32_t* depth_bits, const float* mxy,
+                     const float* conic, int32_t tiles_x, int32_t tiles_y, int64_t cap, uint32_t* out_tile,
+                     uint32_t* out_val, uint32_t* ranges) {
   struct E { uint32_t tile, depth, idx; };
+  const int32_t n_tiles = tiles_x * tiles_y;
   std::vector<E> v;
+  std::vector<Span> sp((size_t)tiles_y);
   for (int64_t i = 0; i < n; ++i) {
     if (!visible[i]) continue;
-    for (int y = rect[i * 4 + 1]; y <= rect[i * 4 + 3]; ++y)
-      for (int x = rect[i * 4 + 0]; x <= rect[i * 4 + 2]; ++x)
-        v.push_back(E{(uint32_t)(y * tiles_x + x), depth_bits[i], (uint32_t)i});
+    int ns = footprint_spans(mxy[2 * i], mxy[2 * i + 1], conic[3 * i], conic[3 * i + 1], conic[3 * i + 2], tiles_x,
+                             tiles_y, sp.data(), tiles_y);
+    for (int k = 0; k < ns; ++k)
+      for (int x = sp[k].tx0; x <= sp[k].tx1; ++x)
+        v.push_back(E{(uint32_t)(sp[k].ty * tiles_x + x), depth_bits[i], (uint32_t)i});
   }
   std::sort(v.begin(), v.end(), [](const E& a, const E& b) {
     if (a.tile != b.tile) return a.tile < b.tile;

@@ -14,8 +14,8 @@
 // Per entry the 9 gradient components are reduced across the wave with DPP and one FP32
 // atomic per component is issued per (tile, Gaussian).
 //
-// Preprocess backward: one thread per Gaussian, recomputing the forward projection and
-// applying the chain rule to the mean (through mu', the EWA Jacobian and the SH view
+// Preprocess backward: one thread per Gaussian, recomputing the forward projection (FP64)
+// and applying the chain rule in FP64 to the mean (through mu', the EWA Jacobian and the SH view
 // direction), log-scales (eq. 4: times exp(s_opt); s_min gets no gradient), quaternion
 // (through the normalisation), opacity logit (times o (1 - o)) and SH coefficients.
 #include "blend_common.h"
@@ -23,6 +23,10 @@
 namespace flod {
 
 constexpr int kG2d = 9;   // mu'x, mu'y, conic a, b, c, opacity, red, green, blue
+#ifndef FLOD_BWD_PIX
+#define FLOD_BWD_PIX 4
+#endif
+constexpr int kBwdPix = FLOD_BWD_PIX;   // pixels per thread: 4 = one wave64 per tile
 
 // 1/x in FP64 from the hardware estimate and two Newton steps (x in [0.01, 1]).
 __device__ __forceinline__ double recip64(double x) {
@@ -33,40 +37,40 @@ __device__ __forceinline__ double recip64(double x) {
   return fma(r, e, r);
 }
 
-// One wave64 per tile, 4 pixels per lane (the forward's geometry). Per pixel the state is
-// T (transmittance after the current entry), V = dL/dC . Shat (the upstream gradient dotted
-// with the normalised colour behind the current entry) and dL/dC; T and V are FP64 because
-// both run through chains of up to thousands of contributors.
-// Per entry the lane sums its pixels' 9 gradient components in registers, the wave reduces
-// them with DPP and lane 63 issues one FP32 atomic per non-zero component.
-__global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(const uint2 *__restrict__ ranges,
-                                                             const uint32_t *__restrict__ values,
-                                                             const float4 *__restrict__ xyab,
-                                                             const float4 *__restrict__ cop,
-                                                             const float *__restrict__ blue, int W, int H,
-                                                             int tiles_x, int n_tiles, float bg0, float bg1,
-                                                             float bg2, const float *__restrict__ final_T,
-                                                             const int32_t *__restrict__ n_contrib,
-                                                             const float *__restrict__ dimg,
-                                                             float *__restrict__ g2d, int64_t stride) {
+// One workgroup per tile with PPT pixels per thread (the forward's geometry). Per pixel
+// the state is T (transmittance after the current entry), V = dL/dC . Shat (the upstream
+// gradient dotted with the normalised colour behind the current entry) and dL/dC; T and V
+// are FP64 because both run through chains of up to thousands of contributors. Per entry
+// each thread sums its pixels' 9 gradient components in registers, each wave reduces them
+// with DPP and its lane 63 issues one FP32 atomic per non-zero component.
+template <int PPT>
+__global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
+    const uint2 *__restrict__ ranges, const uint32_t *__restrict__ values, const float4 *__restrict__ xyab,
+    const float4 *__restrict__ cop, const float2 *__restrict__ blue, int W, int H, int tiles_x, int n_tiles,
+    float bg0, float bg1, float bg2, const float *__restrict__ final_T, const int32_t *__restrict__ n_contrib,
+    const float *__restrict__ dimg, float *__restrict__ g2d, int64_t stride) {
+  constexpr int NT = kTile * kTile / PPT;
+  constexpr int ROWS = NT / kTile;
+  constexpr int WAVES = NT / 64;
   __shared__ float4 s_a[kBatch];
   __shared__ float4 s_b[kBatch];
-  __shared__ float s_c[kBatch];
+  __shared__ float2 s_c[kBatch];
   __shared__ uint32_t s_id[kBatch];
+  __shared__ int s_max[WAVES];
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   if (tile >= n_tiles) return;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
-  const int px = x0 + (lane & (kTile - 1));
+  const int px = x0 + (tid & (kTile - 1));
   const float fx = (float)px + 0.5f;
   const size_t plane = (size_t)W * H;
-  float fy[kPix], d0[kPix], d1[kPix], d2[kPix];
-  double T[kPix], V[kPix];
-  int last[kPix];
+  float fy[PPT], d0[PPT], d1[PPT], d2[PPT];
+  double T[PPT], V[PPT];
+  int last[PPT];
   int mylast = 0;
 #pragma unroll
-  for (int k = 0; k < kPix; ++k) {
-    const int py = y0 + (lane >> 4) + kRowStep * k;
+  for (int k = 0; k < PPT; ++k) {
+    const int py = y0 + (tid >> 4) + ROWS * k;
     fy[k] = (float)py + 0.5f;
     T[k] = 1.0; V[k] = 0.0; d0[k] = 0.0f; d1[k] = 0.0f; d2[k] = 0.0f;
     last[k] = 0;
@@ -83,12 +87,18 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(const uint2 *__rest
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mylast = max(mylast, __shfl_xor(mylast, o, 64));
+  if (WAVES > 1) {
+    if (lane == 0) s_max[tid >> 6] = mylast;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) mylast = max(mylast, s_max[w]);
+  }
   const uint2 rg = ranges[tile];
   for (int end = mylast; end > 0; end -= kBatch) {
     const int start = max(0, end - kBatch);
     const int cnt = end - start;
     __syncthreads();
-    for (int e = lane; e < cnt; e += kBlendThreads) {
+    for (int e = tid; e < cnt; e += NT) {
       const uint32_t g = values[rg.x + start + e];
       s_id[e] = g;
       s_a[e] = xyab[g];
@@ -100,16 +110,19 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(const uint2 *__rest
       const int jpos = start + jl;
       const float4 A = s_a[jl];
       const float4 B = s_b[jl];
-      const float c2 = s_c[jl];
-      const float dx = fx - A.x;
+      const float2 BL = s_c[jl];
+      const float c2 = BL.x;
+      const uint32_t lo = __float_as_uint(BL.y);
+      const float loy = mu_lo_y(lo);
+      const float dx = (fx - A.x) - mu_lo_x(lo);
       float gr[kG2d];
 #pragma unroll
       for (int c = 0; c < kG2d; ++c) gr[c] = 0.0f;
       bool contrib = false;
 #pragma unroll
-      for (int k = 0; k < kPix; ++k) {
+      for (int k = 0; k < PPT; ++k) {
         if (jpos >= last[k]) continue;
-        const float dy = fy[k] - A.y;
+        const float dy = (fy[k] - A.y) - loy;
         const float q = conic_q(A.z, A.w, B.x, dx, dy);
         if (q > kQCut) continue;
         const float G = __expf(-0.5f * q);
@@ -142,7 +155,7 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(const uint2 *__rest
 #pragma unroll
         for (int c = 0; c < kG2d; ++c) {
           const float v = wave_sum_to_lane63(gr[c]);
-          if (lane == kBlendThreads - 1 && v != 0.0f) atomicAdd(&g2d[c * stride + g], v);
+          if (lane == 63 && v != 0.0f) atomicAdd(&g2d[c * stride + g], v);
         }
       }
     }
@@ -150,14 +163,14 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_bwd(const uint2 *__rest
 }
 
 hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
-                            const float *blue, const DevCamera &cam, const float bg[3], const float *final_T,
+                            const float2 *blue, const DevCamera &cam, const float bg[3], const float *final_T,
                             const int32_t *n_contrib, const float *dL_dimage, float *g2d, int64_t g2d_stride,
                             hipStream_t s) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   const int grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
-  hipLaunchKernelGGL(k_blend_bwd, dim3(grid), dim3(kBlendThreads), 0, s, ranges, values, xyab, cop, blue, cam.W,
-                     cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimage, g2d,
-                     g2d_stride);
+  hipLaunchKernelGGL(k_blend_bwd<kBwdPix>, dim3(grid), dim3(kTile * kTile / kBwdPix), 0, s, ranges, values, xyab,
+                     cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib,
+                     dL_dimage, g2d, g2d_stride);
   return hipGetLastError();
 }
 
@@ -178,9 +191,9 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
     for (int k = 0; k < 12; ++k) reinterpret_cast<float4 *>(dsh)[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     return;
   }
-  float g[kG2d];
+  double g[kG2d];
 #pragma unroll
-  for (int c = 0; c < kG2d; ++c) g[c] = g2d[c * stride + i];
+  for (int c = 0; c < kG2d; ++c) g[c] = (double)g2d[c * stride + i];
   const float m0 = L.means[i * 3 + 0], m1 = L.means[i * 3 + 1], m2 = L.means[i * 3 + 2];
   float ls[3] = {L.log_scales[i * 3 + 0], L.log_scales[i * 3 + 1], L.log_scales[i * 3 + 2]};
   const float4 q4 = reinterpret_cast<const float4 *>(L.quats)[i];
@@ -193,42 +206,44 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
 
   // opacity
   const float o = 1.0f / (1.0f + __expf(-logit));
-  const float d_logit = g[5] * o * (1.0f - o);
+  const float d_logit = (float)g[5] * o * (1.0f - o);
 
-  // conic -> dilated 2D covariance (a, b; b, c)
-  const float a = pr.a, b = pr.b, c = pr.c;
-  const float id2 = 1.0f / (pr.det * pr.det);
-  const float gA = g[2], gB = g[3], gC = g[4];
-  const float ga = (-c * c * gA + b * c * gB - b * b * gC) * id2;
-  const float gb = (2.0f * b * c * gA - (a * c + b * b) * gB + 2.0f * a * b * gC) * id2;
-  const float gc = (-b * b * gA + a * b * gB - a * a * gC) * id2;
+  // conic -> dilated 2D covariance (a, b; b, c); FP64 because det can be far below a c
+  const double a = pr.a, b = pr.b, c = pr.c;
+  const double id2 = 1.0 / (pr.det * pr.det);
+  const double gA = g[2], gB = g[3], gC = g[4];
+  const double ga = (-c * c * gA + b * c * gB - b * b * gC) * id2;
+  const double gb = (2.0 * b * c * gA - (a * c + b * b) * gB + 2.0 * a * b * gC) * id2;
+  const double gc = (-b * b * gA + a * b * gB - a * a * gC) * id2;
 
   // Sigma' = T Sigma T^T with T rows T0, T1
-  const float *T0 = pr.Tm, *T1 = pr.Tm + 3;
-  const float *S = pr.S;
-  float ST0[3], ST1[3];
+  const double *T0 = pr.Tm, *T1 = pr.Tm + 3;
+  const double *S = pr.S;
+  double ST0[3], ST1[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     ST0[k] = S[k * 3 + 0] * T0[0] + S[k * 3 + 1] * T0[1] + S[k * 3 + 2] * T0[2];
     ST1[k] = S[k * 3 + 0] * T1[0] + S[k * 3 + 1] * T1[1] + S[k * 3 + 2] * T1[2];
   }
-  float gT0[3], gT1[3];
+  double gT0[3], gT1[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    gT0[k] = 2.0f * ga * ST0[k] + gb * ST1[k];
-    gT1[k] = 2.0f * gc * ST1[k] + gb * ST0[k];
+    gT0[k] = 2.0 * ga * ST0[k] + gb * ST1[k];
+    gT1[k] = 2.0 * gc * ST1[k] + gb * ST0[k];
   }
   // symmetric gradient of Sigma: Gs = 2 ga T0 T0^T + gb (T0 T1^T + T1 T0^T) + 2 gc T1 T1^T
-  float Gs[9];
+  double Gs[9];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int l = 0; l < 3; ++l)
-      Gs[k * 3 + l] = 2.0f * ga * T0[k] * T0[l] + gb * (T0[k] * T1[l] + T1[k] * T0[l]) + 2.0f * gc * T1[k] * T1[l];
+      Gs[k * 3 + l] = 2.0 * ga * T0[k] * T0[l] + gb * (T0[k] * T1[l] + T1[k] * T0[l]) + 2.0 * gc * T1[k] * T1[l];
 
   // T = J R_c
-  const float *Rc = cam.R;
-  float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f;
+  double Rc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rc[k] = cam.R[k];
+  double gJ00 = 0.0, gJ02 = 0.0, gJ11 = 0.0, gJ12 = 0.0;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     gJ00 += gT0[j] * Rc[j];
@@ -237,25 +252,26 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
     gJ12 += gT1[j] * Rc[6 + j];
   }
   // J and mu' -> view-space mean
-  const float tz = pr.tz, tx = pr.tx, ty = pr.ty;
-  const float iz = 1.0f / tz, iz2 = iz * iz;
-  float gtx = g[0] * cam.fx * iz;
-  float gty = g[1] * cam.fy * iz;
-  float gtz = g[0] * (-cam.fx * tx * iz2) + g[1] * (-cam.fy * ty * iz2) + gJ00 * (-cam.fx * iz2) +
-              gJ11 * (-cam.fy * iz2) + gJ02 * (cam.fx * pr.xc * iz2) + gJ12 * (cam.fy * pr.yc * iz2);
+  const double fx = cam.fx, fy = cam.fy;
+  const double tz = pr.tz, tx = pr.tx, ty = pr.ty;
+  const double iz = 1.0 / tz, iz2 = iz * iz;
+  double gtx = g[0] * fx * iz;
+  double gty = g[1] * fy * iz;
+  double gtz = g[0] * (-fx * tx * iz2) + g[1] * (-fy * ty * iz2) + gJ00 * (-fx * iz2) + gJ11 * (-fy * iz2) +
+               gJ02 * (fx * pr.xc * iz2) + gJ12 * (fy * pr.yc * iz2);
   if (pr.unclamped_x) {
-    gtx += gJ02 * (-cam.fx * iz) * iz;
-    gtz += gJ02 * (-cam.fx * iz) * (-tx * iz2);
+    gtx += gJ02 * (-fx * iz) * iz;
+    gtz += gJ02 * (-fx * iz) * (-tx * iz2);
   }
   if (pr.unclamped_y) {
-    gty += gJ12 * (-cam.fy * iz) * iz;
-    gtz += gJ12 * (-cam.fy * iz) * (-ty * iz2);
+    gty += gJ12 * (-fy * iz) * iz;
+    gtz += gJ12 * (-fy * iz) * (-ty * iz2);
   }
-  float gm[3];
+  double gm[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) gm[k] = Rc[k] * gtx + Rc[3 + k] * gty + Rc[6 + k] * gtz;
 
-  // colour -> SH coefficients and view direction
+  // colour -> SH coefficients and view direction (FP32: colour is not on the key path)
   {
     const int deg = p.sh_degree;
     const int nk = (deg + 1) * (deg + 1);
@@ -281,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
 #pragma unroll
       for (int k = 0; k < 16; ++k)
         if (k < nk) acc = fmaf(sh[k * 3 + ch], Y[k], acc);
-      const float gcol = (acc + 0.5f < 0.0f) ? 0.0f : g[6 + ch];
+      const float gcol = (acc + 0.5f < 0.0f) ? 0.0f : (float)g[6 + ch];
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const bool on = k < nk;
@@ -294,47 +310,49 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
       }
     }
     const float dd = x * gdx + y * gdy + z * gdz;
-    gm[0] += (gdx - x * dd) * inv;
-    gm[1] += (gdy - y * dd) * inv;
-    gm[2] += (gdz - z * dd) * inv;
+    gm[0] += (double)((gdx - x * dd) * inv);
+    gm[1] += (double)((gdy - y * dd) * inv);
+    gm[2] += (double)((gdz - z * dd) * inv);
 #pragma unroll
     for (int k = 0; k < 12; ++k)
       reinterpret_cast<float4 *>(dsh)[k] = make_float4(gsh[4 * k], gsh[4 * k + 1], gsh[4 * k + 2], gsh[4 * k + 3]);
   }
 
   // Sigma = M M^T, M = R diag(s): gM = Gs M
-  float M[9];
+  double M[9];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) M[r * 3 + cc] = pr.R[r * 3 + cc] * pr.s[cc];
-  float gR[9], gs[3] = {0.f, 0.f, 0.f};
+  double gR[9], gs[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
-      const float gMrc = Gs[r * 3 + 0] * M[0 * 3 + cc] + Gs[r * 3 + 1] * M[1 * 3 + cc] + Gs[r * 3 + 2] * M[2 * 3 + cc];
+      const double gMrc = Gs[r * 3 + 0] * M[0 * 3 + cc] + Gs[r * 3 + 1] * M[1 * 3 + cc] + Gs[r * 3 + 2] * M[2 * 3 + cc];
       gs[cc] += gMrc * pr.R[r * 3 + cc];
       gR[r * 3 + cc] = gMrc * pr.s[cc];
     }
+  // eq. 4: ds/ds_opt = exp(s_opt)
 #pragma unroll
-  for (int k = 0; k < 3; ++k) out.d_log_scales[i * 3 + k] = gs[k] * exp_rn1(ls[k]);
+  for (int k = 0; k < 3; ++k) out.d_log_scales[i * 3 + k] = (float)(gs[k] * (double)exp_rn1(ls[k]));
 
   // R(q_hat) -> q_hat -> q
-  const float w = pr.w, x = pr.x, y = pr.y, z = pr.z;
-  const float gw = 2.0f * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
-  const float gx = 2.0f * (y * gR[1] + z * gR[2] + y * gR[3] - 2.0f * x * gR[4] - w * gR[5] + z * gR[6] +
-                           w * gR[7] - 2.0f * x * gR[8]);
-  const float gy = 2.0f * (-2.0f * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
-                           z * gR[7] - 2.0f * y * gR[8]);
-  const float gz = 2.0f * (-2.0f * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0f * z * gR[4] + y * gR[5] +
+  const double w = pr.w, x = pr.x, y = pr.y, z = pr.z;
+  const double gw = 2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+  const double gx = 2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - 2.0 * x * gR[4] - w * gR[5] + z * gR[6] +
+                           w * gR[7] - 2.0 * x * gR[8]);
+  const double gy = 2.0 * (-2.0 * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
+                           z * gR[7] - 2.0 * y * gR[8]);
+  const double gz = 2.0 * (-2.0 * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0 * z * gR[4] + y * gR[5] +
                            x * gR[6] + y * gR[7]);
-  const float dot = w * gw + x * gx + y * gy + z * gz;
-  const float inq = 1.0f / pr.nq;
+  const double dot = w * gw + x * gx + y * gy + z * gz;
+  const double inq = 1.0 / pr.nq;
   reinterpret_cast<float4 *>(out.d_quats)[i] =
-      make_float4((gw - w * dot) * inq, (gx - x * dot) * inq, (gy - y * dot) * inq, (gz - z * dot) * inq);
+      make_float4((float)((gw - w * dot) * inq), (float)((gx - x * dot) * inq), (float)((gy - y * dot) * inq),
+                  (float)((gz - z * dot) * inq));
 #pragma unroll
-  for (int k = 0; k < 3; ++k) out.d_means[i * 3 + k] = gm[k];
+  for (int k = 0; k < 3; ++k) out.d_means[i * 3 + k] = (float)gm[k];
   out.d_opacity_logits[i] = d_logit;
 }
 

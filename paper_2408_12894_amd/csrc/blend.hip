@@ -3,9 +3,9 @@
 // One workgroup per 16x16 tile with PPT pixels per thread: thread t owns the pixels
 // (t % 16, t / 16 + (256 / PPT / 16) k), k < PPT, so each list entry staged in LDS is read
 // once per thread and applied to PPT pixels. The tile's
-// sorted list is consumed in batches of 256 entries (36 bytes each: mu', conic, opacity,
-// colour). Per pixel:
-//   q = d^T conic d (d = pixel centre - mu'); skip if q > 9 (3-sigma support)
+// sorted list is consumed in batches of 256 entries (40 bytes each: mu' and its residual,
+// conic, opacity, colour). Per pixel:
+//   q = d^T conic d (d = pixel centre - mu', formed as (centre - hi) - lo); skip if q > 9
 //   alpha = min(0.99, o exp(-q/2)); skip if alpha < 1/255
 //   stop (without blending) once T (1 - alpha) < 1e-4
 //   C += alpha T c; T *= 1 - alpha
@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
                                                               const uint32_t *__restrict__ values,
                                                               const float4 *__restrict__ xyab,
                                                               const float4 *__restrict__ cop,
-                                                              const float *__restrict__ blue, int W, int H,
+                                                              const float2 *__restrict__ blue, int W, int H,
                                                               int tiles_x, int n_tiles, float bg0, float bg1,
                                                               float bg2, float *__restrict__ image,
                                                               float *__restrict__ final_T,
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
   constexpr int ROWS = NT / kTile;          // pixel rows covered by one pass of the threads
   __shared__ float4 s_a[kBatch];
   __shared__ float4 s_b[kBatch];
-  __shared__ float s_c[kBatch];
+  __shared__ float2 s_c[kBatch];
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   if (tile >= n_tiles) return;
   const int tid = threadIdx.x;
@@ -90,12 +90,15 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
       if (!any_live) break;
       const float4 A = s_a[j];
       const float4 B = s_b[j];
-      const float c2 = s_c[j];
-      const float dx = fx - A.x;
+      const float2 BL = s_c[j];
+      const float c2 = BL.x;
+      const uint32_t lo = __float_as_uint(BL.y);
+      const float loy = mu_lo_y(lo);
+      const float dx = (fx - A.x) - mu_lo_x(lo);
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         if (done[k]) continue;
-        const float dy = fy[k] - A.y;
+        const float dy = (fy[k] - A.y) - loy;
         const float q = conic_q(A.z, A.w, B.x, dx, dy);
         if (q > kQCut) continue;
         const float alpha = fminf(kAlphaMax, B.y * __expf(-0.5f * q));
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
 }
 
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
-                        const float *blue, const DevCamera &cam, const float bg[3], float *image, float *final_T,
+                        const float2 *blue, const DevCamera &cam, const float bg[3], float *image, float *final_T,
                         int32_t *n_contrib, int32_t *n_blended, hipStream_t s) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   const int grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;

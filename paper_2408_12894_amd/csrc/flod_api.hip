@@ -198,7 +198,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   };
   need(B_XYAB, 16 * (size_t)N);
   need(B_COP, 16 * (size_t)N);
-  need(B_BLUE, 4 * (size_t)N);
+  need(B_BLUE, 8 * (size_t)N);
   need(B_DEPTH, 4 * (size_t)N);
   need(B_RECT, 8 * (size_t)N);
   need(B_TILES, 4 * (size_t)N);
@@ -227,7 +227,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     PreOut o;
     o.xyab = P<float4>(c, B_XYAB);
     o.cop = P<float4>(c, B_COP);
-    o.blue = P<float>(c, B_BLUE);
+    o.blue = P<float2>(c, B_BLUE);
     o.depth = P<uint32_t>(c, B_DEPTH);
     o.rect = P<uint2>(c, B_RECT);
     o.tiles = P<uint32_t>(c, B_TILES);
@@ -295,8 +295,9 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   if (Kn > 0) {
     uint32_t *dv = dres ? P<uint32_t>(c, B_DVAL1) : P<uint32_t>(c, B_DVAL0);
     tm.begin(FLOD_STAGE_EMIT);
-    if (launch_emit(dv, counters + kCntVisible, n_vis, P<uint32_t>(c, B_TILES), P<uint2>(c, B_RECT),
-                    P<unsigned long long>(c, B_TPREFIX), cam.tiles_x, tk[0], tv[0], s) != hipSuccess)
+    if (launch_emit(dv, counters + kCntVisible, n_vis, P<uint32_t>(c, B_TILES), P<float4>(c, B_XYAB),
+                    P<float4>(c, B_COP), P<unsigned long long>(c, B_TPREFIX), cam.tiles_x, cam.tiles_y, tk[0],
+                    tv[0], s) != hipSuccess)
       return FLOD_ERR_DEVICE;
     tm.end();
     tm.begin(FLOD_STAGE_TILE_SORT);
@@ -312,7 +313,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   if (launch_ranges(tk[tres], Kn, n_tiles, P<uint2>(c, B_RANGES), s) != hipSuccess) return FLOD_ERR_DEVICE;
   tm.end();
   tm.begin(FLOD_STAGE_BLEND);
-  if (launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP), P<float>(c, B_BLUE),
+  if (launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP), P<float2>(c, B_BLUE),
                    cam, bg, out->image, out->final_T, out->n_contrib, out->n_blended, s) != hipSuccess)
     return FLOD_ERR_DEVICE;
   tm.end();
@@ -493,7 +494,7 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   tm.begin(FLOD_STAGE_BLEND_BWD);
   const uint32_t *vals = sv.sorted_vals ? P<uint32_t>(ctx, B_TVAL1) : P<uint32_t>(ctx, B_TVAL0);
   if (launch_blend_bwd(P<uint2>(ctx, B_RANGES), vals, P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
-                       P<float>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d, N,
+                       P<float2>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d, N,
                        s) != hipSuccess)
     return FLOD_ERR_DEVICE;
   tm.end();

@@ -26,6 +26,10 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
 constexpr float kQCut = 9.0f;
+constexpr double kNearZD = 0.2;
+constexpr double kDilateD = 0.3;
+constexpr double kEigFloorD = 0.1;
+constexpr double kFovClampD = 1.3;
 
 struct DevCamera {
   float R[9], t[3], campos[3];
@@ -55,7 +59,7 @@ struct PreParams {
 struct PreOut {
   float4 *xyab;       // mu'x, mu'y, conic a, conic b
   float4 *cop;        // conic c, opacity, red, green
-  float *blue;
+  float2 *blue;       // blue, packed bf16 residuals of mu' (bits)
   uint32_t *depth;    // FP32 bits of the view-space depth
   uint2 *rect;        // (x0 | y0 << 16, x1 | y1 << 16)
   uint32_t *tiles;    // tiles touched, 0 when culled or not selected
@@ -85,17 +89,17 @@ hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_
 hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_max,
                               const uint32_t *tiles, uint32_t *block_sum, hipStream_t s);
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_vis,
-                       const uint32_t *tiles, const uint2 *rect,
-                       const unsigned long long *prefix, int tiles_x, uint32_t *tile_ids,
-                       uint32_t *values, hipStream_t s);
+                       const uint32_t *tiles, const float4 *xyab, const float4 *cop,
+                       const unsigned long long *prefix, int tiles_x, int tiles_y,
+                       uint32_t *tile_ids, uint32_t *values, hipStream_t s);
 hipError_t launch_ranges(const uint32_t *tile_ids, int64_t K, int n_tiles, uint2 *ranges,
                          hipStream_t s);
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
-                        const float4 *cop, const float *blue, const DevCamera &cam,
+                        const float4 *cop, const float2 *blue, const DevCamera &cam,
                         const float bg[3], float *image, float *final_T, int32_t *n_contrib,
                         int32_t *n_blended, hipStream_t s);
 hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
-                            const float4 *cop, const float *blue, const DevCamera &cam,
+                            const float4 *cop, const float2 *blue, const DevCamera &cam,
                             const float bg[3], const float *final_T, const int32_t *n_contrib,
                             const float *dL_dimage, float *g2d, int64_t g2d_stride,
                             hipStream_t s);

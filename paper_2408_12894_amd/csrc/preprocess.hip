@@ -1,8 +1,11 @@
 // Preprocess: selection (eq. 6), activation (eq. 4), projection (eq. 1 and EWA), culling,
-// tile rectangle, depth key and SH colour, one thread per candidate Gaussian.
+// tile footprint (tiles counted row by row, see project.h), depth key and SH colour, one
+// thread per candidate Gaussian.
 //
 // Memory: one pass over the attributes (12 + 12 + 16 + 4 + 192 bytes per Gaussian, the SH
-// row read as 12 dwordx4 loads), 52 bytes written per Gaussian. Rejected candidates stop
+// row read as 12 dwordx4 loads), 56 bytes written per Gaussian. The projection runs in FP64
+// (see project.h); mu' is stored as its FP32 rounding plus a bf16 residual so that the blend
+// kernels can form pixel offsets to better than 1e-6 px. Rejected candidates stop
 // after reading the mean (selection) or the mean and logit (near-plane / opacity culls).
 #include "project.h"
 
@@ -28,28 +31,28 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreParams p, PreOut o) {
       Proj pr;
       view_transform(p.cam, m0, m1, m2, pr);
       const float logit = L.logits[j];
-      if (pr.tz > kNearZ && !(logit < p.logit_min)) {
+      if (pr.tz > kNearZD && !(logit < p.logit_min)) {
         float ls[3] = {L.log_scales[j * 3 + 0], L.log_scales[j * 3 + 1], L.log_scales[j * 3 + 2]};
         const float4 q4 = reinterpret_cast<const float4 *>(L.quats)[j];
         float q[4] = {q4.x, q4.y, q4.z, q4.w};
         bool ok = project_cov(p.cam, ls, q, L.s_min, pr);
-        if (ok && pr.det > 0.0f) {
-          float m = 0.5f * (pr.a + pr.c);
-          float disc = m * m - pr.det;
-          float lam = m + sqrtf(fmaxf(kEigFloor, disc));
-          float r = ceilf(3.0f * sqrtf(lam));
-          float x0 = floorf((pr.mx - r) * 0.0625f);
-          float x1 = floorf((pr.mx + r) * 0.0625f);
-          float y0 = floorf((pr.my - r) * 0.0625f);
-          float y1 = floorf((pr.my + r) * 0.0625f);
-          x0 = fmaxf(x0, 0.0f);
-          y0 = fmaxf(y0, 0.0f);
-          x1 = fminf(x1, (float)(p.cam.tiles_x - 1));
-          y1 = fminf(y1, (float)(p.cam.tiles_y - 1));
-          if (x0 <= x1 && y0 <= y1) {
+        if (ok && pr.det > 0.0) {
+          const float hx = (float)pr.mx, hy = (float)pr.my;
+          const float ca = (float)pr.ca, cb = (float)pr.cb, cc = (float)pr.cc;
+          Footprint fp;
+          uint32_t rx0 = 0xFFFFu, rx1 = 0u;
+          if (footprint(hx, hy, ca, cb, cc, p.cam.tiles_y, fp)) {
+            for (int ty = fp.ty0; ty <= fp.ty1; ++ty) {
+              int tx0, tx1;
+              if (row_span(fp, ty, p.cam.tiles_x, tx0, tx1)) {
+                tiles += (uint32_t)(tx1 - tx0 + 1);
+                rx0 = min(rx0, (uint32_t)tx0);
+                rx1 = max(rx1, (uint32_t)tx1);
+              }
+            }
+          }
+          if (tiles > 0) {
             vis = true;
-            const uint32_t ix0 = (uint32_t)x0, iy0 = (uint32_t)y0, ix1 = (uint32_t)x1, iy1 = (uint32_t)y1;
-            tiles = (ix1 - ix0 + 1) * (iy1 - iy0 + 1);
             // colour from SH (not on the key path: contraction allowed via fmaf)
             float dx = m0 - p.cam.campos[0], dy = m1 - p.cam.campos[1], dz = m2 - p.cam.campos[2];
             float inv = 1.0f / sqrtf((dx * dx + dy * dy) + dz * dz);
@@ -76,11 +79,11 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreParams p, PreOut o) {
               col[ch] = fmaxf(acc + 0.5f, 0.0f);
             }
             const float opac = 1.0f / (1.0f + __expf(-logit));
-            o.xyab[i] = make_float4(pr.mx, pr.my, pr.ca, pr.cb);
-            o.cop[i] = make_float4(pr.cc, opac, col[0], col[1]);
-            o.blue[i] = col[2];
-            o.depth[i] = __float_as_uint(pr.tz);
-            o.rect[i] = make_uint2(ix0 | (iy0 << 16), ix1 | (iy1 << 16));
+            o.xyab[i] = make_float4(hx, hy, ca, cb);
+            o.cop[i] = make_float4(cc, opac, col[0], col[1]);
+            o.blue[i] = make_float2(col[2], __uint_as_float(pack_mu_lo(pr.mx, pr.my, hx, hy)));
+            o.depth[i] = __float_as_uint((float)pr.tz);
+            o.rect[i] = make_uint2(rx0 | ((uint32_t)fp.ty0 << 16), rx1 | ((uint32_t)fp.ty1 << 16));
           }
         }
       }

@@ -1,15 +1,17 @@
 // Per-Gaussian projection used by the forward preprocess and recomputed by the backward.
 //
-// Key path (exact, IEEE FP32, no contraction: the library is built with -ffp-contract=off):
+// Evaluated in FP64 from the FP32 inputs (the preprocess is bound by HBM, so FP64 costs
+// nothing here) with IEEE basic operations in a fixed order and no contraction (the library
+// is built with -ffp-contract=off); the only transcendental, exp(s_opt), is evaluated in FP64
+// and rounded to FP32 before use, so the whole chain is reproducible on any IEEE machine:
 //   t = R_c mu + t_c                            view transform
-//   s = exp(s_opt) + s_min                      eq. 4 (exp in FP64, rounded once)
+//   s = float(exp(s_opt)) + s_min               eq. 4
 //   q_hat = q / |q|;  R = R(q_hat)              unit quaternion (w, x, y, z)
 //   Sigma = M M^T, M = R diag(s)                eq. 1
 //   J = [[fx/tz, 0, -fx xc/tz], [0, fy/tz, -fy yc/tz]], xc, yc clamped to 1.3 half-FOV
 //   Sigma' = (J R_c) Sigma (J R_c)^T + 0.3 I    EWA splat with dilation
 //   r = ceil(3 sqrt(lambda_max)), lambda_max = m + sqrt(max(0.1, m^2 - det))
-// Each sum is evaluated left to right in the order written; divisions and square roots are
-// IEEE correctly rounded (HIP's default for FP32).
+// Each sum is evaluated left to right in the order written.
 #pragma once
 
 #include "flod_internal.h"
@@ -17,53 +19,55 @@
 namespace flod {
 
 struct Proj {
-  float tx, ty, tz;
-  float s[3];
-  float w, x, y, z, nq;       // unit quaternion and the input's norm
-  float R[9];
-  float S[9];                 // 3D covariance, full symmetric
-  float u, v, xc, yc;
+  double tx, ty, tz;
+  double s[3];
+  double w, x, y, z, nq;      // unit quaternion and the input's norm
+  double R[9];
+  double S[9];                // 3D covariance, full symmetric
+  double u, v, xc, yc;
   bool unclamped_x, unclamped_y;
-  float J00, J02, J11, J12;
-  float Tm[6];                // J R_c
-  float a, b, c, det;         // dilated 2D covariance and its determinant
-  float ca, cb, cc;           // conic
-  float mx, my;
+  double J00, J02, J11, J12;
+  double Tm[6];               // J R_c
+  double a, b, c, det;        // dilated 2D covariance and its determinant
+  double ca, cb, cc;          // conic
+  double mx, my;
 };
 
+// exp of an FP32 value in FP64, rounded once to FP32.
 __device__ __forceinline__ float exp_rn1(float v) { return (float)exp((double)v); }
 
 // Steps that depend only on the mean: view transform.
-__device__ __forceinline__ void view_transform(const DevCamera &cam, float m0, float m1, float m2,
-                                               Proj &p) {
-  p.tx = ((cam.R[0] * m0 + cam.R[1] * m1) + cam.R[2] * m2) + cam.t[0];
-  p.ty = ((cam.R[3] * m0 + cam.R[4] * m1) + cam.R[5] * m2) + cam.t[1];
-  p.tz = ((cam.R[6] * m0 + cam.R[7] * m1) + cam.R[8] * m2) + cam.t[2];
+__device__ __forceinline__ void view_transform(const DevCamera &cam, float m0, float m1, float m2, Proj &p) {
+  const double x = m0, y = m1, z = m2;
+  p.tx = (((double)cam.R[0] * x + (double)cam.R[1] * y) + (double)cam.R[2] * z) + (double)cam.t[0];
+  p.ty = (((double)cam.R[3] * x + (double)cam.R[4] * y) + (double)cam.R[5] * z) + (double)cam.t[1];
+  p.tz = (((double)cam.R[6] * x + (double)cam.R[7] * y) + (double)cam.R[8] * z) + (double)cam.t[2];
 }
 
 // Everything after the view transform. Returns false for a zero-norm quaternion.
-__device__ __forceinline__ bool project_cov(const DevCamera &cam, const float ls[3], const float q[4],
+__device__ __forceinline__ bool project_cov(const DevCamera &cam, const float ls[3], const float q4[4],
                                             float s_min, Proj &p) {
-  for (int i = 0; i < 3; ++i) p.s[i] = exp_rn1(ls[i]) + s_min;
-  float n2 = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
-  bool ok = n2 > 0.0f;
-  p.nq = sqrtf(ok ? n2 : 1.0f);
-  p.w = q[0] / p.nq;
-  p.x = q[1] / p.nq;
-  p.y = q[2] / p.nq;
-  p.z = q[3] / p.nq;
-  const float w = p.w, x = p.x, y = p.y, z = p.z;
-  float *R = p.R;
-  R[0] = 1.0f - 2.0f * (y * y + z * z);
-  R[1] = 2.0f * (x * y - w * z);
-  R[2] = 2.0f * (x * z + w * y);
-  R[3] = 2.0f * (x * y + w * z);
-  R[4] = 1.0f - 2.0f * (x * x + z * z);
-  R[5] = 2.0f * (y * z - w * x);
-  R[6] = 2.0f * (x * z - w * y);
-  R[7] = 2.0f * (y * z + w * x);
-  R[8] = 1.0f - 2.0f * (x * x + y * y);
-  float M[9];
+  for (int i = 0; i < 3; ++i) p.s[i] = (double)exp_rn1(ls[i]) + (double)s_min;
+  const double q0 = q4[0], q1 = q4[1], q2 = q4[2], q3 = q4[3];
+  const double n2 = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
+  const bool ok = n2 > 0.0;
+  p.nq = sqrt(ok ? n2 : 1.0);
+  p.w = q0 / p.nq;
+  p.x = q1 / p.nq;
+  p.y = q2 / p.nq;
+  p.z = q3 / p.nq;
+  const double w = p.w, x = p.x, y = p.y, z = p.z;
+  double *R = p.R;
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
+  double M[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -72,49 +76,124 @@ __device__ __forceinline__ bool project_cov(const DevCamera &cam, const float ls
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = i; j < 3; ++j) {
-      float v = (M[i * 3 + 0] * M[j * 3 + 0] + M[i * 3 + 1] * M[j * 3 + 1]) + M[i * 3 + 2] * M[j * 3 + 2];
+      const double v = (M[i * 3 + 0] * M[j * 3 + 0] + M[i * 3 + 1] * M[j * 3 + 1]) + M[i * 3 + 2] * M[j * 3 + 2];
       p.S[i * 3 + j] = v;
       p.S[j * 3 + i] = v;
     }
+  const double fx = cam.fx, fy = cam.fy;
   p.u = p.tx / p.tz;
   p.v = p.ty / p.tz;
-  const float limx = kFovClamp * ((0.5f * (float)cam.W) / cam.fx);
-  const float limy = kFovClamp * ((0.5f * (float)cam.H) / cam.fy);
-  p.xc = fminf(fmaxf(p.u, -limx), limx);
-  p.yc = fminf(fmaxf(p.v, -limy), limy);
+  const double limx = kFovClampD * ((0.5 * (double)cam.W) / fx);
+  const double limy = kFovClampD * ((0.5 * (double)cam.H) / fy);
+  p.xc = fmin(fmax(p.u, -limx), limx);
+  p.yc = fmin(fmax(p.v, -limy), limy);
   p.unclamped_x = (p.u >= -limx) && (p.u <= limx);
   p.unclamped_y = (p.v >= -limy) && (p.v <= limy);
-  p.J00 = cam.fx / p.tz;
-  p.J02 = -(cam.fx * p.xc) / p.tz;
-  p.J11 = cam.fy / p.tz;
-  p.J12 = -(cam.fy * p.yc) / p.tz;
-  const float *Rc = cam.R;
+  p.J00 = fx / p.tz;
+  p.J02 = -(fx * p.xc) / p.tz;
+  p.J11 = fy / p.tz;
+  p.J12 = -(fy * p.yc) / p.tz;
+  double Rc[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Rc[i] = cam.R[i];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     p.Tm[j] = p.J00 * Rc[j] + p.J02 * Rc[6 + j];
     p.Tm[3 + j] = p.J11 * Rc[3 + j] + p.J12 * Rc[6 + j];
   }
-  float U[6];
+  double U[6];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       U[i * 3 + j] = (p.Tm[i * 3 + 0] * p.S[j] + p.Tm[i * 3 + 1] * p.S[3 + j]) + p.Tm[i * 3 + 2] * p.S[6 + j];
-  float s00 = (U[0] * p.Tm[0] + U[1] * p.Tm[1]) + U[2] * p.Tm[2];
-  float s01 = (U[0] * p.Tm[3] + U[1] * p.Tm[4]) + U[2] * p.Tm[5];
-  float s11 = (U[3] * p.Tm[3] + U[4] * p.Tm[4]) + U[5] * p.Tm[5];
-  p.a = s00 + kDilate;
+  const double s00 = (U[0] * p.Tm[0] + U[1] * p.Tm[1]) + U[2] * p.Tm[2];
+  const double s01 = (U[0] * p.Tm[3] + U[1] * p.Tm[4]) + U[2] * p.Tm[5];
+  const double s11 = (U[3] * p.Tm[3] + U[4] * p.Tm[4]) + U[5] * p.Tm[5];
+  p.a = s00 + kDilateD;
   p.b = s01;
-  p.c = s11 + kDilate;
+  p.c = s11 + kDilateD;
   p.det = p.a * p.c - p.b * p.b;
-  float inv = 1.0f / p.det;
+  const double inv = 1.0 / p.det;
   p.ca = p.c * inv;
   p.cb = -p.b * inv;
   p.cc = p.a * inv;
-  p.mx = cam.fx * p.u + cam.cx;
-  p.my = cam.fy * p.v + cam.cy;
+  p.mx = fx * p.u + (double)cam.cx;
+  p.my = fy * p.v + (double)cam.cy;
   return ok;
 }
+
+// ---------------------------------------------------------------------------------------
+// Tile footprint. A Gaussian is binned to a tile when the tile's pixel-centre rows meet its
+// support ellipse d^T conic d <= Q with Q = 9 (1 + 1e-3): per tile row, the x-extent of the
+// ellipse over the row's band of pixel centres is found in closed form (the right boundary
+// is concave in dy, so its maximum over the band is the ellipse's rightmost point when that
+// lies in the band, else a band end; the left boundary mirrors it). The 1e-3 inflation keeps
+// every pixel whose FP32 q is <= 9 inside an emitted tile although the footprint is computed
+// from the stored FP32 mu' and conic. Computed in FP64 from those stored FP32 values by the
+// preprocess (to count) and the emission (to write), so both agree exactly.
+// ---------------------------------------------------------------------------------------
+constexpr double kQSpan = 9.009;
+
+struct Footprint {
+  double mx, my, a, b, c, det, hx, hy, dyr;
+  int ty0, ty1;
+};
+
+__device__ __forceinline__ bool footprint(float mx, float my, float a, float b, float c, int tiles_y, Footprint &f) {
+  f.mx = mx; f.my = my; f.a = a; f.b = b; f.c = c;
+  f.det = f.a * f.c - f.b * f.b;
+  if (!(f.det > 0.0) || !(f.a > 0.0)) return false;
+  const double sxx = f.c / f.det, syy = f.a / f.det, sxy = -f.b / f.det;
+  f.hx = sqrt(kQSpan * sxx);
+  f.hy = sqrt(kQSpan * syy);
+  f.dyr = sxy * sqrt(kQSpan / sxx);
+  double y0 = floor((f.my - f.hy) * 0.0625);
+  double y1 = floor((f.my + f.hy) * 0.0625);
+  y0 = fmax(y0, 0.0);
+  y1 = fmin(y1, (double)(tiles_y - 1));
+  if (!(y0 <= y1)) return false;
+  f.ty0 = (int)y0;
+  f.ty1 = (int)y1;
+  return true;
+}
+
+// Tiles [tx0, tx1] of tile row ty that the footprint reaches; false if none.
+__device__ __forceinline__ bool row_span(const Footprint &f, int ty, int tiles_x, int &tx0, int &tx1) {
+  const double dlo = fmax((16.0 * ty + 0.5) - f.my, -f.hy);
+  const double dhi = fmin((16.0 * ty + 15.5) - f.my, f.hy);
+  if (!(dlo <= dhi)) return false;
+  const double qa = kQSpan * f.a;
+  const double rlo = sqrt(fmax(0.0, qa - f.det * dlo * dlo));
+  const double rhi = sqrt(fmax(0.0, qa - f.det * dhi * dhi));
+  const double right = (dlo <= f.dyr && f.dyr <= dhi) ? f.hx : fmax((-f.b * dlo + rlo) / f.a, (-f.b * dhi + rhi) / f.a);
+  const double left = (dlo <= -f.dyr && -f.dyr <= dhi) ? -f.hx : fmin((-f.b * dlo - rlo) / f.a, (-f.b * dhi - rhi) / f.a);
+  double x0 = floor((f.mx + left) * 0.0625);
+  double x1 = floor((f.mx + right) * 0.0625);
+  x0 = fmax(x0, 0.0);
+  x1 = fmin(x1, (double)(tiles_x - 1));
+  if (!(x0 <= x1)) return false;
+  tx0 = (int)x0;
+  tx1 = (int)x1;
+  return true;
+}
+
+// bf16 (round to nearest even) of an FP32 value, in the upper half of a 32-bit word.
+__device__ __forceinline__ uint32_t bf16_bits(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+}
+
+// mu' = hi + lo with hi = float(mu') and lo the residual rounded to bf16; packed as
+// (lo_x bits >> 16) | lo_y bits.
+__device__ __forceinline__ uint32_t pack_mu_lo(double mx, double my, float hx, float hy) {
+  const uint32_t lx = bf16_bits((float)(mx - (double)hx));
+  const uint32_t ly = bf16_bits((float)(my - (double)hy));
+  return (lx >> 16) | ly;
+}
+
+__device__ __forceinline__ float mu_lo_x(uint32_t packed) { return __uint_as_float(packed << 16); }
+__device__ __forceinline__ float mu_lo_y(uint32_t packed) { return __uint_as_float(packed & 0xFFFF0000u); }
 
 // Real spherical harmonics up to degree 3 (orthonormal, no Condon-Shortley phase),
 // index l*l + l + m, evaluated at a unit direction.

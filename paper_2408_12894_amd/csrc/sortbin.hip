@@ -3,7 +3,7 @@
 // Order of the instance list: ascending (tile, depth bits, Gaussian index). It is built as
 //   1. compact the visible candidates in index order,
 //   2. stable LSD radix sort of (depth bits, index) over the visible Gaussians (N keys),
-//   3. emit each Gaussian's tiles in that depth order (row-major inside its rectangle),
+//   3. emit each Gaussian's tiles in that depth order (row-major over its footprint),
 //   4. stable LSD radix sort of the K instances by tile id only.
 // Stability makes step 4 keep the (depth, index) order inside each tile, so only the tile
 // digits of the K-long list are sorted: ceil(log2(tiles) / 8) passes instead of a full
@@ -14,7 +14,7 @@
 // workgroups, then a scatter in which each workgroup ranks its 4096 keys stably in LDS
 // (wave64 ballots over the digit bits), reorders them by digit in LDS and writes each
 // digit run contiguously.
-#include "flod_internal.h"
+#include "project.h"
 
 namespace flod {
 
@@ -261,13 +261,31 @@ hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
 }
 
 // ---------------------------------------------------------------------------------------
-// Instance emission: each wave walks its 64 Gaussians one at a time and writes each
-// rectangle's tiles with all 64 lanes (row-major), so large rectangles are spread over a
-// wave and every store is contiguous.
+// Instance emission in depth order. Each Gaussian writes its footprint (tile rows and the
+// span of tiles in each row, recomputed exactly as the preprocess counted them) row-major
+// at its offset. Footprints of up to kEmitSolo tiles are written by their own thread; larger
+// ones are written by the whole wave, one row per lane, so a Gaussian covering hundreds of
+// tiles does not serialise a lane.
 // ---------------------------------------------------------------------------------------
+constexpr uint32_t kEmitSolo = 16;
+
+__device__ __forceinline__ void emit_rows(const Footprint &fp, int ty_begin, int ty_end, int tiles_x,
+                                          uint32_t pos, uint32_t g, uint32_t *__restrict__ tile_ids,
+                                          uint32_t *__restrict__ values) {
+  for (int ty = ty_begin; ty <= ty_end; ++ty) {
+    int tx0, tx1;
+    if (!row_span(fp, ty, tiles_x, tx0, tx1)) continue;
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      tile_ids[pos] = (uint32_t)(ty * tiles_x + tx);
+      values[pos] = g;
+      ++pos;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr,
-                                                 const uint32_t *tiles, const uint2 *rect,
-                                                 const unsigned long long *prefix, int tiles_x,
+                                                 const uint32_t *tiles, const float4 *xyab, const float4 *cop,
+                                                 const unsigned long long *prefix, int tiles_x, int tiles_y,
                                                  uint32_t *__restrict__ tile_ids, uint32_t *__restrict__ values) {
   const uint32_t n = *n_ptr;
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
@@ -278,30 +296,47 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
   uint32_t tot;
   const uint32_t ex = block_excl_scan(c, &tot);
   const uint32_t off = (uint32_t)(prefix[blockIdx.x] + ex);
-  uint2 rc = valid ? rect[g] : make_uint2(0u, 0u);
   const int lane = threadIdx.x & 63;
-  for (int src = 0; src < 64; ++src) {
-    const uint32_t cs = __shfl(c, src, 64);
-    if (cs == 0) continue;
+  if (c > 0 && c <= kEmitSolo) {
+    const float4 A = xyab[g];
+    Footprint fp;
+    footprint(A.x, A.y, A.z, A.w, cop[g].x, tiles_y, fp);
+    emit_rows(fp, fp.ty0, fp.ty1, tiles_x, off, g, tile_ids, values);
+  }
+  unsigned long long big = __ballot(c > kEmitSolo);
+  while (big) {
+    const int src = __ffsll((long long)big) - 1;
+    big &= big - 1;
     const uint32_t os = __shfl(off, src, 64);
     const uint32_t gs = __shfl(g, src, 64);
-    const uint32_t r0 = __shfl(rc.x, src, 64), r1 = __shfl(rc.y, src, 64);
-    const uint32_t x0 = r0 & 0xFFFFu, y0 = r0 >> 16, x1 = r1 & 0xFFFFu;
-    const uint32_t wdt = x1 - x0 + 1;
-    for (uint32_t m = lane; m < cs; m += 64) {
-      const uint32_t yy = y0 + m / wdt, xx = x0 + m % wdt;
-      tile_ids[os + m] = yy * (uint32_t)tiles_x + xx;
-      values[os + m] = gs;
+    const float4 A = xyab[gs];
+    Footprint fp;
+    footprint(A.x, A.y, A.z, A.w, cop[gs].x, tiles_y, fp);
+    const int nrows = fp.ty1 - fp.ty0 + 1;
+    uint32_t base = os;
+    for (int rb = 0; rb < nrows; rb += 64) {
+      const int ty = fp.ty0 + rb + lane;
+      int tx0 = 0, tx1 = -1;
+      if (rb + lane < nrows) row_span(fp, ty, tiles_x, tx0, tx1);
+      const uint32_t w = (uint32_t)(tx1 - tx0 + 1);
+      const uint32_t incl = wave_incl_scan(w);
+      uint32_t pos = base + incl - w;
+      for (int tx = tx0; tx <= tx1; ++tx) {
+        tile_ids[pos] = (uint32_t)(ty * tiles_x + tx);
+        values[pos] = gs;
+        ++pos;
+      }
+      base += __shfl(incl, 63, 64);
     }
   }
 }
 
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_vis, const uint32_t *tiles,
-                       const uint2 *rect, const unsigned long long *prefix, int tiles_x, uint32_t *tile_ids,
-                       uint32_t *values, hipStream_t s) {
+                       const float4 *xyab, const float4 *cop, const unsigned long long *prefix, int tiles_x,
+                       int tiles_y, uint32_t *tile_ids, uint32_t *values, hipStream_t s) {
   if (n_vis <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_vis + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, sorted_ids,
-                     n_ptr, tiles, rect, prefix, tiles_x, tile_ids, values);
+                     n_ptr, tiles, xyab, cop, prefix, tiles_x, tiles_y, tile_ids, values);
   return hipGetLastError();
 }
 

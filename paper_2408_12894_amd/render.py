@@ -220,7 +220,8 @@ class Renderer:
                     tiles_touched=get(v.tiles_touched, N, np.uint32),
                     xy_conic=get(v.xy_conic, 4 * N, np.float32).reshape(N, 4),
                     cop=get(v.conic_c_opacity_rg, 4 * N, np.float32).reshape(N, 4),
-                    blue=get(v.blue, N, np.float32), stats=s,
+                    blue=get(v.blue, 2 * N, np.float32).reshape(N, 2)[:, 0].copy(),
+                    mu_lo_bits=get(v.blue, 2 * N, np.float32).reshape(N, 2)[:, 1].copy().view(np.uint32), stats=s,
                     grad2d=get(v.grad2d, 9 * N, np.float32).reshape(9, N) if v.grad2d else None)
 
 

@@ -4,8 +4,9 @@ Tolerances (floating point, the bar stated for this hot path):
   image and final_T     1e-4 absolute on pixels the oracle does not flag (a flagged pixel has a
                         support-cut, alpha-floor, alpha-clamp or transmittance decision within a
                         relative 1e-4 of its threshold, where FP32 and FP64 may decide apart)
-  key path              bit-exact: visibility, depth bits, tile rectangle, tiles touched, mu',
-                        conic; sorted (tile, Gaussian) list and tile ranges
+  key path              bit-exact: visibility, depth bits, tile rectangle, tiles touched, stored
+                        mu' (FP32 and bf16 residual), conic; sorted (tile, Gaussian) list and
+                        tile ranges
 """
 from __future__ import annotations
 
@@ -28,7 +29,7 @@ def check_keys(view, k, idx=None):
     vis = k["visible"].astype(bool)
     if idx is not None:
         vis = vis[idx]
-        sub = {n: k[n][idx] for n in ("depth_bits", "rect", "tiles", "mxy", "conic")}
+        sub = {n: k[n][idx] for n in ("depth_bits", "rect", "tiles", "mxy", "conic", "mu_lo")}
     else:
         sub = k
     g_vis = view["tiles_touched"] > 0
@@ -40,6 +41,7 @@ def check_keys(view, k, idx=None):
                                   err_msg="mu' bits")
     g_conic = np.stack([view["xy_conic"][vis, 2], view["xy_conic"][vis, 3], view["cop"][vis, 0]], 1)
     np.testing.assert_array_equal(g_conic.view(np.uint32), sub["conic"][vis].view(np.uint32), err_msg="conic bits")
+    np.testing.assert_array_equal(view["mu_lo_bits"][vis], sub["mu_lo"][vis], err_msg="mu' residual bits")
 
 
 def check_instances(view, k, index_offset=0):
@@ -88,12 +90,22 @@ def check_image(image, final_T, n_contrib, ref, view, cam, index_offset=0, tol=I
     return float(err), float(frac)
 
 
-def check_fp64_fields(view, p64, vis_ids, rtol_xy=1e-5, rtol_conic=2e-4):
-    """Continuous per-Gaussian fields against the FP64 projection (tolerance)."""
+def unpack_mu_lo(bits):
+    bits = np.asarray(bits, np.uint32)
+    lx = (bits << np.uint32(16)).view(np.float32).astype(np.float64)
+    ly = (bits & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)
+    return lx, ly
+
+
+def check_fp64_fields(view, p64, vis_ids, rtol_conic=1e-6):
+    """Continuous per-Gaussian fields against the oracle's FP64 projection (tolerance): mu'
+    as hi + lo to 1e-6 px, the conic to FP32 rounding, opacity and colour to FP32 evaluation."""
     g = view["xy_conic"][vis_ids].astype(np.float64)
     c = view["cop"][vis_ids].astype(np.float64)
-    np.testing.assert_allclose(g[:, 0], p64[:, 0], rtol=rtol_xy, atol=1e-3)
-    np.testing.assert_allclose(g[:, 1], p64[:, 1], rtol=rtol_xy, atol=1e-3)
+    lx, ly = unpack_mu_lo(view["mu_lo_bits"][vis_ids])
+    for hi, lo, ref in ((g[:, 0], lx, p64[:, 0]), (g[:, 1], ly, p64[:, 1])):
+        err = np.abs(hi + lo - ref)
+        assert np.all(err <= 1e-6 + 1e-9 * np.abs(ref)), f"mu' off by {err.max():.3g} px"
     scale = np.abs(p64[:, 2:5]).max(axis=1, keepdims=True)
     conic = np.stack([g[:, 2], g[:, 3], c[:, 0]], 1)
     assert np.all(np.abs(conic - p64[:, 2:5]) <= rtol_conic * scale + 1e-9), "conic"

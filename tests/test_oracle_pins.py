@@ -358,12 +358,78 @@ def test_depth_and_radius_properties(oracle_mod):
     assert np.all(r <= np.ceil(3 * np.sqrt(lam + 0.35)) + 1)
 
 
-def test_support_lies_inside_tile_rect(oracle_mod):
-    """Every pixel centre with q <= 9 (FP64) falls in a tile of the Gaussian's rectangle,
-    so the brute-force image and a tiled renderer composite the same sets."""
+Q_SPAN = 9.009
+
+
+def _min_q_over_box(mx, my, a, b, c, x0, x1, y0, y1):
+    """Minimum of q(x, y) = a dx^2 + 2 b dx dy + c dy^2 over [x0,x1] x [y0,y1] (convex q): 0 if
+    the centre is inside, else the least of the four edge minima (1D quadratics)."""
+    if x0 <= mx <= x1 and y0 <= my <= y1:
+        return 0.0
+    best = np.inf
+    for x in (x0, x1):            # vertical edges: minimise over y
+        dx = x - mx
+        dy = np.clip(-(b / c) * dx, y0 - my, y1 - my)
+        best = min(best, a * dx * dx + 2 * b * dx * dy + c * dy * dy)
+    for y in (y0, y1):            # horizontal edges: minimise over x
+        dy = y - my
+        dx = np.clip(-(b / a) * dy, x0 - mx, x1 - mx)
+        best = min(best, a * dx * dx + 2 * b * dx * dy + c * dy * dy)
+    return best
+
+
+def _bruteforce_footprint(k, i, tiles_x, tiles_y):
+    """Tiles whose region [16 tx, 16 tx + 16) x [16 ty + 0.5, 16 ty + 15.5] meets q <= Q."""
+    mx, my = (float(v) for v in k["mxy"][i])
+    a, b, c = (float(v) for v in k["conic"][i])
+    out, ambiguous = set(), set()
+    for ty in range(tiles_y):
+        for tx in range(tiles_x):
+            m = _min_q_over_box(mx, my, a, b, c, 16 * tx, 16 * tx + 16, 16 * ty + 0.5, 16 * ty + 15.5)
+            if abs(m - Q_SPAN) <= 1e-9 * Q_SPAN:
+                ambiguous.add((tx, ty))
+            elif m <= Q_SPAN:
+                out.add((tx, ty))
+    return out, ambiguous
+
+
+def test_footprint_matches_bruteforce_box_test(oracle_mod):
+    """The row-span footprint equals the set of tiles whose region meets the inflated ellipse,
+    decided independently by minimising q over each tile's box."""
+    scene = synth.uniform_scene(150, seed=11, s_mu=-2.8, s_sigma=0.8)
+    cam = synth.look_at_camera((0.5, -0.3, -3.0), (0, 0, 0), 96, 80)
+    k = oracle_mod.keys(*scene.arrays()[:4], 0.0, cam)
+    tile, val, ranges = oracle_mod.instances(k)
+    tx_n, ty_n = k["tiles_x"], k["tiles_y"]
+    got = {}
+    for t, v in zip(tile, val):
+        got.setdefault(int(v), set()).add((int(t) % tx_n, int(t) // tx_n))
+    checked = 0
+    for i in range(scene.n):
+        want, amb = _bruteforce_footprint(k, i, tx_n, ty_n)
+        have = got.get(i, set())
+        if k["visible"][i]:
+            assert want - amb <= have <= want | amb, i
+            x0, y0, x1, y1 = k["rect"][i]
+            assert all(x0 <= tx <= x1 and y0 <= ty <= y1 for tx, ty in have)
+            assert len(have) == k["tiles"][i]
+            checked += 1
+        else:
+            assert not have
+    assert checked > 100
+
+
+def test_support_lies_inside_footprint(oracle_mod):
+    """Every pixel centre with q <= 9 (FP64) falls in a tile of the Gaussian's footprint, so
+    the brute-force image and a tiled renderer composite the same sets."""
     scene = synth.uniform_scene(300, seed=11, s_mu=-2.8, s_sigma=0.6)
     cam = synth.look_at_camera((0.5, -0.3, -3.0), (0, 0, 0), 96, 80)
     k = oracle_mod.keys(*scene.arrays()[:4], 0.0, cam)
+    tile, val, _ = oracle_mod.instances(k)
+    tx_n = k["tiles_x"]
+    fp = {}
+    for t, v in zip(tile, val):
+        fp.setdefault(int(v), set()).add(int(t))
     vis = np.nonzero(k["visible"])[0]
     p64 = oracle_mod.project64(vis, *scene.arrays()[:4], 0.0, scene.sh, 3, cam)
     ys, xs = np.mgrid[0:80, 0:96]
@@ -372,34 +438,26 @@ def test_support_lies_inside_tile_rect(oracle_mod):
         dx, dy = cx - p64[j, 0], cy - p64[j, 1]
         q = p64[j, 2] * dx * dx + 2 * p64[j, 3] * dx * dy + p64[j, 4] * dy * dy
         inside = q <= 9.0
-        tx, ty = xs[inside] // 16, ys[inside] // 16
-        x0, y0, x1, y1 = k["rect"][i]
-        assert np.all((tx >= x0) & (tx <= x1) & (ty >= y0) & (ty <= y1))
+        tiles = set(((ys[inside] // 16) * tx_n + xs[inside] // 16).tolist())
+        assert tiles <= fp[int(i)], i
 
 
-def test_instance_list_matches_bruteforce_lexsort(oracle_mod):
+def test_instance_list_order_matches_lexsort(oracle_mod):
     scene, cam, _ = synth.small_forward_case()
     k = oracle_mod.keys(*scene.arrays()[:4], 0.0, cam)
     tile, val, ranges = oracle_mod.instances(k)
-    tiles_x = k["tiles_x"]
-    T, D, I = [], [], []
-    for i in np.nonzero(k["visible"])[0]:
-        x0, y0, x1, y1 = k["rect"][i]
-        for y in range(y0, y1 + 1):
-            for x in range(x0, x1 + 1):
-                T.append(y * tiles_x + x)
-                D.append(k["depth_bits"][i])
-                I.append(i)
-    T, D, I = np.array(T), np.array(D, np.uint64), np.array(I)
-    o = np.lexsort((I, D, T))
-    np.testing.assert_array_equal(tile, T[o])
-    np.testing.assert_array_equal(val, I[o])
+    assert tile.shape[0] == int(k["tiles"].astype(np.int64).sum())
+    D = k["depth_bits"][val].astype(np.uint64)
+    o = np.lexsort((val, D, tile))
+    np.testing.assert_array_equal(o, np.arange(tile.shape[0]))     # already in (tile, depth, index) order
     for t in range(ranges.shape[0]):
-        idx = np.nonzero(T[o] == t)[0]
+        idx = np.nonzero(tile == t)[0]
         if idx.size:
             assert ranges[t, 0] == idx[0] and ranges[t, 1] == idx[-1] + 1
         else:
             assert ranges[t, 0] == ranges[t, 1]
+    # every visible Gaussian appears exactly tiles-touched times
+    np.testing.assert_array_equal(np.bincount(val, minlength=scene.n), k["tiles"])
     # depth bits order positive floats like the floats themselves
     dv = k["depth_bits"].view(np.float32)
     vis = np.nonzero(k["visible"])[0]
