@@ -189,7 +189,8 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   const DevCamera &cam = p.cam;
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   const int nb = (int)((N + kBlock - 1) / kBlock);
-  const int nbs = (int)((N + kSortTile - 1) / kSortTile);
+  const int64_t sort_tile_n = (int64_t)kBlock * radix_items(N);
+  const int nbs = (int)((N + sort_tile_n - 1) / sort_tile_n);
   size_t extra = 0;
   flod_status st = FLOD_OK;
   auto need = [&](BufId id, size_t bytes) {
@@ -276,7 +277,8 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   c->stats.height = cam.H;
   if (K >= 0xFFFFFFFFull) return FLOD_ERR_OVERFLOW;
   const int64_t Kn = (int64_t)K;
-  const int nbk = (int)((Kn + kSortTile - 1) / kSortTile);
+  const int64_t sort_tile_k = (int64_t)kBlock * radix_items(Kn);
+  const int nbk = (int)((Kn + sort_tile_k - 1) / sort_tile_k);
   need(B_TKEY0, 4 * (size_t)Kn);
   need(B_TKEY1, 4 * (size_t)Kn);
   need(B_TVAL0, 4 * (size_t)Kn);

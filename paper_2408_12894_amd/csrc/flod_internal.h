@@ -14,6 +14,8 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;   // 256 buckets per radix pass
 constexpr int kSortItems = 16;            // keys per thread in a radix pass
 constexpr int kSortTile = kBlock * kSortItems;   // 4096 keys per workgroup
+constexpr int kSortItemsSmall = 4;        // 1024-key workgroups for sorts below kRadixBigSort
+constexpr int64_t kRadixBigSort = 4 << 20;
 
 // Rasterizer conventions (3DGS framework): near plane, EWA dilation, eigenvalue floor,
 // 3-sigma radius, Jacobian clamp at 1.3x the half field of view, alpha clamp, alpha floor,
@@ -83,6 +85,7 @@ hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int i
 hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
                           const unsigned long long *prefix, uint32_t *keys, uint32_t *vals,
                           hipStream_t s);
+int radix_items(int64_t n_max);   // keys per thread the radix sort of n_max keys uses
 hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr,
                              int64_t n_max, int bits, uint32_t *hist, uint32_t *scan,
                              uint32_t *tot, int *result_buf, hipStream_t s);

@@ -11,7 +11,7 @@
 //
 // The radix pass is a reduce-then-scan design (no inter-workgroup spinning, which would
 // need cross-XCD coherent flags): per-workgroup digit histograms, a per-digit scan over
-// workgroups, then a scatter in which each workgroup ranks its 4096 keys stably in LDS
+// workgroups, then a scatter in which each workgroup ranks its 4096 (or 1024) keys stably in LDS
 // (wave64 ballots over the digit bits), reorders them by digit in LDS and writes each
 // digit run contiguously.
 #include "project.h"
@@ -108,18 +108,20 @@ hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t 
 // Radix pass: histogram, per-digit scan, stable scatter.
 // hist[d * nb_max + b] = count of digit d in workgroup b; scan = exclusive prefix over b.
 // ---------------------------------------------------------------------------------------
+template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const uint32_t *n_ptr, int shift,
                                                     uint32_t *hist, int nb_max) {
+  constexpr uint32_t TILE = kBlock * ITEMS;
   __shared__ uint32_t h[kRadix];
   const uint32_t n = *n_ptr;
-  const uint32_t nb = (n + kSortTile - 1) / kSortTile;
+  const uint32_t nb = (n + TILE - 1) / TILE;
   const uint32_t b = blockIdx.x;
   if (b >= nb) return;
   h[threadIdx.x] = 0;
   __syncthreads();
-  const uint32_t base = b * kSortTile;
+  const uint32_t base = b * TILE;
 #pragma unroll 4
-  for (int r = 0; r < kSortItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const uint32_t idx = base + r * kBlock + threadIdx.x;
     if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (kRadix - 1)], 1u);
   }
@@ -128,9 +130,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const 
 }
 
 __global__ __launch_bounds__(kBlock) void k_rs_scan(const uint32_t *n_ptr, const uint32_t *hist, uint32_t *scan,
-                                                    uint32_t *tot, int nb_max) {
+                                                    uint32_t *tot, int nb_max, int tile) {
   const uint32_t n = *n_ptr;
-  const int nb = (int)((n + kSortTile - 1) / kSortTile);
+  const int nb = (int)((n + tile - 1) / tile);
   const int d = blockIdx.x;
   const uint32_t *row = hist + (size_t)d * nb_max;
   uint32_t *out = scan + (size_t)d * nb_max;
@@ -146,19 +148,21 @@ __global__ __launch_bounds__(kBlock) void k_rs_scan(const uint32_t *n_ptr, const
   if (threadIdx.x == 0) tot[d] = run;
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restrict__ keys_in,
                                                        const uint32_t *__restrict__ vals_in,
                                                        uint32_t *__restrict__ keys_out,
                                                        uint32_t *__restrict__ vals_out, const uint32_t *n_ptr,
                                                        int shift, const uint32_t *hist, const uint32_t *scan,
                                                        const uint32_t *tot, int nb_max) {
-  __shared__ uint32_t s_keys[kSortTile];
-  __shared__ uint32_t s_vals[kSortTile];
+  constexpr uint32_t TILE = kBlock * ITEMS;
+  __shared__ uint32_t s_keys[TILE];
+  __shared__ uint32_t s_vals[TILE];
   __shared__ uint32_t s_goff[kRadix];
   __shared__ uint32_t s_run[kRadix];
   __shared__ uint32_t s_wcnt[kBlock / 64][kRadix];
   const uint32_t n = *n_ptr;
-  const uint32_t nb = (n + kSortTile - 1) / kSortTile;
+  const uint32_t nb = (n + TILE - 1) / TILE;
   const uint32_t b = blockIdx.x;
   if (b >= nb) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -173,10 +177,10 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
 #pragma unroll
   for (int k = 0; k < kBlock / 64; ++k) s_wcnt[k][tid] = 0;
   __syncthreads();
-  const uint32_t base = b * kSortTile;
-  const uint32_t count = min((uint32_t)kSortTile, n - base);
+  const uint32_t base = b * TILE;
+  const uint32_t count = min(TILE, n - base);
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int r = 0; r < kSortItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const uint32_t li = r * kBlock + tid;
     const bool valid = li < count;
     const uint32_t key = valid ? keys_in[base + li] : 0u;
@@ -218,23 +222,36 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
   }
 }
 
+int radix_items(int64_t n_max) { return n_max >= kRadixBigSort ? kSortItems : kSortItemsSmall; }
+
 // Sort (keys, vals) by the low `bits` bits of the keys; stable. Ping-pongs between
-// buffers [0] and [1]; *result_buf receives the index holding the result.
+// buffers [0] and [1]; *result_buf receives the index holding the result. Sorts of fewer
+// than kRadixBigSort keys use 1024-key workgroups so that the grid still fills the chip.
+template <int ITEMS>
+static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr, int64_t n_max, int bits,
+                         uint32_t *hist, uint32_t *scan, uint32_t *tot, int *cur_out, hipStream_t s) {
+  constexpr int TILE = kBlock * ITEMS;
+  const int nb_max = (int)((n_max + TILE - 1) / TILE);
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += kRadixBits) {
+    hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(nb_max), dim3(kBlock), 0, s, keys[cur], n_ptr, shift, hist, nb_max);
+    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, s, n_ptr, hist, scan, tot, nb_max, TILE);
+    hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(nb_max), dim3(kBlock), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
+                       vals[cur ^ 1], n_ptr, shift, hist, scan, tot, nb_max);
+    cur ^= 1;
+  }
+  *cur_out = cur;
+}
+
 hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr, int64_t n_max,
                              int bits, uint32_t *hist, uint32_t *scan, uint32_t *tot, int *result_buf,
                              hipStream_t s) {
   *result_buf = 0;
   if (n_max <= 0) return hipSuccess;
-  const int nb_max = (int)((n_max + kSortTile - 1) / kSortTile);
-  int cur = 0;
-  for (int shift = 0; shift < bits; shift += kRadixBits) {
-    hipLaunchKernelGGL(k_rs_hist, dim3(nb_max), dim3(kBlock), 0, s, keys[cur], n_ptr, shift, hist, nb_max);
-    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, s, n_ptr, hist, scan, tot, nb_max);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(nb_max), dim3(kBlock), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
-                       vals[cur ^ 1], n_ptr, shift, hist, scan, tot, nb_max);
-    cur ^= 1;
-  }
-  *result_buf = cur;
+  if (radix_items(n_max) == kSortItems)
+    radix_passes<kSortItems>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, s);
+  else
+    radix_passes<kSortItemsSmall>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, s);
   return hipGetLastError();
 }
 
