@@ -137,6 +137,28 @@ flod_status flod_render_selective(flod_ctx *ctx, const flod_level *levels, int n
                                   const float bg[3], flod_frame *out, int64_t *n_selected,
                                   void *stream);
 
+/* Render several levels as one set, every Gaussian of every level included (each level
+   with its own s_min), in one depth order; candidate index = position in the concatenation.
+   This renders a predetermined selection set made by flod_select_compact. Backward after
+   it returns FLOD_ERR_UNSUPPORTED. */
+flod_status flod_render_merged(flod_ctx *ctx, const flod_level *levels, int n_levels, int sh_degree,
+                               const flod_camera *cam, const float bg[3], flod_frame *out, void *stream);
+
+/* Predetermined selection set (section Selective Rendering, predetermined Gaussian set):
+   evaluate the eq. 6 bands of flod_render_selective once around `centre` (host float[3],
+   e.g. the mean training-camera position) and compact each level's kept Gaussians, in
+   index order. n_out: host int64[n_levels], receives the kept count per level (0 outside
+   [l_start, l_end]). out: NULL to count only; else host array of n_levels flod_level whose
+   device arrays receive the kept Gaussians of level l in out[l-1] (on input out[l-1].n is
+   the arrays' capacity in Gaussians, on output the kept count; s_min is copied). Returns
+   FLOD_ERR_WORKSPACE, with flod_ctx_required_bytes() = the count needed, when a level's
+   capacity is too small. One host synchronisation per level (the count).
+   flod_render_merged(out[l_start-1 .. l_end-1]) then renders the same image as
+   flod_render_selective(levels, l_start, l_end, d_proj, centre). */
+flod_status flod_select_compact(flod_ctx *ctx, const flod_level *levels, int n_levels, int l_start, int l_end,
+                                const float *d_proj, const float centre[3], flod_level *out, int64_t *n_out,
+                                void *stream);
+
 /* Backward of the last flod_render_level on ctx: given dL/dimage [3,H,W] (device), write
    dL/d(inputs) into grads. Per-pixel transmittance is recovered from the saved final_T
    and n_contrib (no per-pixel contributor lists are stored). Returns

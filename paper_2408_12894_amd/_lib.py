@@ -25,7 +25,8 @@ STAGES = ("preprocess", "compact", "depth_sort", "offsets", "emit", "tile_sort",
 EXPORTS = ("flod_ctx_create", "flod_ctx_destroy", "flod_ctx_workspace_bytes", "flod_ctx_required_bytes",
            "flod_ctx_trim", "flod_render_level", "flod_render_selective", "flod_render_backward",
            "flod_ctx_stats", "flod_ctx_view", "flod_ctx_set_timing", "flod_ctx_stage_times",
-           "flod_stage_name", "flod_smin", "flod_dproj", "flod_status_str", "flod_copy_to_host")
+           "flod_stage_name", "flod_smin", "flod_dproj", "flod_status_str", "flod_copy_to_host",
+           "flod_render_merged", "flod_select_compact")
 
 
 class FlodError(RuntimeError):
@@ -100,6 +101,12 @@ def load():
                                         C.POINTER(C.c_float), C.c_int, C.POINTER(Camera), C.POINTER(C.c_float),
                                         C.POINTER(Frame), vp, vp]
     L.flod_render_selective.restype = C.c_int
+    L.flod_render_merged.argtypes = [vp, C.POINTER(Level), C.c_int, C.c_int, C.POINTER(Camera),
+                                     C.POINTER(C.c_float), C.POINTER(Frame), vp]
+    L.flod_render_merged.restype = C.c_int
+    L.flod_select_compact.argtypes = [vp, C.POINTER(Level), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_float),
+                                      C.POINTER(C.c_float), C.POINTER(Level), C.POINTER(C.c_int64), vp]
+    L.flod_select_compact.restype = C.c_int
     L.flod_render_backward.argtypes = [vp, vp, C.POINTER(Grads), vp]
     L.flod_render_backward.restype = C.c_int
     L.flod_ctx_stats.argtypes = [vp, C.POINTER(Stats)]

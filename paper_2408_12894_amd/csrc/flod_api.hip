@@ -471,6 +471,103 @@ flod_status flod_render_selective(flod_ctx *ctx, const flod_level *levels, int n
   return st;
 }
 
+flod_status flod_render_merged(flod_ctx *ctx, const flod_level *levels, int n_levels, int sh_degree,
+                               const flod_camera *cam, const float bg[3], flod_frame *out, void *stream) {
+  if (!ctx || !levels || !bg || !frame_ok(out) || sh_degree < 0 || sh_degree > 3) return FLOD_ERR_INVALID_ARG;
+  if (n_levels < 1 || n_levels > FLOD_MAX_LEVELS) return FLOD_ERR_INVALID_ARG;
+  flod_status st = check_camera(cam);
+  if (st != FLOD_OK) return st;
+  for (int l = 0; l < n_levels; ++l)
+    if ((st = check_level(&levels[l])) != FLOD_OK) return st;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  PreParams p = base_params(dev_camera(cam), sh_degree);
+  p.select = 0;
+  int64_t off = 0;
+  for (int l = 0; l < n_levels; ++l) {
+    const flod_level &lv = levels[l];
+    DevLevel &L = p.lv[l];
+    L.means = lv.means; L.log_scales = lv.log_scales; L.quats = lv.quats;
+    L.logits = lv.opacity_logits; L.sh = lv.sh;
+    L.offset = off; L.n = lv.n; L.s_min = lv.s_min;
+    L.lo2 = 0.0f; L.hi2 = INFINITY;
+    off += lv.n;
+  }
+  p.n_levels = n_levels;
+  p.n_total = off;
+  if (off > 0xFFFFFFF0ll) return FLOD_ERR_INVALID_ARG;
+  st = render_common(ctx, p, nullptr, bg, out, (hipStream_t)stream);
+  if (st == FLOD_OK) ctx->saved.is_level = false;
+  return st;
+}
+
+flod_status flod_select_compact(flod_ctx *ctx, const flod_level *levels, int n_levels, int l_start, int l_end,
+                                const float *d_proj, const float centre[3], flod_level *out, int64_t *n_out,
+                                void *stream) {
+  if (!ctx || !levels || !d_proj || !centre || !n_out) return FLOD_ERR_INVALID_ARG;
+  if (n_levels < 1 || n_levels > FLOD_MAX_LEVELS || l_start < 1 || l_end < l_start || l_end > n_levels)
+    return FLOD_ERR_INVALID_ARG;
+  flod_status st;
+  for (int l = l_start; l <= l_end; ++l)
+    if ((st = check_level(&levels[l - 1])) != FLOD_OK) return st;
+  for (int l = 0; l < n_levels; ++l)
+    if (!(d_proj[l] >= 0.0f)) return FLOD_ERR_INVALID_ARG;
+  if (!isfinite(centre[0]) || !isfinite(centre[1]) || !isfinite(centre[2])) return FLOD_ERR_INVALID_ARG;
+  if (out) {
+    for (int l = l_start; l <= l_end; ++l) {
+      const flod_level &o = out[l - 1];
+      if (o.n < 0) return FLOD_ERR_INVALID_ARG;
+      if (o.n > 0 && (!o.means || !o.log_scales || !o.quats || !o.opacity_logits || !o.sh ||
+                      !aligned(o.quats, 16) || !aligned(o.sh, 16)))
+        return FLOD_ERR_INVALID_ARG;
+    }
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  ctx->last_stream = s;
+  ctx->required = 0;
+  ctx->saved.valid = false;
+  for (int l = 0; l < n_levels; ++l) n_out[l] = 0;
+  for (int l = l_start; l <= l_end; ++l) {
+    const flod_level &lv = levels[l - 1];
+    if (lv.n == 0) continue;
+    // eq. 6 band of level l, with d_proj^(l_end) = 0 and d_proj^(l_start - 1) = infinity
+    const float hi = (l == l_start) ? INFINITY : d_proj[l - 2];
+    const float lo = (l == l_end) ? 0.0f : d_proj[l - 1];
+    const float lo2 = sq32(lo), hi2 = sq32(hi);
+    const int nb = (int)((lv.n + kBlock - 1) / kBlock);
+    size_t extra = 0;
+    if (ensure(ctx, B_BLOCKVIS, 4 * (size_t)nb, s, &extra) != FLOD_OK ||
+        ensure(ctx, B_PREFIX, 8 * (size_t)nb, s, &extra) != FLOD_OK ||
+        ensure(ctx, B_COUNTERS, 8 * (size_t)kCntSlots, s, &extra) != FLOD_OK) {
+      ctx->required = ws_bytes(ctx) + extra;
+      return FLOD_ERR_WORKSPACE;
+    }
+    uint32_t *counters = P<uint32_t>(ctx, B_COUNTERS);
+    if (launch_select_count(lv.means, lv.n, centre, lo2, hi2, P<uint32_t>(ctx, B_BLOCKVIS), s) != hipSuccess ||
+        launch_scan_blocks(P<uint32_t>(ctx, B_BLOCKVIS), nullptr, kBlock, P<unsigned long long>(ctx, B_PREFIX),
+                           counters + kCntVisible, nullptr, nb, s) != hipSuccess ||
+        hipMemcpyAsync(ctx->host_counters, counters, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    const int64_t kept = reinterpret_cast<const uint32_t *>(ctx->host_counters)[kCntVisible];
+    n_out[l - 1] = kept;
+    if (!out) continue;
+    flod_level &o = out[l - 1];
+    if (o.n < kept) {
+      ctx->required = (size_t)kept;   // elements needed in level l's output arrays
+      return FLOD_ERR_WORKSPACE;
+    }
+    if (launch_select_copy(lv, centre, lo2, hi2, P<unsigned long long>(ctx, B_PREFIX), o, s) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    o.n = kept;
+    o.s_min = lv.s_min;
+  }
+  if (out)
+    for (int l = 1; l <= n_levels; ++l)
+      if (l < l_start || l > l_end) out[l - 1].n = 0;
+  return FLOD_OK;
+}
+
 flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_grads *grads, void *stream) {
   if (!ctx || !dL_dimage || !grads) return FLOD_ERR_INVALID_ARG;
   const Saved &sv = ctx->saved;

@@ -109,5 +109,9 @@ hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const f
 hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, const float *g2d,
                                  int64_t g2d_stride, const flod_grads &g, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_select_count(const float *means, int64_t n, const float centre[3], float lo2, float hi2,
+                               uint32_t *block_cnt, hipStream_t s);
+hipError_t launch_select_copy(const flod_level &in, const float centre[3], float lo2, float hi2,
+                              const unsigned long long *prefix, const flod_level &out, hipStream_t s);
 
 }  // namespace flod

@@ -155,6 +155,50 @@ class Renderer:
             return image, final_T, n_contrib, counts
         return image, final_T, n_contrib
 
+    def render_merged(self, levels, cam, bg=(0.0, 0.0, 0.0), sh_degree: int = 3, stream=None):
+        """Render every Gaussian of the given levels (each with its own s_min) as one set, in
+        one depth order: the way a stored predetermined selection set is drawn."""
+        n_levels = len(levels)
+        arr = (_lib.Level * n_levels)()
+        for i, lv in enumerate(levels):
+            arr[i] = lv.c_struct()
+        image, final_T, n_contrib, fr = self._frame(cam, levels[0].means.device)
+        cs = camera_struct(cam)
+        st = self.L.flod_render_merged(self.ctx, arr, n_levels, int(sh_degree), C.byref(cs), _floats(bg, 3),
+                                       C.byref(fr), C.c_void_p(_stream_ptr(stream)))
+        _lib.check(st, "flod_render_merged")
+        self.generation += 1
+        self._last_level_forward = None
+        return image, final_T, n_contrib
+
+    def select_compact(self, levels, l_start: int, l_end: int, d_proj, centre, stream=None):
+        """Predetermined selection set: the Gaussians each level keeps under the eq. 6 bands
+        around a fixed `centre`, compacted into new device levels (index order preserved).
+        Returns one GaussianLevel per level in [l_start, l_end] (possibly empty)."""
+        n_levels = len(levels)
+        arr = (_lib.Level * n_levels)()
+        for i, lv in enumerate(levels):
+            arr[i] = lv.c_struct()
+        counts = (C.c_int64 * n_levels)()
+        sp = C.c_void_p(_stream_ptr(stream))
+        dp, ce = _floats(d_proj, n_levels), _floats(centre, 3)
+        _lib.check(self.L.flod_select_compact(self.ctx, arr, n_levels, int(l_start), int(l_end), dp, ce, None,
+                                              counts, sp), "flod_select_compact")
+        out = (_lib.Level * n_levels)()
+        kept = []
+        for l in range(1, n_levels + 1):
+            dev = levels[l - 1].means.device
+            k = int(counts[l - 1])
+            g = GaussianLevel(torch.empty((k, 3), device=dev), torch.empty((k, 3), device=dev),
+                              torch.empty((k, 4), device=dev), torch.empty((k,), device=dev),
+                              torch.empty((k, SH_COEFFS, 3), device=dev), levels[l - 1].s_min)
+            kept.append(g)
+            out[l - 1] = _lib.Level(g.means.data_ptr(), g.log_scales.data_ptr(), g.quats.data_ptr(),
+                                    g.opacity_logits.data_ptr(), g.sh.data_ptr(), k, float(g.s_min))
+        _lib.check(self.L.flod_select_compact(self.ctx, arr, n_levels, int(l_start), int(l_end), dp, ce, out,
+                                              counts, sp), "flod_select_compact")
+        return kept[l_start - 1: l_end]
+
     # ------------------------------------------------------------------ backward
     def backward(self, level: GaussianLevel, dL_dimage: torch.Tensor, stream=None):
         """Gradients of the last render_level with respect to the level's tensors."""
@@ -223,6 +267,36 @@ class Renderer:
                     blue=get(v.blue, 2 * N, np.float32).reshape(N, 2)[:, 0].copy(),
                     mu_lo_bits=get(v.blue, 2 * N, np.float32).reshape(N, 2)[:, 1].copy().view(np.uint32), stats=s,
                     grad2d=get(v.grad2d, 9 * N, np.float32).reshape(9, N) if v.grad2d else None)
+
+
+def save_levels(path: str, levels) -> None:
+    """Store a level stack (or a compacted selection set): one .npz per level plus a JSON
+    level table (index, count, s_min)."""
+    import json
+    import os
+    os.makedirs(path, exist_ok=True)
+    table = []
+    for i, lv in enumerate(levels):
+        np.savez(os.path.join(path, f"level_{i}.npz"), means=lv.means.cpu().numpy(),
+                 log_scales=lv.log_scales.cpu().numpy(), quats=lv.quats.cpu().numpy(),
+                 opacity_logits=lv.opacity_logits.cpu().numpy(), sh=lv.sh.cpu().numpy())
+        table.append({"index": i, "n": lv.n, "s_min": lv.s_min, "file": f"level_{i}.npz"})
+    with open(os.path.join(path, "levels.json"), "w") as f:
+        json.dump({"levels": table}, f, indent=1)
+
+
+def load_levels(path: str, device="cuda"):
+    """Load a stack written by save_levels onto the device (no pickled objects are read)."""
+    import json
+    import os
+    with open(os.path.join(path, "levels.json")) as f:
+        table = json.load(f)["levels"]
+    out = []
+    for e in table:
+        z = np.load(os.path.join(path, e["file"]), allow_pickle=False)
+        out.append(GaussianLevel.from_arrays(z["means"], z["log_scales"], z["quats"], z["opacity_logits"], z["sh"],
+                                             s_min=e["s_min"], device=device))
+    return out
 
 
 def smin_schedule(l: int, l_max: int, lam: float = 0.2, rho: float = 4.0) -> float:
