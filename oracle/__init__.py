@@ -78,6 +78,8 @@ def lib():
         L.or_get_threads.restype = C.c_int
         L.or_sh_basis.argtypes = [C.c_int, vp, vp]
         L.or_select_level.argtypes = [i64, vp, vp, f32, f32, vp]
+        L.or_overlap_prune.argtypes = [i64, vp, C.c_double, vp, vp]
+        L.or_level_transition.argtypes = [i64, vp, C.c_double, C.c_double, vp]
         L.or_keys.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.or_instances.argtypes = [i64, vp, vp, vp, vp, i32, i32, i64, vp, vp, vp]
         L.or_instances.restype = i64
@@ -109,6 +111,29 @@ def smin_schedule(l: int, l_max: int, lam: float = 0.2, rho: float = 4.0) -> flo
 def reparam_next_level(s_level: np.ndarray, s_min_next: float) -> np.ndarray:
     """eq. 5: s_opt for level l+1 from the trained level-l scales, log(s^(l) - s_min^(l+1))."""
     return np.log(np.asarray(s_level, np.float64) - s_min_next)
+
+
+def overlap_prune(means, d_op: float):
+    """Overlap pruning: (keep uint8 [n], d_avg float64 [n]); removed iff the mean distance to
+    the three nearest other Gaussians is below d_op."""
+    m = np.ascontiguousarray(np.asarray(means, np.float32).reshape(-1, 3))
+    n = m.shape[0]
+    keep = np.zeros(n, np.uint8)
+    davg = np.zeros(n, np.float64)
+    if n:
+        lib().or_overlap_prune(n, _p(m), float(d_op), _p(keep), _p(davg))
+    return keep, davg
+
+
+def level_transition(log_scales, s_min_l: float, s_min_next: float) -> np.ndarray:
+    """eq. 5 from level-l scale parameters: log(exp(s_opt) + s_min^(l) - s_min^(l+1)) in FP64,
+    exp rounded once to FP32 as the rasterizer forms s^(l)."""
+    ls = np.ascontiguousarray(np.asarray(log_scales, np.float32))
+    out = np.zeros(ls.shape, np.float64)
+    if ls.size:
+        lib().or_level_transition(ls.size // 3, _p(ls), float(np.float32(s_min_l)), float(np.float32(s_min_next)),
+                                  _p(out))
+    return out
 
 
 def dproj(s_min: float, f: float, gamma: float) -> float:

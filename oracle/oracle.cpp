@@ -23,6 +23,8 @@
 //   Preliminary section           alpha blending in depth order
 //   Section 3D Scale Constraint, eq. 3 and eq. 4   s = exp(s_opt) + s_min
 //   Section Selective Rendering, eq. 6 and eq. 7   distance bands
+//   Section Overlap Pruning                        three-nearest-neighbour mean distance
+//   Section Training Method, eq. 5                 level-transition scale parameter
 // The projection (EWA Jacobian, dilation, radius) and compositing constants are the
 // conventions of the 3DGS framework the paper builds on; the paper does not restate them.
 // Build: g++ -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
@@ -475,6 +477,46 @@ void or_select_level(int64_t n, const float* means, const float* centre, float l
     float dz = means[i * 3 + 2] - centre[2];
     float d2 = (dx * dx + dy * dy) + dz * dz;
     keep[i] = (lo2 <= d2 && d2 < hi2) ? 1 : 0;
+  }
+}
+
+// Overlap pruning (section Overlap Pruning): d_avg of Gaussian i is the mean of its
+// distances to the three nearest other Gaussians, d_1 <= d_2 <= d_3, each the FP64
+// Euclidean distance between the FP32 means (differences taken as double(x_j) - double(x_i),
+// squares summed x, y, z), the three added in ascending order and divided by 3. Gaussian i
+// is removed when d_avg < d_op (d_op = s_min / 2 of the level being trained). With fewer
+// than four Gaussians nobody has three neighbours: d_avg = +inf, all kept. Brute force over
+// all pairs; coincident means are distinct neighbours at distance 0.
+void or_overlap_prune(int64_t n, const float* means, double d_op, uint8_t* keep, double* d_avg) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    double best[3] = {INFINITY, INFINITY, INFINITY};
+    const double xi = means[i * 3 + 0], yi = means[i * 3 + 1], zi = means[i * 3 + 2];
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double dx = (double)means[j * 3 + 0] - xi;
+      const double dy = (double)means[j * 3 + 1] - yi;
+      const double dz = (double)means[j * 3 + 2] - zi;
+      const double d = std::sqrt((dx * dx + dy * dy) + dz * dz);
+      if (d < best[2]) {
+        best[2] = d;
+        if (best[2] < best[1]) std::swap(best[1], best[2]);
+        if (best[1] < best[0]) std::swap(best[0], best[1]);
+      }
+    }
+    const double avg = ((best[0] + best[1]) + best[2]) / 3.0;
+    d_avg[i] = avg;
+    keep[i] = (avg < d_op) ? 0 : 1;
+  }
+}
+
+// Level transition (section Training Method, eq. 5): the next level's scale parameter is
+// log(s^(l) - s_min^(l+1)), with s^(l) = exp(s_opt) + s_min^(l) as the rasterizer forms it
+// (exp rounded once to FP32, sum in FP64). Result in FP64.
+void or_level_transition(int64_t n, const float* log_scales, double s_min_l, double s_min_next, double* out) {
+  for (int64_t i = 0; i < n * 3; ++i) {
+    const double s = (double)(float)std::exp((double)log_scales[i]) + s_min_l;
+    out[i] = std::log(s - s_min_next);
   }
 }
 

@@ -17,12 +17,10 @@ constexpr int kSortTile = kBlock * kSortItems;   // 4096 keys per workgroup
 constexpr int kSortItemsSmall = 4;        // 1024-key workgroups for sorts below kRadixBigSort
 constexpr int64_t kRadixBigSort = 4 << 20;
 
-// Rasterizer conventions (3DGS framework): near plane, EWA dilation, eigenvalue floor,
-// 3-sigma radius, Jacobian clamp at 1.3x the half field of view, alpha clamp, alpha floor,
+// Rasterizer conventions (3DGS framework): near plane, EWA dilation, Jacobian clamp at 1.3x the half field of view, alpha clamp, alpha floor,
 // transmittance floor, support cut q <= 9.
 constexpr float kNearZ = 0.2f;
 constexpr float kDilate = 0.3f;
-constexpr float kEigFloor = 0.1f;
 constexpr float kFovClamp = 1.3f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
@@ -30,7 +28,6 @@ constexpr float kTMin = 1e-4f;
 constexpr float kQCut = 9.0f;
 constexpr double kNearZD = 0.2;
 constexpr double kDilateD = 0.3;
-constexpr double kEigFloorD = 0.1;
 constexpr double kFovClampD = 1.3;
 
 struct DevCamera {

@@ -10,7 +10,7 @@
 //   Sigma = M M^T, M = R diag(s)                eq. 1
 //   J = [[fx/tz, 0, -fx xc/tz], [0, fy/tz, -fy yc/tz]], xc, yc clamped to 1.3 half-FOV
 //   Sigma' = (J R_c) Sigma (J R_c)^T + 0.3 I    EWA splat with dilation
-//   r = ceil(3 sqrt(lambda_max)), lambda_max = m + sqrt(max(0.1, m^2 - det))
+//   tiles: per tile row, the columns where the ellipse q <= 9 (1 + 1e-3) reaches
 // Each sum is evaluated left to right in the order written.
 #pragma once
 

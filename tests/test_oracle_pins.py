@@ -592,3 +592,65 @@ def test_gradient_with_saturated_alpha(oracle_mod):
             flat[j] = th
             fd = (lp - lm) / (2 * h)
             assert abs(g[name].reshape(-1)[j] - fd) <= 1e-6 * max(1.0, abs(fd)), (name, j)
+
+
+# --------------------------------------------------------------------------------------
+# Overlap pruning (section Overlap Pruning) and the level transition (eq. 5)
+# --------------------------------------------------------------------------------------
+
+def test_overlap_prune_hand_values(oracle_mod):
+    # four points on a line at 0, 1, 3, 7: neighbour distances {1,3,7}, {1,2,6}, {2,3,4}, {4,6,7}
+    m = np.zeros((4, 3), np.float32)
+    m[:, 0] = [0.0, 1.0, 3.0, 7.0]
+    keep, davg = oracle_mod.overlap_prune(m, 3.2)
+    np.testing.assert_allclose(davg, [11 / 3, 3.0, 3.0, 17 / 3], rtol=1e-15)
+    assert keep.tolist() == [1, 0, 0, 1]
+
+
+def test_overlap_prune_lattice_threshold_is_strict(oracle_mod):
+    a = 0.25
+    g = np.arange(5, dtype=np.float32) * np.float32(a)
+    m = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    keep, davg = oracle_mod.overlap_prune(m, a)
+    assert np.all(davg == a)                   # every lattice point, corners included, has 3 at a
+    assert keep.all()                           # strictly below the threshold is removed
+    keep, _ = oracle_mod.overlap_prune(m, np.nextafter(a, 1.0))
+    assert not keep.any()
+
+
+def test_overlap_prune_against_kdtree(oracle_mod):
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(12)
+    m = np.concatenate([rng.normal(0, 0.3, (1500, 3)), rng.uniform(-2, 2, (1500, 3))]).astype(np.float32)
+    m[10] = m[11]                               # coincident pair
+    d, _ = cKDTree(m.astype(np.float64)).query(m.astype(np.float64), k=4)
+    ref = d[:, 1:].mean(axis=1)
+    d_op = float(np.median(ref))
+    keep, davg = oracle_mod.overlap_prune(m, d_op)
+    np.testing.assert_allclose(davg, ref, rtol=1e-12)
+    clear = np.abs(ref - d_op) > 1e-9 * d_op
+    np.testing.assert_array_equal(keep[clear].astype(bool), ref[clear] >= d_op)
+    assert davg[10] == davg[11] and d[10, 1] == 0.0
+
+
+def test_overlap_prune_degenerate(oracle_mod):
+    for n in (0, 1, 2, 3):
+        keep, davg = oracle_mod.overlap_prune(np.zeros((n, 3), np.float32), 1.0)
+        assert keep.all() and np.all(np.isinf(davg))
+    m = np.array([[0, 0, 0], [0, 0, 0], [5, 0, 0], [9, 0, 0]], np.float32)
+    keep, davg = oracle_mod.overlap_prune(m, 1.0)
+    np.testing.assert_allclose(davg[:2], [(0 + 5 + 9) / 3] * 2, rtol=1e-15)
+
+
+def test_level_transition_keeps_scale(oracle_mod):
+    rng = np.random.default_rng(4)
+    ls = rng.normal(-3.0, 1.5, (2000, 3)).astype(np.float32)
+    for l in range(1, 5):
+        sl, sn = oracle_mod.smin_schedule(l, 5), oracle_mod.smin_schedule(l + 1, 5)
+        sl32, sn32 = float(np.float32(sl)), float(np.float32(sn))
+        s_l = np.exp(ls.astype(np.float64)).astype(np.float32).astype(np.float64) + sl32
+        nxt = oracle_mod.level_transition(ls, sl, sn)
+        np.testing.assert_allclose(np.exp(nxt) + sn32, s_l, rtol=1e-14)
+    # equal floors and an exp that underflows in FP32: log(0) = -inf keeps s = s_min
+    out = oracle_mod.level_transition(np.full((1, 3), -200.0, np.float32), 0.05, 0.05)
+    assert np.all(np.isneginf(out)) and np.all(np.exp(out) + np.float32(0.05) == np.float32(0.05))
