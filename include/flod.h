@@ -151,13 +151,49 @@ flod_status flod_render_merged(flod_ctx *ctx, const flod_level *levels, int n_le
    [l_start, l_end]). out: NULL to count only; else host array of n_levels flod_level whose
    device arrays receive the kept Gaussians of level l in out[l-1] (on input out[l-1].n is
    the arrays' capacity in Gaussians, on output the kept count; s_min is copied). Returns
-   FLOD_ERR_WORKSPACE, with flod_ctx_required_bytes() = the count needed, when a level's
-   capacity is too small. One host synchronisation per level (the count).
+   FLOD_ERR_WORKSPACE, with flod_ctx_required_bytes() = the bytes of level arrays that the
+   level needs (236 per kept Gaussian), when a level's capacity is too small. One host synchronisation per level (the count).
    flod_render_merged(out[l_start-1 .. l_end-1]) then renders the same image as
    flod_render_selective(levels, l_start, l_end, d_proj, centre). */
 flod_status flod_select_compact(flod_ctx *ctx, const flod_level *levels, int n_levels, int l_start, int l_end,
                                 const float *d_proj, const float centre[3], flod_level *out, int64_t *n_out,
                                 void *stream);
+
+/* Overlap pruning (section Overlap Pruning): Gaussian i of `level` is marked for removal
+   when the mean of its distances to its three nearest other Gaussians of the level is below
+   d_op (the paper uses d_op = s_min^(l) / 2 while training level l; d_op = 0 removes none).
+   Distances are FP64 Euclidean distances between the FP32 means; the three are summed in
+   ascending order and divided by 3; all Gaussians are evaluated on the same input set (no
+   removal changes another's neighbours). A level of fewer than four Gaussians keeps all.
+   keep: device uint8[n], 1 = keep, 0 = remove. d_avg: device double[n] or NULL; receives
+   d_avg exactly when the three nearest lie within 3 d_op (1 + 1e-9), +inf otherwise (such a
+   Gaussian is kept). n_keep: host, the number kept. Workspace about 44 B per Gaussian plus
+   8 B per hash bucket (2^ceil(log2 n) buckets). One host synchronisation (the count) and
+   one check of the neighbour-search size: when the means are so dense relative to d_op
+   that the scan would exceed 2^36 distance evaluations, returns FLOD_ERR_UNSUPPORTED
+   without writing keep. n <= 2^30. */
+flod_status flod_overlap_prune(flod_ctx *ctx, const flod_level *level, float d_op, uint8_t *keep,
+                               double *d_avg, int64_t *n_keep, void *stream);
+
+/* Compact a level by a keep mask (device uint8[n], nonzero = keep), in index order, into
+   `out` (host struct of device arrays; on input out->n = capacity in Gaussians, on output
+   the kept count; s_min is copied). out = NULL counts only. *n_out = kept count. Returns
+   FLOD_ERR_WORKSPACE, with flod_ctx_required_bytes() = 236 B per kept Gaussian, when the
+   capacity is too small. Output arrays must not overlap the input's. */
+flod_status flod_compact_level(flod_ctx *ctx, const flod_level *in, const uint8_t *keep, flod_level *out,
+                               int64_t *n_out, void *stream);
+
+/* Level transition (section Training Method, eq. 5): initialise level l+1 from the trained
+   level l = *in: every attribute copied, and s_opt' = log(s^(l) - s_min_next) with
+   s^(l) = exp(s_opt) + in->s_min formed as the renderer forms it (exp in FP64 rounded once
+   to FP32, the sum and the logarithm in FP64, the result rounded to FP32), so that the
+   renderer's scale at level l+1 equals s^(l) up to that rounding. out: host struct of
+   device arrays of capacity out->n >= in->n; on return out->n = in->n and
+   out->s_min = s_min_next. Each output array either is the input's own (in place; not
+   copied) or does not overlap it. Requires 0 <= s_min_next <= in->s_min (eq. 3 floors
+   decrease with the level). */
+flod_status flod_level_transition(flod_ctx *ctx, const flod_level *in, float s_min_next, flod_level *out,
+                                  void *stream);
 
 /* Backward of the last flod_render_level on ctx: given dL/dimage [3,H,W] (device), write
    dL/d(inputs) into grads. Per-pixel transmittance is recovered from the saved final_T

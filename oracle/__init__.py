@@ -78,7 +78,7 @@ def lib():
         L.or_get_threads.restype = C.c_int
         L.or_sh_basis.argtypes = [C.c_int, vp, vp]
         L.or_select_level.argtypes = [i64, vp, vp, f32, f32, vp]
-        L.or_overlap_prune.argtypes = [i64, vp, C.c_double, vp, vp]
+        L.or_overlap_prune.argtypes = [i64, vp, C.c_double, i64, vp, vp, vp]
         L.or_level_transition.argtypes = [i64, vp, C.c_double, C.c_double, vp]
         L.or_keys.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.or_instances.argtypes = [i64, vp, vp, vp, vp, i32, i32, i64, vp, vp, vp]
@@ -113,15 +113,18 @@ def reparam_next_level(s_level: np.ndarray, s_min_next: float) -> np.ndarray:
     return np.log(np.asarray(s_level, np.float64) - s_min_next)
 
 
-def overlap_prune(means, d_op: float):
-    """Overlap pruning: (keep uint8 [n], d_avg float64 [n]); removed iff the mean distance to
-    the three nearest other Gaussians is below d_op."""
+def overlap_prune(means, d_op: float, ids=None):
+    """Overlap pruning: (keep uint8, d_avg float64); removed iff the mean distance to the three
+    nearest other Gaussians is below d_op. ids: evaluate only these Gaussians (against all)."""
     m = np.ascontiguousarray(np.asarray(means, np.float32).reshape(-1, 3))
     n = m.shape[0]
-    keep = np.zeros(n, np.uint8)
-    davg = np.zeros(n, np.float64)
-    if n:
-        lib().or_overlap_prune(n, _p(m), float(d_op), _p(keep), _p(davg))
+    idx = None if ids is None else np.ascontiguousarray(np.asarray(ids, np.int64))
+    count = n if idx is None else idx.shape[0]
+    keep = np.zeros(count, np.uint8)
+    davg = np.zeros(count, np.float64)
+    if count:
+        lib().or_overlap_prune(n, _p(m), float(d_op), 0 if idx is None else count,
+                               None if idx is None else _p(idx), _p(keep), _p(davg))
     return keep, davg
 
 

@@ -487,9 +487,13 @@ void or_select_level(int64_t n, const float* means, const float* centre, float l
 // is removed when d_avg < d_op (d_op = s_min / 2 of the level being trained). With fewer
 // than four Gaussians nobody has three neighbours: d_avg = +inf, all kept. Brute force over
 // all pairs; coincident means are distinct neighbours at distance 0.
-void or_overlap_prune(int64_t n, const float* means, double d_op, uint8_t* keep, double* d_avg) {
+// ids: NULL for every Gaussian, else the m Gaussians to evaluate (outputs indexed 0..m-1).
+void or_overlap_prune(int64_t n, const float* means, double d_op, int64_t m, const int64_t* ids, uint8_t* keep,
+                      double* d_avg) {
+  const int64_t count = ids ? m : n;
 #pragma omp parallel for schedule(dynamic, 64)
-  for (int64_t i = 0; i < n; ++i) {
+  for (int64_t t = 0; t < count; ++t) {
+    const int64_t i = ids ? ids[t] : t;
     double best[3] = {INFINITY, INFINITY, INFINITY};
     const double xi = means[i * 3 + 0], yi = means[i * 3 + 1], zi = means[i * 3 + 2];
     for (int64_t j = 0; j < n; ++j) {
@@ -505,8 +509,8 @@ void or_overlap_prune(int64_t n, const float* means, double d_op, uint8_t* keep,
       }
     }
     const double avg = ((best[0] + best[1]) + best[2]) / 3.0;
-    d_avg[i] = avg;
-    keep[i] = (avg < d_op) ? 0 : 1;
+    d_avg[t] = avg;
+    keep[t] = (avg < d_op) ? 0 : 1;
   }
 }
 

@@ -26,7 +26,8 @@ EXPORTS = ("flod_ctx_create", "flod_ctx_destroy", "flod_ctx_workspace_bytes", "f
            "flod_ctx_trim", "flod_render_level", "flod_render_selective", "flod_render_backward",
            "flod_ctx_stats", "flod_ctx_view", "flod_ctx_set_timing", "flod_ctx_stage_times",
            "flod_stage_name", "flod_smin", "flod_dproj", "flod_status_str", "flod_copy_to_host",
-           "flod_render_merged", "flod_select_compact")
+           "flod_render_merged", "flod_select_compact", "flod_overlap_prune", "flod_compact_level",
+           "flod_level_transition")
 
 
 class FlodError(RuntimeError):
@@ -107,6 +108,12 @@ def load():
     L.flod_select_compact.argtypes = [vp, C.POINTER(Level), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_float),
                                       C.POINTER(C.c_float), C.POINTER(Level), C.POINTER(C.c_int64), vp]
     L.flod_select_compact.restype = C.c_int
+    L.flod_overlap_prune.argtypes = [vp, C.POINTER(Level), C.c_float, vp, vp, C.POINTER(C.c_int64), vp]
+    L.flod_overlap_prune.restype = C.c_int
+    L.flod_compact_level.argtypes = [vp, C.POINTER(Level), vp, C.POINTER(Level), C.POINTER(C.c_int64), vp]
+    L.flod_compact_level.restype = C.c_int
+    L.flod_level_transition.argtypes = [vp, C.POINTER(Level), C.c_float, C.POINTER(Level), vp]
+    L.flod_level_transition.restype = C.c_int
     L.flod_render_backward.argtypes = [vp, vp, C.POINTER(Grads), vp]
     L.flod_render_backward.restype = C.c_int
     L.flod_ctx_stats.argtypes = [vp, C.POINTER(Stats)]

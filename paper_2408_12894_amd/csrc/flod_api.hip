@@ -500,6 +500,71 @@ flod_status flod_render_merged(flod_ctx *ctx, const flod_level *levels, int n_le
   return st;
 }
 
+}  // extern "C"
+
+namespace {
+
+bool level_arrays_ok(const flod_level &o) {
+  if (o.n < 0) return false;
+  return o.n == 0 || (o.means && o.log_scales && o.quats && o.opacity_logits && o.sh && aligned(o.quats, 16) &&
+                      aligned(o.sh, 16) && aligned(o.means, 4) && aligned(o.log_scales, 4) &&
+                      aligned(o.opacity_logits, 4));
+}
+
+// Count the kept Gaussians of one level (per-workgroup counts, scan, a 4-byte read back)
+// and, when `out` is given, copy them in index order. count(block_cnt) and copy(prefix, out)
+// enqueue the two passes.
+template <class CountFn, class CopyFn>
+flod_status compact_pass(flod_ctx *ctx, int64_t n, hipStream_t s, CountFn count, CopyFn copy, flod_level *out,
+                         float s_min, int64_t *kept_out) {
+  *kept_out = 0;
+  if (n == 0) {
+    if (out) {
+      out->n = 0;
+      out->s_min = s_min;
+    }
+    return FLOD_OK;
+  }
+  const int nb = (int)((n + kBlock - 1) / kBlock);
+  size_t extra = 0;
+  if (ensure(ctx, B_BLOCKVIS, 4 * (size_t)nb, s, &extra) != FLOD_OK ||
+      ensure(ctx, B_PREFIX, 8 * (size_t)nb, s, &extra) != FLOD_OK ||
+      ensure(ctx, B_COUNTERS, 8 * (size_t)kCntSlots, s, &extra) != FLOD_OK) {
+    ctx->required = ws_bytes(ctx) + extra;
+    return FLOD_ERR_WORKSPACE;
+  }
+  uint32_t *counters = P<uint32_t>(ctx, B_COUNTERS);
+  if (count(P<uint32_t>(ctx, B_BLOCKVIS)) != hipSuccess ||
+      launch_scan_blocks(P<uint32_t>(ctx, B_BLOCKVIS), nullptr, kBlock, P<unsigned long long>(ctx, B_PREFIX),
+                         counters + kCntVisible, nullptr, nb, s) != hipSuccess ||
+      hipMemcpyAsync(ctx->host_counters, counters, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FLOD_ERR_DEVICE;
+  const int64_t kept = reinterpret_cast<const uint32_t *>(ctx->host_counters)[kCntVisible];
+  *kept_out = kept;
+  if (!out) return FLOD_OK;
+  if (out->n < kept) {
+    ctx->required = (size_t)kept * kGaussianBytes;
+    return FLOD_ERR_WORKSPACE;
+  }
+  if (copy(P<unsigned long long>(ctx, B_PREFIX), *out) != hipSuccess) return FLOD_ERR_DEVICE;
+  out->n = kept;
+  out->s_min = s_min;
+  return FLOD_OK;
+}
+
+flod_status begin_level_op(flod_ctx *ctx, hipStream_t s) {
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  ctx->last_stream = s;
+  ctx->required = 0;
+  ctx->saved.valid = false;
+  return FLOD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 flod_status flod_select_compact(flod_ctx *ctx, const flod_level *levels, int n_levels, int l_start, int l_end,
                                 const float *d_proj, const float centre[3], flod_level *out, int64_t *n_out,
                                 void *stream) {
@@ -512,59 +577,129 @@ flod_status flod_select_compact(flod_ctx *ctx, const flod_level *levels, int n_l
   for (int l = 0; l < n_levels; ++l)
     if (!(d_proj[l] >= 0.0f)) return FLOD_ERR_INVALID_ARG;
   if (!isfinite(centre[0]) || !isfinite(centre[1]) || !isfinite(centre[2])) return FLOD_ERR_INVALID_ARG;
-  if (out) {
-    for (int l = l_start; l <= l_end; ++l) {
-      const flod_level &o = out[l - 1];
-      if (o.n < 0) return FLOD_ERR_INVALID_ARG;
-      if (o.n > 0 && (!o.means || !o.log_scales || !o.quats || !o.opacity_logits || !o.sh ||
-                      !aligned(o.quats, 16) || !aligned(o.sh, 16)))
-        return FLOD_ERR_INVALID_ARG;
-    }
-  }
-  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  if (out)
+    for (int l = l_start; l <= l_end; ++l)
+      if (!level_arrays_ok(out[l - 1])) return FLOD_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  ctx->last_stream = s;
-  ctx->required = 0;
-  ctx->saved.valid = false;
+  if ((st = begin_level_op(ctx, s)) != FLOD_OK) return st;
   for (int l = 0; l < n_levels; ++l) n_out[l] = 0;
   for (int l = l_start; l <= l_end; ++l) {
     const flod_level &lv = levels[l - 1];
-    if (lv.n == 0) continue;
     // eq. 6 band of level l, with d_proj^(l_end) = 0 and d_proj^(l_start - 1) = infinity
     const float hi = (l == l_start) ? INFINITY : d_proj[l - 2];
     const float lo = (l == l_end) ? 0.0f : d_proj[l - 1];
     const float lo2 = sq32(lo), hi2 = sq32(hi);
-    const int nb = (int)((lv.n + kBlock - 1) / kBlock);
-    size_t extra = 0;
-    if (ensure(ctx, B_BLOCKVIS, 4 * (size_t)nb, s, &extra) != FLOD_OK ||
-        ensure(ctx, B_PREFIX, 8 * (size_t)nb, s, &extra) != FLOD_OK ||
-        ensure(ctx, B_COUNTERS, 8 * (size_t)kCntSlots, s, &extra) != FLOD_OK) {
-      ctx->required = ws_bytes(ctx) + extra;
-      return FLOD_ERR_WORKSPACE;
-    }
-    uint32_t *counters = P<uint32_t>(ctx, B_COUNTERS);
-    if (launch_select_count(lv.means, lv.n, centre, lo2, hi2, P<uint32_t>(ctx, B_BLOCKVIS), s) != hipSuccess ||
-        launch_scan_blocks(P<uint32_t>(ctx, B_BLOCKVIS), nullptr, kBlock, P<unsigned long long>(ctx, B_PREFIX),
-                           counters + kCntVisible, nullptr, nb, s) != hipSuccess ||
-        hipMemcpyAsync(ctx->host_counters, counters, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return FLOD_ERR_DEVICE;
-    const int64_t kept = reinterpret_cast<const uint32_t *>(ctx->host_counters)[kCntVisible];
-    n_out[l - 1] = kept;
-    if (!out) continue;
-    flod_level &o = out[l - 1];
-    if (o.n < kept) {
-      ctx->required = (size_t)kept;   // elements needed in level l's output arrays
-      return FLOD_ERR_WORKSPACE;
-    }
-    if (launch_select_copy(lv, centre, lo2, hi2, P<unsigned long long>(ctx, B_PREFIX), o, s) != hipSuccess)
-      return FLOD_ERR_DEVICE;
-    o.n = kept;
-    o.s_min = lv.s_min;
+    auto count = [&](uint32_t *bc) { return launch_select_count(lv.means, lv.n, centre, lo2, hi2, bc, s); };
+    auto copy = [&](const unsigned long long *prefix, const flod_level &o) {
+      return launch_select_copy(lv, centre, lo2, hi2, prefix, o, s);
+    };
+    if ((st = compact_pass(ctx, lv.n, s, count, copy, out ? &out[l - 1] : nullptr, lv.s_min, &n_out[l - 1])) !=
+        FLOD_OK)
+      return st;
   }
   if (out)
     for (int l = 1; l <= n_levels; ++l)
       if (l < l_start || l > l_end) out[l - 1].n = 0;
+  return FLOD_OK;
+}
+
+flod_status flod_compact_level(flod_ctx *ctx, const flod_level *in, const uint8_t *keep, flod_level *out,
+                               int64_t *n_out, void *stream) {
+  if (!ctx || !in || !n_out || (in->n > 0 && !keep)) return FLOD_ERR_INVALID_ARG;
+  flod_status st = check_level(in);
+  if (st != FLOD_OK) return st;
+  if (out) {
+    if (!level_arrays_ok(*out)) return FLOD_ERR_INVALID_ARG;
+    if (out->n > 0 && (out->means == in->means || out->log_scales == in->log_scales || out->quats == in->quats ||
+                       out->opacity_logits == in->opacity_logits || out->sh == in->sh))
+      return FLOD_ERR_INVALID_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = begin_level_op(ctx, s)) != FLOD_OK) return st;
+  auto count = [&](uint32_t *bc) { return launch_mask_count(keep, in->n, bc, s); };
+  auto copy = [&](const unsigned long long *prefix, const flod_level &o) {
+    return launch_mask_copy(*in, keep, prefix, o, s);
+  };
+  return compact_pass(ctx, in->n, s, count, copy, out, in->s_min, n_out);
+}
+
+flod_status flod_overlap_prune(flod_ctx *ctx, const flod_level *level, float d_op, uint8_t *keep, double *d_avg,
+                               int64_t *n_keep, void *stream) {
+  if (!ctx || !level || !n_keep) return FLOD_ERR_INVALID_ARG;
+  flod_status st = check_level(level);
+  if (st != FLOD_OK) return st;
+  const int64_t n = level->n;
+  if (n > ((int64_t)1 << 30) || !(d_op >= 0.0f) || !isfinite(d_op)) return FLOD_ERR_INVALID_ARG;
+  if (n > 0 && (!keep || (d_avg && !aligned(d_avg, 8)))) return FLOD_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = begin_level_op(ctx, s)) != FLOD_OK) return st;
+  *n_keep = 0;
+  if (n == 0) return FLOD_OK;
+  const int bits = prune_table_bits(n);
+  const int64_t buckets = (int64_t)1 << bits;
+  const int64_t sort_tile_n = (int64_t)kBlock * radix_items(n);
+  const int nbs = (int)((n + sort_tile_n - 1) / sort_tile_n);
+  size_t extra = 0;
+  auto need = [&](BufId id, size_t bytes) {
+    if (ensure(ctx, id, bytes, s, &extra) != FLOD_OK) st = FLOD_ERR_WORKSPACE;
+  };
+  if (d_op > 0.0f) {
+    need(B_DKEY0, 4 * (size_t)n);
+    need(B_DKEY1, 4 * (size_t)n);
+    need(B_DVAL0, 4 * (size_t)n);
+    need(B_DVAL1, 4 * (size_t)n);
+    need(B_XYAB, 16 * (size_t)n);
+    need(B_RANGES, 8 * (size_t)buckets);
+    need(B_HIST, 4 * (size_t)kRadix * nbs);
+    need(B_SCAN, 4 * (size_t)kRadix * nbs);
+    need(B_TOT, 4 * (size_t)kRadix);
+  }
+  need(B_COUNTERS, 8 * (size_t)kCntSlots);
+  if (st != FLOD_OK) {
+    ctx->required = ws_bytes(ctx) + extra;
+    return st;
+  }
+  uint32_t *counters = P<uint32_t>(ctx, B_COUNTERS);
+  const float4 *pts = P<float4>(ctx, B_XYAB);
+  const uint2 *ranges = P<uint2>(ctx, B_RANGES);
+  if (d_op > 0.0f) {
+    uint32_t *dk[2] = {P<uint32_t>(ctx, B_DKEY0), P<uint32_t>(ctx, B_DKEY1)};
+    uint32_t *dv[2] = {P<uint32_t>(ctx, B_DVAL0), P<uint32_t>(ctx, B_DVAL1)};
+    int res = 0;
+    if (launch_fill_u32(counters + kCntVisible, (uint32_t)n, 1, s) != hipSuccess ||
+        launch_fill_u32(counters + kCntTotal64, 0u, 2, s) != hipSuccess ||
+        launch_prune_keys(level->means, n, d_op, dk[0], dv[0], s) != hipSuccess ||
+        launch_radix_sort(dk, dv, counters + kCntVisible, n, bits, P<uint32_t>(ctx, B_HIST),
+                          P<uint32_t>(ctx, B_SCAN), P<uint32_t>(ctx, B_TOT), &res, s) != hipSuccess ||
+        launch_prune_gather(level->means, dv[res], n, P<float4>(ctx, B_XYAB), s) != hipSuccess ||
+        launch_ranges(dk[res], n, (int)buckets, P<uint2>(ctx, B_RANGES), s) != hipSuccess ||
+        launch_prune_cost(pts, ranges, n, d_op, reinterpret_cast<unsigned long long *>(counters + kCntTotal64),
+                          s) != hipSuccess ||
+        hipMemcpyAsync(ctx->host_counters, counters, 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    if (ctx->host_counters[1] > kPruneMaxScan) return FLOD_ERR_UNSUPPORTED;
+  }
+  if (launch_prune_query(pts, ranges, n, d_op, keep, d_avg, s) != hipSuccess) return FLOD_ERR_DEVICE;
+  auto count = [&](uint32_t *bc) { return launch_mask_count(keep, n, bc, s); };
+  auto no_copy = [&](const unsigned long long *, const flod_level &) { return hipSuccess; };
+  return compact_pass(ctx, n, s, count, no_copy, nullptr, level->s_min, n_keep);
+}
+
+flod_status flod_level_transition(flod_ctx *ctx, const flod_level *in, float s_min_next, flod_level *out,
+                                  void *stream) {
+  if (!ctx || !in || !out) return FLOD_ERR_INVALID_ARG;
+  flod_status st = check_level(in);
+  if (st != FLOD_OK) return st;
+  if (!(s_min_next >= 0.0f) || !(s_min_next <= in->s_min)) return FLOD_ERR_INVALID_ARG;
+  if (!level_arrays_ok(*out) || out->n < in->n) return FLOD_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = begin_level_op(ctx, s)) != FLOD_OK) return st;
+  flod_level o = *out;
+  o.n = in->n;
+  if (launch_level_transition(*in, s_min_next, o, s) != hipSuccess) return FLOD_ERR_DEVICE;
+  out->n = in->n;
+  out->s_min = s_min_next;
   return FLOD_OK;
 }
 

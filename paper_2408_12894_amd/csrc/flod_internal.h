@@ -16,6 +16,8 @@ constexpr int kSortItems = 16;            // keys per thread in a radix pass
 constexpr int kSortTile = kBlock * kSortItems;   // 4096 keys per workgroup
 constexpr int kSortItemsSmall = 4;        // 1024-key workgroups for sorts below kRadixBigSort
 constexpr int64_t kRadixBigSort = 4 << 20;
+constexpr size_t kGaussianBytes = (3 + 3 + 4 + 1 + FLOD_SH_COEFFS * 3) * 4;   // 236 B per stored Gaussian
+constexpr unsigned long long kPruneMaxScan = 1ull << 36;   // overlap-pruning neighbour-scan limit
 
 // Rasterizer conventions (3DGS framework): near plane, EWA dilation, Jacobian clamp at 1.3x the half field of view, alpha clamp, alpha floor,
 // transmittance floor, support cut q <= 9.
@@ -110,5 +112,18 @@ hipError_t launch_select_count(const float *means, int64_t n, const float centre
                                uint32_t *block_cnt, hipStream_t s);
 hipError_t launch_select_copy(const flod_level &in, const float centre[3], float lo2, float hi2,
                               const unsigned long long *prefix, const flod_level &out, hipStream_t s);
+hipError_t launch_mask_count(const uint8_t *mask, int64_t n, uint32_t *block_cnt, hipStream_t s);
+hipError_t launch_mask_copy(const flod_level &in, const uint8_t *mask, const unsigned long long *prefix,
+                            const flod_level &out, hipStream_t s);
+hipError_t launch_level_transition(const flod_level &in, float s_min_next, const flod_level &out, hipStream_t s);
+int prune_table_bits(int64_t n);   // log2 of the overlap-pruning hash table size for n points
+hipError_t launch_prune_keys(const float *means, int64_t n, float d_op, uint32_t *keys, uint32_t *vals,
+                             hipStream_t s);
+hipError_t launch_prune_gather(const float *means, const uint32_t *sorted_vals, int64_t n, float4 *pts,
+                               hipStream_t s);
+hipError_t launch_prune_cost(const float4 *pts, const uint2 *ranges, int64_t n, float d_op,
+                             unsigned long long *cost, hipStream_t s);
+hipError_t launch_prune_query(const float4 *pts, const uint2 *ranges, int64_t n, float d_op, uint8_t *keep,
+                              double *d_avg, hipStream_t s);
 
 }  // namespace flod

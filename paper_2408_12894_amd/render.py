@@ -189,15 +189,58 @@ class Renderer:
         for l in range(1, n_levels + 1):
             dev = levels[l - 1].means.device
             k = int(counts[l - 1])
-            g = GaussianLevel(torch.empty((k, 3), device=dev), torch.empty((k, 3), device=dev),
-                              torch.empty((k, 4), device=dev), torch.empty((k,), device=dev),
-                              torch.empty((k, SH_COEFFS, 3), device=dev), levels[l - 1].s_min)
+            g = _empty_level(k, levels[l - 1].s_min, dev)
             kept.append(g)
             out[l - 1] = _lib.Level(g.means.data_ptr(), g.log_scales.data_ptr(), g.quats.data_ptr(),
                                     g.opacity_logits.data_ptr(), g.sh.data_ptr(), k, float(g.s_min))
         _lib.check(self.L.flod_select_compact(self.ctx, arr, n_levels, int(l_start), int(l_end), dp, ce, out,
                                               counts, sp), "flod_select_compact")
         return kept[l_start - 1: l_end]
+
+    def overlap_prune(self, level: GaussianLevel, d_op: float, with_d_avg: bool = False, stream=None):
+        """Overlap pruning decision for every Gaussian of `level` (removed iff the mean
+        distance to its three nearest others is below d_op). Returns (keep uint8 tensor,
+        kept count) and, with with_d_avg, the float64 d_avg tensor (+inf where the three
+        nearest are not all within 3 d_op)."""
+        dev = level.means.device
+        keep = torch.empty((level.n,), dtype=torch.uint8, device=dev)
+        davg = torch.empty((level.n,), dtype=torch.float64, device=dev) if with_d_avg else None
+        cs = level.c_struct()
+        n_keep = C.c_int64(0)
+        _lib.check(self.L.flod_overlap_prune(self.ctx, C.byref(cs), float(d_op), C.c_void_p(keep.data_ptr()),
+                                             C.c_void_p(davg.data_ptr() if davg is not None else 0),
+                                             C.byref(n_keep), C.c_void_p(_stream_ptr(stream))), "flod_overlap_prune")
+        self._last_level_forward = None
+        return (keep, int(n_keep.value), davg) if with_d_avg else (keep, int(n_keep.value))
+
+    def compact(self, level: GaussianLevel, keep: torch.Tensor, stream=None) -> GaussianLevel:
+        """The Gaussians of `level` whose keep byte is nonzero, in index order, as a new level."""
+        if keep.dtype != torch.uint8 or keep.numel() != level.n or not keep.is_contiguous():
+            raise ValueError("keep must be a contiguous uint8 tensor with one entry per Gaussian")
+        cs = level.c_struct()
+        n_out = C.c_int64(0)
+        sp = C.c_void_p(_stream_ptr(stream))
+        _lib.check(self.L.flod_compact_level(self.ctx, C.byref(cs), C.c_void_p(keep.data_ptr()), None,
+                                             C.byref(n_out), sp), "flod_compact_level")
+        g = _empty_level(int(n_out.value), level.s_min, level.means.device)
+        out = g.c_struct()
+        _lib.check(self.L.flod_compact_level(self.ctx, C.byref(cs), C.c_void_p(keep.data_ptr()), C.byref(out),
+                                             C.byref(n_out), sp), "flod_compact_level")
+        self._last_level_forward = None
+        return g
+
+    def level_transition(self, level: GaussianLevel, s_min_next: float, in_place: bool = False,
+                         stream=None) -> GaussianLevel:
+        """eq. 5: the initial state of the next level (same Gaussians, scale parameters
+        re-expressed so that the scale under s_min_next equals the scale under level.s_min)."""
+        cs = level.c_struct()
+        g = level if in_place else _empty_level(level.n, level.s_min, level.means.device)
+        out = g.c_struct()
+        _lib.check(self.L.flod_level_transition(self.ctx, C.byref(cs), float(s_min_next), C.byref(out),
+                                                C.c_void_p(_stream_ptr(stream))), "flod_level_transition")
+        g.s_min = float(out.s_min)
+        self._last_level_forward = None
+        return g
 
     # ------------------------------------------------------------------ backward
     def backward(self, level: GaussianLevel, dL_dimage: torch.Tensor, stream=None):
@@ -267,6 +310,12 @@ class Renderer:
                     blue=get(v.blue, 2 * N, np.float32).reshape(N, 2)[:, 0].copy(),
                     mu_lo_bits=get(v.blue, 2 * N, np.float32).reshape(N, 2)[:, 1].copy().view(np.uint32), stats=s,
                     grad2d=get(v.grad2d, 9 * N, np.float32).reshape(9, N) if v.grad2d else None)
+
+
+def _empty_level(n: int, s_min: float, device) -> GaussianLevel:
+    return GaussianLevel(torch.empty((n, 3), device=device), torch.empty((n, 3), device=device),
+                         torch.empty((n, 4), device=device), torch.empty((n,), device=device),
+                         torch.empty((n, SH_COEFFS, 3), device=device), float(s_min))
 
 
 def save_levels(path: str, levels) -> None:

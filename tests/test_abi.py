@@ -74,6 +74,12 @@ def test_validation_before_any_device_call(lib):
     bg = (C.c_float * 3)(0, 0, 0)
     assert lib.flod_render_level(None, C.byref(lv), 3, C.byref(cam), bg, C.byref(fr), None) == bad
     assert lib.flod_render_backward(None, None, None, None) == bad
+    n64 = C.c_int64(0)
+    assert lib.flod_render_merged(None, C.byref(lv), 1, 3, C.byref(cam), bg, C.byref(fr), None) == bad
+    assert lib.flod_select_compact(None, C.byref(lv), 1, 1, 1, None, None, None, C.byref(n64), None) == bad
+    assert lib.flod_overlap_prune(None, C.byref(lv), 0.1, None, None, C.byref(n64), None) == bad
+    assert lib.flod_compact_level(None, C.byref(lv), None, None, C.byref(n64), None) == bad
+    assert lib.flod_level_transition(None, C.byref(lv), 0.0, C.byref(lv), None) == bad
     assert lib.flod_ctx_stats(None, None) == bad
     assert lib.flod_ctx_view(None, None) == bad
     assert lib.flod_ctx_set_timing(None, 1) == bad

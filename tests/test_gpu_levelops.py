@@ -1,0 +1,178 @@
+"""Level operations on the device against the oracle: overlap pruning (section Overlap
+Pruning), compaction by a keep mask, and the eq. 5 level transition."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_12894_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def r():
+    from paper_2408_12894_amd import render
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return render.Renderer(0)
+
+
+def _level(means, s_min=0.05, seed=0):
+    from paper_2408_12894_amd import render
+    n = means.shape[0]
+    sc = synth.uniform_scene(n, seed=seed)
+    return render.GaussianLevel.from_arrays(np.asarray(means, np.float32), sc.log_scales, sc.quats,
+                                            sc.opacity_logits, sc.sh, s_min=s_min)
+
+
+def _check_prune(r, means, d_op, ids=None):
+    lv = _level(means)
+    keep, n_keep, davg = r.overlap_prune(lv, d_op, with_d_avg=True)
+    keep, davg = keep.cpu().numpy(), davg.cpu().numpy()
+    ok, od = oracle.overlap_prune(means, d_op, ids=ids)
+    sel = np.arange(means.shape[0]) if ids is None else np.asarray(ids)
+    np.testing.assert_array_equal(keep[sel], ok)
+    found = np.isfinite(davg[sel])
+    np.testing.assert_array_equal(davg[sel][found], od[found])     # same FP64 operations
+    assert np.all(od[~found] >= d_op)                              # not found within 3 d_op: kept
+    assert n_keep == int(keep.sum())
+    return keep, davg
+
+
+@pytest.mark.parametrize("n,seed", [(3000, 1), (20000, 2)])
+@pytest.mark.parametrize("level", [1, 3, 4])
+def test_prune_cluster_levels(r, n, seed, level):
+    print(f"[case] prune cluster n={n} seed={seed} level={level}", flush=True)
+    sc = synth.cluster_scene(n, seed=seed, layout_seed=1)
+    d_op = synth.LEVEL_SMIN[level - 1] / 2
+    keep, _ = _check_prune(r, sc.means, d_op)
+    assert 0 < keep.sum() <= n
+
+
+def test_prune_half_removed_threshold(r):
+    print("[case] prune at the median d_avg", flush=True)
+    rng = np.random.default_rng(7)
+    m = rng.normal(0, 0.5, (8000, 3)).astype(np.float32)
+    _, od = oracle.overlap_prune(m, 1.0)
+    d_op = float(np.median(od))
+    keep, _ = _check_prune(r, m, d_op)
+    assert 0.3 < keep.mean() < 0.7
+
+
+def test_prune_edge_cases(r):
+    print("[case] prune edge cases", flush=True)
+    for n in (1, 2, 3, 4, 5):
+        m = np.random.default_rng(n).normal(0, 0.01, (n, 3)).astype(np.float32)
+        _check_prune(r, m, 0.5)
+    m = np.zeros((6, 3), np.float32)                              # all coincident
+    keep, _ = _check_prune(r, m, 1e-3)
+    assert not keep.any()
+    rng = np.random.default_rng(3)
+    m = rng.normal(0, 1, (3000, 3)).astype(np.float32)
+    m[100:110] = m[100]                                            # a stack of duplicates
+    _check_prune(r, m, 0.05)
+    keep, davg = _check_prune(r, m, 0.0)                          # d_op = 0 removes nothing
+    assert keep.all() and np.all(np.isinf(davg))
+    far = np.concatenate([m, m[:500] * 1e6]).astype(np.float32)   # coordinates beyond the clamped grid
+    _check_prune(r, far, 0.01)
+    lv = _level(np.zeros((0, 3), np.float32))
+    keep, n_keep = r.overlap_prune(lv, 0.1)
+    assert keep.numel() == 0 and n_keep == 0
+
+
+def test_prune_one_cell(r):
+    print("[case] prune with every point in one cell", flush=True)
+    m = np.random.default_rng(4).uniform(-0.1, 0.1, (4000, 3)).astype(np.float32)
+    _check_prune(r, m, 1.0)
+
+
+def test_prune_refuses_a_huge_scan(r):
+    from paper_2408_12894_amd import _lib
+    print("[case] prune scan-size limit", flush=True)
+    m = np.random.default_rng(5).uniform(-0.01, 0.01, (300_000, 3)).astype(np.float32)
+    lv = _level(m)
+    with pytest.raises(_lib.FlodError) as e:
+        r.overlap_prune(lv, 10.0)
+    assert e.value.status == _lib.FLOD_ERR_UNSUPPORTED
+
+
+def test_prune_full_level_sampled(r):
+    print("[case] prune level 4 (1.2M) sampled", flush=True)
+    sc = synth.cluster_scene(synth.LEVEL_SIZES[3], seed=14, layout_seed=1, s_min=synth.LEVEL_SMIN[3])
+    ids = np.random.default_rng(9).choice(sc.n, 400, replace=False)
+    keep, _ = _check_prune(r, sc.means, synth.LEVEL_SMIN[3] / 2, ids=ids)
+    print(f"  kept {keep.mean():.4f}", flush=True)
+
+
+def test_compact_by_mask(r):
+    print("[case] compaction by mask", flush=True)
+    sc = synth.cluster_scene(50_000, seed=3, layout_seed=1, s_min=0.1)
+    from paper_2408_12894_amd import render
+    lv = render.GaussianLevel.from_scene(sc)
+    mask = (np.random.default_rng(1).random(sc.n) < 0.37).astype(np.uint8)
+    out = r.compact(lv, torch.as_tensor(mask).cuda())
+    assert out.n == int(mask.sum()) and out.s_min == lv.s_min
+    for name, arr in zip(("means", "log_scales", "quats", "opacity_logits", "sh"), sc.arrays()):
+        np.testing.assert_array_equal(getattr(out, name).cpu().numpy(), arr[mask.astype(bool)], err_msg=name)
+    empty = r.compact(lv, torch.zeros(sc.n, dtype=torch.uint8, device="cuda"))
+    assert empty.n == 0
+
+
+def test_prune_then_compact(r):
+    print("[case] prune then compact", flush=True)
+    sc = synth.cluster_scene(20_000, seed=6, layout_seed=1, s_min=0.2)
+    from paper_2408_12894_amd import render
+    lv = render.GaussianLevel.from_scene(sc)
+    keep, n_keep = r.overlap_prune(lv, 0.1)
+    out = r.compact(lv, keep)
+    ok, _ = oracle.overlap_prune(sc.means, 0.1)
+    assert out.n == n_keep == int(ok.sum())
+    np.testing.assert_array_equal(out.means.cpu().numpy(), sc.means[ok.astype(bool)])
+
+
+def _ulp_diff(a, b):
+    ai = a.view(np.int32).astype(np.int64)
+    bi = b.view(np.int32).astype(np.int64)
+    return np.abs(ai - bi)
+
+
+@pytest.mark.parametrize("level", [1, 2, 3, 4])
+def test_level_transition(r, level):
+    from paper_2408_12894_amd import render
+    print(f"[case] eq. 5 transition level {level}", flush=True)
+    sl, sn = synth.LEVEL_SMIN[level - 1], synth.LEVEL_SMIN[level] if level < 5 else 0.0
+    sc = synth.cluster_scene(30_000, seed=20 + level, layout_seed=1, s_mu=-4.0, s_sigma=1.5, s_min=sl)
+    lv = render.GaussianLevel.from_scene(sc)
+    nxt = r.level_transition(lv, sn)
+    assert nxt.s_min == np.float32(sn) and nxt.n == lv.n
+    got = nxt.log_scales.cpu().numpy()
+    ref = oracle.level_transition(sc.log_scales, sl, sn).astype(np.float32)
+    u = _ulp_diff(got, ref)
+    assert u.max() <= 1 and (u == 0).mean() >= 0.999
+    for name in ("means", "quats", "opacity_logits", "sh"):
+        np.testing.assert_array_equal(getattr(nxt, name).cpu().numpy(), getattr(sc, name), err_msg=name)
+    # in place gives the same bits
+    lv2 = render.GaussianLevel.from_scene(sc)
+    r.level_transition(lv2, sn, in_place=True)
+    np.testing.assert_array_equal(lv2.log_scales.cpu().numpy(), got)
+    assert lv2.s_min == nxt.s_min
+    # the next level renders as the trained one did
+    cam = synth.look_at_camera((0.0, 1.0, 9.0), (0, 0, 0), 320, 240)
+    a = r.render_level(lv, cam)[0].cpu().numpy()
+    b = r.render_level(nxt, cam)[0].cpu().numpy()
+    assert np.abs(a - b).max() <= 1e-3 and np.abs(a - b).mean() <= 1e-6
+
+
+def test_level_transition_rejects_rising_floor(r):
+    from paper_2408_12894_amd import _lib, render
+    print("[case] eq. 5 transition argument checks", flush=True)
+    sc = synth.cluster_scene(100, seed=1, layout_seed=1, s_min=0.05)
+    lv = render.GaussianLevel.from_scene(sc)
+    with pytest.raises(_lib.FlodError):
+        r.level_transition(lv, 0.1)
+    small = render._empty_level(10, 0.0, "cuda")
+    cs, out = lv.c_struct(), small.c_struct()
+    assert r.L.flod_level_transition(r.ctx, C.byref(cs), 0.01, C.byref(out), None) == _lib.FLOD_ERR_INVALID_ARG

@@ -654,3 +654,13 @@ def test_level_transition_keeps_scale(oracle_mod):
     # equal floors and an exp that underflows in FP32: log(0) = -inf keeps s = s_min
     out = oracle_mod.level_transition(np.full((1, 3), -200.0, np.float32), 0.05, 0.05)
     assert np.all(np.isneginf(out)) and np.all(np.exp(out) + np.float32(0.05) == np.float32(0.05))
+
+
+def test_overlap_prune_sampled_equals_full(oracle_mod):
+    rng = np.random.default_rng(5)
+    m = rng.normal(0, 1, (800, 3)).astype(np.float32)
+    keep, davg = oracle_mod.overlap_prune(m, 0.2)
+    ids = rng.choice(800, 50, replace=False)
+    k2, d2 = oracle_mod.overlap_prune(m, 0.2, ids=ids)
+    np.testing.assert_array_equal(k2, keep[ids])
+    np.testing.assert_array_equal(d2, davg[ids])
