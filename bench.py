@@ -240,6 +240,30 @@ def main():
             "selective_vs_max_level": t_l5 / t_sel, "selected_per_level_cam0": sel_counts,
             "K_max_level": k_l5, "K_selective": k_sel, "per_level": per_level}
         log(f"stack: L5 {1 / t_l5:.1f} FPS, selective[1,5] {1 / t_sel:.1f} FPS, selected {sel_counts}")
+        # predetermined selection set around the mean camera position: compact once, render the subset
+        centre = np.mean([c.campos for c in cams], axis=0).astype(np.float32)
+        t0 = time.perf_counter()
+        gsel = r.select_compact(stack, 1, 5, synth.LEVEL_BANDS, centre)
+        sync()
+        t_compact = time.perf_counter() - t0
+        t_pre = timed(lambda i: r.render_merged(gsel, cams[i % 8], bg), 16, 8, sync)
+        out_extra["predetermined_1080p"] = {
+            "resident_bytes": int(sum(x.nbytes() for x in gsel)), "kept_per_level": [x.n for x in gsel],
+            "compact_ms": 1e3 * t_compact, "render_fps": 1.0 / t_pre}
+        log(f"predetermined: {sum(x.nbytes() for x in gsel) / 2**30:.3f} GiB resident, compact "
+            f"{1e3 * t_compact:.1f} ms, render {1 / t_pre:.1f} FPS")
+        del gsel
+        # overlap pruning (d_op = s_min / 2) and the eq. 5 transition, levels 1-4
+        ops = {}
+        for l in range(1, 5):
+            lvl = stack[l - 1]
+            kept = r.overlap_prune(lvl, lvl.s_min / 2)[1]
+            t_pr = timed(lambda i: r.overlap_prune(lvl, lvl.s_min / 2), 5, 1, sync)
+            t_tr = timed(lambda i: r.level_transition(lvl, stack[l].s_min), 5, 1, sync)
+            ops[f"L{l}"] = {"n": lvl.n, "prune_ms": 1e3 * t_pr, "kept": kept,
+                            "transition_ms": 1e3 * t_tr, "transition_GBs": 2 * 236 * lvl.n / t_tr / 1e9}
+            log(f"L{l}: prune {1e3 * t_pr:.2f} ms (kept {kept}/{lvl.n}), transition {1e3 * t_tr:.3f} ms")
+        out_extra["level_ops"] = ops
         # -------------------------------------------------------------- serving
         if not args.no_serving:
             trace = synth.serving_trace(seed=30, count=args.serving_requests)
