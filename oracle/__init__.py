@@ -304,3 +304,6 @@ def render(scene_arrays, smin, cam, bg, deg=3, keep=None, pix=None) -> dict:
     img["keys"] = k
     img["order"] = order
     return img
+
+
+from . import ssim  # noqa: E402  (L1 + SSIM training loss, numpy FP64)
