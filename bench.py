@@ -217,6 +217,20 @@ def main():
                                    "K": r.stats()["n_instances"]}
         log(f"train 720p/500k: {1e3 * t:.3f} ms ({1 / t:.1f} it/s)")
         del tr_params, tr_lv, tr_tgt
+        # -------------------------------------------------------------- L1 + SSIM loss at 1080p
+        g = torch.Generator(device=dev).manual_seed(5)
+        ls_x = torch.rand((3, 1080, 1920), device=dev, generator=g).requires_grad_(True)
+        ls_y = torch.rand((3, 1080, 1920), device=dev, generator=g)
+
+        def loss_step(i):
+            ls_x.grad = None
+            render.l1_ssim_loss(ls_x, ls_y, 0.2, renderer=r).backward()
+
+        t = timed(loss_step, 30, 5, sync)
+        out_extra["l1_ssim_1080p"] = {"ms_fwd_bwd": 1e3 * t,
+                                      "GBs_algorithmic": (3 * 1080 * 1920 * (8 + 12 + 12 + 12)) / t / 1e9}
+        log(f"L1+SSIM 1080p fwd+bwd: {1e3 * t:.3f} ms")
+        del ls_x, ls_y
         # -------------------------------------------------------------- 5-level stack at 1080p
         log("5-level stack (4.39M resident)")
         stack_scenes = synth.level_stack()

@@ -183,6 +183,25 @@ flod_status flod_overlap_prune(flod_ctx *ctx, const flod_level *level, float d_o
 flod_status flod_compact_level(flod_ctx *ctx, const flod_level *in, const uint8_t *keep, flod_level *out,
                                int64_t *n_out, void *stream);
 
+/* Training loss (section Implementation: L1 and SSIM, as in the backbone model):
+   loss = (1 - lambda) mean|x - y| + lambda (1 - SSIM(x, y)), SSIM with an 11 x 11 Gaussian
+   window (sigma 1.5, normalised), zeros outside the image, C1 = 0.01^2, C2 = 0.03^2, averaged
+   over channels and pixels. image, target: device float[channels, height, width]
+   (contiguous). loss: device double[1] (written; no host synchronisation). dmaps: device
+   float[3, channels, height, width] or NULL; when given, receives the per-pixel derivatives
+   of SSIM with respect to the windowed mean, second moment and cross moment of the image,
+   which flod_l1_ssim_backward consumes. Moments and sums in FP64; the loss is reduced in a
+   fixed order (deterministic). 0 <= lambda <= 1; 1 <= channels <= 64, sizes <= 65536. */
+flod_status flod_l1_ssim_forward(flod_ctx *ctx, const float *image, const float *target, int channels, int height,
+                                 int width, float lambda, double *loss, float *dmaps, void *stream);
+
+/* Gradient of the loss above with respect to image, times *dloss (device double[1], NULL
+   for 1): d_image, device float[channels, height, width]. dmaps from flod_l1_ssim_forward on
+   the same image, target and lambda. d|t|/dt is taken as 0 at t = 0. */
+flod_status flod_l1_ssim_backward(flod_ctx *ctx, const float *image, const float *target, int channels, int height,
+                                  int width, float lambda, const float *dmaps, const double *dloss, float *d_image,
+                                  void *stream);
+
 /* Level transition (section Training Method, eq. 5): initialise level l+1 from the trained
    level l = *in: every attribute copied, and s_opt' = log(s^(l) - s_min_next) with
    s^(l) = exp(s_opt) + in->s_min formed as the renderer forms it (exp in FP64 rounded once

@@ -20,7 +20,7 @@ enum BufId {
   B_XYAB, B_COP, B_BLUE, B_DEPTH, B_RECT, B_TILES, B_BLOCKVIS, B_PREFIX,
   B_DKEY0, B_DKEY1, B_DVAL0, B_DVAL1, B_TBSUM, B_TPREFIX,
   B_TKEY0, B_TKEY1, B_TVAL0, B_TVAL1, B_HIST, B_SCAN, B_TOT, B_RANGES, B_COUNTERS,
-  B_G2D, B_COUNT
+  B_G2D, B_SSIM, B_COUNT
 };
 
 struct Saved {
@@ -684,6 +684,39 @@ flod_status flod_overlap_prune(flod_ctx *ctx, const flod_level *level, float d_o
   auto count = [&](uint32_t *bc) { return launch_mask_count(keep, n, bc, s); };
   auto no_copy = [&](const unsigned long long *, const flod_level &) { return hipSuccess; };
   return compact_pass(ctx, n, s, count, no_copy, nullptr, level->s_min, n_keep);
+}
+
+flod_status flod_l1_ssim_forward(flod_ctx *ctx, const float *image, const float *target, int channels, int height,
+                                 int width, float lambda, double *loss, float *dmaps, void *stream) {
+  if (!ctx || !image || !target || !loss) return FLOD_ERR_INVALID_ARG;
+  if (channels < 1 || height < 1 || width < 1 || height > 65536 || width > 65536 || channels > 64)
+    return FLOD_ERR_INVALID_ARG;
+  if (!(lambda >= 0.0f && lambda <= 1.0f) || !aligned(loss, 8)) return FLOD_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  ctx->last_stream = s;
+  ctx->required = 0;
+  size_t extra = 0;
+  if (ensure(ctx, B_SSIM, 16 * (size_t)ssim_blocks(channels, height, width), s, &extra) != FLOD_OK) {
+    ctx->required = ws_bytes(ctx) + extra;
+    return FLOD_ERR_WORKSPACE;
+  }
+  return dev(launch_ssim_forward(image, target, channels, height, width, lambda, loss, dmaps,
+                                 P<double2>(ctx, B_SSIM), s));
+}
+
+flod_status flod_l1_ssim_backward(flod_ctx *ctx, const float *image, const float *target, int channels, int height,
+                                  int width, float lambda, const float *dmaps, const double *dloss, float *d_image,
+                                  void *stream) {
+  if (!ctx || !image || !target || !dmaps || !d_image) return FLOD_ERR_INVALID_ARG;
+  if (channels < 1 || height < 1 || width < 1 || height > 65536 || width > 65536 || channels > 64)
+    return FLOD_ERR_INVALID_ARG;
+  if (!(lambda >= 0.0f && lambda <= 1.0f) || (dloss && !aligned(dloss, 8))) return FLOD_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  ctx->last_stream = s;
+  ctx->required = 0;
+  return dev(launch_ssim_backward(image, target, channels, height, width, lambda, dmaps, dloss, d_image, s));
 }
 
 flod_status flod_level_transition(flod_ctx *ctx, const flod_level *in, float s_min_next, flod_level *out,

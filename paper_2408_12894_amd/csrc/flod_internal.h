@@ -116,6 +116,11 @@ hipError_t launch_mask_count(const uint8_t *mask, int64_t n, uint32_t *block_cnt
 hipError_t launch_mask_copy(const flod_level &in, const uint8_t *mask, const unsigned long long *prefix,
                             const flod_level &out, hipStream_t s);
 hipError_t launch_level_transition(const flod_level &in, float s_min_next, const flod_level &out, hipStream_t s);
+int64_t ssim_blocks(int C, int H, int W);   // workgroups (and loss partials) of the SSIM kernels
+hipError_t launch_ssim_forward(const float *x, const float *y, int C, int H, int W, float lam, double *loss,
+                               float *gmap, double2 *partials, hipStream_t s);
+hipError_t launch_ssim_backward(const float *x, const float *y, int C, int H, int W, float lam, const float *gmap,
+                                const double *dloss, float *dx, hipStream_t s);
 int prune_table_bits(int64_t n);   // log2 of the overlap-pruning hash table size for n points
 hipError_t launch_prune_keys(const float *means, int64_t n, float d_op, uint32_t *keys, uint32_t *vals,
                              hipStream_t s);

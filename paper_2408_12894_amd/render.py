@@ -402,3 +402,50 @@ def _default_renderer() -> Renderer:
     if dev not in _DEFAULT:
         _DEFAULT[dev] = Renderer(dev)
     return _DEFAULT[dev]
+
+
+# ---------------------------------------------------------------------------------------
+# Training loss: (1 - lam) L1 + lam (1 - SSIM)
+# ---------------------------------------------------------------------------------------
+
+class L1SsimLoss(torch.autograd.Function):
+    """Scalar FP64 loss of image [C,H,W] against target; forward and backward in HIP."""
+
+    @staticmethod
+    def forward(ctx, image, target, renderer, lam):
+        image = image.detach().contiguous()
+        target = target.detach().contiguous()
+        if image.dtype != torch.float32 or target.dtype != torch.float32 or image.shape != target.shape \
+                or image.dim() != 3 or not image.is_cuda:
+            raise ValueError("image and target must be float32 CUDA tensors of the same [C,H,W] shape")
+        C_, H, W = image.shape
+        loss = torch.empty((), dtype=torch.float64, device=image.device)
+        dmaps = torch.empty((3, C_, H, W), dtype=torch.float32, device=image.device) \
+            if ctx.needs_input_grad[0] else None
+        _lib.check(renderer.L.flod_l1_ssim_forward(
+            renderer.ctx, C.c_void_p(image.data_ptr()), C.c_void_p(target.data_ptr()), C_, H, W, float(lam),
+            C.c_void_p(loss.data_ptr()), C.c_void_p(dmaps.data_ptr() if dmaps is not None else 0),
+            C.c_void_p(_stream_ptr(None))), "flod_l1_ssim_forward")
+        ctx.save_for_backward(image, target, dmaps)
+        ctx.renderer, ctx.lam = renderer, float(lam)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        image, target, dmaps = ctx.saved_tensors
+        r = ctx.renderer
+        C_, H, W = image.shape
+        g = grad_loss.to(torch.float64).contiguous()
+        d = torch.empty_like(image)
+        _lib.check(r.L.flod_l1_ssim_backward(
+            r.ctx, C.c_void_p(image.data_ptr()), C.c_void_p(target.data_ptr()), C_, H, W, ctx.lam,
+            C.c_void_p(dmaps.data_ptr()), C.c_void_p(g.data_ptr()), C.c_void_p(d.data_ptr()),
+            C.c_void_p(_stream_ptr(None))), "flod_l1_ssim_backward")
+        return d, None, None, None
+
+
+def l1_ssim_loss(image, target, lam: float = 0.2, renderer: Renderer | None = None):
+    """(1 - lam) mean|image - target| + lam (1 - SSIM(image, target)); FP64 scalar."""
+    if renderer is None:
+        renderer = _default_renderer()
+    return L1SsimLoss.apply(image, target, renderer, lam)
