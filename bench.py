@@ -186,6 +186,21 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": byts}
     roof["avg_launch_ms"] = dom_ms
+    # whole-step roofline: sum over stages of the larger of the HBM time and the ALU time
+    t_roof = 0.0
+    for k, v in per_stage.items():
+        t_b = algorithmic_bytes(k, N, n_vis, K, P, tiles) / (HBM_PEAK_GBS * 1e9)
+        t_a = 0.0
+        if k == "blend":
+            t_a = (FLOPS_EVAL * Pi_walk + FLOPS_BLEND_FWD * Pi_blend) / (FP32_VALU_PEAK_TFLOPS * 1e12)
+        elif k == "blend_bwd":
+            t_a = (FLOPS_EVAL * Pi_walk + FLOPS_BLEND_BWD * Pi_blend) / (FP32_VALU_PEAK_TFLOPS * 1e12)
+        v["roofline_ms"] = 1e3 * max(t_b, t_a)
+        v["frac"] = v["roofline_ms"] / v["ms"]
+        t_roof += max(t_b, t_a)
+    stage_sum_ms = sum(v["ms"] for v in per_stage.values())
+    out_extra["step_roofline"] = {"roofline_ms": 1e3 * t_roof, "stages_ms": stage_sum_ms,
+                                  "frac_of_stages": 1e3 * t_roof / stage_sum_ms, "frac_of_step": 1e3 * t_roof / ms_step}
     log(f"step {ms_step:.3f} ms ({iters_s:.1f} it/s); K={K:.0f} visible={n_vis:.0f} "
         f"pairs walked {Pi_walk:.3g} blended {Pi_blend:.3g}")
     log(f"tile list length mean {lens.mean():.0f} p50 {np.median(lens):.0f} p99 {np.percentile(lens, 99):.0f} "
@@ -197,7 +212,21 @@ def main():
         # -------------------------------------------------------------- forward FPS
         t = timed(lambda i: r.render_level(lv, cams[i % 8], bg), 8 * 8, 8, sync)
         out_extra["render_fps"] = 1.0 / t
-        log(f"render: {1e3 * t:.3f} ms/frame ({1 / t:.1f} FPS)")
+        # per-frame device time (events on the render stream): 8 cameras x 20 repetitions
+        evs = []
+        for rep in range(20):
+            for c in cams:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                r.render_level(lv, c, bg)
+                e1.record()
+                evs.append((e0, e1))
+        sync()
+        fms = np.array([a.elapsed_time(b) for a, b in evs])
+        out_extra["render_frame_ms"] = {"median": float(np.median(fms)), "p10": float(np.percentile(fms, 10)),
+                                        "p90": float(np.percentile(fms, 90)), "fps_median": 1e3 / float(np.median(fms))}
+        log(f"render: {1e3 * t:.3f} ms/frame ({1 / t:.1f} FPS); device median {np.median(fms):.3f} ms "
+            f"p10 {np.percentile(fms, 10):.3f} p90 {np.percentile(fms, 90):.3f}")
         del params, targets
         # -------------------------------------------------------------- 720p training step
         tr_scene, tr_target, tr_cam, _ = synth.training_case()
