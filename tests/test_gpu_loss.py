@@ -35,6 +35,7 @@ def _run(r, x, y, lam=0.2, scale=None):
 
 
 def _check(x, y, loss, grad, lam=0.2, scale=1.0):
+    lam = float(np.float32(lam))          # the library takes lambda as FP32
     ref = S.loss(x, y, lam)
     assert abs(loss - ref) <= 1e-12 * max(1.0, abs(ref)), (loss, ref)
     g = S.loss_grad(x, y, lam) * scale
@@ -84,7 +85,7 @@ def test_forward_only_and_argument_checks(r):
     loss = torch.empty((), dtype=torch.float64, device="cuda")
     st = r.L.flod_l1_ssim_forward(r.ctx, xt.data_ptr(), yt.data_ptr(), 3, 20, 30, 0.2, loss.data_ptr(), None, None)
     torch.cuda.synchronize()
-    assert st == _lib.FLOD_OK and abs(loss.item() - S.loss(x, y)) <= 1e-12
+    assert st == _lib.FLOD_OK and abs(loss.item() - S.loss(x, y, float(np.float32(0.2)))) <= 1e-12
     assert r.L.flod_l1_ssim_forward(r.ctx, xt.data_ptr(), yt.data_ptr(), 3, 20, 30, 1.5, loss.data_ptr(), None,
                                     None) == _lib.FLOD_ERR_INVALID_ARG
     assert r.L.flod_l1_ssim_forward(r.ctx, xt.data_ptr(), yt.data_ptr(), 0, 20, 30, 0.2, loss.data_ptr(), None,
