@@ -298,7 +298,8 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     uint32_t *dv = dres ? P<uint32_t>(c, B_DVAL1) : P<uint32_t>(c, B_DVAL0);
     tm.begin(FLOD_STAGE_EMIT);
     if (launch_emit(dv, counters + kCntVisible, n_vis, P<uint32_t>(c, B_TILES), P<float4>(c, B_XYAB),
-                    P<float4>(c, B_COP), P<unsigned long long>(c, B_TPREFIX), cam.tiles_x, cam.tiles_y, tk[0],
+                    P<float4>(c, B_COP), P<uint2>(c, B_RECT), P<unsigned long long>(c, B_TPREFIX), cam.tiles_x,
+                    cam.tiles_y, tk[0],
                     tv[0], s) != hipSuccess)
       return FLOD_ERR_DEVICE;
     tm.end();

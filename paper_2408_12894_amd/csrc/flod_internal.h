@@ -91,7 +91,7 @@ hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_
 hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_max,
                               const uint32_t *tiles, uint32_t *block_sum, hipStream_t s);
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_vis,
-                       const uint32_t *tiles, const float4 *xyab, const float4 *cop,
+                       const uint32_t *tiles, const float4 *xyab, const float4 *cop, const uint2 *rect,
                        const unsigned long long *prefix, int tiles_x, int tiles_y,
                        uint32_t *tile_ids, uint32_t *values, hipStream_t s);
 hipError_t launch_ranges(const uint32_t *tile_ids, int64_t K, int n_tiles, uint2 *ranges,

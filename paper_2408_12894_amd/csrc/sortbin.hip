@@ -282,7 +282,9 @@ hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
 // span of tiles in each row, recomputed exactly as the preprocess counted them) row-major
 // at its offset. Footprints of up to kEmitSolo tiles are written by their own thread; larger
 // ones are written by the whole wave, one row per lane, so a Gaussian covering hundreds of
-// tiles does not serialise a lane.
+// tiles does not serialise a lane. When the footprint fills its bounding rectangle (its tile
+// count equals the rectangle's area, the common case for small Gaussians) the rectangle is
+// written directly and the per-row spans are not recomputed.
 // ---------------------------------------------------------------------------------------
 constexpr uint32_t kEmitSolo = 16;
 
@@ -300,10 +302,26 @@ __device__ __forceinline__ void emit_rows(const Footprint &fp, int ty_begin, int
   }
 }
 
+struct RectSpan {
+  int x0, y0, x1, y1;
+  bool full;   // the footprint is the whole rectangle
+};
+
+__device__ __forceinline__ RectSpan rect_of(uint2 r, uint32_t count) {
+  RectSpan q;
+  q.x0 = (int)(r.x & 0xFFFFu);
+  q.y0 = (int)(r.x >> 16);
+  q.x1 = (int)(r.y & 0xFFFFu);
+  q.y1 = (int)(r.y >> 16);
+  q.full = (uint32_t)((q.x1 - q.x0 + 1) * (q.y1 - q.y0 + 1)) == count;
+  return q;
+}
+
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr,
                                                  const uint32_t *tiles, const float4 *xyab, const float4 *cop,
-                                                 const unsigned long long *prefix, int tiles_x, int tiles_y,
-                                                 uint32_t *__restrict__ tile_ids, uint32_t *__restrict__ values) {
+                                                 const uint2 *rect, const unsigned long long *prefix, int tiles_x,
+                                                 int tiles_y, uint32_t *__restrict__ tile_ids,
+                                                 uint32_t *__restrict__ values) {
   const uint32_t n = *n_ptr;
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
   if (blockIdx.x * kBlock >= n) return;
@@ -315,10 +333,21 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
   const uint32_t off = (uint32_t)(prefix[blockIdx.x] + ex);
   const int lane = threadIdx.x & 63;
   if (c > 0 && c <= kEmitSolo) {
-    const float4 A = xyab[g];
-    Footprint fp;
-    footprint(A.x, A.y, A.z, A.w, cop[g].x, tiles_y, fp);
-    emit_rows(fp, fp.ty0, fp.ty1, tiles_x, off, g, tile_ids, values);
+    const RectSpan rs = rect_of(rect[g], c);
+    if (rs.full) {
+      uint32_t pos = off;
+      for (int ty = rs.y0; ty <= rs.y1; ++ty)
+        for (int tx = rs.x0; tx <= rs.x1; ++tx) {
+          tile_ids[pos] = (uint32_t)(ty * tiles_x + tx);
+          values[pos] = g;
+          ++pos;
+        }
+    } else {
+      const float4 A = xyab[g];
+      Footprint fp;
+      footprint(A.x, A.y, A.z, A.w, cop[g].x, tiles_y, fp);
+      emit_rows(fp, fp.ty0, fp.ty1, tiles_x, off, g, tile_ids, values);
+    }
   }
   unsigned long long big = __ballot(c > kEmitSolo);
   while (big) {
@@ -326,15 +355,29 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
     big &= big - 1;
     const uint32_t os = __shfl(off, src, 64);
     const uint32_t gs = __shfl(g, src, 64);
-    const float4 A = xyab[gs];
+    const uint32_t cs = __shfl(c, src, 64);
+    const RectSpan rs = rect_of(rect[gs], cs);
     Footprint fp;
-    footprint(A.x, A.y, A.z, A.w, cop[gs].x, tiles_y, fp);
+    if (!rs.full) {
+      const float4 A = xyab[gs];
+      footprint(A.x, A.y, A.z, A.w, cop[gs].x, tiles_y, fp);
+    } else {
+      fp.ty0 = rs.y0;
+      fp.ty1 = rs.y1;
+    }
     const int nrows = fp.ty1 - fp.ty0 + 1;
     uint32_t base = os;
     for (int rb = 0; rb < nrows; rb += 64) {
       const int ty = fp.ty0 + rb + lane;
       int tx0 = 0, tx1 = -1;
-      if (rb + lane < nrows) row_span(fp, ty, tiles_x, tx0, tx1);
+      if (rb + lane < nrows) {
+        if (rs.full) {
+          tx0 = rs.x0;
+          tx1 = rs.x1;
+        } else {
+          row_span(fp, ty, tiles_x, tx0, tx1);
+        }
+      }
       const uint32_t w = (uint32_t)(tx1 - tx0 + 1);
       const uint32_t incl = wave_incl_scan(w);
       uint32_t pos = base + incl - w;
@@ -349,11 +392,11 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
 }
 
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_vis, const uint32_t *tiles,
-                       const float4 *xyab, const float4 *cop, const unsigned long long *prefix, int tiles_x,
-                       int tiles_y, uint32_t *tile_ids, uint32_t *values, hipStream_t s) {
+                       const float4 *xyab, const float4 *cop, const uint2 *rect, const unsigned long long *prefix,
+                       int tiles_x, int tiles_y, uint32_t *tile_ids, uint32_t *values, hipStream_t s) {
   if (n_vis <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_vis + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, sorted_ids,
-                     n_ptr, tiles, xyab, cop, prefix, tiles_x, tiles_y, tile_ids, values);
+                     n_ptr, tiles, xyab, cop, rect, prefix, tiles_x, tiles_y, tile_ids, values);
   return hipGetLastError();
 }
 
