@@ -11,8 +11,8 @@
 //   Shat_{i-1} = alpha_i c_i + (1 - alpha_i) Shat_i,  Shat_last = bg,
 // which avoids the cancellation between T_i c_i and S_i / (1 - alpha_i) in FP32.
 // Then alpha -> (opacity, q) unless the 0.99 clamp is active, q -> (conic, mu').
-// Per entry the 9 gradient components are reduced across the wave with DPP and one FP32
-// atomic per component is issued per (tile, Gaussian).
+// Per entry the 9 gradient components are reduced across the wave with DPP (the nine chains
+// interleaved) and lane 63 issues one FP32 atomic per component per (tile, Gaussian).
 //
 // Preprocess backward: one thread per Gaussian, recomputing the forward projection (FP64)
 // and applying the chain rule in FP64 to the mean (through mu', the EWA Jacobian and the SH view
@@ -27,6 +27,12 @@ constexpr int kG2d = 9;   // mu'x, mu'y, conic a, b, c, opacity, red, green, blu
 #define FLOD_BWD_PIX 4
 #endif
 constexpr int kBwdPix = FLOD_BWD_PIX;   // pixels per thread: 4 = one wave64 per tile
+#ifndef FLOD_BWD_BATCH
+#define FLOD_BWD_BATCH 128
+#endif
+// List entries staged in LDS per batch: 128 x 44 B = 5.6 KB per one-wave workgroup, so LDS
+// does not cap the waves a CU holds below what the registers allow.
+constexpr int kBwdBatch = FLOD_BWD_BATCH;
 
 // 1/x in FP64 from the hardware estimate and two Newton steps (x in [0.01, 1]).
 __device__ __forceinline__ double recip64(double x) {
@@ -52,10 +58,10 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   constexpr int NT = kTile * kTile / PPT;
   constexpr int ROWS = NT / kTile;
   constexpr int WAVES = NT / 64;
-  __shared__ float4 s_a[kBatch];
-  __shared__ float4 s_b[kBatch];
-  __shared__ float2 s_c[kBatch];
-  __shared__ uint32_t s_id[kBatch];
+  __shared__ float4 s_a[kBwdBatch];
+  __shared__ float4 s_b[kBwdBatch];
+  __shared__ float2 s_c[kBwdBatch];
+  __shared__ uint32_t s_id[kBwdBatch];
   __shared__ int s_max[WAVES];
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   if (tile >= n_tiles) return;
@@ -94,8 +100,8 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
     for (int w = 0; w < WAVES; ++w) mylast = max(mylast, s_max[w]);
   }
   const uint2 rg = ranges[tile];
-  for (int end = mylast; end > 0; end -= kBatch) {
-    const int start = max(0, end - kBatch);
+  for (int end = mylast; end > 0; end -= kBwdBatch) {
+    const int start = max(0, end - kBwdBatch);
     const int cnt = end - start;
     __syncthreads();
     for (int e = tid; e < cnt; e += NT) {
@@ -119,43 +125,43 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
 #pragma unroll
       for (int c = 0; c < kG2d; ++c) gr[c] = 0.0f;
       bool contrib = false;
+      // predicated like the forward: a pixel that does not take part adds exact zeros
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
-        if (jpos >= last[k]) continue;
         const float dy = (fy[k] - A.y) - loy;
         const float q = conic_q(A.z, A.w, B.x, dx, dy);
-        if (q > kQCut) continue;
         const float G = __expf(-0.5f * q);
         const float a0 = B.y * G;
         const float alpha = fminf(kAlphaMax, a0);
-        if (alpha < kAlphaMin) continue;
-        contrib = true;
+        const bool ok = jpos < last[k] && q <= kQCut && alpha >= kAlphaMin;
+        contrib = contrib || ok;
         const double Ti64 = T[k] * recip64(1.0 - (double)alpha);
-        const float Ti = (float)Ti64;
-        const float wT = alpha * Ti;
+        const float wT = ok ? alpha * (float)Ti64 : 0.0f;
         const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * c2;   // dL/dC . c
-        const float dalpha = (float)(Ti64 * ((double)dcc - V[k]));
+        const float dalpha = (ok && a0 <= kAlphaMax) ? (float)(Ti64 * ((double)dcc - V[k])) : 0.0f;
         gr[6] = fmaf(wT, d0[k], gr[6]);
         gr[7] = fmaf(wT, d1[k], gr[7]);
         gr[8] = fmaf(wT, d2[k], gr[8]);
-        V[k] = fma((double)alpha, (double)dcc - V[k], V[k]);   // alpha dcc + (1 - alpha) V
-        T[k] = Ti64;
-        if (a0 <= kAlphaMax) {
-          gr[5] = fmaf(dalpha, G, gr[5]);
-          const float dq = -0.5f * alpha * dalpha;
-          gr[2] = fmaf(dq * dx, dx, gr[2]);
-          gr[3] = fmaf(dq * 2.0f * dx, dy, gr[3]);
-          gr[4] = fmaf(dq * dy, dy, gr[4]);
-          gr[0] = fmaf(dq, -2.0f * (A.z * dx + A.w * dy), gr[0]);
-          gr[1] = fmaf(dq, -2.0f * (A.w * dx + B.x * dy), gr[1]);
-        }
+        V[k] = ok ? fma((double)alpha, (double)dcc - V[k], V[k]) : V[k];   // alpha dcc + (1 - alpha) V
+        T[k] = ok ? Ti64 : T[k];
+        gr[5] = fmaf(dalpha, G, gr[5]);
+        const float dq = -0.5f * alpha * dalpha;
+        gr[2] = fmaf(dq * dx, dx, gr[2]);
+        gr[3] = fmaf(dq * 2.0f * dx, dy, gr[3]);
+        gr[4] = fmaf(dq * dy, dy, gr[4]);
+        gr[0] = fmaf(dq, -2.0f * (A.z * dx + A.w * dy), gr[0]);
+        gr[1] = fmaf(dq, -2.0f * (A.w * dx + B.x * dy), gr[1]);
       }
       if (__any(contrib)) {
-        const uint32_t g = s_id[jl];
+        // the nine reductions have no control flow between them, so their DPP chains
+        // interleave; lane 63 then adds all nine (a zero adds nothing)
+        float v[kG2d];
 #pragma unroll
-        for (int c = 0; c < kG2d; ++c) {
-          const float v = wave_sum_to_lane63(gr[c]);
-          if (lane == 63 && v != 0.0f) atomicAdd(&g2d[c * stride + g], v);
+        for (int c = 0; c < kG2d; ++c) v[c] = wave_sum_to_lane63(gr[c]);
+        if (lane == 63) {
+          const uint32_t g = s_id[jl];
+#pragma unroll
+          for (int c = 0; c < kG2d; ++c) atomicAdd(&g2d[c * stride + g], v[c]);
         }
       }
     }
