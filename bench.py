@@ -134,8 +134,7 @@ def main():
         for p in params:
             p.grad = None
         img = render.rasterize(*params, cams[i % len(cams)], scene.s_min, bg, renderer=r)
-        loss = (img - targets[i % len(cams)]).abs().mean()
-        loss.backward()
+        render.l1_loss(img, targets[i % len(cams)], renderer=r).backward()
 
     log("fwd+bwd step")
     for i in range(args.warmup):
@@ -239,7 +238,7 @@ def main():
             for p in tr_params:
                 p.grad = None
             img = render.rasterize(*tr_params, tr_cam, tr_scene.s_min, bg, renderer=r)
-            (img - tr_tgt).abs().mean().backward()
+            render.l1_loss(img, tr_tgt, renderer=r).backward()
 
         t = timed(tr_step, 30, 5, sync)
         out_extra["train_720p"] = {"iters_s": 1.0 / t, "ms": 1e3 * t, "n_gaussians": tr_scene.n,

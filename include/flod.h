@@ -202,6 +202,16 @@ flod_status flod_l1_ssim_backward(flod_ctx *ctx, const float *image, const float
                                   int width, float lambda, const float *dmaps, const double *dloss, float *d_image,
                                   void *stream);
 
+/* Plain L1 image loss, mean |x - y| over `count` elements (image, target: device float[count]);
+   loss: device double[1], summed in FP64 in a fixed order (deterministic), no host
+   synchronisation. */
+flod_status flod_l1_loss_forward(flod_ctx *ctx, const float *image, const float *target, int64_t count,
+                                 double *loss, void *stream);
+
+/* d_image = sign(x - y) / count times *dloss (device double[1], NULL for 1); 0 where x = y. */
+flod_status flod_l1_loss_backward(flod_ctx *ctx, const float *image, const float *target, int64_t count,
+                                  const double *dloss, float *d_image, void *stream);
+
 /* Level transition (section Training Method, eq. 5): initialise level l+1 from the trained
    level l = *in: every attribute copied, and s_opt' = log(s^(l) - s_min_next) with
    s^(l) = exp(s_opt) + in->s_min formed as the renderer forms it (exp in FP64 rounded once

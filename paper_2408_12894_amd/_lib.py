@@ -27,7 +27,8 @@ EXPORTS = ("flod_ctx_create", "flod_ctx_destroy", "flod_ctx_workspace_bytes", "f
            "flod_ctx_stats", "flod_ctx_view", "flod_ctx_set_timing", "flod_ctx_stage_times",
            "flod_stage_name", "flod_smin", "flod_dproj", "flod_status_str", "flod_copy_to_host",
            "flod_render_merged", "flod_select_compact", "flod_overlap_prune", "flod_compact_level",
-           "flod_level_transition", "flod_l1_ssim_forward", "flod_l1_ssim_backward")
+           "flod_level_transition", "flod_l1_ssim_forward", "flod_l1_ssim_backward",
+           "flod_l1_loss_forward", "flod_l1_loss_backward")
 
 
 class FlodError(RuntimeError):
@@ -119,6 +120,10 @@ def load():
     L.flod_l1_ssim_forward.restype = C.c_int
     L.flod_l1_ssim_backward.argtypes = [vp, vp, vp, ci, ci, ci, C.c_float, vp, vp, vp, vp]
     L.flod_l1_ssim_backward.restype = C.c_int
+    L.flod_l1_loss_forward.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
+    L.flod_l1_loss_forward.restype = C.c_int
+    L.flod_l1_loss_backward.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
+    L.flod_l1_loss_backward.restype = C.c_int
     L.flod_render_backward.argtypes = [vp, vp, C.POINTER(Grads), vp]
     L.flod_render_backward.restype = C.c_int
     L.flod_ctx_stats.argtypes = [vp, C.POINTER(Stats)]

@@ -720,6 +720,32 @@ flod_status flod_l1_ssim_backward(flod_ctx *ctx, const float *image, const float
   return dev(launch_ssim_backward(image, target, channels, height, width, lambda, dmaps, dloss, d_image, s));
 }
 
+flod_status flod_l1_loss_forward(flod_ctx *ctx, const float *image, const float *target, int64_t count,
+                                 double *loss, void *stream) {
+  if (!ctx || !image || !target || !loss || count < 1 || !aligned(loss, 8)) return FLOD_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  ctx->last_stream = s;
+  ctx->required = 0;
+  size_t extra = 0;
+  if (ensure(ctx, B_SSIM, 16 * (size_t)l1_blocks(), s, &extra) != FLOD_OK) {
+    ctx->required = ws_bytes(ctx) + extra;
+    return FLOD_ERR_WORKSPACE;
+  }
+  return dev(launch_l1_forward(image, target, count, loss, P<double2>(ctx, B_SSIM), s));
+}
+
+flod_status flod_l1_loss_backward(flod_ctx *ctx, const float *image, const float *target, int64_t count,
+                                  const double *dloss, float *d_image, void *stream) {
+  if (!ctx || !image || !target || !d_image || count < 1 || (dloss && !aligned(dloss, 8)))
+    return FLOD_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  ctx->last_stream = s;
+  ctx->required = 0;
+  return dev(launch_l1_backward(image, target, count, dloss, d_image, s));
+}
+
 flod_status flod_level_transition(flod_ctx *ctx, const flod_level *in, float s_min_next, flod_level *out,
                                   void *stream) {
   if (!ctx || !in || !out) return FLOD_ERR_INVALID_ARG;

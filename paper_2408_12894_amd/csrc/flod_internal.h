@@ -121,6 +121,11 @@ hipError_t launch_ssim_forward(const float *x, const float *y, int C, int H, int
                                float *gmap, double2 *partials, hipStream_t s);
 hipError_t launch_ssim_backward(const float *x, const float *y, int C, int H, int W, float lam, const float *gmap,
                                 const double *dloss, float *dx, hipStream_t s);
+int64_t l1_blocks();   // workgroups (and loss partials) of the L1 forward
+hipError_t launch_l1_forward(const float *x, const float *y, int64_t n, double *loss, double2 *partials,
+                             hipStream_t s);
+hipError_t launch_l1_backward(const float *x, const float *y, int64_t n, const double *dloss, float *dx,
+                              hipStream_t s);
 int prune_table_bits(int64_t n);   // log2 of the overlap-pruning hash table size for n points
 hipError_t launch_prune_keys(const float *means, int64_t n, float d_op, uint32_t *keys, uint32_t *vals,
                              hipStream_t s);

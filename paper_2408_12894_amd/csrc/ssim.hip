@@ -233,4 +233,64 @@ hipError_t launch_ssim_backward(const float *x, const float *y, int C, int H, in
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------
+// Plain L1 loss, mean|x - y| over `count` elements (the image loss of the training step):
+// a grid-stride FP64 sum per workgroup, then the fixed-order reduction above; the backward
+// writes sign(x - y) / count times the incoming loss gradient.
+// ---------------------------------------------------------------------------------------
+constexpr int kL1Blocks = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_l1_fwd(const float4 *__restrict__ x, const float4 *__restrict__ y,
+                                                   const float *__restrict__ xs, const float *__restrict__ ys,
+                                                   int64_t n4, int64_t n, double2 *partials) {
+  __shared__ double red[kBlock / 64];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += (int64_t)gridDim.x * kBlock) {
+    const float4 a = x[i], b = y[i];
+    acc += (double)fabsf(a.x - b.x) + (double)fabsf(a.y - b.y) + (double)fabsf(a.z - b.z) +
+           (double)fabsf(a.w - b.w);
+  }
+  if (blockIdx.x == 0)
+    for (int64_t i = n4 * 4 + threadIdx.x; i < n; i += kBlock) acc += (double)fabsf(xs[i] - ys[i]);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+    partials[blockIdx.x] = make_double2(0.0, t);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_l1_bwd(const float *__restrict__ x, const float *__restrict__ y,
+                                                   int64_t n, double inv_n, const double *dloss,
+                                                   float *__restrict__ dx) {
+  const float scale = (float)(dloss ? inv_n * dloss[0] : inv_n);
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const float t = x[i] - y[i];
+    dx[i] = t > 0.0f ? scale : (t < 0.0f ? -scale : 0.0f);
+  }
+}
+
+int64_t l1_blocks() { return kL1Blocks; }
+
+hipError_t launch_l1_forward(const float *x, const float *y, int64_t n, double *loss, double2 *partials,
+                             hipStream_t s) {
+  const bool vec = (reinterpret_cast<uintptr_t>(x) % 16 == 0) && (reinterpret_cast<uintptr_t>(y) % 16 == 0);
+  const int64_t n4 = vec ? n / 4 : 0;
+  hipLaunchKernelGGL(k_l1_fwd, dim3(kL1Blocks), dim3(kBlock), 0, s, reinterpret_cast<const float4 *>(x),
+                     reinterpret_cast<const float4 *>(y), x, y, n4, n, partials);
+  // (1 - lam) L1 + lam (1 - S) with lam = 0 and the S sums zero: the mean of |x - y|
+  hipLaunchKernelGGL(k_ssim_reduce, dim3(1), dim3(kBlock), 0, s, partials, (int64_t)kL1Blocks, 0.0,
+                     1.0 / (double)n, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_l1_backward(const float *x, const float *y, int64_t n, const double *dloss, float *dx,
+                              hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_l1_bwd, dim3((unsigned)blocks), dim3(kBlock), 0, s, x, y, n, 1.0 / (double)n, dloss, dx);
+  return hipGetLastError();
+}
+
 }  // namespace flod

@@ -449,3 +449,41 @@ def l1_ssim_loss(image, target, lam: float = 0.2, renderer: Renderer | None = No
     if renderer is None:
         renderer = _default_renderer()
     return L1SsimLoss.apply(image, target, renderer, lam)
+
+
+class L1Loss(torch.autograd.Function):
+    """mean|image - target| as an FP64 scalar; forward and backward in HIP."""
+
+    @staticmethod
+    def forward(ctx, image, target, renderer):
+        image = image.detach().contiguous()
+        target = target.detach().contiguous()
+        if image.dtype != torch.float32 or target.dtype != torch.float32 or image.shape != target.shape \
+                or not image.is_cuda:
+            raise ValueError("image and target must be float32 CUDA tensors of the same shape")
+        loss = torch.empty((), dtype=torch.float64, device=image.device)
+        _lib.check(renderer.L.flod_l1_loss_forward(renderer.ctx, C.c_void_p(image.data_ptr()),
+                                                   C.c_void_p(target.data_ptr()), image.numel(),
+                                                   C.c_void_p(loss.data_ptr()), C.c_void_p(_stream_ptr(None))),
+                   "flod_l1_loss_forward")
+        ctx.save_for_backward(image, target)
+        ctx.renderer = renderer
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        image, target = ctx.saved_tensors
+        r = ctx.renderer
+        g = grad_loss.to(torch.float64).contiguous()
+        d = torch.empty_like(image)
+        _lib.check(r.L.flod_l1_loss_backward(r.ctx, C.c_void_p(image.data_ptr()), C.c_void_p(target.data_ptr()),
+                                             image.numel(), C.c_void_p(g.data_ptr()), C.c_void_p(d.data_ptr()),
+                                             C.c_void_p(_stream_ptr(None))), "flod_l1_loss_backward")
+        return d, None, None
+
+
+def l1_loss(image, target, renderer: Renderer | None = None):
+    """mean|image - target| (FP64 scalar) through the library's fused kernels."""
+    if renderer is None:
+        renderer = _default_renderer()
+    return L1Loss.apply(image, target, renderer)

@@ -82,6 +82,8 @@ def test_validation_before_any_device_call(lib):
     assert lib.flod_level_transition(None, C.byref(lv), 0.0, C.byref(lv), None) == bad
     assert lib.flod_l1_ssim_forward(None, None, None, 3, 4, 4, 0.2, None, None, None) == bad
     assert lib.flod_l1_ssim_backward(None, None, None, 3, 4, 4, 0.2, None, None, None, None) == bad
+    assert lib.flod_l1_loss_forward(None, None, None, 16, None, None) == bad
+    assert lib.flod_l1_loss_backward(None, None, None, 16, None, None, None) == bad
     assert lib.flod_ctx_stats(None, None) == bad
     assert lib.flod_ctx_view(None, None) == bad
     assert lib.flod_ctx_set_timing(None, 1) == bad

@@ -90,3 +90,21 @@ def test_forward_only_and_argument_checks(r):
                                     None) == _lib.FLOD_ERR_INVALID_ARG
     assert r.L.flod_l1_ssim_forward(r.ctx, xt.data_ptr(), yt.data_ptr(), 0, 20, 30, 0.2, loss.data_ptr(), None,
                                     None) == _lib.FLOD_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("n", [1, 7, 4096, 3 * 1080 * 1920 + 3])
+def test_plain_l1(r, n):
+    from paper_2408_12894_amd import render
+    print(f"[case] l1 n={n}", flush=True)
+    rng = np.random.default_rng(n)
+    x = rng.random(n).astype(np.float32)
+    y = rng.random(n).astype(np.float32)
+    y[::5] = x[::5]                                   # ties: zero gradient
+    xt = torch.as_tensor(x).cuda().requires_grad_(True)
+    loss = render.l1_loss(xt, torch.as_tensor(y).cuda(), renderer=r)
+    (loss * 2.0).backward()
+    d = x.astype(np.float64) - y.astype(np.float64)
+    ref = np.abs(x - y).astype(np.float64).mean()
+    assert abs(loss.item() - ref) <= 1e-12 * max(ref, 1e-30)
+    g = xt.grad.cpu().numpy()
+    np.testing.assert_array_equal(g, (np.sign(d) * np.float32(2.0 / n)).astype(np.float32))
