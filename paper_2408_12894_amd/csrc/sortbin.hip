@@ -279,12 +279,15 @@ hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
 
 // ---------------------------------------------------------------------------------------
 // Instance emission in depth order. Each Gaussian writes its footprint (tile rows and the
-// span of tiles in each row, recomputed exactly as the preprocess counted them) row-major
-// at its offset. Footprints of up to kEmitSolo tiles are written by their own thread; larger
-// ones are written by the whole wave, one row per lane, so a Gaussian covering hundreds of
-// tiles does not serialise a lane. When the footprint fills its bounding rectangle (its tile
-// count equals the rectangle's area, the common case for small Gaussians) the rectangle is
-// written directly and the per-row spans are not recomputed.
+// span of tiles in each row, as the preprocess counted them) row-major at its offset.
+//  - Footprints that fill their bounding rectangle (tile count = rectangle area; the common
+//    case) are written by the whole wave together: output slot v of the wave's rectangles
+//    finds its Gaussian by a binary search over the lanes' inclusive counts, so each store
+//    instruction writes consecutive positions.
+//  - Other footprints of up to kEmitSolo tiles are written by their own thread, row spans
+//    recomputed in FP64 exactly as the preprocess computed them.
+//  - Larger ones are written by the whole wave, one row span per lane, then the same
+//    search over the row widths gives consecutive stores.
 // ---------------------------------------------------------------------------------------
 constexpr uint32_t kEmitSolo = 16;
 
@@ -317,6 +320,18 @@ __device__ __forceinline__ RectSpan rect_of(uint2 r, uint32_t count) {
   return q;
 }
 
+// Lane that owns slot v: the number of lanes whose inclusive count is <= v (incl is
+// non-decreasing over the lanes and v < incl of lane 63). All lanes must take part.
+__device__ __forceinline__ int owner_lane(uint32_t incl, uint32_t v) {
+  int lo = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1) {
+    const uint32_t x = __shfl(incl, lo + step - 1, 64);
+    if (x <= v) lo += step;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr,
                                                  const uint32_t *tiles, const float4 *xyab, const float4 *cop,
                                                  const uint2 *rect, const unsigned long long *prefix, int tiles_x,
@@ -332,61 +347,69 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
   const uint32_t ex = block_excl_scan(c, &tot);
   const uint32_t off = (uint32_t)(prefix[blockIdx.x] + ex);
   const int lane = threadIdx.x & 63;
-  if (c > 0 && c <= kEmitSolo) {
-    const RectSpan rs = rect_of(rect[g], c);
-    if (rs.full) {
-      uint32_t pos = off;
-      for (int ty = rs.y0; ty <= rs.y1; ++ty)
-        for (int tx = rs.x0; tx <= rs.x1; ++tx) {
-          tile_ids[pos] = (uint32_t)(ty * tiles_x + tx);
-          values[pos] = g;
-          ++pos;
-        }
-    } else {
-      const float4 A = xyab[g];
-      Footprint fp;
-      footprint(A.x, A.y, A.z, A.w, cop[g].x, tiles_y, fp);
-      emit_rows(fp, fp.ty0, fp.ty1, tiles_x, off, g, tile_ids, values);
+  RectSpan rs{0, 0, 0, 0, false};
+  if (c > 0) rs = rect_of(rect[g], c);
+
+  // full rectangles, the whole wave at once
+  {
+    const uint32_t cf = rs.full ? c : 0u;
+    const uint32_t incl = wave_incl_scan(cf);
+    const uint32_t total = __shfl(incl, 63, 64);
+    const uint32_t w = rs.full ? (uint32_t)(rs.x1 - rs.x0 + 1) : 1u;
+    const uint32_t first = (uint32_t)(rs.y0 * tiles_x + rs.x0);
+    for (uint32_t v0 = 0; v0 < total; v0 += 64) {
+      const uint32_t v = min(v0 + (uint32_t)lane, total - 1u);
+      const int o = owner_lane(incl, v);
+      const uint32_t t = v - (__shfl(incl, o, 64) - __shfl(cf, o, 64));
+      const uint32_t wo = __shfl(w, o, 64);
+      const uint32_t row = t / wo;
+      const uint32_t tile = __shfl(first, o, 64) + row * (uint32_t)tiles_x + (t - row * wo);
+      const uint32_t pos = __shfl(off, o, 64) + t;
+      const uint32_t go = __shfl(g, o, 64);
+      if (v0 + (uint32_t)lane < total) {
+        tile_ids[pos] = tile;
+        values[pos] = go;
+      }
     }
   }
-  unsigned long long big = __ballot(c > kEmitSolo);
+  // small footprints that do not fill their rectangle, one thread each
+  if (c > 0 && c <= kEmitSolo && !rs.full) {
+    const float4 A = xyab[g];
+    Footprint fp;
+    footprint(A.x, A.y, A.z, A.w, cop[g].x, tiles_y, fp);
+    emit_rows(fp, fp.ty0, fp.ty1, tiles_x, off, g, tile_ids, values);
+  }
+  // large footprints that do not fill their rectangle, one at a time per wave
+  unsigned long long big = __ballot(c > kEmitSolo && !rs.full);
   while (big) {
     const int src = __ffsll((long long)big) - 1;
     big &= big - 1;
     const uint32_t os = __shfl(off, src, 64);
     const uint32_t gs = __shfl(g, src, 64);
-    const uint32_t cs = __shfl(c, src, 64);
-    const RectSpan rs = rect_of(rect[gs], cs);
+    const float4 A = xyab[gs];
     Footprint fp;
-    if (!rs.full) {
-      const float4 A = xyab[gs];
-      footprint(A.x, A.y, A.z, A.w, cop[gs].x, tiles_y, fp);
-    } else {
-      fp.ty0 = rs.y0;
-      fp.ty1 = rs.y1;
-    }
+    footprint(A.x, A.y, A.z, A.w, cop[gs].x, tiles_y, fp);
     const int nrows = fp.ty1 - fp.ty0 + 1;
     uint32_t base = os;
     for (int rb = 0; rb < nrows; rb += 64) {
       const int ty = fp.ty0 + rb + lane;
       int tx0 = 0, tx1 = -1;
-      if (rb + lane < nrows) {
-        if (rs.full) {
-          tx0 = rs.x0;
-          tx1 = rs.x1;
-        } else {
-          row_span(fp, ty, tiles_x, tx0, tx1);
+      if (rb + lane < nrows) row_span(fp, ty, tiles_x, tx0, tx1);
+      const uint32_t wr = (uint32_t)(tx1 - tx0 + 1);
+      const uint32_t incl = wave_incl_scan(wr);
+      const uint32_t total = __shfl(incl, 63, 64);
+      const uint32_t first = (uint32_t)(ty * tiles_x + tx0);
+      for (uint32_t v0 = 0; v0 < total; v0 += 64) {
+        const uint32_t v = min(v0 + (uint32_t)lane, total - 1u);
+        const int o = owner_lane(incl, v);
+        const uint32_t t = v - (__shfl(incl, o, 64) - __shfl(wr, o, 64));
+        const uint32_t tile = __shfl(first, o, 64) + t;
+        if (v0 + (uint32_t)lane < total) {
+          tile_ids[base + v] = tile;
+          values[base + v] = gs;
         }
       }
-      const uint32_t w = (uint32_t)(tx1 - tx0 + 1);
-      const uint32_t incl = wave_incl_scan(w);
-      uint32_t pos = base + incl - w;
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        tile_ids[pos] = (uint32_t)(ty * tiles_x + tx);
-        values[pos] = gs;
-        ++pos;
-      }
-      base += __shfl(incl, 63, 64);
+      base += total;
     }
   }
 }
