@@ -311,11 +311,14 @@ struct Span { int ty, tx0, tx1; };
 const double kQSpan = 9.009;
 
 int footprint_spans(float mxf, float myf, float af, float bf, float cf, int tiles_x, int tiles_y, Span* out,
-                    int max_rows) {
+                    int max_rows, int* row0, int* row1) {
   const double mx = mxf, my = myf, a = af, b = bf, c = cf;
   const double det = a * c - b * b;
   if (!(det > 0.0) || !(a > 0.0)) return 0;
-  const double sxx = c / det, syy = a / det, sxy = -b / det;
+  // reciprocals taken once: every row then multiplies (the footprint is inflated by 1e-3 in
+  // Q, far above the rounding this changes)
+  const double idet = 1.0 / det, ia = 1.0 / a;
+  const double sxx = c * idet, syy = a * idet, sxy = -b * idet;
   const double hx = std::sqrt(kQSpan * sxx);
   const double hy = std::sqrt(kQSpan * syy);
   const double dyr = sxy * std::sqrt(kQSpan / sxx);
@@ -324,6 +327,8 @@ int footprint_spans(float mxf, float myf, float af, float bf, float cf, int tile
   y0 = std::max(y0, 0.0);
   y1 = std::min(y1, (double)(tiles_y - 1));
   if (!(y0 <= y1)) return 0;
+  *row0 = (int)y0;
+  *row1 = (int)y1;
   int n = 0;
   for (int ty = (int)y0; ty <= (int)y1 && n < max_rows; ++ty) {
     // band of pixel-centre offsets in this row, clipped to the ellipse's y-extent
@@ -334,8 +339,8 @@ int footprint_spans(float mxf, float myf, float af, float bf, float cf, int tile
     const double rlo = std::sqrt(std::max(0.0, qa - det * dlo * dlo));
     const double rhi = std::sqrt(std::max(0.0, qa - det * dhi * dhi));
     // x = (-b dy +/- sqrt(Q a - det dy^2)) / a; the extreme points sit at dy = +/- dyr
-    const double right = (dlo <= dyr && dyr <= dhi) ? hx : std::max((-b * dlo + rlo) / a, (-b * dhi + rhi) / a);
-    const double left = (dlo <= -dyr && -dyr <= dhi) ? -hx : std::min((-b * dlo - rlo) / a, (-b * dhi - rhi) / a);
+    const double right = (dlo <= dyr && dyr <= dhi) ? hx : std::max((-b * dlo + rlo) * ia, (-b * dhi + rhi) * ia);
+    const double left = (dlo <= -dyr && -dyr <= dhi) ? -hx : std::min((-b * dlo - rlo) * ia, (-b * dhi - rhi) * ia);
     double x0 = std::floor((mx + left) * 0.0625);
     double x1 = std::floor((mx + right) * 0.0625);
     x0 = std::max(x0, 0.0);
@@ -375,7 +380,8 @@ void key_one(const float* muf, const float* lsf, const float* qf, float logit, f
   o.mx = (float)p.mx; o.my = (float)p.my;
   o.ca = (float)p.ca; o.cb = (float)p.cb; o.cc = (float)p.cc;
   std::vector<Span> sp((size_t)tiles_y);
-  int ns = footprint_spans(o.mx, o.my, o.ca, o.cb, o.cc, tiles_x, tiles_y, sp.data(), tiles_y);
+  int row0 = 0, row1 = -1;
+  int ns = footprint_spans(o.mx, o.my, o.ca, o.cb, o.cc, tiles_x, tiles_y, sp.data(), tiles_y, &row0, &row1);
   uint32_t count = 0;
   int rx0 = 0xFFFF, rx1 = 0;
   for (int k = 0; k < ns; ++k) {
@@ -385,13 +391,10 @@ void key_one(const float* muf, const float* lsf, const float* qf, float logit, f
   }
   if (count == 0) return;
   // rectangle reported: tile rows of the footprint's y-extent, columns of the spans
-  const double sy = std::sqrt(kQSpan * ((double)o.ca / ((double)o.ca * o.cc - (double)o.cb * o.cb)));
-  double y0 = std::max(std::floor(((double)o.my - sy) * 0.0625), 0.0);
-  double y1 = std::min(std::floor(((double)o.my + sy) * 0.0625), (double)(tiles_y - 1));
   o.visible = 1;
   float tzf = (float)p.tz;
   std::memcpy(&o.depth_bits, &tzf, 4);
-  o.rect[0] = rx0; o.rect[1] = (int32_t)y0; o.rect[2] = rx1; o.rect[3] = (int32_t)y1;
+  o.rect[0] = rx0; o.rect[1] = row0; o.rect[2] = rx1; o.rect[3] = row1;
   o.tiles = count;
   o.radius = (float)r;
   uint32_t lx = bf16_rne((float)(p.mx - (double)o.mx)), ly = bf16_rne((float)(p.my - (double)o.my));
@@ -561,8 +564,9 @@ int64_t or_instances(int64_t n, const uint8_t* visible, const uint32_t* depth_bi
   std::vector<Span> sp((size_t)tiles_y);
   for (int64_t i = 0; i < n; ++i) {
     if (!visible[i]) continue;
+    int r0 = 0, r1 = -1;
     int ns = footprint_spans(mxy[2 * i], mxy[2 * i + 1], conic[3 * i], conic[3 * i + 1], conic[3 * i + 2], tiles_x,
-                             tiles_y, sp.data(), tiles_y);
+                             tiles_y, sp.data(), tiles_y, &r0, &r1);
     for (int k = 0; k < ns; ++k)
       for (int x = sp[k].tx0; x <= sp[k].tx1; ++x)
         v.push_back(E{(uint32_t)(sp[k].ty * tiles_x + x), depth_bits[i], (uint32_t)i});
