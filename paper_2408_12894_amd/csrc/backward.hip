@@ -11,8 +11,9 @@
 //   Shat_{i-1} = alpha_i c_i + (1 - alpha_i) Shat_i,  Shat_last = bg,
 // which avoids the cancellation between T_i c_i and S_i / (1 - alpha_i) in FP32.
 // Then alpha -> (opacity, q) unless the 0.99 clamp is active, q -> (conic, mu').
-// Per entry the 9 gradient components are reduced across the wave with DPP (the nine chains
-// interleaved) and lane 63 issues one FP32 atomic per component per (tile, Gaussian).
+// Per entry the 9 gradient components are reduced across the wave (DPP within rows, then
+// two cross-row exchanges of one packed register) and lanes 0..8 issue one FP32 atomic each
+// per (tile, Gaussian).
 //
 // Preprocess backward: one thread per Gaussian, recomputing the forward projection (FP64)
 // and applying the chain rule in FP64 to the mean (through mu', the EWA Jacobian and the SH view
@@ -47,8 +48,8 @@ __device__ __forceinline__ double recip64(double x) {
 // the state is T (transmittance after the current entry), V = dL/dC . Shat (the upstream
 // gradient dotted with the normalised colour behind the current entry) and dL/dC; T and V
 // are FP64 because both run through chains of up to thousands of contributors. Per entry
-// each thread sums its pixels' 9 gradient components in registers, each wave reduces them
-// with DPP and its lane 63 issues one FP32 atomic per non-zero component.
+// each thread sums its pixels' 9 gradient components in registers and the wave reduces
+// them (see below) before one atomic instruction adds the nine sums.
 template <int PPT>
 __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ values, const float4 *__restrict__ xyab,
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   __shared__ int s_max[WAVES];
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   if (tile >= n_tiles) return;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, lane16 = tid & 15;
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
   const int px = x0 + (tid & (kTile - 1));
   const float fx = (float)px + 0.5f;
@@ -153,16 +154,18 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         gr[1] = fmaf(dq, -2.0f * (A.w * dx + B.x * dy), gr[1]);
       }
       if (__any(contrib)) {
-        // the nine reductions have no control flow between them, so their DPP chains
-        // interleave; lane 63 then adds all nine (a zero adds nothing)
-        float v[kG2d];
+        // nine in-row DPP reductions (interleaved, no control flow between them) leave each
+        // row's sums in all its lanes; lane 16 r + c keeps component c, two cross-row
+        // exchanges complete the sums, and lanes 0..8 add them with one atomic instruction
+        float x = 0.0f;
 #pragma unroll
-        for (int c = 0; c < kG2d; ++c) v[c] = wave_sum_to_lane63(gr[c]);
-        if (lane == 63) {
-          const uint32_t g = s_id[jl];
-#pragma unroll
-          for (int c = 0; c < kG2d; ++c) atomicAdd(&g2d[c * stride + g], v[c]);
+        for (int c = 0; c < kG2d; ++c) {
+          const float rs = row_sum16(gr[c]);
+          x = (lane16 == c) ? rs : x;
         }
+        x += __shfl_xor(x, 16, 64);
+        x += __shfl_xor(x, 32, 64);
+        if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[lane * stride + s_id[jl]], x);
       }
     }
   }

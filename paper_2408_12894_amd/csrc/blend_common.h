@@ -22,15 +22,14 @@ __device__ __forceinline__ float dpp_or_zero(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, true));
 }
 
-// Sum over the 64 lanes; the total is valid in lane 63.
-__device__ __forceinline__ float wave_sum_to_lane63(float x) {
+// Sum over the 16 lanes of each DPP row; every lane of the row receives its row's sum.
+__device__ __forceinline__ float row_sum16(float x) {
   x += dpp_or_zero<0xB1>(x);         // quad_perm [1,0,3,2]
   x += dpp_or_zero<0x4E>(x);         // quad_perm [2,3,0,1]
   x += dpp_or_zero<0x141>(x);        // row_half_mirror
-  x += dpp_or_zero<0x140>(x);        // row_mirror: every lane holds its row's sum
-  x += dpp_or_zero<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
-  x += dpp_or_zero<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+  x += dpp_or_zero<0x140>(x);        // row_mirror
   return x;
 }
+
 
 }  // namespace flod

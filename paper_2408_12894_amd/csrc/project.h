@@ -136,7 +136,7 @@ __device__ __forceinline__ bool project_cov(const DevCamera &cam, const float ls
 constexpr double kQSpan = 9.009;
 
 struct Footprint {
-  double mx, my, a, b, c, det, hx, hy, dyr;
+  double mx, my, a, b, c, det, ia, hx, hy, dyr;
   int ty0, ty1;
 };
 
@@ -144,7 +144,10 @@ __device__ __forceinline__ bool footprint(float mx, float my, float a, float b, 
   f.mx = mx; f.my = my; f.a = a; f.b = b; f.c = c;
   f.det = f.a * f.c - f.b * f.b;
   if (!(f.det > 0.0) || !(f.a > 0.0)) return false;
-  const double sxx = f.c / f.det, syy = f.a / f.det, sxy = -f.b / f.det;
+  // reciprocals taken once; the rows multiply by them
+  const double idet = 1.0 / f.det;
+  f.ia = 1.0 / f.a;
+  const double sxx = f.c * idet, syy = f.a * idet, sxy = -f.b * idet;
   f.hx = sqrt(kQSpan * sxx);
   f.hy = sqrt(kQSpan * syy);
   f.dyr = sxy * sqrt(kQSpan / sxx);
@@ -166,8 +169,8 @@ __device__ __forceinline__ bool row_span(const Footprint &f, int ty, int tiles_x
   const double qa = kQSpan * f.a;
   const double rlo = sqrt(fmax(0.0, qa - f.det * dlo * dlo));
   const double rhi = sqrt(fmax(0.0, qa - f.det * dhi * dhi));
-  const double right = (dlo <= f.dyr && f.dyr <= dhi) ? f.hx : fmax((-f.b * dlo + rlo) / f.a, (-f.b * dhi + rhi) / f.a);
-  const double left = (dlo <= -f.dyr && -f.dyr <= dhi) ? -f.hx : fmin((-f.b * dlo - rlo) / f.a, (-f.b * dhi - rhi) / f.a);
+  const double right = (dlo <= f.dyr && f.dyr <= dhi) ? f.hx : fmax((-f.b * dlo + rlo) * f.ia, (-f.b * dhi + rhi) * f.ia);
+  const double left = (dlo <= -f.dyr && -f.dyr <= dhi) ? -f.hx : fmin((-f.b * dlo - rlo) * f.ia, (-f.b * dhi - rhi) * f.ia);
   double x0 = floor((f.mx + left) * 0.0625);
   double x1 = floor((f.mx + right) * 0.0625);
   x0 = fmax(x0, 0.0);
