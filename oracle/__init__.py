@@ -80,8 +80,8 @@ def lib():
         L.or_select_level.argtypes = [i64, vp, vp, f32, f32, vp]
         L.or_overlap_prune.argtypes = [i64, vp, C.c_double, i64, vp, vp, vp]
         L.or_level_transition.argtypes = [i64, vp, C.c_double, C.c_double, vp]
-        L.or_keys.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
-        L.or_instances.argtypes = [i64, vp, vp, vp, vp, i32, i32, i64, vp, vp, vp]
+        L.or_keys.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.or_instances.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, i64, vp, vp, vp]
         L.or_instances.restype = i64
         L.or_project64.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp]
         L.or_image.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -188,11 +188,11 @@ def keys(means, log_scales, quats, logits, smin, cam, keep=None) -> dict:
     out = dict(visible=np.zeros(n, np.uint8), depth_bits=np.zeros(n, np.uint32),
                rect=np.zeros((n, 4), np.int32), tiles=np.zeros(n, np.uint32),
                radius=np.zeros(n, np.float32), mxy=np.zeros((n, 2), np.float32),
-               conic=np.zeros((n, 3), np.float32), mu_lo=np.zeros(n, np.uint32))
+               conic=np.zeros((n, 3), np.float32), mu_lo=np.zeros(n, np.uint32), qsup=np.zeros(n, np.float32))
     c = _cam(cam)
     lib().or_keys(n, _p(m), _p(ls), _p(q), _p(lg), _p(sm), None if kp is None else _p(kp), C.byref(c),
                   _p(out["visible"]), _p(out["depth_bits"]), _p(out["rect"]), _p(out["tiles"]),
-                  _p(out["radius"]), _p(out["mxy"]), _p(out["conic"]), _p(out["mu_lo"]))
+                  _p(out["radius"]), _p(out["mxy"]), _p(out["conic"]), _p(out["mu_lo"]), _p(out["qsup"]))
     out["tiles_x"] = (int(cam.width) + TILE - 1) // TILE
     out["tiles_y"] = (int(cam.height) + TILE - 1) // TILE
     return out
@@ -207,7 +207,7 @@ def instances(k: dict):
     val = np.zeros(max(K, 1), np.uint32)
     ranges = np.zeros((n_tiles, 2), np.uint32)
     got = lib().or_instances(n, _p(k["visible"]), _p(k["depth_bits"]), _p(k["mxy"]), _p(k["conic"]),
-                             k["tiles_x"], k["tiles_y"], K, _p(tile), _p(val), _p(ranges))
+                             _p(k["qsup"]), k["tiles_x"], k["tiles_y"], K, _p(tile), _p(val), _p(ranges))
     assert got == K
     return tile[:K], val[:K], ranges
 

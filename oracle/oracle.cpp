@@ -300,18 +300,30 @@ struct KeyOut {
   int32_t rect[4];       // xmin, ymin, xmax, ymax (inclusive tiles)
   uint32_t tiles;
   float radius;
+  float qsup;                 // support bound Q_g of the opacity (see support_q)
   float mx, my, ca, cb, cc;   // FP32 roundings of mu' and the conic
   uint32_t mu_lo;        // bf16 residuals of mu': x in the low half, y in the high half
 };
 
-// Tile footprint of a Gaussian from its stored FP32 mu' and conic: per tile row, the tiles
-// whose [16 tx, 16 tx + 16) meets the x-extent of the ellipse d^T conic d <= Q (Q = 9.009)
-// over the row's band of pixel centres. FP64, fixed operation order.
-struct Span { int ty, tx0, tx1; };
-const double kQSpan = 9.009;
+// Support of a Gaussian: a pixel blends only if q <= 9 and o exp(-q/2) >= 1/255, i.e.
+// q <= Q_g = min(9, 2 ln(255 o)). Q_g is formed from o = 1/(1 + exp(-logit)) in FP64, each
+// rounded to FP32 (so that last-bit differences between exp/log implementations vanish),
+// and the footprint uses Q = Q_g (1 + 1e-3) + 1e-3: at q = Q, o exp(-q/2) <= (1/255) e^-5e-4,
+// a margin far above FP32 and fast-exp error, so no pixel outside the footprint can blend.
+float support_q(float logit) {
+  const float o = (float)(1.0 / (1.0 + std::exp(-(double)logit)));
+  return (float)std::min(9.0, std::max(0.0, 2.0 * std::log(255.0 * (double)o)));
+}
 
-int footprint_spans(float mxf, float myf, float af, float bf, float cf, int tiles_x, int tiles_y, Span* out,
-                    int max_rows, int* row0, int* row1) {
+double support_span(float qg) { return (double)qg * 1.001 + 1e-3; }
+
+// Tile footprint of a Gaussian from its stored FP32 mu' and conic: per tile row, the tiles
+// whose [16 tx, 16 tx + 16) meets the x-extent of the ellipse d^T conic d <= Q (Q from
+// support_span) over the row's band of pixel centres. FP64, fixed operation order.
+struct Span { int ty, tx0, tx1; };
+
+int footprint_spans(float mxf, float myf, float af, float bf, float cf, double kQSpan, int tiles_x, int tiles_y,
+                    Span* out, int max_rows, int* row0, int* row1) {
   const double mx = mxf, my = myf, a = af, b = bf, c = cf;
   const double det = a * c - b * b;
   if (!(det > 0.0) || !(a > 0.0)) return 0;
@@ -381,7 +393,9 @@ void key_one(const float* muf, const float* lsf, const float* qf, float logit, f
   o.ca = (float)p.ca; o.cb = (float)p.cb; o.cc = (float)p.cc;
   std::vector<Span> sp((size_t)tiles_y);
   int row0 = 0, row1 = -1;
-  int ns = footprint_spans(o.mx, o.my, o.ca, o.cb, o.cc, tiles_x, tiles_y, sp.data(), tiles_y, &row0, &row1);
+  o.qsup = support_q(logit);
+  int ns = footprint_spans(o.mx, o.my, o.ca, o.cb, o.cc, support_span(o.qsup), tiles_x, tiles_y, sp.data(), tiles_y,
+                           &row0, &row1);
   uint32_t count = 0;
   int rx0 = 0xFFFF, rx1 = 0;
   for (int k = 0; k < ns; ++k) {
@@ -531,7 +545,7 @@ void or_level_transition(int64_t n, const float* log_scales, double s_min_l, dou
 void or_keys(int64_t n, const float* means, const float* ls, const float* q, const float* logits,
              const float* smin, const uint8_t* keep, const CamIn* camin,
              uint8_t* visible, uint32_t* depth_bits, int32_t* rect, uint32_t* tiles, float* radius,
-             float* mxy, float* conic, uint32_t* mu_lo) {
+             float* mxy, float* conic, uint32_t* mu_lo, float* qsup) {
   Cam<double> cam = cam_as<double>(*camin);
   int tx = (cam.W + TILE - 1) / TILE, ty = (cam.H + TILE - 1) / TILE;
 #pragma omp parallel for schedule(static)
@@ -547,6 +561,7 @@ void or_keys(int64_t n, const float* means, const float* ls, const float* q, con
     for (int j = 0; j < 4; ++j) rect[i * 4 + j] = o.rect[j];
     tiles[i] = o.tiles;
     radius[i] = o.radius;
+    qsup[i] = o.qsup;
     mxy[i * 2 + 0] = o.mx; mxy[i * 2 + 1] = o.my;
     conic[i * 3 + 0] = o.ca; conic[i * 3 + 1] = o.cb; conic[i * 3 + 2] = o.cc;
     mu_lo[i] = o.mu_lo;
@@ -556,7 +571,8 @@ void or_keys(int64_t n, const float* means, const float* ls, const float* q, con
 // O1: instance list sorted by (tile, depth bits, index); each visible Gaussian's footprint
 // enumerated row by row. Returns K; writes at most cap entries. ranges: [2 * n_tiles].
 int64_t or_instances(int64_t n, const uint8_t* visible, const uint32_t* depth_bits, const float* mxy,
-                     const float* conic, int32_t tiles_x, int32_t tiles_y, int64_t cap, uint32_t* out_tile,
+                     const float* conic, const float* qsup, int32_t tiles_x, int32_t tiles_y, int64_t cap,
+                     uint32_t* out_tile,
                      uint32_t* out_val, uint32_t* ranges) {
   struct E { uint32_t tile, depth, idx; };
   const int32_t n_tiles = tiles_x * tiles_y;
@@ -565,8 +581,8 @@ int64_t or_instances(int64_t n, const uint8_t* visible, const uint32_t* depth_bi
   for (int64_t i = 0; i < n; ++i) {
     if (!visible[i]) continue;
     int r0 = 0, r1 = -1;
-    int ns = footprint_spans(mxy[2 * i], mxy[2 * i + 1], conic[3 * i], conic[3 * i + 1], conic[3 * i + 2], tiles_x,
-                             tiles_y, sp.data(), tiles_y, &r0, &r1);
+    int ns = footprint_spans(mxy[2 * i], mxy[2 * i + 1], conic[3 * i], conic[3 * i + 1], conic[3 * i + 2],
+                             support_span(qsup[i]), tiles_x, tiles_y, sp.data(), tiles_y, &r0, &r1);
     for (int k = 0; k < ns; ++k)
       for (int x = sp[k].tx0; x <= sp[k].tx1; ++x)
         v.push_back(E{(uint32_t)(sp[k].ty * tiles_x + x), depth_bits[i], (uint32_t)i});

@@ -20,7 +20,7 @@ enum BufId {
   B_XYAB, B_COP, B_BLUE, B_DEPTH, B_RECT, B_TILES, B_BLOCKVIS, B_PREFIX,
   B_DKEY0, B_DKEY1, B_DVAL0, B_DVAL1, B_TBSUM, B_TPREFIX,
   B_TKEY0, B_TKEY1, B_TVAL0, B_TVAL1, B_HIST, B_SCAN, B_TOT, B_RANGES, B_COUNTERS,
-  B_G2D, B_SSIM, B_COUNT
+  B_G2D, B_SSIM, B_QSUP, B_COUNT
 };
 
 struct Saved {
@@ -203,6 +203,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   need(B_DEPTH, 4 * (size_t)N);
   need(B_RECT, 8 * (size_t)N);
   need(B_TILES, 4 * (size_t)N);
+  need(B_QSUP, 4 * (size_t)N);
   need(B_BLOCKVIS, 4 * (size_t)nb);
   need(B_PREFIX, 8 * (size_t)nb);
   need(B_DKEY0, 4 * (size_t)N);
@@ -232,6 +233,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     o.depth = P<uint32_t>(c, B_DEPTH);
     o.rect = P<uint2>(c, B_RECT);
     o.tiles = P<uint32_t>(c, B_TILES);
+    o.qsup = P<float>(c, B_QSUP);
     o.block_vis = P<uint32_t>(c, B_BLOCKVIS);
     o.n_selected = reinterpret_cast<unsigned long long *>(n_selected);
     tm.begin(FLOD_STAGE_PREPROCESS);
@@ -298,7 +300,8 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     uint32_t *dv = dres ? P<uint32_t>(c, B_DVAL1) : P<uint32_t>(c, B_DVAL0);
     tm.begin(FLOD_STAGE_EMIT);
     if (launch_emit(dv, counters + kCntVisible, n_vis, P<uint32_t>(c, B_TILES), P<float4>(c, B_XYAB),
-                    P<float4>(c, B_COP), P<uint2>(c, B_RECT), P<unsigned long long>(c, B_TPREFIX), cam.tiles_x,
+                    P<float4>(c, B_COP), P<uint2>(c, B_RECT), P<float>(c, B_QSUP),
+                    P<unsigned long long>(c, B_TPREFIX), cam.tiles_x,
                     cam.tiles_y, tk[0],
                     tv[0], s) != hipSuccess)
       return FLOD_ERR_DEVICE;

@@ -64,6 +64,7 @@ struct PreOut {
   uint32_t *depth;    // FP32 bits of the view-space depth
   uint2 *rect;        // (x0 | y0 << 16, x1 | y1 << 16)
   uint32_t *tiles;    // tiles touched, 0 when culled or not selected
+  float *qsup;        // support bound Q_g of the opacity (footprint input)
   uint32_t *block_vis;  // per-workgroup count of visible candidates
   unsigned long long *n_selected;   // per-level selected counts (may be null)
 };
@@ -92,6 +93,7 @@ hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
                               const uint32_t *tiles, uint32_t *block_sum, hipStream_t s);
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_vis,
                        const uint32_t *tiles, const float4 *xyab, const float4 *cop, const uint2 *rect,
+                       const float *qsup,
                        const unsigned long long *prefix, int tiles_x, int tiles_y,
                        uint32_t *tile_ids, uint32_t *values, hipStream_t s);
 hipError_t launch_ranges(const uint32_t *tile_ids, int64_t K, int n_tiles, uint2 *ranges,

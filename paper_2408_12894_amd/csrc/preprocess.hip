@@ -41,7 +41,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreParams p, PreOut o) {
           const float ca = (float)pr.ca, cb = (float)pr.cb, cc = (float)pr.cc;
           Footprint fp;
           uint32_t rx0 = 0xFFFFu, rx1 = 0u;
-          if (footprint(hx, hy, ca, cb, cc, p.cam.tiles_y, fp)) {
+          const float qg = support_q(logit);
+          if (footprint(hx, hy, ca, cb, cc, support_span(qg), p.cam.tiles_y, fp)) {
             for (int ty = fp.ty0; ty <= fp.ty1; ++ty) {
               int tx0, tx1;
               if (row_span(fp, ty, p.cam.tiles_x, tx0, tx1)) {
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreParams p, PreOut o) {
             o.blue[i] = make_float2(col[2], __uint_as_float(pack_mu_lo(pr.mx, pr.my, hx, hy)));
             o.depth[i] = __float_as_uint((float)pr.tz);
             o.rect[i] = make_uint2(rx0 | ((uint32_t)fp.ty0 << 16), rx1 | ((uint32_t)fp.ty1 << 16));
+            o.qsup[i] = qg;
           }
         }
       }

@@ -124,33 +124,43 @@ __device__ __forceinline__ bool project_cov(const DevCamera &cam, const float ls
 }
 
 // ---------------------------------------------------------------------------------------
-// Tile footprint. A Gaussian is binned to a tile when the tile's pixel-centre rows meet its
-// support ellipse d^T conic d <= Q with Q = 9 (1 + 1e-3): per tile row, the x-extent of the
+// Tile footprint. A pixel blends a Gaussian only if q <= 9 and o exp(-q/2) >= 1/255, i.e.
+// q <= Q_g = min(9, 2 ln(255 o)); Q_g is formed from the FP32 logit with exp and log in
+// FP64, each result rounded to FP32, so that any last-bit difference between math libraries
+// vanishes. A Gaussian is binned to a tile when the tile's pixel-centre rows meet the ellipse
+// d^T conic d <= Q with Q = Q_g (1 + 1e-3) + 1e-3 (at that q the blend's alpha is below 1/255
+// by a relative 5e-4, far above FP32 and fast-exp error): per tile row, the x-extent of the
 // ellipse over the row's band of pixel centres is found in closed form (the right boundary
 // is concave in dy, so its maximum over the band is the ellipse's rightmost point when that
-// lies in the band, else a band end; the left boundary mirrors it). The 1e-3 inflation keeps
-// every pixel whose FP32 q is <= 9 inside an emitted tile although the footprint is computed
-// from the stored FP32 mu' and conic. Computed in FP64 from those stored FP32 values by the
-// preprocess (to count) and the emission (to write), so both agree exactly.
+// lies in the band, else a band end; the left boundary mirrors it). Computed in FP64 from the
+// stored FP32 mu', conic and Q_g by the preprocess (to count) and the emission (to write), so
+// both agree exactly.
 // ---------------------------------------------------------------------------------------
-constexpr double kQSpan = 9.009;
+__device__ __forceinline__ float support_q(float logit) {
+  const float o = (float)(1.0 / (1.0 + exp(-(double)logit)));
+  return (float)fmin(9.0, fmax(0.0, 2.0 * log(255.0 * (double)o)));
+}
+
+__device__ __forceinline__ double support_span(float qg) { return (double)qg * 1.001 + 1e-3; }
+
 
 struct Footprint {
-  double mx, my, a, b, c, det, ia, hx, hy, dyr;
+  double mx, my, a, b, c, det, ia, hx, hy, dyr, Q;
   int ty0, ty1;
 };
 
-__device__ __forceinline__ bool footprint(float mx, float my, float a, float b, float c, int tiles_y, Footprint &f) {
-  f.mx = mx; f.my = my; f.a = a; f.b = b; f.c = c;
+__device__ __forceinline__ bool footprint(float mx, float my, float a, float b, float c, double Q, int tiles_y,
+                                          Footprint &f) {
+  f.mx = mx; f.my = my; f.a = a; f.b = b; f.c = c; f.Q = Q;
   f.det = f.a * f.c - f.b * f.b;
   if (!(f.det > 0.0) || !(f.a > 0.0)) return false;
   // reciprocals taken once; the rows multiply by them
   const double idet = 1.0 / f.det;
   f.ia = 1.0 / f.a;
   const double sxx = f.c * idet, syy = f.a * idet, sxy = -f.b * idet;
-  f.hx = sqrt(kQSpan * sxx);
-  f.hy = sqrt(kQSpan * syy);
-  f.dyr = sxy * sqrt(kQSpan / sxx);
+  f.hx = sqrt(Q * sxx);
+  f.hy = sqrt(Q * syy);
+  f.dyr = sxy * sqrt(Q / sxx);
   double y0 = floor((f.my - f.hy) * 0.0625);
   double y1 = floor((f.my + f.hy) * 0.0625);
   y0 = fmax(y0, 0.0);
@@ -166,7 +176,7 @@ __device__ __forceinline__ bool row_span(const Footprint &f, int ty, int tiles_x
   const double dlo = fmax((16.0 * ty + 0.5) - f.my, -f.hy);
   const double dhi = fmin((16.0 * ty + 15.5) - f.my, f.hy);
   if (!(dlo <= dhi)) return false;
-  const double qa = kQSpan * f.a;
+  const double qa = f.Q * f.a;
   const double rlo = sqrt(fmax(0.0, qa - f.det * dlo * dlo));
   const double rhi = sqrt(fmax(0.0, qa - f.det * dhi * dhi));
   const double right = (dlo <= f.dyr && f.dyr <= dhi) ? f.hx : fmax((-f.b * dlo + rlo) * f.ia, (-f.b * dhi + rhi) * f.ia);

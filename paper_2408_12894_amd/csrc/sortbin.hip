@@ -334,7 +334,8 @@ __device__ __forceinline__ int owner_lane(uint32_t incl, uint32_t v) {
 
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr,
                                                  const uint32_t *tiles, const float4 *xyab, const float4 *cop,
-                                                 const uint2 *rect, const unsigned long long *prefix, int tiles_x,
+                                                 const uint2 *rect, const float *qsup,
+                                                 const unsigned long long *prefix, int tiles_x,
                                                  int tiles_y, uint32_t *__restrict__ tile_ids,
                                                  uint32_t *__restrict__ values) {
   const uint32_t n = *n_ptr;
@@ -376,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
   if (c > 0 && c <= kEmitSolo && !rs.full) {
     const float4 A = xyab[g];
     Footprint fp;
-    footprint(A.x, A.y, A.z, A.w, cop[g].x, tiles_y, fp);
+    footprint(A.x, A.y, A.z, A.w, cop[g].x, support_span(qsup[g]), tiles_y, fp);
     emit_rows(fp, fp.ty0, fp.ty1, tiles_x, off, g, tile_ids, values);
   }
   // large footprints that do not fill their rectangle, one at a time per wave
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
     const uint32_t gs = __shfl(g, src, 64);
     const float4 A = xyab[gs];
     Footprint fp;
-    footprint(A.x, A.y, A.z, A.w, cop[gs].x, tiles_y, fp);
+    footprint(A.x, A.y, A.z, A.w, cop[gs].x, support_span(qsup[gs]), tiles_y, fp);
     const int nrows = fp.ty1 - fp.ty0 + 1;
     uint32_t base = os;
     for (int rb = 0; rb < nrows; rb += 64) {
@@ -415,11 +416,12 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
 }
 
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_vis, const uint32_t *tiles,
-                       const float4 *xyab, const float4 *cop, const uint2 *rect, const unsigned long long *prefix,
-                       int tiles_x, int tiles_y, uint32_t *tile_ids, uint32_t *values, hipStream_t s) {
+                       const float4 *xyab, const float4 *cop, const uint2 *rect, const float *qsup,
+                       const unsigned long long *prefix, int tiles_x, int tiles_y, uint32_t *tile_ids,
+                       uint32_t *values, hipStream_t s) {
   if (n_vis <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_vis + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, sorted_ids,
-                     n_ptr, tiles, xyab, cop, rect, prefix, tiles_x, tiles_y, tile_ids, values);
+                     n_ptr, tiles, xyab, cop, rect, qsup, prefix, tiles_x, tiles_y, tile_ids, values);
   return hipGetLastError();
 }
 

@@ -358,7 +358,9 @@ def test_depth_and_radius_properties(oracle_mod):
     assert np.all(r <= np.ceil(3 * np.sqrt(lam + 0.35)) + 1)
 
 
-Q_SPAN = 9.009
+def _q_span(qsup):
+    """Footprint bound from the stored support Q_g: Q_g (1 + 1e-3) + 1e-3 (FP64)."""
+    return float(qsup) * 1.001 + 1e-3
 
 
 def _min_q_over_box(mx, my, a, b, c, x0, x1, y0, y1):
@@ -382,13 +384,14 @@ def _bruteforce_footprint(k, i, tiles_x, tiles_y):
     """Tiles whose region [16 tx, 16 tx + 16) x [16 ty + 0.5, 16 ty + 15.5] meets q <= Q."""
     mx, my = (float(v) for v in k["mxy"][i])
     a, b, c = (float(v) for v in k["conic"][i])
+    Q = _q_span(k["qsup"][i])
     out, ambiguous = set(), set()
     for ty in range(tiles_y):
         for tx in range(tiles_x):
             m = _min_q_over_box(mx, my, a, b, c, 16 * tx, 16 * tx + 16, 16 * ty + 0.5, 16 * ty + 15.5)
-            if abs(m - Q_SPAN) <= 1e-9 * Q_SPAN:
+            if abs(m - Q) <= 1e-9 * Q:
                 ambiguous.add((tx, ty))
-            elif m <= Q_SPAN:
+            elif m <= Q:
                 out.add((tx, ty))
     return out, ambiguous
 
@@ -420,9 +423,10 @@ def test_footprint_matches_bruteforce_box_test(oracle_mod):
 
 
 def test_support_lies_inside_footprint(oracle_mod):
-    """Every pixel centre with q <= 9 (FP64) falls in a tile of the Gaussian's footprint, so
-    the brute-force image and a tiled renderer composite the same sets."""
-    scene = synth.uniform_scene(300, seed=11, s_mu=-2.8, s_sigma=0.6)
+    """Every pixel centre a Gaussian can blend into (FP64: q <= 9 and o exp(-q/2) >= 1/255)
+    falls in a tile of its footprint, so the brute-force image and a tiled renderer composite
+    the same sets; and for low opacities the footprint is smaller than the q <= 9 ellipse's."""
+    scene = synth.uniform_scene(300, seed=11, s_mu=-2.8, s_sigma=0.6, a_sigma=2.0)
     cam = synth.look_at_camera((0.5, -0.3, -3.0), (0, 0, 0), 96, 80)
     k = oracle_mod.keys(*scene.arrays()[:4], 0.0, cam)
     tile, val, _ = oracle_mod.instances(k)
@@ -432,14 +436,19 @@ def test_support_lies_inside_footprint(oracle_mod):
         fp.setdefault(int(v), set()).add(int(t))
     vis = np.nonzero(k["visible"])[0]
     p64 = oracle_mod.project64(vis, *scene.arrays()[:4], 0.0, scene.sh, 3, cam)
+    o64 = 1.0 / (1.0 + np.exp(-scene.opacity_logits.astype(np.float64)))
     ys, xs = np.mgrid[0:80, 0:96]
     cx, cy = xs + 0.5, ys + 0.5
+    smaller = 0
     for j, i in enumerate(vis):
         dx, dy = cx - p64[j, 0], cy - p64[j, 1]
         q = p64[j, 2] * dx * dx + 2 * p64[j, 3] * dx * dy + p64[j, 4] * dy * dy
-        inside = q <= 9.0
-        tiles = set(((ys[inside] // 16) * tx_n + xs[inside] // 16).tolist())
+        blends = (q <= 9.0) & (o64[i] * np.exp(-0.5 * q) >= 1.0 / 255.0)
+        tiles = set(((ys[blends] // 16) * tx_n + xs[blends] // 16).tolist())
         assert tiles <= fp[int(i)], i
+        q9 = set(((ys[q <= 9.0] // 16) * tx_n + xs[q <= 9.0] // 16).tolist())
+        smaller += len(fp[int(i)]) < len(q9)
+    assert smaller > 10
 
 
 def test_instance_list_order_matches_lexsort(oracle_mod):
