@@ -1,0 +1,297 @@
+/*
+ * flod.h - C ABI of the MI355X (gfx950) FLoD-3DGS rasterizer.
+ *
+ * What it computes (FLoD, "Integrating Flexible Level of Detail into 3D Gaussian Splatting"):
+ *   - a level G^(l) of 3D Gaussians with mean mu, opacity o = sigmoid(logit), covariance
+ *     Sigma = R S S^T R^T (Preliminary section, eq. 1) where R comes from a quaternion and
+ *     S = diag(s) with s = exp(s_opt) + s_min^(l) (section 3D Scale Constraint, eq. 4);
+ *   - their projection to the image, the per-pixel opacity of eq. 2 and front-to-back alpha
+ *     blending in depth order (Preliminary section);
+ *   - single-level rendering (section Single-level Rendering) and selective rendering over a
+ *     level range [l_start, l_end] with distance bands d_proj (section Selective Rendering,
+ *     eq. 6 and eq. 7);
+ *   - the gradient of a loss through the rasterizer with respect to every Gaussian attribute
+ *     (the rasterize-and-backpropagate step of the training algorithm, Algorithm 1).
+ * The projection, tiling and compositing constants follow the 3DGS framework that the paper
+ * builds on; they are listed under "Conventions" below.
+ *
+ * Memory: every array pointer is a DEVICE pointer to contiguous row-major data on the
+ * context's device, owned by the caller, unless the comment says "host". Inputs must stay
+ * valid and unmodified until the enqueued work has run; for render_level they must also
+ * stay valid until the matching render_backward has run.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the legacy default stream). All work is
+ * enqueued on it. Each render performs exactly one host synchronisation: a stream-ordered
+ * read of the instance count (8 bytes) needed to size the sort buffers.
+ *
+ * Errors: no function throws or aborts. Arguments are validated before any launch; on
+ * FLOD_ERR_INVALID_ARG the outputs are untouched. flod_status_str() describes a code.
+ *
+ * Threads: a context is used by one host thread at a time; distinct contexts are fully
+ * independent and may run concurrently on different streams.
+ */
+#ifndef FLOD_H
+#define FLOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FLOD_OK = 0,
+  FLOD_ERR_INVALID_ARG = -1,  /* null pointer, bad size, bad level range, sh_degree outside 0..3 */
+  FLOD_ERR_WORKSPACE = -2,    /* the allocator callback refused; see flod_ctx_required_bytes */
+  FLOD_ERR_OVERFLOW = -3,     /* more than 2^32 - 1 tile instances */
+  FLOD_ERR_DEVICE = -4,       /* a HIP runtime call failed */
+  FLOD_ERR_UNSUPPORTED = -5   /* e.g. backward after a selective render */
+} flod_status;
+
+#define FLOD_MAX_LEVELS 8
+#define FLOD_TILE 16
+#define FLOD_SH_COEFFS 16
+
+/* One level G^(l) of the multi-level stack (section Single-level Rendering). n may be 0. */
+typedef struct {
+  const float *means;           /* [n,3]    mu                                           */
+  const float *log_scales;      /* [n,3]    s_opt of eq. 4                               */
+  const float *quats;           /* [n,4]    (w,x,y,z); any norm > 0, zero norm = culled  */
+  const float *opacity_logits;  /* [n]      o = 1 / (1 + exp(-logit))                    */
+  const float *sh;              /* [n,16,3] SH coefficients, index l*l+l+m, channel last;
+                                   must be 16-byte aligned                               */
+  int64_t n;
+  float s_min;                  /* s_min^(l) >= 0 of eq. 3 / eq. 4                       */
+} flod_level;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward): x_cam = R x_world + t.
+   eq. 7 uses f := fx. */
+typedef struct {
+  float R[9];        /* row-major world->camera rotation */
+  float t[3];
+  float campos[3];   /* eye position in world coordinates (view direction of SH colour) */
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} flod_camera;
+
+/* Outputs of a forward render (all device, caller-allocated). */
+typedef struct {
+  float *image;        /* [3,H,W] planar RGB: composite + final_T * background, no clamp */
+  float *final_T;      /* [H,W]   transmittance left after the last blended Gaussian     */
+  int32_t *n_contrib;  /* [H,W]   tile-list position (1-based) of the last blended entry  */
+  int32_t *n_blended;  /* [H,W]   number of Gaussians blended into the pixel; may be NULL */
+} flod_frame;
+
+/* Gradients of the loss with respect to the level's inputs (device, caller-allocated,
+   same shapes as flod_level; every entry is overwritten). */
+typedef struct {
+  float *d_means;           /* [n,3]    */
+  float *d_log_scales;      /* [n,3]    */
+  float *d_quats;           /* [n,4]    */
+  float *d_opacity_logits;  /* [n]      */
+  float *d_sh;              /* [n,16,3] */
+} flod_grads;
+
+/* Workspace allocator. alloc returns a device pointer (256-byte aligned) or NULL to refuse;
+   release frees a pointer alloc returned. `stream` is the stream the memory is used on.
+   Passing NULL callbacks selects hipMallocAsync / hipFreeAsync on that stream. */
+typedef void *(*flod_alloc_fn)(void *user, size_t bytes, void *stream);
+typedef void (*flod_free_fn)(void *user, void *ptr, size_t bytes, void *stream);
+
+typedef struct flod_ctx flod_ctx;   /* workspace plus the state kept for the backward pass */
+
+/* Create a context bound to HIP device `device`. Returns FLOD_ERR_DEVICE if the device is
+   not usable. *ctx is set only on success. */
+flod_status flod_ctx_create(flod_ctx **ctx, int device, flod_alloc_fn alloc, flod_free_fn release,
+                            void *user);
+/* Release the workspace (stream-ordered on the last stream used) and the context. */
+void flod_ctx_destroy(flod_ctx *ctx);
+/* Bytes the context currently holds. */
+size_t flod_ctx_workspace_bytes(const flod_ctx *ctx);
+/* After FLOD_ERR_WORKSPACE: the total bytes the failed call needed (else 0). */
+size_t flod_ctx_required_bytes(const flod_ctx *ctx);
+/* Free all workspace buffers now (stream-ordered); the saved backward state is dropped. */
+flod_status flod_ctx_trim(flod_ctx *ctx, void *stream);
+
+/* Render one level (section Single-level Rendering; eq. 1, eq. 2, eq. 4).
+   bg: host float[3] background colour. sh_degree in 0..3 (first (d+1)^2 coefficients).
+   The state needed by flod_render_backward is kept in ctx until the next render. */
+flod_status flod_render_level(flod_ctx *ctx, const flod_level *level, int sh_degree,
+                              const flod_camera *cam, const float bg[3], flod_frame *out,
+                              void *stream);
+
+/* Selective rendering (section Selective Rendering, eq. 6): from the levels
+   l_start..l_end (1-based, 1 <= l_start <= l_end <= n_levels <= FLOD_MAX_LEVELS), keep a
+   Gaussian of level l iff d_proj^(l-1) > |mu - centre| >= d_proj^(l), with
+   d_proj^(l_end) = 0 and d_proj^(l_start-1) = infinity; the kept Gaussians of all levels
+   form one set rendered in one depth order (global index = level offset + local index,
+   levels concatenated in ascending order). Distances are compared squared in FP32.
+   d_proj: host float[n_levels], d_proj[l-1] = d_proj^(l) (eq. 7 or explicit bands).
+   centre: host float[3]; the eye for per-view selection, a fixed point (e.g. the mean
+   training-camera position) for a predetermined set.
+   n_selected: device int64[n_levels] (may be NULL): per-level count of kept Gaussians. */
+flod_status flod_render_selective(flod_ctx *ctx, const flod_level *levels, int n_levels,
+                                  int l_start, int l_end, const float *d_proj,
+                                  const float centre[3], int sh_degree, const flod_camera *cam,
+                                  const float bg[3], flod_frame *out, int64_t *n_selected,
+                                  void *stream);
+
+/* Render several levels as one set, every Gaussian of every level included (each level
+   with its own s_min), in one depth order; candidate index = position in the concatenation.
+   This renders a predetermined selection set made by flod_select_compact. Backward after
+   it returns FLOD_ERR_UNSUPPORTED. */
+flod_status flod_render_merged(flod_ctx *ctx, const flod_level *levels, int n_levels, int sh_degree,
+                               const flod_camera *cam, const float bg[3], flod_frame *out, void *stream);
+
+/* Predetermined selection set (section Selective Rendering, predetermined Gaussian set):
+   evaluate the eq. 6 bands of flod_render_selective once around `centre` (host float[3],
+   e.g. the mean training-camera position) and compact each level's kept Gaussians, in
+   index order. n_out: host int64[n_levels], receives the kept count per level (0 outside
+   [l_start, l_end]). out: NULL to count only; else host array of n_levels flod_level whose
+   device arrays receive the kept Gaussians of level l in out[l-1] (on input out[l-1].n is
+   the arrays' capacity in Gaussians, on output the kept count; s_min is copied). Returns
+   FLOD_ERR_WORKSPACE, with flod_ctx_required_bytes() = the bytes of level arrays that the
+   level needs (236 per kept Gaussian), when a level's capacity is too small. One host synchronisation per level (the count).
+   flod_render_merged(out[l_start-1 .. l_end-1]) then renders the same image as
+   flod_render_selective(levels, l_start, l_end, d_proj, centre). */
+flod_status flod_select_compact(flod_ctx *ctx, const flod_level *levels, int n_levels, int l_start, int l_end,
+                                const float *d_proj, const float centre[3], flod_level *out, int64_t *n_out,
+                                void *stream);
+
+/* Overlap pruning (section Overlap Pruning): Gaussian i of `level` is marked for removal
+   when the mean of its distances to its three nearest other Gaussians of the level is below
+   d_op (the paper uses d_op = s_min^(l) / 2 while training level l; d_op = 0 removes none).
+   Distances are FP64 Euclidean distances between the FP32 means; the three are summed in
+   ascending order and divided by 3; all Gaussians are evaluated on the same input set (no
+   removal changes another's neighbours). A level of fewer than four Gaussians keeps all.
+   keep: device uint8[n], 1 = keep, 0 = remove. d_avg: device double[n] or NULL; receives
+   d_avg exactly when the three nearest lie within 3 d_op (1 + 1e-9), +inf otherwise (such a
+   Gaussian is kept). n_keep: host, the number kept. Workspace about 44 B per Gaussian plus
+   8 B per hash bucket (2^ceil(log2 n) buckets). One host synchronisation (the count) and
+   one check of the neighbour-search size: when the means are so dense relative to d_op
+   that the scan would exceed 2^36 distance evaluations, returns FLOD_ERR_UNSUPPORTED
+   without writing keep. n <= 2^30. */
+flod_status flod_overlap_prune(flod_ctx *ctx, const flod_level *level, float d_op, uint8_t *keep,
+                               double *d_avg, int64_t *n_keep, void *stream);
+
+/* Compact a level by a keep mask (device uint8[n], nonzero = keep), in index order, into
+   `out` (host struct of device arrays; on input out->n = capacity in Gaussians, on output
+   the kept count; s_min is copied). out = NULL counts only. *n_out = kept count. Returns
+   FLOD_ERR_WORKSPACE, with flod_ctx_required_bytes() = 236 B per kept Gaussian, when the
+   capacity is too small. Output arrays must not overlap the input's. */
+flod_status flod_compact_level(flod_ctx *ctx, const flod_level *in, const uint8_t *keep, flod_level *out,
+                               int64_t *n_out, void *stream);
+
+/* Training loss (section Implementation: L1 and SSIM, as in the backbone model):
+   loss = (1 - lambda) mean|x - y| + lambda (1 - SSIM(x, y)), SSIM with an 11 x 11 Gaussian
+   window (sigma 1.5, normalised), zeros outside the image, C1 = 0.01^2, C2 = 0.03^2, averaged
+   over channels and pixels. image, target: device float[channels, height, width]
+   (contiguous). loss: device double[1] (written; no host synchronisation). dmaps: device
+   float[3, channels, height, width] or NULL; when given, receives the per-pixel derivatives
+   of SSIM with respect to the windowed mean, second moment and cross moment of the image,
+   which flod_l1_ssim_backward consumes. Moments and sums in FP64; the loss is reduced in a
+   fixed order (deterministic). 0 <= lambda <= 1; 1 <= channels <= 64, sizes <= 65536. */
+flod_status flod_l1_ssim_forward(flod_ctx *ctx, const float *image, const float *target, int channels, int height,
+                                 int width, float lambda, double *loss, float *dmaps, void *stream);
+
+/* Gradient of the loss above with respect to image, times *dloss (device double[1], NULL
+   for 1): d_image, device float[channels, height, width]. dmaps from flod_l1_ssim_forward on
+   the same image, target and lambda. d|t|/dt is taken as 0 at t = 0. */
+flod_status flod_l1_ssim_backward(flod_ctx *ctx, const float *image, const float *target, int channels, int height,
+                                  int width, float lambda, const float *dmaps, const double *dloss, float *d_image,
+                                  void *stream);
+
+/* Plain L1 image loss, mean |x - y| over `count` elements (image, target: device float[count]);
+   loss: device double[1], summed in FP64 in a fixed order (deterministic), no host
+   synchronisation. */
+flod_status flod_l1_loss_forward(flod_ctx *ctx, const float *image, const float *target, int64_t count,
+                                 double *loss, void *stream);
+
+/* d_image = sign(x - y) / count times *dloss (device double[1], NULL for 1); 0 where x = y. */
+flod_status flod_l1_loss_backward(flod_ctx *ctx, const float *image, const float *target, int64_t count,
+                                  const double *dloss, float *d_image, void *stream);
+
+/* Level transition (section Training Method, eq. 5): initialise level l+1 from the trained
+   level l = *in: every attribute copied, and s_opt' = log(s^(l) - s_min_next) with
+   s^(l) = exp(s_opt) + in->s_min formed as the renderer forms it (exp in FP64 rounded once
+   to FP32, the sum and the logarithm in FP64, the result rounded to FP32), so that the
+   renderer's scale at level l+1 equals s^(l) up to that rounding. out: host struct of
+   device arrays of capacity out->n >= in->n; on return out->n = in->n and
+   out->s_min = s_min_next. Each output array either is the input's own (in place; not
+   copied) or does not overlap it. Requires 0 <= s_min_next <= in->s_min (eq. 3 floors
+   decrease with the level). */
+flod_status flod_level_transition(flod_ctx *ctx, const flod_level *in, float s_min_next, flod_level *out,
+                                  void *stream);
+
+/* Backward of the last flod_render_level on ctx: given dL/dimage [3,H,W] (device), write
+   dL/d(inputs) into grads. Per-pixel transmittance is recovered from the saved final_T
+   and n_contrib (no per-pixel contributor lists are stored). Returns
+   FLOD_ERR_UNSUPPORTED after a selective render or when no render preceded it. FP32
+   atomic accumulation: results are deterministic up to summation order. */
+flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_grads *grads,
+                                 void *stream);
+
+/* Counts of the last render (host). */
+typedef struct {
+  int64_t n_candidates;   /* Gaussians considered (all levels in range) */
+  int64_t n_visible;      /* Gaussians that survived selection and culling */
+  int64_t n_instances;    /* K: (tile, Gaussian) pairs */
+  int32_t tiles_x, tiles_y;
+  int32_t width, height;
+} flod_stats;
+flod_status flod_ctx_stats(const flod_ctx *ctx, flod_stats *out);
+
+/* Device pointers to the last render's intermediate buffers, owned by ctx, valid until
+   the next call on ctx. For inspection and tests. */
+typedef struct {
+  const uint32_t *tile_ids;     /* [n_instances] tile id of each sorted instance          */
+  const uint32_t *values;       /* [n_instances] Gaussian (global) index, sorted by
+                                   (tile, depth bits, index)                              */
+  const uint32_t *ranges;       /* [tiles,2] [start, end) of each tile in the list          */
+  const uint32_t *depth_bits;   /* [n_candidates] bits of the view-space depth (FP32)       */
+  const uint32_t *rect;         /* [n_candidates,2] (x0 | y0<<16, x1 | y1<<16) inclusive    */
+  const uint32_t *tiles_touched;/* [n_candidates] 0 = not rendered                          */
+  const float *xy_conic;        /* [n_candidates,4] mu'x, mu'y (FP32 rounding of the FP64
+                                   projection), conic a, conic b                            */
+  const float *conic_c_opacity_rg; /* [n_candidates,4] conic c, opacity, red, green         */
+  const float *blue;            /* [n_candidates,2] blue, and (bits) the residual of mu' as
+                                   two bf16: x in the low half, y in the high half          */
+  const float *grad2d;          /* [9, n_candidates] after flod_render_backward: dL/d(mu'x,
+                                   mu'y, conic a, b, c, opacity, red, green, blue), with b
+                                   the off-diagonal conic entry; NULL before a backward   */
+} flod_view;
+flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out);
+
+/* Per-stage device timing with HIP events on the render stream (off by default). */
+enum {
+  FLOD_STAGE_PREPROCESS = 0,  /* selection (eq. 6), activation (eq. 4), projection, SH */
+  FLOD_STAGE_COMPACT,         /* visible-set compaction                              */
+  FLOD_STAGE_DEPTH_SORT,      /* radix sort of visible Gaussians by depth            */
+  FLOD_STAGE_OFFSETS,         /* tile counts in depth order, scan, count readback    */
+  FLOD_STAGE_EMIT,            /* (tile, Gaussian) instance emission                  */
+  FLOD_STAGE_TILE_SORT,       /* stable radix sort of instances by tile              */
+  FLOD_STAGE_RANGES,          /* per-tile [start, end)                               */
+  FLOD_STAGE_BLEND,           /* front-to-back compositing (eq. 2)                   */
+  FLOD_STAGE_BLEND_BWD,       /* reverse compositing                                 */
+  FLOD_STAGE_PREPROCESS_BWD,  /* chain rule to the 3D attributes                     */
+  FLOD_NUM_STAGES
+};
+flod_status flod_ctx_set_timing(flod_ctx *ctx, int enable);
+/* Accumulated milliseconds and call counts per stage since the last reset; synchronises
+   on the last recorded events. ms and calls: host arrays of FLOD_NUM_STAGES. */
+flod_status flod_ctx_stage_times(flod_ctx *ctx, double *ms, int64_t *calls, int reset);
+const char *flod_stage_name(int stage);
+
+/* eq. 3: s_min^(l) = lambda * rho^(1-l) for l < l_max, 0 for l = l_max. */
+float flod_smin(int l, int l_max, float lambda, float rho);
+/* eq. 7: d_proj = s_min / gamma * f. */
+float flod_dproj(float s_min, float f, float gamma);
+const char *flod_status_str(flod_status status);
+/* Blocking device-to-host copy (for tests reading flod_view buffers). */
+flod_status flod_copy_to_host(void *dst_host, const void *src_device, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLOD_H */

@@ -122,24 +122,34 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       const uint32_t lo = __float_as_uint(BL.y);
       const float loy = mu_lo_y(lo);
       const float dx = (fx - A.x) - mu_lo_x(lo);
+      // first only what decides whether a pixel takes part; the transmittance recovery and
+      // the gradient run when some pixel of the wave does (predicated per pixel: a pixel
+      // that does not take part adds exact zeros and keeps its T and V)
+      float dyv[PPT], Gv[PPT], a0v[PPT], alv[PPT];
+      bool okv[PPT];
+      bool contrib = false;
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        dyv[k] = (fy[k] - A.y) - loy;
+        const float q = conic_q(A.z, A.w, B.x, dx, dyv[k]);
+        Gv[k] = __expf(-0.5f * q);
+        a0v[k] = B.y * Gv[k];
+        alv[k] = fminf(kAlphaMax, a0v[k]);
+        okv[k] = jpos < last[k] && q <= kQCut && alv[k] >= kAlphaMin;
+        contrib = contrib || okv[k];
+      }
+      if (!__any(contrib)) continue;
       float gr[kG2d];
 #pragma unroll
       for (int c = 0; c < kG2d; ++c) gr[c] = 0.0f;
-      bool contrib = false;
-      // predicated like the forward: a pixel that does not take part adds exact zeros
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
-        const float dy = (fy[k] - A.y) - loy;
-        const float q = conic_q(A.z, A.w, B.x, dx, dy);
-        const float G = __expf(-0.5f * q);
-        const float a0 = B.y * G;
-        const float alpha = fminf(kAlphaMax, a0);
-        const bool ok = jpos < last[k] && q <= kQCut && alpha >= kAlphaMin;
-        contrib = contrib || ok;
+        const bool ok = okv[k];
+        const float alpha = alv[k], G = Gv[k], dy = dyv[k];
         const double Ti64 = T[k] * recip64(1.0 - (double)alpha);
         const float wT = ok ? alpha * (float)Ti64 : 0.0f;
         const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * c2;   // dL/dC . c
-        const float dalpha = (ok && a0 <= kAlphaMax) ? (float)(Ti64 * ((double)dcc - V[k])) : 0.0f;
+        const float dalpha = (ok && a0v[k] <= kAlphaMax) ? (float)(Ti64 * ((double)dcc - V[k])) : 0.0f;
         gr[6] = fmaf(wT, d0[k], gr[6]);
         gr[7] = fmaf(wT, d1[k], gr[7]);
         gr[8] = fmaf(wT, d2[k], gr[8]);
@@ -153,7 +163,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         gr[0] = fmaf(dq, -2.0f * (A.z * dx + A.w * dy), gr[0]);
         gr[1] = fmaf(dq, -2.0f * (A.w * dx + B.x * dy), gr[1]);
       }
-      if (__any(contrib)) {
+      {
         // nine in-row DPP reductions (interleaved, no control flow between them) leave each
         // row's sums in all its lanes; lane 16 r + c keeps component c, two cross-row
         // exchanges complete the sums, and lanes 0..8 add them with one atomic instruction

@@ -289,7 +289,7 @@ hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
 //  - Larger ones are written by the whole wave, one row span per lane, then the same
 //    search over the row widths gives consecutive stores.
 // ---------------------------------------------------------------------------------------
-constexpr uint32_t kEmitSolo = 16;
+constexpr uint32_t kEmitSolo = 64;
 
 __device__ __forceinline__ void emit_rows(const Footprint &fp, int ty_begin, int ty_end, int tiles_x,
                                           uint32_t pos, uint32_t g, uint32_t *__restrict__ tile_ids,
