@@ -87,41 +87,34 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
       bool any_live = false;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) any_live = any_live || !done[k];
-      if (!__any(any_live)) break;
+      if (!any_live) break;
       const float4 A = s_a[j];
       const float4 B = s_b[j];
       const float2 BL = s_c[j];
+      const float c2 = BL.x;
       const uint32_t lo = __float_as_uint(BL.y);
       const float loy = mu_lo_y(lo);
       const float dx = (fx - A.x) - mu_lo_x(lo);
-      // decide first (predicated); the FP64 transmittance update and the colour run only when
-      // some pixel of the wave takes the entry
-      float alv[PPT];
-      bool okv[PPT];
-      bool any_ok = false;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
+        if (done[k]) continue;
         const float dy = (fy[k] - A.y) - loy;
         const float q = conic_q(A.z, A.w, B.x, dx, dy);
-        alv[k] = fminf(kAlphaMax, B.y * __expf(-0.5f * q));
-        okv[k] = !done[k] && q <= kQCut && alv[k] >= kAlphaMin;
-        any_ok = any_ok || okv[k];
-      }
-      if (!__any(any_ok)) continue;
-#pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        const float alpha = alv[k];
+        if (q > kQCut) continue;
+        const float alpha = fminf(kAlphaMax, B.y * __expf(-0.5f * q));
+        if (alpha < kAlphaMin) continue;
         const double Tn = T[k] * (1.0 - (double)alpha);
-        const bool stop = okv[k] && Tn < (double)kTMin;
-        const bool blend = okv[k] && !stop;
-        const float wgt = blend ? alpha * (float)T[k] : 0.0f;
+        if (Tn < (double)kTMin) {
+          done[k] = true;
+          continue;
+        }
+        const float wgt = alpha * (float)T[k];
         C0[k] = fmaf(wgt, B.z, C0[k]);
         C1[k] = fmaf(wgt, B.w, C1[k]);
-        C2[k] = fmaf(wgt, BL.x, C2[k]);
-        T[k] = blend ? Tn : T[k];
-        last[k] = blend ? start + j + 1 : last[k];
-        nbl[k] += blend ? 1 : 0;
-        done[k] = done[k] || stop;
+        C2[k] = fmaf(wgt, c2, C2[k]);
+        T[k] = Tn;
+        last[k] = start + j + 1;
+        ++nbl[k];
       }
     }
   }
