@@ -31,6 +31,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+import hashlib
+
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X fp32 vector, TFLOP/s
 
@@ -41,6 +43,25 @@ FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X fp32 vector, TFLOP/s
 FLOPS_EVAL = 15
 FLOPS_BLEND_FWD = 9
 FLOPS_BLEND_BWD = 46
+
+
+# Measured HBM traffic per launch of a kernel, from two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE) of `bench.py --no-extras --no-cpu --steps 3 --warmup 1`, each counter
+# scaled by its reading for a 1 GiB device-to-device copy (profiles/
+# step_1080p_1M_hbm_counters.md). A figure holds only for the kernel sources it was taken
+# with: the sha256 over the listed files must match, else the traffic is reported as null.
+PROFILED_TRAFFIC = {}
+
+
+def profiled_traffic(kernel: str):
+    e = PROFILED_TRAFFIC.get(kernel)
+    if not e:
+        return None
+    h = hashlib.sha256()
+    for f in e["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return e["bytes"] if h.hexdigest() == e["sha256"] else None
 
 
 def parse():
@@ -80,7 +101,7 @@ def algorithmic_bytes(stage, N, n_vis, K, P, tiles):
         "compact": 8 * N + 8 * n_vis,
         "depth_sort": 4 * 2 * 8 * n_vis,
         "offsets": 8 * n_vis,
-        "emit": 28 * n_vis + 8 * K,
+        "emit": 32 * n_vis + 8 * K,
         "tile_sort": 2 * (4 + 16) * K,
         "ranges": 4 * K + 8 * tiles,
         "blend": 44 * K + 20 * P,
@@ -177,13 +198,13 @@ def main():
         flops = FLOPS_EVAL * Pi_walk + per_pair * Pi_blend
         ach = flops / (dom_ms * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None, "algorithmic_flops_per_launch": flops,
+                "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": profiled_traffic(dom), "algorithmic_flops_per_launch": flops,
                 "pairs_walked": Pi_walk, "pairs_blended": Pi_blend}
     else:
         byts = algorithmic_bytes(dom, N, n_vis, K, P, tiles)
         ach = byts / (dom_ms * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": byts}
+                "frac": ach / HBM_PEAK_GBS, "traffic": profiled_traffic(dom), "algorithmic_bytes_per_launch": byts}
     roof["avg_launch_ms"] = dom_ms
     # whole-step roofline: sum over stages of the larger of the HBM time and the ALU time
     t_roof = 0.0
