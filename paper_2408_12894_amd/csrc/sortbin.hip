@@ -148,6 +148,13 @@ __global__ __launch_bounds__(kBlock) void k_rs_scan(const uint32_t *n_ptr, const
   if (threadIdx.x == 0) tot[d] = run;
 }
 
+// Stable scatter of one workgroup's TILE keys. Wave w owns the contiguous keys
+// [w * 64 ITEMS, (w + 1) * 64 ITEMS) of the tile, read round by round (64 consecutive keys per
+// round), so (wave, round, lane) order is the input order. Each key's rank among equal digits
+// of its wave comes from ballots over the digit bits plus a wave-private LDS count carried
+// across rounds (a wave's LDS accesses complete in program order, so no barrier is needed
+// between rounds); one barrier then turns the per-wave counts into offsets, keys are placed
+// in LDS in digit order, and each digit's run is written out contiguously.
 template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restrict__ keys_in,
                                                        const uint32_t *__restrict__ vals_in,
@@ -156,11 +163,12 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
                                                        int shift, const uint32_t *hist, const uint32_t *scan,
                                                        const uint32_t *tot, int nb_max) {
   constexpr uint32_t TILE = kBlock * ITEMS;
+  constexpr int WAVES = kBlock / 64;
+  constexpr uint32_t WTILE = 64 * ITEMS;
   __shared__ uint32_t s_keys[TILE];
   __shared__ uint32_t s_vals[TILE];
   __shared__ uint32_t s_goff[kRadix];
-  __shared__ uint32_t s_run[kRadix];
-  __shared__ uint32_t s_wcnt[kBlock / 64][kRadix];
+  __shared__ uint32_t s_wcnt[WAVES][kRadix];
   const uint32_t n = *n_ptr;
   const uint32_t nb = (n + TILE - 1) / TILE;
   const uint32_t b = blockIdx.x;
@@ -171,22 +179,23 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
   uint32_t dbase = block_excl_scan(tot[tid], &t_all);
   const uint32_t cnt = hist[(size_t)tid * nb_max + b];
   uint32_t t_loc;
-  uint32_t lbase = block_excl_scan(cnt, &t_loc);
+  const uint32_t lbase = block_excl_scan(cnt, &t_loc);
   s_goff[tid] = dbase + scan[(size_t)tid * nb_max + b] - lbase;
-  s_run[tid] = lbase;
 #pragma unroll
-  for (int k = 0; k < kBlock / 64; ++k) s_wcnt[k][tid] = 0;
+  for (int k = 0; k < WAVES; ++k) s_wcnt[k][tid] = 0;
   __syncthreads();
   const uint32_t base = b * TILE;
   const uint32_t count = min(TILE, n - base);
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t kr[ITEMS], vr[ITEMS], rr[ITEMS];
+#pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
-    const uint32_t li = r * kBlock + tid;
+    const uint32_t li = (uint32_t)w * WTILE + (uint32_t)r * 64u + (uint32_t)lane;
     const bool valid = li < count;
     const uint32_t key = valid ? keys_in[base + li] : 0u;
-    const uint32_t val = valid ? vals_in[base + li] : 0u;
+    kr[r] = key;
+    vr[r] = valid ? vals_in[base + li] : 0u;
     const uint32_t d = (key >> shift) & (kRadix - 1);
-    // lanes of this wave holding the same digit
     unsigned long long peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < kRadixBits; ++bit) {
@@ -194,25 +203,32 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
       const unsigned long long bb = __ballot(set);
       peers &= set ? bb : ~bb;
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = s_run[d] + rank;
-      for (int k = 0; k < w; ++k) pos += s_wcnt[k][d];
-      s_keys[pos] = key;
-      s_vals[pos] = val;
-    }
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int k = 0; k < kBlock / 64; ++k) {
-      add += s_wcnt[k][tid];
-      s_wcnt[k][tid] = 0;
-    }
-    s_run[tid] += add;
-    __syncthreads();
+    const uint32_t in_round = (uint32_t)__popcll(peers & lt);
+    const uint32_t prev = s_wcnt[w][d];
+    rr[r] = prev + in_round;
+    if (valid && in_round == 0) s_wcnt[w][d] = prev + (uint32_t)__popcll(peers);
   }
+  __syncthreads();
+  {
+    uint32_t acc = lbase;   // this thread's digit is tid
+#pragma unroll
+    for (int k = 0; k < WAVES; ++k) {
+      const uint32_t c = s_wcnt[k][tid];
+      s_wcnt[k][tid] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const uint32_t li = (uint32_t)w * WTILE + (uint32_t)r * 64u + (uint32_t)lane;
+    if (li < count) {
+      const uint32_t pos = s_wcnt[w][(kr[r] >> shift) & (kRadix - 1)] + rr[r];
+      s_keys[pos] = kr[r];
+      s_vals[pos] = vr[r];
+    }
+  }
+  __syncthreads();
   for (uint32_t li = tid; li < count; li += kBlock) {
     const uint32_t key = s_keys[li];
     const uint32_t d = (key >> shift) & (kRadix - 1);
