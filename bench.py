@@ -50,7 +50,10 @@ FLOPS_BLEND_BWD = 46
 # scaled by its reading for a 1 GiB device-to-device copy (profiles/
 # step_1080p_1M_hbm_counters.md). A figure holds only for the kernel sources it was taken
 # with: the sha256 over the listed files must match, else the traffic is reported as null.
-PROFILED_TRAFFIC = {}
+PROFILED_TRAFFIC = {
+    "blend_bwd": {"bytes": 313113270, "sha256": "5af9dad69a4112323d5fd5467a5ff01bfcccfbab1d827781190f19c762909f6c",
+                  "sources": ['paper_2408_12894_amd/csrc/backward.hip', 'paper_2408_12894_amd/csrc/blend_common.h', 'paper_2408_12894_amd/csrc/project.h', 'paper_2408_12894_amd/csrc/flod_internal.h']},
+}
 
 
 def profiled_traffic(kernel: str):
