@@ -257,9 +257,10 @@ typedef struct {
   const float *conic_c_opacity_rg; /* [n_candidates,4] conic c, opacity, red, green         */
   const float *blue;            /* [n_candidates,2] blue, and (bits) the residual of mu' as
                                    two bf16: x in the low half, y in the high half          */
-  const float *grad2d;          /* [9, n_candidates] after flod_render_backward: dL/d(mu'x,
-                                   mu'y, conic a, b, c, opacity, red, green, blue), with b
-                                   the off-diagonal conic entry; NULL before a backward   */
+  const float *grad2d;          /* [n_candidates, 9] after flod_render_backward: per
+                                   Gaussian dL/d(mu'x, mu'y, conic a, b, c, opacity, red,
+                                   green, blue), with b the off-diagonal conic entry; NULL
+                                   before a backward                                       */
 } flod_view;
 flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out);
 

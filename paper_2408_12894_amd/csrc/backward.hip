@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ values, const float4 *__restrict__ xyab,
     const float4 *__restrict__ cop, const float2 *__restrict__ blue, int W, int H, int tiles_x, int n_tiles,
     float bg0, float bg1, float bg2, const float *__restrict__ final_T, const int32_t *__restrict__ n_contrib,
-    const float *__restrict__ dimg, float *__restrict__ g2d, int64_t stride) {
+    const float *__restrict__ dimg, float *__restrict__ g2d) {
   constexpr int NT = kTile * kTile / PPT;
   constexpr int ROWS = NT / kTile;
   constexpr int WAVES = NT / 64;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         }
         x += __shfl_xor(x, 16, 64);
         x += __shfl_xor(x, 32, 64);
-        if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[lane * stride + s_id[jl]], x);
+        if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[(size_t)s_id[jl] * kG2d + lane], x);
       }
     }
   }
@@ -183,20 +183,20 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
 
 hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
                             const float2 *blue, const DevCamera &cam, const float bg[3], const float *final_T,
-                            const int32_t *n_contrib, const float *dL_dimage, float *g2d, int64_t g2d_stride,
+                            const int32_t *n_contrib, const float *dL_dimage, float *g2d,
                             hipStream_t s) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   const int grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
   hipLaunchKernelGGL(k_blend_bwd<kBwdPix>, dim3(grid), dim3(kTile * kTile / kBwdPix), 0, s, ranges, values, xyab,
                      cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib,
-                     dL_dimage, g2d, g2d_stride);
+                     dL_dimage, g2d);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const uint32_t *__restrict__ tiles,
-                                                           const float *__restrict__ g2d, int64_t stride,
+                                                           const float *__restrict__ g2d,
                                                            flod_grads out) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const DevLevel L = p.lv[0];
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
   }
   double g[kG2d];
 #pragma unroll
-  for (int c = 0; c < kG2d; ++c) g[c] = (double)g2d[c * stride + i];
+  for (int c = 0; c < kG2d; ++c) g[c] = (double)g2d[i * kG2d + c];
   const float m0 = L.means[i * 3 + 0], m1 = L.means[i * 3 + 1], m2 = L.means[i * 3 + 2];
   float ls[3] = {L.log_scales[i * 3 + 0], L.log_scales[i * 3 + 1], L.log_scales[i * 3 + 2]};
   const float4 q4 = reinterpret_cast<const float4 *>(L.quats)[i];
@@ -375,12 +375,12 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
   out.d_opacity_logits[i] = d_logit;
 }
 
-hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, const float *g2d, int64_t g2d_stride,
+hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, const float *g2d,
                                  const flod_grads &g, hipStream_t s) {
   const int64_t n = p.lv[0].n;
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, tiles,
-                     g2d, g2d_stride, g);
+                     g2d, g);
   return hipGetLastError();
 }
 

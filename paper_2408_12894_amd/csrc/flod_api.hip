@@ -791,7 +791,7 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   tm.begin(FLOD_STAGE_BLEND_BWD);
   const uint32_t *vals = sv.sorted_vals ? P<uint32_t>(ctx, B_TVAL1) : P<uint32_t>(ctx, B_TVAL0);
   if (launch_blend_bwd(P<uint2>(ctx, B_RANGES), vals, P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
-                       P<float2>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d, N,
+                       P<float2>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d,
                        s) != hipSuccess)
     return FLOD_ERR_DEVICE;
   tm.end();
@@ -803,7 +803,7 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   L.logits = sv.level.opacity_logits; L.sh = sv.level.sh;
   L.offset = 0; L.n = N; L.s_min = sv.level.s_min;
   p.n_total = N;
-  if (launch_preprocess_bwd(p, P<uint32_t>(ctx, B_TILES), g2d, N, *grads, s) != hipSuccess) return FLOD_ERR_DEVICE;
+  if (launch_preprocess_bwd(p, P<uint32_t>(ctx, B_TILES), g2d, *grads, s) != hipSuccess) return FLOD_ERR_DEVICE;
   tm.end();
   ctx->saved.has_grad2d = true;
   return FLOD_OK;

@@ -105,10 +105,10 @@ hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float
 hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
                             const float4 *cop, const float2 *blue, const DevCamera &cam,
                             const float bg[3], const float *final_T, const int32_t *n_contrib,
-                            const float *dL_dimage, float *g2d, int64_t g2d_stride,
+                            const float *dL_dimage, float *g2d,
                             hipStream_t s);
 hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, const float *g2d,
-                                 int64_t g2d_stride, const flod_grads &g, hipStream_t s);
+                                 const flod_grads &g, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_select_count(const float *means, int64_t n, const float centre[3], float lo2, float hi2,
                                uint32_t *block_cnt, hipStream_t s);

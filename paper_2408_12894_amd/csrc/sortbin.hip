@@ -295,31 +295,20 @@ hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
 
 // ---------------------------------------------------------------------------------------
 // Instance emission in depth order. Each Gaussian writes its footprint (tile rows and the
-// span of tiles in each row, as the preprocess counted them) row-major at its offset.
-//  - Footprints that fill their bounding rectangle (tile count = rectangle area; the common
-//    case) are written by the whole wave together: output slot v of the wave's rectangles
-//    finds its Gaussian by a binary search over the lanes' inclusive counts, so each store
-//    instruction writes consecutive positions.
-//  - Other footprints of up to kEmitSolo tiles are written by their own thread, row spans
+// span of tiles in each row, as the preprocess counted them) row-major at its offset. A
+// workgroup's 256 Gaussians own one contiguous output range; it is assembled in LDS in
+// windows of kEmitCap instances and each window is then written out with consecutive stores.
+//  - Footprints that fill their bounding rectangle (tile count = rectangle area) are placed by
+//    the whole wave: output slot v of the wave's rectangles finds its Gaussian by a binary
+//    search over the lanes' inclusive counts.
+//  - Other footprints of up to kEmitSolo tiles are placed by their own thread, row spans
 //    recomputed in FP64 exactly as the preprocess computed them.
-//  - Larger ones are written by the whole wave, one row span per lane, then the same
-//    search over the row widths gives consecutive stores.
+//  - Larger ones are placed by the whole wave, one row span per lane, then the same search
+//    over the row widths.
+// A Gaussian whose range does not meet the current window is skipped for that window.
 // ---------------------------------------------------------------------------------------
 constexpr uint32_t kEmitSolo = 64;
-
-__device__ __forceinline__ void emit_rows(const Footprint &fp, int ty_begin, int ty_end, int tiles_x,
-                                          uint32_t pos, uint32_t g, uint32_t *__restrict__ tile_ids,
-                                          uint32_t *__restrict__ values) {
-  for (int ty = ty_begin; ty <= ty_end; ++ty) {
-    int tx0, tx1;
-    if (!row_span(fp, ty, tiles_x, tx0, tx1)) continue;
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      tile_ids[pos] = (uint32_t)(ty * tiles_x + tx);
-      values[pos] = g;
-      ++pos;
-    }
-  }
-}
+constexpr uint32_t kEmitCap = 4096;   // instances staged per window (32 KB of LDS)
 
 struct RectSpan {
   int x0, y0, x1, y1;
@@ -348,12 +337,26 @@ __device__ __forceinline__ int owner_lane(uint32_t incl, uint32_t v) {
   return lo;
 }
 
+struct EmitWindow {
+  uint32_t w0, w1;         // local positions [w0, w1) of this window
+  uint32_t *t, *v;         // LDS staging, indexed by position - w0
+  __device__ __forceinline__ bool meets(uint32_t lo, uint32_t hi) const { return lo < w1 && hi > w0; }
+  __device__ __forceinline__ void put(uint32_t p, uint32_t tile, uint32_t g) const {
+    if (p >= w0 && p < w1) {
+      t[p - w0] = tile;
+      v[p - w0] = g;
+    }
+  }
+};
+
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr,
                                                  const uint32_t *tiles, const float4 *xyab, const float4 *cop,
                                                  const uint2 *rect, const float *qsup,
                                                  const unsigned long long *prefix, int tiles_x,
                                                  int tiles_y, uint32_t *__restrict__ tile_ids,
                                                  uint32_t *__restrict__ values) {
+  __shared__ uint32_t s_tile[kEmitCap];
+  __shared__ uint32_t s_val[kEmitCap];
   const uint32_t n = *n_ptr;
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
   if (blockIdx.x * kBlock >= n) return;
@@ -361,73 +364,85 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
   const uint32_t g = valid ? sorted_ids[j] : 0u;
   const uint32_t c = valid ? tiles[g] : 0u;
   uint32_t tot;
-  const uint32_t ex = block_excl_scan(c, &tot);
-  const uint32_t off = (uint32_t)(prefix[blockIdx.x] + ex);
+  const uint32_t off = block_excl_scan(c, &tot);     // local position of this Gaussian's first instance
+  const unsigned long long obase = prefix[blockIdx.x];
   const int lane = threadIdx.x & 63;
   RectSpan rs{0, 0, 0, 0, false};
   if (c > 0) rs = rect_of(rect[g], c);
+  const uint32_t cf = rs.full ? c : 0u;
+  const uint32_t incl_f = wave_incl_scan(cf);
+  const uint32_t total_f = __shfl(incl_f, 63, 64);
+  const uint32_t wf = rs.full ? (uint32_t)(rs.x1 - rs.x0 + 1) : 1u;
+  const uint32_t first_f = (uint32_t)(rs.y0 * tiles_x + rs.x0);
+  const uint32_t wave_lo = __shfl(off, 0, 64), wave_hi = __shfl(off + c, 63, 64);
+  const unsigned long long big_all = __ballot(c > kEmitSolo && !rs.full);
 
-  // full rectangles, the whole wave at once
-  {
-    const uint32_t cf = rs.full ? c : 0u;
-    const uint32_t incl = wave_incl_scan(cf);
-    const uint32_t total = __shfl(incl, 63, 64);
-    const uint32_t w = rs.full ? (uint32_t)(rs.x1 - rs.x0 + 1) : 1u;
-    const uint32_t first = (uint32_t)(rs.y0 * tiles_x + rs.x0);
-    for (uint32_t v0 = 0; v0 < total; v0 += 64) {
-      const uint32_t v = min(v0 + (uint32_t)lane, total - 1u);
-      const int o = owner_lane(incl, v);
-      const uint32_t t = v - (__shfl(incl, o, 64) - __shfl(cf, o, 64));
-      const uint32_t wo = __shfl(w, o, 64);
-      const uint32_t row = t / wo;
-      const uint32_t tile = __shfl(first, o, 64) + row * (uint32_t)tiles_x + (t - row * wo);
-      const uint32_t pos = __shfl(off, o, 64) + t;
-      const uint32_t go = __shfl(g, o, 64);
-      if (v0 + (uint32_t)lane < total) {
-        tile_ids[pos] = tile;
-        values[pos] = go;
+  for (uint32_t w0 = 0; w0 < tot; w0 += kEmitCap) {
+    const EmitWindow win{w0, min(w0 + kEmitCap, tot), s_tile, s_val};
+    if (win.meets(wave_lo, wave_hi)) {
+      // full rectangles, the whole wave at once
+      for (uint32_t v0 = 0; v0 < total_f; v0 += 64) {
+        const uint32_t v = min(v0 + (uint32_t)lane, total_f - 1u);
+        const int o = owner_lane(incl_f, v);
+        const uint32_t t = v - (__shfl(incl_f, o, 64) - __shfl(cf, o, 64));
+        const uint32_t wo = __shfl(wf, o, 64);
+        const uint32_t row = t / wo;
+        const uint32_t tile = __shfl(first_f, o, 64) + row * (uint32_t)tiles_x + (t - row * wo);
+        const uint32_t pos = __shfl(off, o, 64) + t;
+        const uint32_t go = __shfl(g, o, 64);
+        if (v0 + (uint32_t)lane < total_f) win.put(pos, tile, go);
       }
-    }
-  }
-  // small footprints that do not fill their rectangle, one thread each
-  if (c > 0 && c <= kEmitSolo && !rs.full) {
-    const float4 A = xyab[g];
-    Footprint fp;
-    footprint(A.x, A.y, A.z, A.w, cop[g].x, support_span(qsup[g]), tiles_y, fp);
-    emit_rows(fp, fp.ty0, fp.ty1, tiles_x, off, g, tile_ids, values);
-  }
-  // large footprints that do not fill their rectangle, one at a time per wave
-  unsigned long long big = __ballot(c > kEmitSolo && !rs.full);
-  while (big) {
-    const int src = __ffsll((long long)big) - 1;
-    big &= big - 1;
-    const uint32_t os = __shfl(off, src, 64);
-    const uint32_t gs = __shfl(g, src, 64);
-    const float4 A = xyab[gs];
-    Footprint fp;
-    footprint(A.x, A.y, A.z, A.w, cop[gs].x, support_span(qsup[gs]), tiles_y, fp);
-    const int nrows = fp.ty1 - fp.ty0 + 1;
-    uint32_t base = os;
-    for (int rb = 0; rb < nrows; rb += 64) {
-      const int ty = fp.ty0 + rb + lane;
-      int tx0 = 0, tx1 = -1;
-      if (rb + lane < nrows) row_span(fp, ty, tiles_x, tx0, tx1);
-      const uint32_t wr = (uint32_t)(tx1 - tx0 + 1);
-      const uint32_t incl = wave_incl_scan(wr);
-      const uint32_t total = __shfl(incl, 63, 64);
-      const uint32_t first = (uint32_t)(ty * tiles_x + tx0);
-      for (uint32_t v0 = 0; v0 < total; v0 += 64) {
-        const uint32_t v = min(v0 + (uint32_t)lane, total - 1u);
-        const int o = owner_lane(incl, v);
-        const uint32_t t = v - (__shfl(incl, o, 64) - __shfl(wr, o, 64));
-        const uint32_t tile = __shfl(first, o, 64) + t;
-        if (v0 + (uint32_t)lane < total) {
-          tile_ids[base + v] = tile;
-          values[base + v] = gs;
+      // small footprints that do not fill their rectangle, one thread each
+      if (c > 0 && c <= kEmitSolo && !rs.full && win.meets(off, off + c)) {
+        const float4 A = xyab[g];
+        Footprint fp;
+        footprint(A.x, A.y, A.z, A.w, cop[g].x, support_span(qsup[g]), tiles_y, fp);
+        uint32_t pos = off;
+        for (int ty = fp.ty0; ty <= fp.ty1; ++ty) {
+          int tx0, tx1;
+          if (!row_span(fp, ty, tiles_x, tx0, tx1)) continue;
+          for (int tx = tx0; tx <= tx1; ++tx) win.put(pos++, (uint32_t)(ty * tiles_x + tx), g);
         }
       }
-      base += total;
+      // large footprints that do not fill their rectangle, one at a time per wave
+      unsigned long long big = big_all;
+      while (big) {
+        const int src = __ffsll((long long)big) - 1;
+        big &= big - 1;
+        const uint32_t os = __shfl(off, src, 64);
+        const uint32_t cs = __shfl(c, src, 64);
+        if (!win.meets(os, os + cs)) continue;
+        const uint32_t gs = __shfl(g, src, 64);
+        const float4 A = xyab[gs];
+        Footprint fp;
+        footprint(A.x, A.y, A.z, A.w, cop[gs].x, support_span(qsup[gs]), tiles_y, fp);
+        const int nrows = fp.ty1 - fp.ty0 + 1;
+        uint32_t base = os;
+        for (int rb = 0; rb < nrows; rb += 64) {
+          const int ty = fp.ty0 + rb + lane;
+          int tx0 = 0, tx1 = -1;
+          if (rb + lane < nrows) row_span(fp, ty, tiles_x, tx0, tx1);
+          const uint32_t wr = (uint32_t)(tx1 - tx0 + 1);
+          const uint32_t incl = wave_incl_scan(wr);
+          const uint32_t total = __shfl(incl, 63, 64);
+          const uint32_t first = (uint32_t)(ty * tiles_x + tx0);
+          for (uint32_t v0 = 0; v0 < total; v0 += 64) {
+            const uint32_t v = min(v0 + (uint32_t)lane, total - 1u);
+            const int o = owner_lane(incl, v);
+            const uint32_t t = v - (__shfl(incl, o, 64) - __shfl(wr, o, 64));
+            const uint32_t tile = __shfl(first, o, 64) + t;
+            if (v0 + (uint32_t)lane < total) win.put(base + v, tile, gs);
+          }
+          base += total;
+        }
+      }
     }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < win.w1 - win.w0; i += kBlock) {
+      tile_ids[obase + w0 + i] = s_tile[i];
+      values[obase + w0 + i] = s_val[i];
+    }
+    __syncthreads();
   }
 }
 
