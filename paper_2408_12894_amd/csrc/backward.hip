@@ -142,6 +142,10 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       float gr[kG2d];
 #pragma unroll
       for (int c = 0; c < kG2d; ++c) gr[c] = 0.0f;
+      // a lane's pixels share their column, so the q-derivatives need only the sums of dq,
+      // dq dy and dq dy^2 over them: dL/d(a, b, c) = (dx^2 S0, 2 dx S1, S2) and
+      // dL/dmu' = -2 (a dx S0 + b S1, b dx S0 + c S1)
+      float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         const bool ok = okv[k];
@@ -157,12 +161,16 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         T[k] = ok ? Ti64 : T[k];
         gr[5] = fmaf(dalpha, G, gr[5]);
         const float dq = -0.5f * alpha * dalpha;
-        gr[2] = fmaf(dq * dx, dx, gr[2]);
-        gr[3] = fmaf(dq * 2.0f * dx, dy, gr[3]);
-        gr[4] = fmaf(dq * dy, dy, gr[4]);
-        gr[0] = fmaf(dq, -2.0f * (A.z * dx + A.w * dy), gr[0]);
-        gr[1] = fmaf(dq, -2.0f * (A.w * dx + B.x * dy), gr[1]);
+        const float dqy = dq * dy;
+        S0 += dq;
+        S1 += dqy;
+        S2 = fmaf(dqy, dy, S2);
       }
+      gr[2] = dx * dx * S0;
+      gr[3] = 2.0f * dx * S1;
+      gr[4] = S2;
+      gr[0] = -2.0f * (A.z * dx * S0 + A.w * S1);
+      gr[1] = -2.0f * (A.w * dx * S0 + B.x * S1);
       {
         // nine in-row DPP reductions (interleaved, no control flow between them) leave each
         // row's sums in all its lanes; lane 16 r + c keeps component c, two cross-row
