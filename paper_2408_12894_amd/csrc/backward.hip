@@ -203,90 +203,24 @@ hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const f
 
 // ---------------------------------------------------------------------------------------
 
-// Colour part of the preprocess backward: dL/dSH and the view-direction term of dL/dmean
-// (written to d_means, which the geometry part then adds to). FP32, as the colour is not on
-// the key path. The SH row is streamed twice (colour, then gradients) as 12 dwordx4 loads so
-// that no 48-entry arrays stay live.
-__global__ __launch_bounds__(kBlock) void k_preprocess_bwd_sh(PreParams p, const uint32_t *__restrict__ tiles,
-                                                              const float *__restrict__ g2d, flod_grads out) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const DevLevel L = p.lv[0];
-  if (i >= L.n) return;
-  float4 *dsh = reinterpret_cast<float4 *>(out.d_sh + i * (FLOD_SH_COEFFS * 3));
-  if (tiles[i] == 0u) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) out.d_means[i * 3 + k] = 0.f;
-#pragma unroll
-    for (int k = 0; k < 12; ++k) dsh[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    return;
-  }
-  const DevCamera &cam = p.cam;
-  const int deg = p.sh_degree;
-  const int nk = (deg + 1) * (deg + 1);
-  const float m0 = L.means[i * 3 + 0], m1 = L.means[i * 3 + 1], m2 = L.means[i * 3 + 2];
-  const float vx = m0 - cam.campos[0], vy = m1 - cam.campos[1], vz = m2 - cam.campos[2];
-  const float nv = sqrtf((vx * vx + vy * vy) + vz * vz);
-  const float inv = 1.0f / nv;
-  const float x = vx * inv, y = vy * inv, z = vz * inv;
-  float Y[16], Gx[16], Gy[16], Gz[16];
-  sh_basis(deg, x, y, z, Y);
-  sh_basis_grad(deg, x, y, z, Gx, Gy, Gz);
-  const float4 *shv = reinterpret_cast<const float4 *>(L.sh + i * (FLOD_SH_COEFFS * 3));
-  float acc[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int q = 0; q < 12; ++q) {
-    const float4 v = shv[q];
-    const float e[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int el = 4 * q + u, k = el / 3, ch = el % 3;
-      if (k < nk) acc[ch] = fmaf(e[u], Y[k], acc[ch]);
-    }
-  }
-  float gcol[3];
-#pragma unroll
-  for (int ch = 0; ch < 3; ++ch) gcol[ch] = (acc[ch] + 0.5f < 0.0f) ? 0.0f : g2d[i * kG2d + 6 + ch];
-  float gdx = 0.f, gdy = 0.f, gdz = 0.f;
-#pragma unroll
-  for (int q = 0; q < 12; ++q) {
-    const float4 v = shv[q];
-    const float e[4] = {v.x, v.y, v.z, v.w};
-    float o4[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int el = 4 * q + u, k = el / 3, ch = el % 3;
-      const bool on = k < nk;
-      o4[u] = on ? gcol[ch] * Y[k] : 0.0f;
-      if (on) {
-        gdx += gcol[ch] * e[u] * Gx[k];
-        gdy += gcol[ch] * e[u] * Gy[k];
-        gdz += gcol[ch] * e[u] * Gz[k];
-      }
-    }
-    dsh[q] = make_float4(o4[0], o4[1], o4[2], o4[3]);
-  }
-  const float dd = x * gdx + y * gdy + z * gdz;
-  out.d_means[i * 3 + 0] = (gdx - x * dd) * inv;
-  out.d_means[i * 3 + 1] = (gdy - y * dd) * inv;
-  out.d_means[i * 3 + 2] = (gdz - z * dd) * inv;
-}
-
 __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const uint32_t *__restrict__ tiles,
                                                            const float *__restrict__ g2d,
                                                            flod_grads out) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const DevLevel L = p.lv[0];
   if (i >= L.n) return;
+  float *dsh = out.d_sh + i * (FLOD_SH_COEFFS * 3);
   if (tiles[i] == 0u) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) out.d_log_scales[i * 3 + k] = 0.f;
+    for (int k = 0; k < 3; ++k) { out.d_means[i * 3 + k] = 0.f; out.d_log_scales[i * 3 + k] = 0.f; }
     reinterpret_cast<float4 *>(out.d_quats)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     out.d_opacity_logits[i] = 0.f;
-    return;   // d_means and d_sh were zeroed by the colour part
+    for (int k = 0; k < 12; ++k) reinterpret_cast<float4 *>(dsh)[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
   }
-  double g[6];
+  double g[kG2d];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) g[c] = (double)g2d[i * kG2d + c];
+  for (int c = 0; c < kG2d; ++c) g[c] = (double)g2d[i * kG2d + c];
   const float m0 = L.means[i * 3 + 0], m1 = L.means[i * 3 + 1], m2 = L.means[i * 3 + 2];
   float ls[3] = {L.log_scales[i * 3 + 0], L.log_scales[i * 3 + 1], L.log_scales[i * 3 + 2]};
   const float4 q4 = reinterpret_cast<const float4 *>(L.quats)[i];
@@ -364,9 +298,52 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
 #pragma unroll
   for (int k = 0; k < 3; ++k) gm[k] = Rc[k] * gtx + Rc[3 + k] * gty + Rc[6 + k] * gtz;
 
-  // view-direction term of the colour, computed by the colour part
+  // colour -> SH coefficients and view direction (FP32: colour is not on the key path)
+  {
+    const int deg = p.sh_degree;
+    const int nk = (deg + 1) * (deg + 1);
+    const float vx = m0 - cam.campos[0], vy = m1 - cam.campos[1], vz = m2 - cam.campos[2];
+    const float nv = sqrtf((vx * vx + vy * vy) + vz * vz);
+    const float inv = 1.0f / nv;
+    const float x = vx * inv, y = vy * inv, z = vz * inv;
+    float Y[16], Gx[16], Gy[16], Gz[16];
+    sh_basis(deg, x, y, z, Y);
+    sh_basis_grad(deg, x, y, z, Gx, Gy, Gz);
+    const float4 *shv = reinterpret_cast<const float4 *>(L.sh + i * (FLOD_SH_COEFFS * 3));
+    float sh[48];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) gm[k] += (double)out.d_means[i * 3 + k];
+    for (int k = 0; k < 12; ++k) {
+      float4 v = shv[k];
+      sh[4 * k + 0] = v.x; sh[4 * k + 1] = v.y; sh[4 * k + 2] = v.z; sh[4 * k + 3] = v.w;
+    }
+    float gsh[48];
+    float gdx = 0.f, gdy = 0.f, gdz = 0.f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < nk) acc = fmaf(sh[k * 3 + ch], Y[k], acc);
+      const float gcol = (acc + 0.5f < 0.0f) ? 0.0f : (float)g[6 + ch];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const bool on = k < nk;
+        gsh[k * 3 + ch] = on ? gcol * Y[k] : 0.0f;
+        if (on) {
+          gdx += gcol * sh[k * 3 + ch] * Gx[k];
+          gdy += gcol * sh[k * 3 + ch] * Gy[k];
+          gdz += gcol * sh[k * 3 + ch] * Gz[k];
+        }
+      }
+    }
+    const float dd = x * gdx + y * gdy + z * gdz;
+    gm[0] += (double)((gdx - x * dd) * inv);
+    gm[1] += (double)((gdy - y * dd) * inv);
+    gm[2] += (double)((gdz - z * dd) * inv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+      reinterpret_cast<float4 *>(dsh)[k] = make_float4(gsh[4 * k], gsh[4 * k + 1], gsh[4 * k + 2], gsh[4 * k + 3]);
+  }
 
   // Sigma = M M^T, M = R diag(s): gM = Gs M
   double M[9];
@@ -410,8 +387,6 @@ hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, cons
                                  const flod_grads &g, hipStream_t s) {
   const int64_t n = p.lv[0].n;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_preprocess_bwd_sh, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, tiles,
-                     g2d, g);
   hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, tiles,
                      g2d, g);
   return hipGetLastError();
