@@ -161,20 +161,32 @@ def main():
         render.l1_loss(img, targets[i % len(cams)], renderer=r).backward()
 
     log("fwd+bwd step")
+    # warm-up with every stage timed, to find the dominant kernel
+    r.set_timing(True)
+    r.stage_times(reset=True)
     for i in range(args.warmup):
         train_step(i)
     sync()
-    r.set_timing(True)
-    r.stage_times(reset=True)
+    warm = r.stage_times(reset=True)
+    dom = max((k for k, (ms, c) in warm.items() if c), key=lambda k: warm[k][0] / warm[k][1])
+    # timed steps: HIP events only around the dominant kernel (each recorded stage adds two
+    # event records to the stream, which would otherwise inflate the step)
+    r.set_timing(True, stages=[dom])
     t0 = time.perf_counter()
     for i in range(args.steps):
         train_step(i)
     sync()
     t1 = time.perf_counter()
-    stage = r.stage_times(reset=True)
-    r.set_timing(False)
+    dom_live = r.stage_times(reset=True)[dom]
     ms_step = (t1 - t0) * 1e3 / args.steps
     iters_s = 1e3 / ms_step
+    # per-stage breakdown from separate steps with every stage timed
+    r.set_timing(True)
+    for i in range(min(args.steps, 16)):
+        train_step(i)
+    sync()
+    stage = r.stage_times(reset=True)
+    r.set_timing(False)
 
     # workload counts per camera (K, visible, pairs walked and blended)
     Ks, vis, walk, blended = [], [], [], []
@@ -194,8 +206,7 @@ def main():
     per_stage = {k: {"ms": ms / c} for k, (ms, c) in stage.items() if c}
     for k, v in per_stage.items():
         v["GBs_algorithmic"] = algorithmic_bytes(k, N, n_vis, K, P, tiles) / (v["ms"] * 1e-3) / 1e9
-    dom = max(per_stage, key=lambda k: per_stage[k]["ms"])
-    dom_ms = per_stage[dom]["ms"]
+    dom_ms = dom_live[0] / dom_live[1]        # live, inside the timed steps
     if dom in ("blend", "blend_bwd"):
         per_pair = FLOPS_BLEND_BWD if dom == "blend_bwd" else FLOPS_BLEND_FWD
         flops = FLOPS_EVAL * Pi_walk + per_pair * Pi_blend

@@ -278,7 +278,11 @@ enum {
   FLOD_STAGE_PREPROCESS_BWD,  /* chain rule to the 3D attributes                     */
   FLOD_NUM_STAGES
 };
+/* enable != 0 records every stage. */
 flod_status flod_ctx_set_timing(flod_ctx *ctx, int enable);
+/* Record only the stages whose bit (1 << FLOD_STAGE_...) is set; 0 turns timing off. Each
+   recorded stage adds two event records to the stream. */
+flod_status flod_ctx_set_timing_stages(flod_ctx *ctx, unsigned int stage_mask);
 /* Accumulated milliseconds and call counts per stage since the last reset; synchronises
    on the last recorded events. ms and calls: host arrays of FLOD_NUM_STAGES. */
 flod_status flod_ctx_stage_times(flod_ctx *ctx, double *ms, int64_t *calls, int reset);

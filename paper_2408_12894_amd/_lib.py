@@ -24,7 +24,7 @@ STAGES = ("preprocess", "compact", "depth_sort", "offsets", "emit", "tile_sort",
 
 EXPORTS = ("flod_ctx_create", "flod_ctx_destroy", "flod_ctx_workspace_bytes", "flod_ctx_required_bytes",
            "flod_ctx_trim", "flod_render_level", "flod_render_selective", "flod_render_backward",
-           "flod_ctx_stats", "flod_ctx_view", "flod_ctx_set_timing", "flod_ctx_stage_times",
+           "flod_ctx_stats", "flod_ctx_view", "flod_ctx_set_timing", "flod_ctx_set_timing_stages", "flod_ctx_stage_times",
            "flod_stage_name", "flod_smin", "flod_dproj", "flod_status_str", "flod_copy_to_host",
            "flod_render_merged", "flod_select_compact", "flod_overlap_prune", "flod_compact_level",
            "flod_level_transition", "flod_l1_ssim_forward", "flod_l1_ssim_backward",
@@ -132,6 +132,8 @@ def load():
     L.flod_ctx_view.restype = C.c_int
     L.flod_ctx_set_timing.argtypes = [vp, C.c_int]
     L.flod_ctx_set_timing.restype = C.c_int
+    L.flod_ctx_set_timing_stages.argtypes = [vp, C.c_uint]
+    L.flod_ctx_set_timing_stages.restype = C.c_int
     L.flod_ctx_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
     L.flod_ctx_stage_times.restype = C.c_int
     L.flod_stage_name.argtypes = [C.c_int]

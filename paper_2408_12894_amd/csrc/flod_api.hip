@@ -53,6 +53,8 @@ struct flod_ctx {
   flod_stats stats{};
   // timing
   bool timing = false;
+  uint32_t timing_mask = 0;           // stages recorded when timing is on
+  hipEvent_t ev_sync = nullptr;       // marks the instance-count read-back
   hipEvent_t ev[FLOD_NUM_STAGES][2];
   bool ev_pending[FLOD_NUM_STAGES];
   double ms[FLOD_NUM_STAGES];
@@ -124,7 +126,7 @@ struct StageTimer {
   int stage = -1;
   StageTimer(flod_ctx *c_, hipStream_t s_) : c(c_), s(s_) {}
   void begin(int k) {
-    if (!c->timing) return;
+    if (!c->timing || !((c->timing_mask >> k) & 1u)) return;
     stage = k;
     (void)hipEventRecord(c->ev[k][0], s);
   }
@@ -135,6 +137,22 @@ struct StageTimer {
     stage = -1;
   }
 };
+
+// Wait until the work enqueued on s so far has finished: poll an event (a few microseconds
+// of wake-up instead of a blocking wait's), falling back to a blocking wait after ~2 ms.
+hipError_t wait_for_stream(flod_ctx *c, hipStream_t s) {
+  if (!c->ev_sync && hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming) != hipSuccess) {
+    c->ev_sync = nullptr;
+    return hipStreamSynchronize(s);
+  }
+  hipError_t e = hipEventRecord(c->ev_sync, s);
+  if (e != hipSuccess) return e;
+  for (int spin = 0; spin < 20000; ++spin) {
+    e = hipEventQuery(c->ev_sync);
+    if (e != hipErrorNotReady) return e;
+  }
+  return hipEventSynchronize(c->ev_sync);
+}
 
 int ceil_log2(int64_t v) {
   int b = 0;
@@ -264,7 +282,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     // the one host synchronisation: instance count to size the sort
     if (hipMemcpyAsync(c->host_counters, counters, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
       return FLOD_ERR_DEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return FLOD_ERR_DEVICE;
+    if (wait_for_stream(c, s) != hipSuccess) return FLOD_ERR_DEVICE;
     tm.end();
     const uint32_t *hc = reinterpret_cast<const uint32_t *>(c->host_counters);
     n_vis = hc[kCntVisible];
@@ -385,6 +403,7 @@ void flod_ctx_destroy(flod_ctx *ctx) {
       (void)hipEventDestroy(ctx->ev[k][0]);
       (void)hipEventDestroy(ctx->ev[k][1]);
     }
+  if (ctx->ev_sync) (void)hipEventDestroy(ctx->ev_sync);
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
   delete ctx;
 }
@@ -835,7 +854,12 @@ flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out) {
 }
 
 flod_status flod_ctx_set_timing(flod_ctx *ctx, int enable) {
+  return flod_ctx_set_timing_stages(ctx, enable ? ((1u << FLOD_NUM_STAGES) - 1u) : 0u);
+}
+
+flod_status flod_ctx_set_timing_stages(flod_ctx *ctx, unsigned int stage_mask) {
   if (!ctx) return FLOD_ERR_INVALID_ARG;
+  const int enable = stage_mask != 0u;
   if (enable && !ctx->events_made) {
     if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
     for (int k = 0; k < FLOD_NUM_STAGES; ++k) {
@@ -845,6 +869,7 @@ flod_status flod_ctx_set_timing(flod_ctx *ctx, int enable) {
     ctx->events_made = true;
   }
   ctx->timing = enable != 0;
+  ctx->timing_mask = stage_mask;
   return FLOD_OK;
 }
 

@@ -71,6 +71,16 @@ def _floats(vals, n):
     return arr
 
 
+def _stage_index(L, name: str) -> int:
+    for k in range(32):
+        n = L.flod_stage_name(k).decode()
+        if n == "unknown":
+            break
+        if n == name:
+            return k
+    raise ValueError(f"unknown stage {name!r}")
+
+
 def _stream_ptr(stream) -> int:
     s = stream if stream is not None else torch.cuda.current_stream()
     return int(s.cuda_stream)
@@ -275,8 +285,16 @@ class Renderer:
     def trim(self, stream=None):
         _lib.check(self.L.flod_ctx_trim(self.ctx, C.c_void_p(_stream_ptr(stream))), "flod_ctx_trim")
 
-    def set_timing(self, on: bool):
-        _lib.check(self.L.flod_ctx_set_timing(self.ctx, int(bool(on))), "flod_ctx_set_timing")
+    def set_timing(self, on: bool, stages=None):
+        """Per-stage device timing; `stages` (names) restricts it to those stages."""
+        if stages is None:
+            _lib.check(self.L.flod_ctx_set_timing(self.ctx, int(bool(on))), "flod_ctx_set_timing")
+            return
+        mask = 0
+        if on:
+            for name in stages:
+                mask |= 1 << _stage_index(self.L, name)
+        _lib.check(self.L.flod_ctx_set_timing_stages(self.ctx, mask), "flod_ctx_set_timing_stages")
 
     def stage_times(self, reset: bool = False) -> dict:
         ms = (C.c_double * _lib.NUM_STAGES)()
