@@ -1,10 +1,8 @@
 // Front-to-back alpha compositing (Preliminary section: eq. 2 and blending in depth order).
 //
 // One workgroup per 16x16 tile with PPT pixels per thread: thread t owns the pixels
-// (t % 16, PPT (t / 16) + k), k < PPT, so each list entry staged in LDS is read once per
-// thread and applied to PPT pixels, and each wave owns a band of 64 PPT / 16 whole rows: an
-// entry whose support ellipse cannot reach the band's rows (its vertical reach is staged
-// with it) is skipped by the whole wave. The tile's
+// (t % 16, t / 16 + (256 / PPT / 16) k), k < PPT, so each list entry staged in LDS is read
+// once per thread and applied to PPT pixels. The tile's
 // sorted list is consumed in batches of 256 entries (40 bytes each: mu' and its residual,
 // conic, opacity, colour). Per pixel:
 //   q = d^T conic d (d = pixel centre - mu', formed as (centre - hi) - lo); skip if q > 9
@@ -30,26 +28,23 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
                                                               const uint32_t *__restrict__ values,
                                                               const float4 *__restrict__ xyab,
                                                               const float4 *__restrict__ cop,
-                                                              const float2 *__restrict__ blue,
-                                                              const float2 *__restrict__ yext, int W, int H,
+                                                              const float2 *__restrict__ blue, int W, int H,
                                                               int tiles_x, int n_tiles, float bg0, float bg1,
                                                               float bg2, float *__restrict__ image,
                                                               float *__restrict__ final_T,
                                                               int32_t *__restrict__ n_contrib,
                                                               int32_t *__restrict__ n_blended) {
   constexpr int NT = kTile * kTile / PPT;   // threads per tile
+  constexpr int ROWS = NT / kTile;          // pixel rows covered by one pass of the threads
   __shared__ float4 s_a[kBatch];
   __shared__ float4 s_b[kBatch];
   __shared__ float2 s_c[kBatch];
-  __shared__ float2 s_y[kBatch];
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   if (tile >= n_tiles) return;
   const int tid = threadIdx.x;
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
   const int px = x0 + (tid & (kTile - 1));
   const float fx = (float)px + 0.5f;
-  // this wave's band of rows (pixel centres)
-  const float band_lo = (float)(y0 + 4 * PPT * (tid >> 6)) + 0.5f, band_hi = band_lo + (float)(4 * PPT - 1);
   float fy[PPT];
   bool inside[PPT];
   double T[PPT];
@@ -58,7 +53,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
   bool done[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int py = y0 + PPT * (tid >> 4) + k;
+    const int py = y0 + (tid >> 4) + ROWS * k;
     fy[k] = (float)py + 0.5f;
     inside[k] = px < W && py < H;
     T[k] = 1.0; C0[k] = 0.0f; C1[k] = 0.0f; C2[k] = 0.0f;
@@ -84,7 +79,6 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
         s_a[e] = xyab[g];
         s_b[e] = cop[g];
         s_c[e] = blue[g];
-        s_y[e] = yext[g];
       }
     }
     __syncthreads();
@@ -96,8 +90,6 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
 #pragma unroll
       for (int k = 0; k < PPT; ++k) any_live = any_live || !done[k];
       if (!any_live) break;
-      const float2 YR = s_y[j];
-      if (YR.y < band_lo || YR.x > band_hi) continue;   // cannot reach this wave's rows
       const float4 A = s_a[j];
       const float4 B = s_b[j];
       const float2 BL = s_c[j];
@@ -132,7 +124,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     if (!inside[k]) continue;
-    const size_t pix = (size_t)(y0 + PPT * (tid >> 4) + k) * W + px;
+    const size_t pix = (size_t)(y0 + (tid >> 4) + ROWS * k) * W + px;
     const float Tf = (float)T[k];
     image[pix] = fmaf(Tf, bg0, C0[k]);
     image[plane + pix] = fmaf(Tf, bg1, C1[k]);
@@ -144,14 +136,14 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
 }
 
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
-                        const float2 *blue, const float2 *yext, const DevCamera &cam, const float bg[3], float *image, float *final_T,
+                        const float2 *blue, const DevCamera &cam, const float bg[3], float *image, float *final_T,
                         int32_t *n_contrib, int32_t *n_blended, hipStream_t s) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   const int grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
   // 2 pixels per thread (2 waves per tile) measured fastest at 1080p: 0.51 ms against 0.59 ms
   // with 1 and 0.74 ms with 4 on the 1M-Gaussian frame.
   hipLaunchKernelGGL(k_blend<kFwdPix>, dim3(grid), dim3(kTile * kTile / kFwdPix), 0, s, ranges, values, xyab, cop,
-                     blue, yext, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], image, final_T, n_contrib,
+                     blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], image, final_T, n_contrib,
                      n_blended);
   return hipGetLastError();
 }

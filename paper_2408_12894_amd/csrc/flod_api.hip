@@ -20,7 +20,7 @@ enum BufId {
   B_XYAB, B_COP, B_BLUE, B_DEPTH, B_RECT, B_TILES, B_BLOCKVIS, B_PREFIX,
   B_DKEY0, B_DKEY1, B_DVAL0, B_DVAL1, B_TBSUM, B_TPREFIX,
   B_TKEY0, B_TKEY1, B_TVAL0, B_TVAL1, B_HIST, B_SCAN, B_TOT, B_RANGES, B_COUNTERS,
-  B_G2D, B_SSIM, B_QSUP, B_YEXT, B_COUNT
+  B_G2D, B_SSIM, B_QSUP, B_COUNT
 };
 
 struct Saved {
@@ -222,7 +222,6 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   need(B_RECT, 8 * (size_t)N);
   need(B_TILES, 4 * (size_t)N);
   need(B_QSUP, 4 * (size_t)N);
-  need(B_YEXT, 8 * (size_t)N);
   need(B_BLOCKVIS, 4 * (size_t)nb);
   need(B_PREFIX, 8 * (size_t)nb);
   need(B_DKEY0, 4 * (size_t)N);
@@ -253,7 +252,6 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     o.rect = P<uint2>(c, B_RECT);
     o.tiles = P<uint32_t>(c, B_TILES);
     o.qsup = P<float>(c, B_QSUP);
-    o.yext = P<float2>(c, B_YEXT);
     o.block_vis = P<uint32_t>(c, B_BLOCKVIS);
     o.n_selected = reinterpret_cast<unsigned long long *>(n_selected);
     tm.begin(FLOD_STAGE_PREPROCESS);
@@ -340,7 +338,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   tm.end();
   tm.begin(FLOD_STAGE_BLEND);
   if (launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP), P<float2>(c, B_BLUE),
-                   P<float2>(c, B_YEXT), cam, bg, out->image, out->final_T, out->n_contrib, out->n_blended, s) != hipSuccess)
+                   cam, bg, out->image, out->final_T, out->n_contrib, out->n_blended, s) != hipSuccess)
     return FLOD_ERR_DEVICE;
   tm.end();
   Saved &sv = c->saved;

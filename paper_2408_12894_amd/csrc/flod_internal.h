@@ -61,7 +61,6 @@ struct PreOut {
   float4 *xyab;       // mu'x, mu'y, conic a, conic b
   float4 *cop;        // conic c, opacity, red, green
   float2 *blue;       // blue, packed bf16 residuals of mu' (bits)
-  float2 *yext;       // rows the support can reach: [my - hy - 1, my + hy + 1] (pixel units)
   uint32_t *depth;    // FP32 bits of the view-space depth
   uint2 *rect;        // (x0 | y0 << 16, x1 | y1 << 16)
   uint32_t *tiles;    // tiles touched, 0 when culled or not selected
@@ -100,7 +99,7 @@ hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_
 hipError_t launch_ranges(const uint32_t *tile_ids, int64_t K, int n_tiles, uint2 *ranges,
                          hipStream_t s);
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
-                        const float4 *cop, const float2 *blue, const float2 *yext, const DevCamera &cam,
+                        const float4 *cop, const float2 *blue, const DevCamera &cam,
                         const float bg[3], float *image, float *final_T, int32_t *n_contrib,
                         int32_t *n_blended, hipStream_t s);
 hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab,

@@ -86,9 +86,6 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreParams p, PreOut o) {
             o.depth[i] = __float_as_uint((float)pr.tz);
             o.rect[i] = make_uint2(rx0 | ((uint32_t)fp.ty0 << 16), rx1 | ((uint32_t)fp.ty1 << 16));
             o.qsup[i] = qg;
-            // vertical reach of the support ellipse, widened by a pixel so that FP32 rounding
-            // can only make it larger
-            o.yext[i] = make_float2((float)(fp.my - fp.hy) - 1.0f, (float)(fp.my + fp.hy) + 1.0f);
           }
         }
       }
