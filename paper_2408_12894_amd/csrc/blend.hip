@@ -21,7 +21,7 @@
 
 namespace flod {
 
-constexpr int kFwdPix = 2;
+constexpr int kFwdPix = 1;
 
 template <int PPT>
 __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__restrict__ ranges,
@@ -140,8 +140,8 @@ hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float
                         int32_t *n_contrib, int32_t *n_blended, hipStream_t s) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   const int grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
-  // 2 pixels per thread (2 waves per tile) measured fastest at 1080p: 0.51 ms against 0.59 ms
-  // with 1 and 0.74 ms with 4 on the 1M-Gaussian frame.
+  // 1 pixel per thread (4 waves per tile) measured fastest at 1080p / 1M with the entry loop
+  // unrolled by two: 0.218 ms against 0.242 ms with 2 and 0.353 ms with 4.
   hipLaunchKernelGGL(k_blend<kFwdPix>, dim3(grid), dim3(kTile * kTile / kFwdPix), 0, s, ranges, values, xyab, cop,
                      blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], image, final_T, n_contrib,
                      n_blended);
