@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ values, const float4 *__restrict__ xyab,
     const float4 *__restrict__ cop, const float2 *__restrict__ blue, int W, int H, int tiles_x, int n_tiles,
     float bg0, float bg1, float bg2, const float *__restrict__ final_T, const int32_t *__restrict__ n_contrib,
-    const float *__restrict__ dimg, float *__restrict__ g2d) {
+    const float *__restrict__ dimg, float *__restrict__ g2d, const uint8_t *__restrict__ taken) {
   constexpr int NT = kTile * kTile / PPT;
   constexpr int ROWS = NT / kTile;
   constexpr int WAVES = NT / 64;
@@ -63,6 +63,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   __shared__ float4 s_b[kBwdBatch];
   __shared__ float2 s_c[kBwdBatch];
   __shared__ uint32_t s_id[kBwdBatch];
+  __shared__ int s_pos[kBwdBatch];
   __shared__ int s_max[WAVES];
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   if (tile >= n_tiles) return;
@@ -101,20 +102,37 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
     for (int w = 0; w < WAVES; ++w) mylast = max(mylast, s_max[w]);
   }
   const uint2 rg = ranges[tile];
+  const unsigned long long lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int end = mylast; end > 0; end -= kBwdBatch) {
     const int start = max(0, end - kBwdBatch);
     const int cnt = end - start;
     __syncthreads();
-    for (int e = tid; e < cnt; e += NT) {
-      const uint32_t g = values[rg.x + start + e];
-      s_id[e] = g;
-      s_a[e] = xyab[g];
-      s_b[e] = cop[g];
-      s_c[e] = blue[g];
+    // stage only the entries the forward blended into some pixel of the tile (its taken
+    // flags), compacted in list order: the others change no T, no suffix and no gradient
+    int cntc = 0;
+    for (int e0 = 0; e0 < cnt; e0 += NT) {
+      const int e = e0 + tid;
+      const bool f = e < cnt && (NT != 64 || taken[rg.x + start + e] != 0);
+      int idx = e;
+      if (NT == 64) {
+        const unsigned long long m = __ballot(f);
+        idx = cntc + (int)__popcll(m & lanes_below);
+        cntc += (int)__popcll(m);
+      } else {
+        cntc = cnt;
+      }
+      if (f) {
+        const uint32_t g = values[rg.x + start + e];
+        s_id[idx] = g;
+        s_pos[idx] = start + e;
+        s_a[idx] = xyab[g];
+        s_b[idx] = cop[g];
+        s_c[idx] = blue[g];
+      }
     }
     __syncthreads();
-    for (int jl = cnt - 1; jl >= 0; --jl) {
-      const int jpos = start + jl;
+    for (int jl = cntc - 1; jl >= 0; --jl) {
+      const int jpos = s_pos[jl];
       const float4 A = s_a[jl];
       const float4 B = s_b[jl];
       const float2 BL = s_c[jl];
@@ -191,13 +209,13 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
 
 hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
                             const float2 *blue, const DevCamera &cam, const float bg[3], const float *final_T,
-                            const int32_t *n_contrib, const float *dL_dimage, float *g2d,
+                            const int32_t *n_contrib, const float *dL_dimage, float *g2d, const uint8_t *taken,
                             hipStream_t s) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   const int grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
   hipLaunchKernelGGL(k_blend_bwd<kBwdPix>, dim3(grid), dim3(kTile * kTile / kBwdPix), 0, s, ranges, values, xyab,
                      cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib,
-                     dL_dimage, g2d);
+                     dL_dimage, g2d, taken);
   return hipGetLastError();
 }
 

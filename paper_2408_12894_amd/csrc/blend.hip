@@ -33,12 +33,14 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
                                                               float bg2, float *__restrict__ image,
                                                               float *__restrict__ final_T,
                                                               int32_t *__restrict__ n_contrib,
-                                                              int32_t *__restrict__ n_blended) {
+                                                              int32_t *__restrict__ n_blended,
+                                                              uint8_t *__restrict__ taken) {
   constexpr int NT = kTile * kTile / PPT;   // threads per tile
   constexpr int ROWS = NT / kTile;          // pixel rows covered by one pass of the threads
   __shared__ float4 s_a[kBatch];
   __shared__ float4 s_b[kBatch];
   __shared__ float2 s_c[kBatch];
+  __shared__ uint8_t s_taken[kBatch];
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   if (tile >= n_tiles) return;
   const int tid = threadIdx.x;
@@ -63,6 +65,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
   }
   const uint2 rg = ranges[tile];
   const int n = (int)(rg.y - rg.x);
+  int last_start = -1;   // start of the last batch walked
   for (int start = 0; start < n; start += kBatch) {
     bool all_done = true;
 #pragma unroll
@@ -72,6 +75,11 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
       __syncthreads();
     } else {
       if (__syncthreads_and(all_done)) break;
+    }
+    // the previous batch's taken flags leave (consecutive bytes), this batch's start at zero
+    for (int e = tid; e < kBatch; e += NT) {
+      if (start > 0) taken[rg.x + start - kBatch + e] = s_taken[e];
+      s_taken[e] = 0;
     }
     for (int e = tid; e < kBatch; e += NT) {
       if (start + e < n) {
@@ -118,9 +126,16 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
         T[k] = Tn;
         last[k] = start + j + 1;
         ++nbl[k];
+        s_taken[j] = 1;
       }
     }
+    last_start = start;
   }
+  // flags of the last batch walked (entries past the walk are never read by the backward,
+  // which stops at the last blended entry)
+  __syncthreads();
+  if (last_start >= 0)
+    for (int e = tid; e < kBatch && last_start + e < n; e += NT) taken[rg.x + last_start + e] = s_taken[e];
   const size_t plane = (size_t)W * H;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
@@ -138,14 +153,14 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
 
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
                         const float2 *blue, const DevCamera &cam, const float bg[3], float *image, float *final_T,
-                        int32_t *n_contrib, int32_t *n_blended, hipStream_t s) {
+                        int32_t *n_contrib, int32_t *n_blended, uint8_t *taken, hipStream_t s) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   const int grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
   // 1 pixel per thread (4 waves per tile) measured fastest at 1080p / 1M: 0.218 ms against
   // 0.242 ms with 2 and 0.353 ms with 4 (entry loop unrolled by two in that comparison).
   hipLaunchKernelGGL(k_blend<kFwdPix>, dim3(grid), dim3(kTile * kTile / kFwdPix), 0, s, ranges, values, xyab, cop,
                      blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], image, final_T, n_contrib,
-                     n_blended);
+                     n_blended, taken);
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ enum BufId {
   B_XYAB, B_COP, B_BLUE, B_DEPTH, B_RECT, B_TILES, B_BLOCKVIS, B_PREFIX,
   B_DKEY0, B_DKEY1, B_DVAL0, B_DVAL1, B_TBSUM, B_TPREFIX,
   B_TKEY0, B_TKEY1, B_TVAL0, B_TVAL1, B_HIST, B_SCAN, B_TOT, B_RANGES, B_COUNTERS,
-  B_G2D, B_SSIM, B_QSUP, B_COUNT
+  B_G2D, B_SSIM, B_QSUP, B_TAKEN, B_COUNT
 };
 
 struct Saved {
@@ -303,6 +303,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   need(B_TKEY1, 4 * (size_t)Kn);
   need(B_TVAL0, 4 * (size_t)Kn);
   need(B_TVAL1, 4 * (size_t)Kn);
+  need(B_TAKEN, (size_t)Kn + 4);
   if (nbk > nbs) {
     need(B_HIST, 4 * (size_t)kRadix * nbk);
     need(B_SCAN, 4 * (size_t)kRadix * nbk);
@@ -338,7 +339,8 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   tm.end();
   tm.begin(FLOD_STAGE_BLEND);
   if (launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP), P<float2>(c, B_BLUE),
-                   cam, bg, out->image, out->final_T, out->n_contrib, out->n_blended, s) != hipSuccess)
+                   cam, bg, out->image, out->final_T, out->n_contrib, out->n_blended, P<uint8_t>(c, B_TAKEN),
+                   s) != hipSuccess)
     return FLOD_ERR_DEVICE;
   tm.end();
   Saved &sv = c->saved;
@@ -811,7 +813,7 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   const uint32_t *vals = sv.sorted_vals ? P<uint32_t>(ctx, B_TVAL1) : P<uint32_t>(ctx, B_TVAL0);
   if (launch_blend_bwd(P<uint2>(ctx, B_RANGES), vals, P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
                        P<float2>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d,
-                       s) != hipSuccess)
+                       P<uint8_t>(ctx, B_TAKEN), s) != hipSuccess)
     return FLOD_ERR_DEVICE;
   tm.end();
   tm.begin(FLOD_STAGE_PREPROCESS_BWD);

@@ -101,11 +101,11 @@ hipError_t launch_ranges(const uint32_t *tile_ids, int64_t K, int n_tiles, uint2
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
                         const float4 *cop, const float2 *blue, const DevCamera &cam,
                         const float bg[3], float *image, float *final_T, int32_t *n_contrib,
-                        int32_t *n_blended, hipStream_t s);
+                        int32_t *n_blended, uint8_t *taken, hipStream_t s);
 hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
                             const float4 *cop, const float2 *blue, const DevCamera &cam,
                             const float bg[3], const float *final_T, const int32_t *n_contrib,
-                            const float *dL_dimage, float *g2d,
+                            const float *dL_dimage, float *g2d, const uint8_t *taken,
                             hipStream_t s);
 hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, const float *g2d,
                                  const flod_grads &g, hipStream_t s);
