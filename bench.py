@@ -51,7 +51,7 @@ FLOPS_BLEND_BWD = 46
 # step_1080p_1M_hbm_counters.md). A figure holds only for the kernel sources it was taken
 # with: the sha256 over the listed files must match, else the traffic is reported as null.
 PROFILED_TRAFFIC = {
-    "blend_bwd": {"bytes": 145772774, "sha256": "860acb7fd7006752c5a28fbaef88d6cee5869c7a20b30386300460b3e0153d96",
+    "blend_bwd": {"bytes": 138894152, "sha256": "02791e0157ef852eef1d20224e299b426860c76f4a22293f248f24499ec488d6",
                   "sources": ['paper_2408_12894_amd/csrc/backward.hip', 'paper_2408_12894_amd/csrc/blend_common.h', 'paper_2408_12894_amd/csrc/project.h', 'paper_2408_12894_amd/csrc/flod_internal.h']},
 }
 
