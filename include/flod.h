@@ -21,8 +21,13 @@
  * stay valid until the matching render_backward has run.
  *
  * Streams: `stream` is a hipStream_t (NULL = the legacy default stream). All work is
- * enqueued on it. Each render performs exactly one host synchronisation: a stream-ordered
- * read of the instance count (8 bytes) needed to size the sort buffers.
+ * enqueued on it. A render enqueues the whole frame before it waits for anything: the
+ * emission, tile sort and blend are sized for the instances the context's buffers hold and
+ * read the instance count K on the device, doing nothing when K exceeds that capacity. The
+ * host then waits for a stream-ordered 16-byte read of the counts (it completes once the
+ * binning offsets are known, while the rest of the frame is still queued), fills the
+ * statistics and, when K exceeded the capacity, grows the buffers and enqueues the frame's
+ * tail again. A context's first render, with no buffers yet, waits for K before the tail.
  *
  * Errors: no function throws or aborts. Arguments are validated before any launch; on
  * FLOD_ERR_INVALID_ARG the outputs are untouched. flod_status_str() describes a code.

@@ -138,15 +138,19 @@ struct StageTimer {
   }
 };
 
-// Wait until the work enqueued on s so far has finished: poll an event (a few microseconds
-// of wake-up instead of a blocking wait's), falling back to a blocking wait after ~2 ms.
-hipError_t wait_for_stream(flod_ctx *c, hipStream_t s) {
+// Mark the work enqueued on s so far; wait_marked() returns once it has finished.
+hipError_t mark_stream(flod_ctx *c, hipStream_t s) {
   if (!c->ev_sync && hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming) != hipSuccess) {
     c->ev_sync = nullptr;
-    return hipStreamSynchronize(s);
+    return hipErrorOutOfMemory;
   }
-  hipError_t e = hipEventRecord(c->ev_sync, s);
-  if (e != hipSuccess) return e;
+  return hipEventRecord(c->ev_sync, s);
+}
+
+// Poll the mark (a few microseconds of wake-up instead of a blocking wait's), falling back to
+// a blocking wait after ~20000 polls.
+hipError_t wait_marked(flod_ctx *c) {
+  hipError_t e = hipSuccess;
   for (int spin = 0; spin < 20000; ++spin) {
     e = hipEventQuery(c->ev_sync);
     if (e != hipErrorNotReady) return e;
@@ -194,7 +198,30 @@ DevCamera dev_camera(const flod_camera *cam) {
 
 float sq32(float d) { return isinf(d) ? INFINITY : (float)((double)d * (double)d); }
 
+// Instances the tail buffers (tile keys and values, both ping-pong halves, taken flags) hold.
+int64_t instance_capacity(const flod_ctx *c) {
+  size_t b = c->buf[B_TKEY0].cap;
+  for (BufId id : {B_TKEY1, B_TVAL0, B_TVAL1}) b = b < c->buf[id].cap ? b : c->buf[id].cap;
+  int64_t k = (int64_t)(b / 4);
+  const int64_t t = (int64_t)c->buf[B_TAKEN].cap - 4;
+  if (t < k) k = t;
+  if (k > 0xFFFFFFFEll) k = 0xFFFFFFFEll;
+  return k > 0 ? k : 0;
+}
+
+size_t hist_bytes(int64_t n_max) {
+  const int64_t tile = (int64_t)kBlock * radix_items(n_max);
+  return 4 * (size_t)kRadix * (size_t)((n_max + tile - 1) / tile);
+}
+
 // The forward pipeline over the candidate set described by p.
+//
+// The instance count K is known on the device only after the tile-count scan. The emission,
+// tile sort, ranges and blend that follow are enqueued at once, sized for the instances the
+// context's buffers hold (cap); the scan hands them K when K <= cap and 0 otherwise, in which
+// case they do nothing. Meanwhile the host reads K back (stream-ordered, 16 bytes) for the
+// statistics and the capacity check: when K > cap it grows the buffers and enqueues the scan's
+// count and the tail again. A context's first render (cap = 0) waits for K before enqueuing.
 flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const float bg[3],
                           flod_frame *out, hipStream_t s) {
   c->required = 0;
@@ -207,14 +234,14 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   const DevCamera &cam = p.cam;
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   const int nb = (int)((N + kBlock - 1) / kBlock);
-  const int64_t sort_tile_n = (int64_t)kBlock * radix_items(N);
-  const int nbs = (int)((N + sort_tile_n - 1) / sort_tile_n);
+  int64_t cap = instance_capacity(c);
   size_t extra = 0;
   flod_status st = FLOD_OK;
   auto need = [&](BufId id, size_t bytes) {
     flod_status r = ensure(c, id, bytes, s, &extra);
     if (r != FLOD_OK) st = r;
   };
+  const size_t hist = hist_bytes(N) > hist_bytes(cap) ? hist_bytes(N) : hist_bytes(cap);
   need(B_XYAB, 16 * (size_t)N);
   need(B_COP, 16 * (size_t)N);
   need(B_BLUE, 8 * (size_t)N);
@@ -230,8 +257,8 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   need(B_DVAL1, 4 * (size_t)N);
   need(B_TBSUM, 4 * (size_t)nb);
   need(B_TPREFIX, 8 * (size_t)nb);
-  need(B_HIST, 4 * (size_t)kRadix * nbs);
-  need(B_SCAN, 4 * (size_t)kRadix * nbs);
+  need(B_HIST, hist);
+  need(B_SCAN, hist);
   need(B_TOT, 4 * (size_t)kRadix);
   need(B_RANGES, 8 * (size_t)n_tiles);
   need(B_COUNTERS, 8 * (size_t)kCntSlots);
@@ -240,9 +267,15 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     return st;
   }
   uint32_t *counters = P<uint32_t>(c, B_COUNTERS);
-  int64_t n_vis = 0;
-  unsigned long long K = 0;
+  const bool speculate = N > 0 && cap > 0;
   int dres = 0;
+  // tile counts in depth order and their scan; K (guarded by `guard`) to counters[kCntInstances]
+  auto offsets = [&](int64_t guard) -> hipError_t {
+    return launch_scan_blocks(P<uint32_t>(c, B_TBSUM), counters + kCntVisible, kBlock,
+                              P<unsigned long long>(c, B_TPREFIX), counters + kCntInstances,
+                              reinterpret_cast<unsigned long long *>(counters + kCntTotal64), nb, s,
+                              (unsigned long long)guard);
+  };
   if (N > 0) {
     PreOut o;
     o.xyab = P<float4>(c, B_XYAB);
@@ -273,19 +306,54 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
       return FLOD_ERR_DEVICE;
     tm.end();
     tm.begin(FLOD_STAGE_OFFSETS);
-    if (launch_tile_counts(dv[dres], counters + kCntVisible, N, o.tiles, P<uint32_t>(c, B_TBSUM), s) != hipSuccess)
+    if (launch_tile_counts(dv[dres], counters + kCntVisible, N, o.tiles, P<uint32_t>(c, B_TBSUM), s) != hipSuccess ||
+        offsets(speculate ? cap : 0xFFFFFFFEll) != hipSuccess)
       return FLOD_ERR_DEVICE;
-    if (launch_scan_blocks(P<uint32_t>(c, B_TBSUM), counters + kCntVisible, kBlock,
-                           P<unsigned long long>(c, B_TPREFIX), counters + kCntInstances,
-                           reinterpret_cast<unsigned long long *>(counters + kCntTotal64), nb, s) != hipSuccess)
+    // the count read-back: [visible u32 | guarded K u32], [K u64]
+    if (hipMemcpyAsync(c->host_counters, counters, 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        mark_stream(c, s) != hipSuccess)
       return FLOD_ERR_DEVICE;
-    // the one host synchronisation: instance count to size the sort
-    if (hipMemcpyAsync(c->host_counters, counters, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
-      return FLOD_ERR_DEVICE;
-    if (wait_for_stream(c, s) != hipSuccess) return FLOD_ERR_DEVICE;
     tm.end();
-    const uint32_t *hc = reinterpret_cast<const uint32_t *>(c->host_counters);
-    n_vis = hc[kCntVisible];
+  }
+  int tres = 0;
+  // emission, tile sort, ranges and blend for at most k_max instances
+  auto tail = [&](int64_t k_max) -> flod_status {
+    uint32_t *tk[2] = {P<uint32_t>(c, B_TKEY0), P<uint32_t>(c, B_TKEY1)};
+    uint32_t *tv[2] = {P<uint32_t>(c, B_TVAL0), P<uint32_t>(c, B_TVAL1)};
+    tres = 0;
+    if (k_max > 0) {
+      uint32_t *dv = dres ? P<uint32_t>(c, B_DVAL1) : P<uint32_t>(c, B_DVAL0);
+      tm.begin(FLOD_STAGE_EMIT);
+      if (launch_emit(dv, counters + kCntVisible, counters + kCntInstances, N, P<uint32_t>(c, B_TILES),
+                      P<float4>(c, B_XYAB), P<float4>(c, B_COP), P<uint2>(c, B_RECT), P<float>(c, B_QSUP),
+                      P<unsigned long long>(c, B_TPREFIX), cam.tiles_x, cam.tiles_y, tk[0], tv[0], s) != hipSuccess)
+        return FLOD_ERR_DEVICE;
+      tm.end();
+      tm.begin(FLOD_STAGE_TILE_SORT);
+      const int bits = ceil_log2(n_tiles);
+      if (bits > 0 && launch_radix_sort(tk, tv, counters + kCntInstances, k_max, bits, P<uint32_t>(c, B_HIST),
+                                        P<uint32_t>(c, B_SCAN), P<uint32_t>(c, B_TOT), &tres, s) != hipSuccess)
+        return FLOD_ERR_DEVICE;
+      tm.end();
+    }
+    tm.begin(FLOD_STAGE_RANGES);
+    if (launch_ranges(tk[tres], counters + kCntInstances, k_max, n_tiles, P<uint2>(c, B_RANGES), s) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    tm.end();
+    tm.begin(FLOD_STAGE_BLEND);
+    if (launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP),
+                     P<float2>(c, B_BLUE), cam, bg, out->image, out->final_T, out->n_contrib, out->n_blended,
+                     P<uint8_t>(c, B_TAKEN), s) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    tm.end();
+    return FLOD_OK;
+  };
+  if (speculate && (st = tail(cap)) != FLOD_OK) return st;
+  int64_t n_vis = 0;
+  unsigned long long K = 0;
+  if (N > 0) {
+    if (wait_marked(c) != hipSuccess) return FLOD_ERR_DEVICE;
+    n_vis = reinterpret_cast<const uint32_t *>(c->host_counters)[kCntVisible];
     K = c->host_counters[1];
   }
   c->stats.n_candidates = N;
@@ -296,53 +364,27 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   c->stats.width = cam.W;
   c->stats.height = cam.H;
   if (K >= 0xFFFFFFFFull) return FLOD_ERR_OVERFLOW;
-  const int64_t Kn = (int64_t)K;
-  const int64_t sort_tile_k = (int64_t)kBlock * radix_items(Kn);
-  const int nbk = (int)((Kn + sort_tile_k - 1) / sort_tile_k);
-  need(B_TKEY0, 4 * (size_t)Kn);
-  need(B_TKEY1, 4 * (size_t)Kn);
-  need(B_TVAL0, 4 * (size_t)Kn);
-  need(B_TVAL1, 4 * (size_t)Kn);
-  need(B_TAKEN, (size_t)Kn + 4);
-  if (nbk > nbs) {
-    need(B_HIST, 4 * (size_t)kRadix * nbk);
-    need(B_SCAN, 4 * (size_t)kRadix * nbk);
-  }
-  if (st != FLOD_OK) {
-    c->required = ws_bytes(c) + extra;
-    return st;
-  }
-  uint32_t *tk[2] = {P<uint32_t>(c, B_TKEY0), P<uint32_t>(c, B_TKEY1)};
-  uint32_t *tv[2] = {P<uint32_t>(c, B_TVAL0), P<uint32_t>(c, B_TVAL1)};
-  int tres = 0;
-  if (Kn > 0) {
-    uint32_t *dv = dres ? P<uint32_t>(c, B_DVAL1) : P<uint32_t>(c, B_DVAL0);
-    tm.begin(FLOD_STAGE_EMIT);
-    if (launch_emit(dv, counters + kCntVisible, n_vis, P<uint32_t>(c, B_TILES), P<float4>(c, B_XYAB),
-                    P<float4>(c, B_COP), P<uint2>(c, B_RECT), P<float>(c, B_QSUP),
-                    P<unsigned long long>(c, B_TPREFIX), cam.tiles_x,
-                    cam.tiles_y, tk[0],
-                    tv[0], s) != hipSuccess)
-      return FLOD_ERR_DEVICE;
-    tm.end();
-    tm.begin(FLOD_STAGE_TILE_SORT);
-    const int bits = ceil_log2(n_tiles);
-    if (bits > 0) {
-      if (launch_radix_sort(tk, tv, counters + kCntInstances, Kn, bits, P<uint32_t>(c, B_HIST),
-                            P<uint32_t>(c, B_SCAN), P<uint32_t>(c, B_TOT), &tres, s) != hipSuccess)
-        return FLOD_ERR_DEVICE;
+  if (!speculate || (int64_t)K > cap) {
+    if ((int64_t)K > cap) {
+      const int64_t Kn = (int64_t)K;
+      need(B_TKEY0, 4 * (size_t)Kn);
+      need(B_TKEY1, 4 * (size_t)Kn);
+      need(B_TVAL0, 4 * (size_t)Kn);
+      need(B_TVAL1, 4 * (size_t)Kn);
+      need(B_TAKEN, (size_t)Kn + 4);
+      if (st == FLOD_OK) {
+        cap = instance_capacity(c);
+        need(B_HIST, hist_bytes(cap));
+        need(B_SCAN, hist_bytes(cap));
+      }
+      if (st != FLOD_OK) {
+        c->required = ws_bytes(c) + extra;
+        return st;
+      }
+      if (speculate && offsets(cap) != hipSuccess) return FLOD_ERR_DEVICE;
     }
-    tm.end();
+    if ((st = tail(N > 0 ? cap : 0)) != FLOD_OK) return st;
   }
-  tm.begin(FLOD_STAGE_RANGES);
-  if (launch_ranges(tk[tres], Kn, n_tiles, P<uint2>(c, B_RANGES), s) != hipSuccess) return FLOD_ERR_DEVICE;
-  tm.end();
-  tm.begin(FLOD_STAGE_BLEND);
-  if (launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP), P<float2>(c, B_BLUE),
-                   cam, bg, out->image, out->final_T, out->n_contrib, out->n_blended, P<uint8_t>(c, B_TAKEN),
-                   s) != hipSuccess)
-    return FLOD_ERR_DEVICE;
-  tm.end();
   Saved &sv = c->saved;
   sv.valid = true;
   sv.cam = cam;
@@ -697,7 +739,7 @@ flod_status flod_overlap_prune(flod_ctx *ctx, const flod_level *level, float d_o
         launch_radix_sort(dk, dv, counters + kCntVisible, n, bits, P<uint32_t>(ctx, B_HIST),
                           P<uint32_t>(ctx, B_SCAN), P<uint32_t>(ctx, B_TOT), &res, s) != hipSuccess ||
         launch_prune_gather(level->means, dv[res], n, P<float4>(ctx, B_XYAB), s) != hipSuccess ||
-        launch_ranges(dk[res], n, (int)buckets, P<uint2>(ctx, B_RANGES), s) != hipSuccess ||
+        launch_ranges(dk[res], counters + kCntVisible, n, (int)buckets, P<uint2>(ctx, B_RANGES), s) != hipSuccess ||
         launch_prune_cost(pts, ranges, n, d_op, reinterpret_cast<unsigned long long *>(counters + kCntTotal64),
                           s) != hipSuccess ||
         hipMemcpyAsync(ctx->host_counters, counters, 16, hipMemcpyDeviceToHost, s) != hipSuccess ||

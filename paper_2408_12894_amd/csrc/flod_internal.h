@@ -72,7 +72,7 @@ struct PreOut {
 // Counters in device memory (one small array per context).
 enum : int {
   kCntVisible = 0,      // u32 count of visible candidates
-  kCntInstances = 1,    // u32 count of instances (valid when the u64 total fits)
+  kCntInstances = 1,    // u32 count of instances; 0 when it exceeds the instance buffers
   kCntTotal64 = 2,      // u64 scratch for totals (two u32 slots: 2, 3)
   kCntSlots = 8
 };
@@ -81,7 +81,8 @@ enum : int {
 hipError_t launch_preprocess(const PreParams &p, const PreOut &o, hipStream_t s);
 hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int items_per_block,
                               unsigned long long *prefix, uint32_t *total32,
-                              unsigned long long *total64, int max_blocks, hipStream_t s);
+                              unsigned long long *total64, int max_blocks, hipStream_t s,
+                              unsigned long long cap32 = 0xFFFFFFFFull);
 hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
                           const unsigned long long *prefix, uint32_t *keys, uint32_t *vals,
                           hipStream_t s);
@@ -91,13 +92,12 @@ hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_
                              uint32_t *tot, int *result_buf, hipStream_t s);
 hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_max,
                               const uint32_t *tiles, uint32_t *block_sum, hipStream_t s);
-hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_vis,
-                       const uint32_t *tiles, const float4 *xyab, const float4 *cop, const uint2 *rect,
-                       const float *qsup,
-                       const unsigned long long *prefix, int tiles_x, int tiles_y,
-                       uint32_t *tile_ids, uint32_t *values, hipStream_t s);
-hipError_t launch_ranges(const uint32_t *tile_ids, int64_t K, int n_tiles, uint2 *ranges,
-                         hipStream_t s);
+hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const uint32_t *k_ptr,
+                       int64_t n_max, const uint32_t *tiles, const float4 *xyab, const float4 *cop,
+                       const uint2 *rect, const float *qsup, const unsigned long long *prefix,
+                       int tiles_x, int tiles_y, uint32_t *tile_ids, uint32_t *values, hipStream_t s);
+hipError_t launch_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, int64_t k_max, int n_tiles,
+                         uint2 *ranges, hipStream_t s);
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
                         const float4 *cop, const float2 *blue, const DevCamera &cam,
                         const float bg[3], float *image, float *final_T, int32_t *n_contrib,

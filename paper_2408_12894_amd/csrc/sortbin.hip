@@ -49,11 +49,13 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
 
 // ---------------------------------------------------------------------------------------
 // Scan of per-workgroup counts (one workgroup): 64-bit exclusive prefixes and the total.
+// total32 receives the total when it is at most cap32 and 0 otherwise: kernels sized for
+// cap32 items read it as their item count and then do nothing.
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_scan_blocks(const uint32_t *in, const uint32_t *n_items,
                                                         int items_per_block, unsigned long long *prefix,
                                                         uint32_t *total32, unsigned long long *total64,
-                                                        int max_blocks) {
+                                                        unsigned long long cap32, int max_blocks) {
   int nb = max_blocks;
   if (n_items) nb = (int)(((unsigned long long)*n_items + items_per_block - 1) / items_per_block);
   unsigned long long run = 0;
@@ -67,15 +69,16 @@ __global__ __launch_bounds__(kBlock) void k_scan_blocks(const uint32_t *in, cons
   }
   if (threadIdx.x == 0) {
     if (total64) *total64 = run;
-    if (total32) *total32 = run > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)run;
+    if (total32) *total32 = run > cap32 ? 0u : (uint32_t)run;
   }
 }
 
 hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int items_per_block,
                               unsigned long long *prefix, uint32_t *total32, unsigned long long *total64,
-                              int max_blocks, hipStream_t s) {
+                              int max_blocks, hipStream_t s, unsigned long long cap32) {
+  if (cap32 > 0xFFFFFFFFull) cap32 = 0xFFFFFFFFull;
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, s, in, n_items, items_per_block, prefix,
-                     total32, total64, max_blocks);
+                     total32, total64, cap32, max_blocks);
   return hipGetLastError();
 }
 
@@ -350,7 +353,8 @@ struct EmitWindow {
 };
 
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr,
-                                                 const uint32_t *tiles, const float4 *xyab, const float4 *cop,
+                                                 const uint32_t *k_ptr, const uint32_t *tiles,
+                                                 const float4 *xyab, const float4 *cop,
                                                  const uint2 *rect, const float *qsup,
                                                  const unsigned long long *prefix, int tiles_x,
                                                  int tiles_y, uint32_t *__restrict__ tile_ids,
@@ -359,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
   __shared__ uint32_t s_val[kEmitCap];
   const uint32_t n = *n_ptr;
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  if (blockIdx.x * kBlock >= n) return;
+  if (blockIdx.x * kBlock >= n || *k_ptr == 0u) return;   // no instances, or more than the buffers hold
   const bool valid = j < n;
   const uint32_t g = valid ? sorted_ids[j] : 0u;
   const uint32_t c = valid ? tiles[g] : 0u;
@@ -446,25 +450,27 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
   }
 }
 
-hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_vis, const uint32_t *tiles,
-                       const float4 *xyab, const float4 *cop, const uint2 *rect, const float *qsup,
-                       const unsigned long long *prefix, int tiles_x, int tiles_y, uint32_t *tile_ids,
-                       uint32_t *values, hipStream_t s) {
-  if (n_vis <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_vis + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, sorted_ids,
-                     n_ptr, tiles, xyab, cop, rect, qsup, prefix, tiles_x, tiles_y, tile_ids, values);
+hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const uint32_t *k_ptr, int64_t n_max,
+                       const uint32_t *tiles, const float4 *xyab, const float4 *cop, const uint2 *rect,
+                       const float *qsup, const unsigned long long *prefix, int tiles_x, int tiles_y,
+                       uint32_t *tile_ids, uint32_t *values, hipStream_t s) {
+  if (n_max <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_max + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, sorted_ids,
+                     n_ptr, k_ptr, tiles, xyab, cop, rect, qsup, prefix, tiles_x, tiles_y, tile_ids, values);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
-// Tile ranges from the sorted tile ids (ranges zeroed beforehand).
+// Tile ranges from the sorted tile ids (ranges zeroed beforehand); the id count is read on
+// the device, the grid covers k_max ids.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *tile_ids, int64_t K, uint2 *ranges) {
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, uint2 *ranges) {
+  const uint32_t K = *k_ptr;
+  const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
   if (k >= K) return;
   const uint32_t t = tile_ids[k];
-  if (k == 0 || tile_ids[k - 1] != t) ranges[t].x = (uint32_t)k;
-  if (k == K - 1 || tile_ids[k + 1] != t) ranges[t].y = (uint32_t)(k + 1);
+  if (k == 0 || tile_ids[k - 1] != t) ranges[t].x = k;
+  if (k == K - 1 || tile_ids[k + 1] != t) ranges[t].y = k + 1;
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
@@ -478,11 +484,12 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_ranges(const uint32_t *tile_ids, int64_t K, int n_tiles, uint2 *ranges, hipStream_t s) {
+hipError_t launch_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, int64_t k_max, int n_tiles,
+                         uint2 *ranges, hipStream_t s) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * (int64_t)n_tiles, s);
-  if (e != hipSuccess || K <= 0) return e;
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)((K + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tile_ids, K,
-                     ranges);
+  if (e != hipSuccess || k_max <= 0) return e;
+  hipLaunchKernelGGL(k_ranges, dim3((unsigned)((k_max + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tile_ids,
+                     k_ptr, ranges);
   return hipGetLastError();
 }
 

@@ -153,3 +153,33 @@ def test_hd_full_size_sampled(renderer):
     pix = np.stack([rng.integers(0, 1920, 384), rng.integers(0, 1080, 384)], 1).astype(np.int32)
     err, frac, view = full_parity(renderer, scene, cam, bg, pix=pix, frac_max=0.02)
     print(f"K={view['stats']['n_instances']} visible={view['stats']['n_visible']} err={err:.2e}")
+
+
+def test_instance_capacity_growth():
+    """A context's frame tail is enqueued before the instance count is read back, sized for the
+    instances its buffers hold: a frame with more instances than that grows the buffers and
+    runs the tail again. Every frame of a small -> large -> small -> large sequence on one
+    context is bit-identical to the same frame on a fresh context, and matches the oracle."""
+    from paper_2408_12894_amd import render
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    small = synth.uniform_scene(300, seed=60, s_mu=-3.5, s_sigma=0.5)
+    large = synth.uniform_scene(4000, seed=61, s_mu=-2.5, s_sigma=0.7)
+    cam = synth.look_at_camera((0.3, -0.2, -3.8), (0, 0, 0), 144, 112)
+    bg = np.array([0.1, 0.3, 0.5], np.float32)
+    shared = render.Renderer(0)
+    k_seen = []
+    for step, scene in enumerate([small, large, small, large]):
+        _say(f"capacity growth frame {step} (n={scene.n})")
+        got = gpu_render(shared, scene, cam, bg)
+        ref = gpu_render(render.Renderer(0), scene, cam, bg)
+        for a, b in zip(got[:3], ref[:3]):
+            np.testing.assert_array_equal(a, b)
+        K = got[3]["stats"]["n_instances"]
+        assert K == ref[3]["stats"]["n_instances"]
+        np.testing.assert_array_equal(got[3]["values"], ref[3]["values"])
+        np.testing.assert_array_equal(got[3]["tile_ids"], ref[3]["tile_ids"])
+        k_seen.append(K)
+        if step < 2:
+            full_parity(shared, scene, cam, bg)
+    assert k_seen[1] > 2 * k_seen[0]   # the second frame outgrows the first frame's buffers
