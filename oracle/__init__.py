@@ -12,6 +12,7 @@ Parts (see oracle.cpp for the arithmetic):
   image()         O2 FP64 brute-force image at chosen pixels, with ambiguity flags
   grad()          O3 FP64 gradient of sum(dL_dimage * image) over chosen pixels
   select()        eq. 6 band selection over a level range, FP32 squared distances
+  ssim, adam      the training loss (L1 + SSIM) and the optimiser step (numpy modules)
 Host helpers for eq. 3, eq. 5 and eq. 7 are plain formulas on scalars.
 
 Pins (tests/test_oracle_pins.py): eq. 3/5/7 closed forms and identities; eq. 6 band
@@ -307,3 +308,4 @@ def render(scene_arrays, smin, cam, bg, deg=3, keep=None, pix=None) -> dict:
 
 
 from . import ssim  # noqa: E402  (L1 + SSIM training loss, numpy FP64)
+from . import adam  # noqa: E402  (the training loop's Adam step, numpy FP64)
