@@ -279,7 +279,27 @@ def main():
         out_extra["train_720p"] = {"iters_s": 1.0 / t, "ms": 1e3 * t, "n_gaussians": tr_scene.n,
                                    "K": r.stats()["n_instances"]}
         log(f"train 720p/500k: {1e3 * t:.3f} ms ({1 / t:.1f} it/s)")
-        del tr_params, tr_lv, tr_tgt
+        # one iteration of the level-training loop: render, L1 + SSIM, backward, fused Adam
+        from paper_2408_12894_amd import fit
+        fl = fit.clone_level(tr_lv)
+        opt = fit.LevelAdam(fl)
+        fit_grads = {}
+
+        def fit_step(i):
+            image, _, _ = r.render_level(fl, tr_cam, bg)
+            x = image.detach().requires_grad_(True)
+            render.l1_ssim_loss(x, tr_tgt, 0.2, renderer=r).backward()
+            fit_grads.update(r.backward(fl, x.grad))
+            opt.step(r, fl, fit_grads)
+
+        t = timed(fit_step, 30, 5, sync)
+        t_adam = timed(lambda i: opt.step(r, fl, fit_grads), 50, 5, sync)
+        adam_bytes = 28 * 59 * fl.n
+        out_extra["fit_iter_720p"] = {"iters_s": 1.0 / t, "ms": 1e3 * t, "n_gaussians": fl.n,
+                                      "adam_ms": 1e3 * t_adam, "adam_GBs_algorithmic": adam_bytes / t_adam / 1e9}
+        log(f"level-training iteration 720p/500k (L1+SSIM, Adam): {1e3 * t:.3f} ms ({1 / t:.1f} it/s); "
+            f"Adam {1e3 * t_adam:.3f} ms, {adam_bytes / t_adam / 1e9:.0f} GB/s algorithmic")
+        del tr_params, tr_lv, tr_tgt, fl, opt, fit_grads
         # -------------------------------------------------------------- L1 + SSIM loss at 1080p
         g = torch.Generator(device=dev).manual_seed(5)
         ls_x = torch.rand((3, 1080, 1920), device=dev, generator=g).requires_grad_(True)

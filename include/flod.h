@@ -217,6 +217,39 @@ flod_status flod_l1_loss_forward(flod_ctx *ctx, const float *image, const float 
 flod_status flod_l1_loss_backward(flod_ctx *ctx, const float *image, const float *target, int64_t count,
                                   const double *dloss, float *d_image, void *stream);
 
+/* Arrays with a level's shapes (means [n,3], log_scales [n,3], quats [n,4], opacity_logits
+   [n], sh [n,16,3]; device, writable): a level's trainable parameters or an optimiser's
+   moment estimates. */
+typedef struct {
+  float *means;
+  float *log_scales;
+  float *quats;
+  float *opacity_logits;
+  float *sh;
+} flod_level_state;
+
+/* Adam hyper-parameters for one step over a level: a learning rate per attribute group (SH:
+   the degree-0 row, i.e. the first 3 floats of each Gaussian's 48, and the other 15 rows),
+   the moment decay rates and eps, and the 1-based step count t of the bias corrections. */
+typedef struct {
+  float lr_means, lr_log_scales, lr_quats, lr_opacity, lr_sh_dc, lr_sh_rest;
+  float beta1, beta2, eps;
+  int64_t step;
+} flod_adam_params;
+
+/* One Adam step over every attribute of an n-Gaussian level, in place (the optimiser of the
+   per-level training loop, section Training Method, Algorithm 1; Kingma and Ba's update):
+     m <- beta1 m + (1 - beta1) g,   v <- beta2 v + (1 - beta2) g^2,
+     p <- p - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+   FP32 arithmetic; the bias corrections are formed in FP64 and rounded once. params, m, v:
+   writable device arrays (m = v = 0 before step 1); grads as flod_render_backward writes
+   them. No array may overlap another. One launch, no host synchronisation.
+   FLOD_ERR_INVALID_ARG for a NULL pointer with n > 0, n < 0, step < 1, a beta outside
+   [0, 1), eps < 0 or a non-finite rate. */
+flod_status flod_adam_step(flod_ctx *ctx, const flod_level_state *params, const flod_grads *grads,
+                           const flod_level_state *m, const flod_level_state *v, int64_t n,
+                           const flod_adam_params *hp, void *stream);
+
 /* Level transition (section Training Method, eq. 5): initialise level l+1 from the trained
    level l = *in: every attribute copied, and s_opt' = log(s^(l) - s_min_next) with
    s^(l) = exp(s_opt) + in->s_min formed as the renderer forms it (exp in FP64 rounded once

@@ -27,7 +27,7 @@ EXPORTS = ("flod_ctx_create", "flod_ctx_destroy", "flod_ctx_workspace_bytes", "f
            "flod_ctx_stats", "flod_ctx_view", "flod_ctx_set_timing", "flod_ctx_set_timing_stages", "flod_ctx_stage_times",
            "flod_stage_name", "flod_smin", "flod_dproj", "flod_status_str", "flod_copy_to_host",
            "flod_render_merged", "flod_select_compact", "flod_overlap_prune", "flod_compact_level",
-           "flod_level_transition", "flod_l1_ssim_forward", "flod_l1_ssim_backward",
+           "flod_level_transition", "flod_adam_step", "flod_l1_ssim_forward", "flod_l1_ssim_backward",
            "flod_l1_loss_forward", "flod_l1_loss_backward")
 
 
@@ -51,6 +51,17 @@ class Camera(C.Structure):
 class Frame(C.Structure):
     _fields_ = [("image", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
                 ("n_blended", C.c_void_p)]
+
+
+class LevelState(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity_logits", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class AdamParams(C.Structure):
+    _fields_ = [("lr_means", C.c_float), ("lr_log_scales", C.c_float), ("lr_quats", C.c_float),
+                ("lr_opacity", C.c_float), ("lr_sh_dc", C.c_float), ("lr_sh_rest", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("step", C.c_int64)]
 
 
 class Grads(C.Structure):
@@ -115,6 +126,9 @@ def load():
     L.flod_compact_level.restype = C.c_int
     L.flod_level_transition.argtypes = [vp, C.POINTER(Level), C.c_float, C.POINTER(Level), vp]
     L.flod_level_transition.restype = C.c_int
+    L.flod_adam_step.argtypes = [vp, C.POINTER(LevelState), C.POINTER(Grads), C.POINTER(LevelState),
+                                 C.POINTER(LevelState), C.c_int64, C.POINTER(AdamParams), vp]
+    L.flod_adam_step.restype = C.c_int
     ci = C.c_int
     L.flod_l1_ssim_forward.argtypes = [vp, vp, vp, ci, ci, ci, C.c_float, vp, vp, vp]
     L.flod_l1_ssim_forward.restype = C.c_int

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libflod.so")
 BUILD_DIR = os.path.join(ROOT, "_build", "flod")
-SOURCES = ["preprocess.hip", "sortbin.hip", "blend.hip", "backward.hip", "levels.hip", "prune.hip", "ssim.hip", "flod_api.hip"]
+SOURCES = ["preprocess.hip", "sortbin.hip", "blend.hip", "backward.hip", "levels.hip", "prune.hip", "ssim.hip", "optim.hip", "flod_api.hip"]
 ARCH = os.environ.get("FLOD_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -812,6 +812,52 @@ flod_status flod_l1_loss_backward(flod_ctx *ctx, const float *image, const float
   return dev(launch_l1_backward(image, target, count, dloss, d_image, s));
 }
 
+flod_status flod_adam_step(flod_ctx *ctx, const flod_level_state *params, const flod_grads *grads,
+                           const flod_level_state *m, const flod_level_state *v, int64_t n,
+                           const flod_adam_params *hp, void *stream) {
+  if (!ctx || !params || !grads || !m || !v || !hp || n < 0) return FLOD_ERR_INVALID_ARG;
+  if (hp->step < 1 || !(hp->beta1 >= 0.0f && hp->beta1 < 1.0f) || !(hp->beta2 >= 0.0f && hp->beta2 < 1.0f) ||
+      !(hp->eps >= 0.0f) || !isfinite(hp->eps))
+    return FLOD_ERR_INVALID_ARG;
+  const float lrs[6] = {hp->lr_means, hp->lr_log_scales, hp->lr_quats, hp->lr_opacity, hp->lr_sh_dc, hp->lr_sh_rest};
+  for (float r : lrs)
+    if (!isfinite(r)) return FLOD_ERR_INVALID_ARG;
+  float *P5[5] = {params->means, params->log_scales, params->quats, params->opacity_logits, params->sh};
+  const float *G5[5] = {grads->d_means, grads->d_log_scales, grads->d_quats, grads->d_opacity_logits, grads->d_sh};
+  float *M5[5] = {m->means, m->log_scales, m->quats, m->opacity_logits, m->sh};
+  float *V5[5] = {v->means, v->log_scales, v->quats, v->opacity_logits, v->sh};
+  const int64_t width[5] = {3, 3, 4, 1, FLOD_SH_COEFFS * 3};
+  if (n > 0)
+    for (int k = 0; k < 5; ++k)
+      if (!P5[k] || !G5[k] || !M5[k] || !V5[k] || !aligned(P5[k], 4) || !aligned(G5[k], 4) || !aligned(M5[k], 4) ||
+          !aligned(V5[k], 4))
+        return FLOD_ERR_INVALID_ARG;
+  if (n > ((int64_t)1 << 40)) return FLOD_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  AdamArgs a;
+  memset(&a, 0, sizeof(a));
+  int64_t slot = 0;
+  for (int k = 0; k < 5; ++k) {
+    AdamSeg &S = a.seg[k];
+    S.p = P5[k]; S.g = G5[k]; S.m = M5[k]; S.v = V5[k];
+    S.len = n * width[k];
+    S.first4 = slot;
+    S.lr = lrs[k];
+    S.vec = aligned(S.p, 16) && aligned(S.g, 16) && aligned(S.m, 16) && aligned(S.v, 16);
+    slot += (S.len + 3) / 4;
+  }
+  a.total4 = slot;
+  a.lr_sh_rest = hp->lr_sh_rest;
+  a.b1 = hp->beta1;
+  a.b2 = hp->beta2;
+  a.omb1 = (float)(1.0 - (double)hp->beta1);
+  a.omb2 = (float)(1.0 - (double)hp->beta2);
+  a.inv_bc1 = (float)(1.0 / (1.0 - pow((double)hp->beta1, (double)hp->step)));
+  a.inv_bc2 = (float)(1.0 / (1.0 - pow((double)hp->beta2, (double)hp->step)));
+  a.eps = hp->eps;
+  return dev(launch_adam(a, (hipStream_t)stream));
+}
+
 flod_status flod_level_transition(flod_ctx *ctx, const flod_level *in, float s_min_next, flod_level *out,
                                   void *stream) {
   if (!ctx || !in || !out) return FLOD_ERR_INVALID_ARG;

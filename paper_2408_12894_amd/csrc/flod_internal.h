@@ -69,6 +69,27 @@ struct PreOut {
   unsigned long long *n_selected;   // per-level selected counts (may be null)
 };
 
+// One attribute array of a level in an Adam step: parameter, gradient and the two moment
+// arrays (same length), its first float4 slot in the launch and its learning rate.
+struct AdamSeg {
+  float *p;
+  const float *g;
+  float *m, *v;
+  int64_t len;      // floats
+  int64_t first4;   // first float4 slot of the segment
+  float lr;         // for the SH segment: the degree-0 rate
+  int vec;          // all four arrays 16-byte aligned
+};
+
+struct AdamArgs {
+  AdamSeg seg[5];   // means, log_scales, quats, opacity logits, SH
+  float lr_sh_rest;
+  float b1, b2, omb1, omb2;   // beta1, beta2, 1 - beta1, 1 - beta2
+  float inv_bc1, inv_bc2;     // 1 / (1 - beta^t), formed in FP64 and rounded once
+  float eps;
+  int64_t total4;
+};
+
 // Counters in device memory (one small array per context).
 enum : int {
   kCntVisible = 0,      // u32 count of visible candidates
@@ -118,6 +139,7 @@ hipError_t launch_mask_count(const uint8_t *mask, int64_t n, uint32_t *block_cnt
 hipError_t launch_mask_copy(const flod_level &in, const uint8_t *mask, const unsigned long long *prefix,
                             const flod_level &out, hipStream_t s);
 hipError_t launch_level_transition(const flod_level &in, float s_min_next, const flod_level &out, hipStream_t s);
+hipError_t launch_adam(const AdamArgs &a, hipStream_t s);
 int64_t ssim_blocks(int C, int H, int W);   // workgroups (and loss partials) of the SSIM kernels
 hipError_t launch_ssim_forward(const float *x, const float *y, int C, int H, int W, float lam, double *loss,
                                float *gmap, double2 *partials, hipStream_t s);

@@ -80,6 +80,8 @@ def test_validation_before_any_device_call(lib):
     assert lib.flod_overlap_prune(None, C.byref(lv), 0.1, None, None, C.byref(n64), None) == bad
     assert lib.flod_compact_level(None, C.byref(lv), None, None, C.byref(n64), None) == bad
     assert lib.flod_level_transition(None, C.byref(lv), 0.0, C.byref(lv), None) == bad
+    st, gr, hp = _lib.LevelState(), _lib.Grads(), _lib.AdamParams()
+    assert lib.flod_adam_step(None, C.byref(st), C.byref(gr), C.byref(st), C.byref(st), 4, C.byref(hp), None) == bad
     assert lib.flod_l1_ssim_forward(None, None, None, 3, 4, 4, 0.2, None, None, None) == bad
     assert lib.flod_l1_ssim_backward(None, None, None, 3, 4, 4, 0.2, None, None, None, None) == bad
     assert lib.flod_l1_loss_forward(None, None, None, 16, None, None) == bad
