@@ -14,9 +14,11 @@
 // pass can recover every T_i from the stored final T; colours accumulate in FP32.
 // The workgroup leaves the list as soon as all 256 pixels have stopped.
 //
-// Workgroup -> tile mapping is XCD-aware: workgroups are dispatched round-robin over the 8
-// XCDs, so workgroup i is sent to tile (i % 8) * chunk + i / 8 and each XCD's L2 serves a
-// contiguous band of tiles, which share most of their Gaussians.
+// Workgroup -> tile mapping is XCD-aware (xcd_tile): XCD x takes every eighth row of tiles,
+// so the XCDs share the frame's work evenly and each XCD's L2 serves rows of neighbouring
+// tiles, which share most of their Gaussians. Each tile also records how many of its list
+// entries it blended into some pixel (the entries its backward pass processes), from which
+// the backward orders its tiles longest first.
 #include "blend_common.h"
 
 namespace flod {
@@ -34,15 +36,17 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
                                                               float *__restrict__ final_T,
                                                               int32_t *__restrict__ n_contrib,
                                                               int32_t *__restrict__ n_blended,
-                                                              uint8_t *__restrict__ taken) {
+                                                              uint8_t *__restrict__ taken,
+                                                              uint32_t *__restrict__ tile_taken) {
   constexpr int NT = kTile * kTile / PPT;   // threads per tile
   constexpr int ROWS = NT / kTile;          // pixel rows covered by one pass of the threads
   __shared__ float4 s_a[kBatch];
   __shared__ float4 s_b[kBatch];
   __shared__ float2 s_c[kBatch];
   __shared__ uint8_t s_taken[kBatch];
-  const int tile = xcd_tile(blockIdx.x, n_tiles);
-  if (tile >= n_tiles) return;
+  __shared__ int s_count[NT / 64];
+  const int tile = xcd_tile(blockIdx.x, tiles_x, n_tiles / tiles_x);
+  if (tile < 0) return;
   const int tid = threadIdx.x;
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
   const int px = x0 + (tid & (kTile - 1));
@@ -66,6 +70,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
   const uint2 rg = ranges[tile];
   const int n = (int)(rg.y - rg.x);
   int last_start = -1;   // start of the last batch walked
+  int my_taken = 0;      // taken flags this thread wrote out
   for (int start = 0; start < n; start += kBatch) {
     bool all_done = true;
 #pragma unroll
@@ -78,7 +83,10 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
     }
     // the previous batch's taken flags leave (consecutive bytes), this batch's start at zero
     for (int e = tid; e < kBatch; e += NT) {
-      if (start > 0) taken[rg.x + start - kBatch + e] = s_taken[e];
+      if (start > 0) {
+        taken[rg.x + start - kBatch + e] = s_taken[e];
+        my_taken += s_taken[e];
+      }
       s_taken[e] = 0;
     }
     for (int e = tid; e < kBatch; e += NT) {
@@ -135,7 +143,20 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
   // which stops at the last blended entry)
   __syncthreads();
   if (last_start >= 0)
-    for (int e = tid; e < kBatch && last_start + e < n; e += NT) taken[rg.x + last_start + e] = s_taken[e];
+    for (int e = tid; e < kBatch && last_start + e < n; e += NT) {
+      taken[rg.x + last_start + e] = s_taken[e];
+      my_taken += s_taken[e];
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) my_taken += __shfl_xor(my_taken, o, 64);
+  if ((tid & 63) == 0) s_count[tid >> 6] = my_taken;
+  __syncthreads();
+  if (tid == 0) {
+    int t = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) t += s_count[w];
+    tile_taken[tile] = (uint32_t)t;
+  }
   const size_t plane = (size_t)W * H;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
@@ -153,14 +174,15 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
 
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
                         const float2 *blue, const DevCamera &cam, const float bg[3], float *image, float *final_T,
-                        int32_t *n_contrib, int32_t *n_blended, uint8_t *taken, hipStream_t s) {
+                        int32_t *n_contrib, int32_t *n_blended, uint8_t *taken, uint32_t *tile_taken,
+                        hipStream_t s) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
-  const int grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
+  const int grid = xcd_grid(cam.tiles_x, cam.tiles_y);
   // 1 pixel per thread (4 waves per tile) measured fastest at 1080p / 1M: 0.218 ms against
   // 0.242 ms with 2 and 0.353 ms with 4 (entry loop unrolled by two in that comparison).
   hipLaunchKernelGGL(k_blend<kFwdPix>, dim3(grid), dim3(kTile * kTile / kFwdPix), 0, s, ranges, values, xyab, cop,
                      blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], image, final_T, n_contrib,
-                     n_blended, taken);
+                     n_blended, taken, tile_taken);
   return hipGetLastError();
 }
 

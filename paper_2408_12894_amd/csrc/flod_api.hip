@@ -20,7 +20,7 @@ enum BufId {
   B_XYAB, B_COP, B_BLUE, B_DEPTH, B_RECT, B_TILES, B_BLOCKVIS, B_PREFIX,
   B_DKEY0, B_DKEY1, B_DVAL0, B_DVAL1, B_TBSUM, B_TPREFIX,
   B_TKEY0, B_TKEY1, B_TVAL0, B_TVAL1, B_HIST, B_SCAN, B_TOT, B_RANGES, B_COUNTERS,
-  B_G2D, B_SSIM, B_QSUP, B_TAKEN, B_COUNT
+  B_G2D, B_SSIM, B_QSUP, B_TAKEN, B_TILE_TAKEN, B_TILE_ORDER, B_COUNT
 };
 
 struct Saved {
@@ -261,6 +261,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   need(B_SCAN, hist);
   need(B_TOT, 4 * (size_t)kRadix);
   need(B_RANGES, 8 * (size_t)n_tiles);
+  need(B_TILE_TAKEN, 4 * (size_t)n_tiles);
   need(B_COUNTERS, 8 * (size_t)kCntSlots);
   if (st != FLOD_OK) {
     c->required = ws_bytes(c) + extra;
@@ -343,7 +344,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     tm.begin(FLOD_STAGE_BLEND);
     if (launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP),
                      P<float2>(c, B_BLUE), cam, bg, out->image, out->final_T, out->n_contrib, out->n_blended,
-                     P<uint8_t>(c, B_TAKEN), s) != hipSuccess)
+                     P<uint8_t>(c, B_TAKEN), P<uint32_t>(c, B_TILE_TAKEN), s) != hipSuccess)
       return FLOD_ERR_DEVICE;
     tm.end();
     return FLOD_OK;
@@ -891,7 +892,9 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   StageTimer tm(ctx, s);
   if (N == 0) return FLOD_OK;
   size_t extra = 0;
-  if (ensure(ctx, B_G2D, 9 * 4 * (size_t)N, s, &extra) != FLOD_OK) {
+  const int n_tiles = sv.cam.tiles_x * sv.cam.tiles_y;
+  if (ensure(ctx, B_G2D, 9 * 4 * (size_t)N, s, &extra) != FLOD_OK ||
+      ensure(ctx, B_TILE_ORDER, 4 * (size_t)n_tiles, s, &extra) != FLOD_OK) {
     ctx->required = ws_bytes(ctx) + extra;
     return FLOD_ERR_WORKSPACE;
   }
@@ -899,9 +902,11 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   if (launch_fill_u32(reinterpret_cast<uint32_t *>(g2d), 0u, 9 * N, s) != hipSuccess) return FLOD_ERR_DEVICE;
   tm.begin(FLOD_STAGE_BLEND_BWD);
   const uint32_t *vals = sv.sorted_vals ? P<uint32_t>(ctx, B_TVAL1) : P<uint32_t>(ctx, B_TVAL0);
-  if (launch_blend_bwd(P<uint2>(ctx, B_RANGES), vals, P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
+  uint32_t *order = P<uint32_t>(ctx, B_TILE_ORDER);
+  if (launch_tile_order(P<uint32_t>(ctx, B_TILE_TAKEN), n_tiles, order, s) != hipSuccess ||
+      launch_blend_bwd(P<uint2>(ctx, B_RANGES), vals, P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
                        P<float2>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d,
-                       P<uint8_t>(ctx, B_TAKEN), s) != hipSuccess)
+                       P<uint8_t>(ctx, B_TAKEN), order, s) != hipSuccess)
     return FLOD_ERR_DEVICE;
   tm.end();
   tm.begin(FLOD_STAGE_PREPROCESS_BWD);
