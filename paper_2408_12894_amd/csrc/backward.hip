@@ -207,49 +207,6 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   }
 }
 
-// Tiles ordered by the work of their backward pass, longest first (LPT order). The blend
-// backward's cost per tile is close to proportional to the entries the forward blended into
-// some pixel of it, and it varies by orders of magnitude between tiles; dispatched in frame
-// order, the tiles with the most work often started last and the kernel ended in a long
-// ramp with most wave slots idle. One workgroup: a histogram over 256 buckets of the count
-// (8 per octave), descending bucket offsets, then a scatter (order inside a bucket is
-// whatever the LDS atomics give: it changes only the schedule, not any result).
-constexpr int kOrderThreads = 1024;
-constexpr int kOrderBuckets = 256;
-
-__device__ __forceinline__ int cost_bucket(uint32_t c) {
-  if (c < 8u) return (int)c;
-  const int e = 31 - __clz(c);                     // c in [2^e, 2^(e+1)), e >= 3
-  const int m = (int)((c >> (e - 3)) & 7u);        // next three bits
-  return min(kOrderBuckets - 1, 8 + (e - 3) * 8 + m);
-}
-
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t *__restrict__ cost, int n,
-                                                              uint32_t *__restrict__ order) {
-  __shared__ uint32_t s_hist[kOrderBuckets];
-  __shared__ uint32_t s_pos[kOrderBuckets];
-  const int tid = threadIdx.x;
-  if (tid < kOrderBuckets) s_hist[tid] = 0;
-  __syncthreads();
-  for (int t = tid; t < n; t += kOrderThreads) atomicAdd(&s_hist[cost_bucket(cost[t])], 1u);
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t run = 0;
-    for (int b = kOrderBuckets - 1; b >= 0; --b) {
-      s_pos[b] = run;
-      run += s_hist[b];
-    }
-  }
-  __syncthreads();
-  for (int t = tid; t < n; t += kOrderThreads) order[atomicAdd(&s_pos[cost_bucket(cost[t])], 1u)] = (uint32_t)t;
-}
-
-hipError_t launch_tile_order(const uint32_t *cost, int n_tiles, uint32_t *order, hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, cost, n_tiles, order);
-  return hipGetLastError();
-}
-
 hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
                             const float2 *blue, const DevCamera &cam, const float bg[3], const float *final_T,
                             const int32_t *n_contrib, const float *dL_dimage, float *g2d, const uint8_t *taken,

@@ -14,11 +14,9 @@
 // pass can recover every T_i from the stored final T; colours accumulate in FP32.
 // The workgroup leaves the list as soon as all 256 pixels have stopped.
 //
-// Workgroup -> tile mapping is XCD-aware (xcd_tile): XCD x takes every eighth row of tiles,
-// so the XCDs share the frame's work evenly and each XCD's L2 serves rows of neighbouring
-// tiles, which share most of their Gaussians. Each tile also records how many of its list
-// entries it blended into some pixel (the entries its backward pass processes), from which
-// the backward orders its tiles longest first.
+// Workgroups take the tiles in order of decreasing list length (k_tile_order). Each tile also
+// records how many of its list entries it blended into some pixel (the entries its backward
+// pass processes), from which the backward orders its tiles.
 #include "blend_common.h"
 
 namespace flod {
@@ -37,7 +35,8 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
                                                               int32_t *__restrict__ n_contrib,
                                                               int32_t *__restrict__ n_blended,
                                                               uint8_t *__restrict__ taken,
-                                                              uint32_t *__restrict__ tile_taken) {
+                                                              uint32_t *__restrict__ tile_taken,
+                                                              const uint32_t *__restrict__ order) {
   constexpr int NT = kTile * kTile / PPT;   // threads per tile
   constexpr int ROWS = NT / kTile;          // pixel rows covered by one pass of the threads
   __shared__ float4 s_a[kBatch];
@@ -45,8 +44,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
   __shared__ float2 s_c[kBatch];
   __shared__ uint8_t s_taken[kBatch];
   __shared__ int s_count[NT / 64];
-  const int tile = xcd_tile(blockIdx.x, tiles_x, n_tiles / tiles_x);
-  if (tile < 0) return;
+  const int tile = (int)order[blockIdx.x];
   const int tid = threadIdx.x;
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
   const int px = x0 + (tid & (kTile - 1));
@@ -175,14 +173,27 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
                         const float2 *blue, const DevCamera &cam, const float bg[3], float *image, float *final_T,
                         int32_t *n_contrib, int32_t *n_blended, uint8_t *taken, uint32_t *tile_taken,
-                        hipStream_t s) {
+                        const uint32_t *order, hipStream_t s) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
-  const int grid = xcd_grid(cam.tiles_x, cam.tiles_y);
   // 1 pixel per thread (4 waves per tile) measured fastest at 1080p / 1M: 0.218 ms against
   // 0.242 ms with 2 and 0.353 ms with 4 (entry loop unrolled by two in that comparison).
-  hipLaunchKernelGGL(k_blend<kFwdPix>, dim3(grid), dim3(kTile * kTile / kFwdPix), 0, s, ranges, values, xyab, cop,
-                     blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], image, final_T, n_contrib,
-                     n_blended, taken, tile_taken);
+  hipLaunchKernelGGL(k_blend<kFwdPix>, dim3(n_tiles), dim3(kTile * kTile / kFwdPix), 0, s, ranges, values, xyab,
+                     cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], image, final_T, n_contrib,
+                     n_blended, taken, tile_taken, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_order_by_length(const uint2 *ranges, int n_tiles, uint32_t *order, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_order<ListLengthCost>, dim3(1), dim3(kOrderThreads), 0, s, ListLengthCost{ranges},
+                     n_tiles, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_order_by_count(const uint32_t *count, int n_tiles, uint32_t *order, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_order<CountCost>, dim3(1), dim3(kOrderThreads), 0, s, CountCost{count}, n_tiles,
+                     order);
   return hipGetLastError();
 }
 

@@ -1,31 +1,60 @@
-// Shared by the forward and backward blend kernels: tile/lane geometry, the XCD-aware tile
-// order and wave64 reductions through DPP (no LDS crossbar traffic).
+// Shared by the forward and backward blend kernels: tile geometry, the longest-first tile
+// orders and wave64 reductions through DPP (no LDS crossbar traffic).
 #pragma once
 
 #include "project.h"
 
 namespace flod {
 
-constexpr int kXcds = 8;
-constexpr int kBlendThreads = 64;                          // one wave64 per 16x16 tile
-constexpr int kPix = (kTile * kTile) / kBlendThreads;      // 4 pixels per lane
-constexpr int kRowStep = kBlendThreads / kTile;            // lane rows 0..3, then +4, +8, +12
 constexpr int kBatch = 256;                                // list entries staged in LDS at once
 
-// Tile of workgroup `bid`. Workgroups go to the 8 XCDs round-robin (XCD = bid % 8); XCD x
-// takes the tile rows r with r % 8 == x, each row left to right. Every XCD so gets an even
-// share of the frame (the work concentrates in its middle rows: contiguous blocks of rows per
-// XCD left one XCD with 1.4-1.5x the mean list length at 1080p), and the tiles it holds in
-// flight are horizontal neighbours that share Gaussians in its L2. Returns -1 for the padding
-// workgroups of the last row group.
-__device__ __forceinline__ int xcd_tile(int bid, int tiles_x, int tiles_y) {
-  const int x = bid % kXcds, j = bid / kXcds;
-  const int row = x + kXcds * (j / tiles_x);
-  return row < tiles_y ? row * tiles_x + j % tiles_x : -1;
+// Tile orders, longest first (LPT order). The blend kernels' cost per tile varies by orders of
+// magnitude between tiles; dispatched in frame order, tiles with much work often started last
+// and a kernel ended in a long ramp with most wave slots idle. The forward orders its tiles by
+// list length, the backward by the entries the forward blended into some pixel of the tile
+// (the entries it processes). One workgroup: a histogram over 256 buckets of the cost (8 per
+// octave), descending bucket offsets, then a scatter; the order inside a bucket is whatever
+// the LDS atomics give, which changes only the schedule, never a result. Consecutive
+// workgroups go to different XCDs (round-robin), so every XCD receives an even share.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 256;
+
+__device__ __forceinline__ int cost_bucket(uint32_t c) {
+  if (c < 8u) return (int)c;
+  const int e = 31 - __clz(c);                     // c in [2^e, 2^(e+1)), e >= 3
+  const int m = (int)((c >> (e - 3)) & 7u);        // next three bits
+  return min(kOrderBuckets - 1, 8 + (e - 3) * 8 + m);
 }
 
-// Workgroups that xcd_tile() maps onto every tile of a tiles_x x tiles_y grid.
-inline int xcd_grid(int tiles_x, int tiles_y) { return kXcds * tiles_x * ((tiles_y + kXcds - 1) / kXcds); }
+struct ListLengthCost {   // forward: entries in the tile's list
+  const uint2 *ranges;
+  __device__ __forceinline__ uint32_t operator()(int t) const { return ranges[t].y - ranges[t].x; }
+};
+
+struct CountCost {        // backward: entries the forward blended somewhere in the tile
+  const uint32_t *count;
+  __device__ __forceinline__ uint32_t operator()(int t) const { return count[t]; }
+};
+
+template <class Cost>
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, uint32_t *__restrict__ order) {
+  __shared__ uint32_t s_hist[kOrderBuckets];
+  __shared__ uint32_t s_pos[kOrderBuckets];
+  const int tid = threadIdx.x;
+  if (tid < kOrderBuckets) s_hist[tid] = 0;
+  __syncthreads();
+  for (int t = tid; t < n; t += kOrderThreads) atomicAdd(&s_hist[cost_bucket(cost(t))], 1u);
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (int b = kOrderBuckets - 1; b >= 0; --b) {
+      s_pos[b] = run;
+      run += s_hist[b];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < n; t += kOrderThreads) order[atomicAdd(&s_pos[cost_bucket(cost(t))], 1u)] = (uint32_t)t;
+}
 
 template <int CTRL, int ROW_MASK = 0xF>
 __device__ __forceinline__ float dpp_or_zero(float x) {

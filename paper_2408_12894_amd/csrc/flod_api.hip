@@ -262,6 +262,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   need(B_TOT, 4 * (size_t)kRadix);
   need(B_RANGES, 8 * (size_t)n_tiles);
   need(B_TILE_TAKEN, 4 * (size_t)n_tiles);
+  need(B_TILE_ORDER, 4 * (size_t)n_tiles);
   need(B_COUNTERS, 8 * (size_t)kCntSlots);
   if (st != FLOD_OK) {
     c->required = ws_bytes(c) + extra;
@@ -342,9 +343,11 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
       return FLOD_ERR_DEVICE;
     tm.end();
     tm.begin(FLOD_STAGE_BLEND);
-    if (launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP),
+    uint32_t *order = P<uint32_t>(c, B_TILE_ORDER);
+    if (launch_tile_order_by_length(P<uint2>(c, B_RANGES), n_tiles, order, s) != hipSuccess ||
+        launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP),
                      P<float2>(c, B_BLUE), cam, bg, out->image, out->final_T, out->n_contrib, out->n_blended,
-                     P<uint8_t>(c, B_TAKEN), P<uint32_t>(c, B_TILE_TAKEN), s) != hipSuccess)
+                     P<uint8_t>(c, B_TAKEN), P<uint32_t>(c, B_TILE_TAKEN), order, s) != hipSuccess)
       return FLOD_ERR_DEVICE;
     tm.end();
     return FLOD_OK;
@@ -903,7 +906,7 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   tm.begin(FLOD_STAGE_BLEND_BWD);
   const uint32_t *vals = sv.sorted_vals ? P<uint32_t>(ctx, B_TVAL1) : P<uint32_t>(ctx, B_TVAL0);
   uint32_t *order = P<uint32_t>(ctx, B_TILE_ORDER);
-  if (launch_tile_order(P<uint32_t>(ctx, B_TILE_TAKEN), n_tiles, order, s) != hipSuccess ||
+  if (launch_tile_order_by_count(P<uint32_t>(ctx, B_TILE_TAKEN), n_tiles, order, s) != hipSuccess ||
       launch_blend_bwd(P<uint2>(ctx, B_RANGES), vals, P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
                        P<float2>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d,
                        P<uint8_t>(ctx, B_TAKEN), order, s) != hipSuccess)

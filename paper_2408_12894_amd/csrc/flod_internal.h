@@ -122,13 +122,15 @@ hipError_t launch_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, int64_
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
                         const float4 *cop, const float2 *blue, const DevCamera &cam,
                         const float bg[3], float *image, float *final_T, int32_t *n_contrib,
-                        int32_t *n_blended, uint8_t *taken, uint32_t *tile_taken, hipStream_t s);
+                        int32_t *n_blended, uint8_t *taken, uint32_t *tile_taken, const uint32_t *order,
+                        hipStream_t s);
 hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
                             const float4 *cop, const float2 *blue, const DevCamera &cam,
                             const float bg[3], const float *final_T, const int32_t *n_contrib,
                             const float *dL_dimage, float *g2d, const uint8_t *taken,
                             const uint32_t *order, hipStream_t s);
-hipError_t launch_tile_order(const uint32_t *cost, int n_tiles, uint32_t *order, hipStream_t s);
+hipError_t launch_tile_order_by_length(const uint2 *ranges, int n_tiles, uint32_t *order, hipStream_t s);
+hipError_t launch_tile_order_by_count(const uint32_t *count, int n_tiles, uint32_t *order, hipStream_t s);
 hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, const float *g2d,
                                  const flod_grads &g, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
