@@ -109,8 +109,24 @@ hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t 
 
 // ---------------------------------------------------------------------------------------
 // Radix pass: histogram, per-digit scan, stable scatter.
-// hist[d * nb_max + b] = count of digit d in workgroup b; scan = exclusive prefix over b.
+// hist[d * nb_max + b] = count of digit d in block b; scan = exclusive prefix over b.
+//
+// Block of a histogram or scatter workgroup: workgroups go to the 8 XCDs round-robin, and
+// each XCD takes runs of kXcdRun consecutive blocks. The counts of adjacent blocks share
+// cache lines; written and read from one XCD's L2 they move as whole lines (spread over the
+// 8 XCDs every line went out as 8 partial writes: 8x the histogram's bytes).
 // ---------------------------------------------------------------------------------------
+constexpr uint32_t kXcdRun = 16;
+
+__device__ __forceinline__ uint32_t radix_block(uint32_t wg) {
+  const uint32_t x = wg % 8u, j = wg / 8u;
+  return (j / kXcdRun) * (8u * kXcdRun) + x * kXcdRun + (j % kXcdRun);
+}
+
+static unsigned radix_grid(int nb_max) {
+  const int g = 8 * (int)kXcdRun;
+  return (unsigned)(((nb_max + g - 1) / g) * g);
+}
 template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const uint32_t *n_ptr, int shift,
                                                     uint32_t *hist, int nb_max) {
@@ -118,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const 
   __shared__ uint32_t h[kRadix];
   const uint32_t n = *n_ptr;
   const uint32_t nb = (n + TILE - 1) / TILE;
-  const uint32_t b = blockIdx.x;
+  const uint32_t b = radix_block(blockIdx.x);
   if (b >= nb) return;
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -174,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
   __shared__ uint32_t s_wcnt[WAVES][kRadix];
   const uint32_t n = *n_ptr;
   const uint32_t nb = (n + TILE - 1) / TILE;
-  const uint32_t b = blockIdx.x;
+  const uint32_t b = radix_block(blockIdx.x);
   if (b >= nb) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   // digit bases over the whole array and this workgroup's local digit bases
@@ -253,9 +269,10 @@ static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n
   const int nb_max = (int)((n_max + TILE - 1) / TILE);
   int cur = 0;
   for (int shift = 0; shift < bits; shift += kRadixBits) {
-    hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(nb_max), dim3(kBlock), 0, s, keys[cur], n_ptr, shift, hist, nb_max);
+    hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], n_ptr, shift, hist,
+                       nb_max);
     hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, s, n_ptr, hist, scan, tot, nb_max, TILE);
-    hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(nb_max), dim3(kBlock), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
+    hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
                        vals[cur ^ 1], n_ptr, shift, hist, scan, tot, nb_max);
     cur ^= 1;
   }
