@@ -2,8 +2,9 @@
 //
 // Blend backward: one wave per tile (4 pixels per lane), walking the tile list back to
 // front from the last blended entry. The per-pixel transmittance before entry i is
-// recovered from the saved final T as T_i = T_{i+1} / (1 - alpha_i) (alpha <= 0.99, FP64
-// reciprocal: the chain runs through up to thousands of contributors), and
+// recovered from the saved final T as T_i = T_{i+1} / (1 - alpha_i) (alpha <= 0.99, FP32
+// reciprocal: about one rounding per blended contributor, so the relative error after m of
+// them grows like sqrt(m) ulp, far below the FP32 summation error of the gradients), and
 //   dC/dc_i     = alpha_i T_i
 //   dC/dalpha_i = T_i c_i - S_i / (1 - alpha_i),  S_i = sum_{j>i} alpha_j T_j c_j + T_final bg
 //               = T_i (c_i - Shat_i),  Shat_i = S_i / T_{i+1}
@@ -35,19 +36,10 @@ constexpr int kBwdPix = FLOD_BWD_PIX;   // pixels per thread: 4 = one wave64 per
 // does not cap the waves a CU holds below what the registers allow.
 constexpr int kBwdBatch = FLOD_BWD_BATCH;
 
-// 1/x in FP64 from the hardware estimate and two Newton steps (x in [0.01, 1]).
-__device__ __forceinline__ double recip64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-
 // One workgroup per tile with PPT pixels per thread (the forward's geometry). Per pixel
 // the state is T (transmittance after the current entry), V = dL/dC . Shat (the upstream
-// gradient dotted with the normalised colour behind the current entry) and dL/dC; T and V
-// are FP64 because both run through chains of up to thousands of contributors. Per entry
+// gradient dotted with the normalised colour behind the current entry) and dL/dC, all FP32
+// (V is a convex combination per step, so its error does not grow along the chain). Per entry
 // each thread sums its pixels' 9 gradient components in registers and the wave reduces
 // them (see below) before one atomic instruction adds the nine sums.
 template <int PPT>
@@ -73,23 +65,23 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   const float fx = (float)px + 0.5f;
   const size_t plane = (size_t)W * H;
   float fy[PPT], d0[PPT], d1[PPT], d2[PPT];
-  double T[PPT], V[PPT];
+  float T[PPT], V[PPT];
   int last[PPT];
   int mylast = 0;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int py = y0 + (tid >> 4) + ROWS * k;
     fy[k] = (float)py + 0.5f;
-    T[k] = 1.0; V[k] = 0.0; d0[k] = 0.0f; d1[k] = 0.0f; d2[k] = 0.0f;
+    T[k] = 1.0f; V[k] = 0.0f; d0[k] = 0.0f; d1[k] = 0.0f; d2[k] = 0.0f;
     last[k] = 0;
     if (px < W && py < H) {
       const size_t pix = (size_t)py * W + px;
-      T[k] = (double)final_T[pix];
+      T[k] = final_T[pix];
       last[k] = n_contrib[pix];
       d0[k] = dimg[pix];
       d1[k] = dimg[plane + pix];
       d2[k] = dimg[2 * plane + pix];
-      V[k] = (double)(d0[k] * bg0 + d1[k] * bg1 + d2[k] * bg2);
+      V[k] = d0[k] * bg0 + d1[k] * bg1 + d2[k] * bg2;
       mylast = max(mylast, last[k]);
     }
   }
@@ -157,6 +149,10 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         contrib = contrib || okv[k];
       }
       if (!__any(contrib)) continue;
+      {
+      // the gradient arithmetic may contract into FMAs (the decision above must not: it
+      // repeats the forward's, bit for bit)
+#pragma clang fp contract(fast)
       float gr[kG2d];
 #pragma unroll
       for (int c = 0; c < kG2d; ++c) gr[c] = 0.0f;
@@ -168,15 +164,15 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       for (int k = 0; k < PPT; ++k) {
         const bool ok = okv[k];
         const float alpha = alv[k], G = Gv[k], dy = dyv[k];
-        const double Ti64 = T[k] * recip64(1.0 - (double)alpha);
-        const float wT = ok ? alpha * (float)Ti64 : 0.0f;
+        const float Ti = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
+        const float wT = ok ? alpha * Ti : 0.0f;
         const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * c2;   // dL/dC . c
-        const float dalpha = (ok && a0v[k] <= kAlphaMax) ? (float)(Ti64 * ((double)dcc - V[k])) : 0.0f;
+        const float dalpha = (ok && a0v[k] <= kAlphaMax) ? Ti * (dcc - V[k]) : 0.0f;
         gr[6] = fmaf(wT, d0[k], gr[6]);
         gr[7] = fmaf(wT, d1[k], gr[7]);
         gr[8] = fmaf(wT, d2[k], gr[8]);
-        V[k] = ok ? fma((double)alpha, (double)dcc - V[k], V[k]) : V[k];   // alpha dcc + (1 - alpha) V
-        T[k] = ok ? Ti64 : T[k];
+        V[k] = ok ? fmaf(alpha, dcc - V[k], V[k]) : V[k];   // alpha dcc + (1 - alpha) V
+        T[k] = ok ? Ti : T[k];
         gr[5] = fmaf(dalpha, G, gr[5]);
         const float dq = -0.5f * alpha * dalpha;
         const float dqy = dq * dy;
@@ -202,6 +198,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         x += __shfl_xor(x, 16, 64);
         x += __shfl_xor(x, 32, 64);
         if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[(size_t)s_id[jl] * kG2d + lane], x);
+      }
       }
     }
   }
