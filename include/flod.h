@@ -288,7 +288,9 @@ typedef struct {
                                    (tile, depth bits, index)                              */
   const uint32_t *ranges;       /* [tiles,2] [start, end) of each tile in the list          */
   const uint32_t *depth_bits;   /* [n_candidates] bits of the view-space depth (FP32)       */
-  const uint32_t *rect;         /* [n_candidates,2] (x0 | y0<<16, x1 | y1<<16) inclusive    */
+  const float *bin;             /* [n_candidates,8] binning record of rendered candidates:
+                                   mu'x, mu'y, conic a, b, c, support bound Q_g, then (bits)
+                                   the tile rectangle x0 | y0<<16 and x1 | y1<<16, inclusive */
   const uint32_t *tiles_touched;/* [n_candidates] 0 = not rendered                          */
   const float *xy_conic;        /* [n_candidates,4] mu'x, mu'y (FP32 rounding of the FP64
                                    projection), conic a, conic b                            */

@@ -17,10 +17,10 @@ struct Buf {
 };
 
 enum BufId {
-  B_XYAB, B_COP, B_BLUE, B_DEPTH, B_RECT, B_TILES, B_BLOCKVIS, B_PREFIX,
+  B_XYAB, B_COP, B_BLUE, B_DEPTH, B_BIN, B_TILES, B_BLOCKVIS, B_PREFIX,
   B_DKEY0, B_DKEY1, B_DVAL0, B_DVAL1, B_TBSUM, B_TPREFIX,
   B_TKEY0, B_TKEY1, B_TVAL0, B_TVAL1, B_HIST, B_SCAN, B_TOT, B_RANGES, B_COUNTERS,
-  B_G2D, B_SSIM, B_QSUP, B_TAKEN, B_TILE_TAKEN, B_TILE_ORDER, B_COUNT
+  B_G2D, B_SSIM, B_TAKEN, B_TILE_TAKEN, B_TILE_ORDER, B_COUNT
 };
 
 struct Saved {
@@ -246,9 +246,8 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   need(B_COP, 16 * (size_t)N);
   need(B_BLUE, 8 * (size_t)N);
   need(B_DEPTH, 4 * (size_t)N);
-  need(B_RECT, 8 * (size_t)N);
+  need(B_BIN, 32 * (size_t)N);
   need(B_TILES, 4 * (size_t)N);
-  need(B_QSUP, 4 * (size_t)N);
   need(B_BLOCKVIS, 4 * (size_t)nb);
   need(B_PREFIX, 8 * (size_t)nb);
   need(B_DKEY0, 4 * (size_t)N);
@@ -271,6 +270,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   uint32_t *counters = P<uint32_t>(c, B_COUNTERS);
   const bool speculate = N > 0 && cap > 0;
   int dres = 0;
+  uint32_t *sorted_tiles = nullptr;
   // tile counts in depth order and their scan; K (guarded by `guard`) to counters[kCntInstances]
   auto offsets = [&](int64_t guard) -> hipError_t {
     return launch_scan_blocks(P<uint32_t>(c, B_TBSUM), counters + kCntVisible, kBlock,
@@ -284,9 +284,8 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     o.cop = P<float4>(c, B_COP);
     o.blue = P<float2>(c, B_BLUE);
     o.depth = P<uint32_t>(c, B_DEPTH);
-    o.rect = P<uint2>(c, B_RECT);
+    o.bin = P<float4>(c, B_BIN);
     o.tiles = P<uint32_t>(c, B_TILES);
-    o.qsup = P<float>(c, B_QSUP);
     o.block_vis = P<uint32_t>(c, B_BLOCKVIS);
     o.n_selected = reinterpret_cast<unsigned long long *>(n_selected);
     tm.begin(FLOD_STAGE_PREPROCESS);
@@ -308,7 +307,10 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
       return FLOD_ERR_DEVICE;
     tm.end();
     tm.begin(FLOD_STAGE_OFFSETS);
-    if (launch_tile_counts(dv[dres], counters + kCntVisible, N, o.tiles, P<uint32_t>(c, B_TBSUM), s) != hipSuccess ||
+    // tile counts in depth order go to the depth sort's spare key buffer, for the emission
+    sorted_tiles = dk[dres ^ 1];
+    if (launch_tile_counts(dv[dres], counters + kCntVisible, N, o.tiles, P<uint32_t>(c, B_TBSUM), sorted_tiles,
+                           s) != hipSuccess ||
         offsets(speculate ? cap : 0xFFFFFFFEll) != hipSuccess)
       return FLOD_ERR_DEVICE;
     // the count read-back: [visible u32 | guarded K u32], [K u64]
@@ -326,8 +328,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     if (k_max > 0) {
       uint32_t *dv = dres ? P<uint32_t>(c, B_DVAL1) : P<uint32_t>(c, B_DVAL0);
       tm.begin(FLOD_STAGE_EMIT);
-      if (launch_emit(dv, counters + kCntVisible, counters + kCntInstances, N, P<uint32_t>(c, B_TILES),
-                      P<float4>(c, B_XYAB), P<float4>(c, B_COP), P<uint2>(c, B_RECT), P<float>(c, B_QSUP),
+      if (launch_emit(dv, counters + kCntVisible, counters + kCntInstances, N, sorted_tiles, P<float4>(c, B_BIN),
                       P<unsigned long long>(c, B_TPREFIX), cam.tiles_x, cam.tiles_y, tk[0], tv[0], s) != hipSuccess)
         return FLOD_ERR_DEVICE;
       tm.end();
@@ -942,7 +943,7 @@ flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out) {
   out->values = sv.sorted_vals ? P<uint32_t>(c, B_TVAL1) : P<uint32_t>(c, B_TVAL0);
   out->ranges = P<uint32_t>(c, B_RANGES);
   out->depth_bits = P<uint32_t>(c, B_DEPTH);
-  out->rect = P<uint32_t>(c, B_RECT);
+  out->bin = P<float>(c, B_BIN);
   out->tiles_touched = P<uint32_t>(c, B_TILES);
   out->xy_conic = P<float>(c, B_XYAB);
   out->conic_c_opacity_rg = P<float>(c, B_COP);

@@ -62,9 +62,9 @@ struct PreOut {
   float4 *cop;        // conic c, opacity, red, green
   float2 *blue;       // blue, packed bf16 residuals of mu' (bits)
   uint32_t *depth;    // FP32 bits of the view-space depth
-  uint2 *rect;        // (x0 | y0 << 16, x1 | y1 << 16)
+  float4 *bin;        // binning record, two per candidate: (mu'x, mu'y, conic a, conic b) and
+                      // (conic c, support bound Q_g, bits of x0 | y0 << 16, bits of x1 | y1 << 16)
   uint32_t *tiles;    // tiles touched, 0 when culled or not selected
-  float *qsup;        // support bound Q_g of the opacity (footprint input)
   uint32_t *block_vis;  // per-workgroup count of visible candidates
   unsigned long long *n_selected;   // per-level selected counts (may be null)
 };
@@ -112,11 +112,12 @@ hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_
                              int64_t n_max, int bits, uint32_t *hist, uint32_t *scan,
                              uint32_t *tot, int *result_buf, hipStream_t s);
 hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_max,
-                              const uint32_t *tiles, uint32_t *block_sum, hipStream_t s);
+                              const uint32_t *tiles, uint32_t *block_sum, uint32_t *sorted_tiles,
+                              hipStream_t s);
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const uint32_t *k_ptr,
-                       int64_t n_max, const uint32_t *tiles, const float4 *xyab, const float4 *cop,
-                       const uint2 *rect, const float *qsup, const unsigned long long *prefix,
-                       int tiles_x, int tiles_y, uint32_t *tile_ids, uint32_t *values, hipStream_t s);
+                       int64_t n_max, const uint32_t *sorted_tiles, const float4 *bin,
+                       const unsigned long long *prefix, int tiles_x, int tiles_y, uint32_t *tile_ids,
+                       uint32_t *values, hipStream_t s);
 hipError_t launch_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, int64_t k_max, int n_tiles,
                          uint2 *ranges, hipStream_t s);
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab,

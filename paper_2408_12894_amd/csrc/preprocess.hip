@@ -84,8 +84,9 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreParams p, PreOut o) {
             o.cop[i] = make_float4(cc, opac, col[0], col[1]);
             o.blue[i] = make_float2(col[2], __uint_as_float(pack_mu_lo(pr.mx, pr.my, hx, hy)));
             o.depth[i] = __float_as_uint((float)pr.tz);
-            o.rect[i] = make_uint2(rx0 | ((uint32_t)fp.ty0 << 16), rx1 | ((uint32_t)fp.ty1 << 16));
-            o.qsup[i] = qg;
+            o.bin[2 * i] = make_float4(hx, hy, ca, cb);
+            o.bin[2 * i + 1] = make_float4(cc, qg, __uint_as_float(rx0 | ((uint32_t)fp.ty0 << 16)),
+                                           __uint_as_float(rx1 | ((uint32_t)fp.ty1 << 16)));
           }
         }
       }

@@ -295,21 +295,24 @@ hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_
 // Tiles touched in depth order: per-workgroup sums over the sorted visible Gaussians.
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
-                                                        const uint32_t *tiles, uint32_t *block_sum) {
+                                                        const uint32_t *tiles, uint32_t *block_sum,
+                                                        uint32_t *sorted_tiles) {
   const uint32_t n = *n_ptr;
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
   if (blockIdx.x * kBlock >= n) return;
   const uint32_t c = (j < n) ? tiles[sorted_ids[j]] : 0u;
+  if (j < n) sorted_tiles[j] = c;
   uint32_t tot;
   block_excl_scan(c, &tot);
   if (threadIdx.x == 0) block_sum[blockIdx.x] = tot;
 }
 
 hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_max,
-                              const uint32_t *tiles, uint32_t *block_sum, hipStream_t s) {
+                              const uint32_t *tiles, uint32_t *block_sum, uint32_t *sorted_tiles,
+                              hipStream_t s) {
   if (n_max <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)((n_max + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     sorted_ids, n_ptr, tiles, block_sum);
+                     sorted_ids, n_ptr, tiles, block_sum, sorted_tiles);
   return hipGetLastError();
 }
 
@@ -370,11 +373,9 @@ struct EmitWindow {
 };
 
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr,
-                                                 const uint32_t *k_ptr, const uint32_t *tiles,
-                                                 const float4 *xyab, const float4 *cop,
-                                                 const uint2 *rect, const float *qsup,
-                                                 const unsigned long long *prefix, int tiles_x,
-                                                 int tiles_y, uint32_t *__restrict__ tile_ids,
+                                                 const uint32_t *k_ptr, const uint32_t *sorted_tiles,
+                                                 const float4 *bin, const unsigned long long *prefix,
+                                                 int tiles_x, int tiles_y, uint32_t *__restrict__ tile_ids,
                                                  uint32_t *__restrict__ values) {
   __shared__ uint32_t s_tile[kEmitCap];
   __shared__ uint32_t s_val[kEmitCap];
@@ -383,13 +384,19 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
   if (blockIdx.x * kBlock >= n || *k_ptr == 0u) return;   // no instances, or more than the buffers hold
   const bool valid = j < n;
   const uint32_t g = valid ? sorted_ids[j] : 0u;
-  const uint32_t c = valid ? tiles[g] : 0u;
+  const uint32_t c = valid ? sorted_tiles[j] : 0u;
   uint32_t tot;
   const uint32_t off = block_excl_scan(c, &tot);     // local position of this Gaussian's first instance
   const unsigned long long obase = prefix[blockIdx.x];
   const int lane = threadIdx.x & 63;
+  // the Gaussian's binning record: one 32-byte gather (mu', conic, support bound, rectangle)
+  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+  if (c > 0) {
+    r0 = bin[2 * (size_t)g];
+    r1 = bin[2 * (size_t)g + 1];
+  }
   RectSpan rs{0, 0, 0, 0, false};
-  if (c > 0) rs = rect_of(rect[g], c);
+  if (c > 0) rs = rect_of(make_uint2(__float_as_uint(r1.z), __float_as_uint(r1.w)), c);
   const uint32_t cf = rs.full ? c : 0u;
   const uint32_t incl_f = wave_incl_scan(cf);
   const uint32_t total_f = __shfl(incl_f, 63, 64);
@@ -415,9 +422,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
       }
       // small footprints that do not fill their rectangle, one thread each
       if (c > 0 && c <= kEmitSolo && !rs.full && win.meets(off, off + c)) {
-        const float4 A = xyab[g];
         Footprint fp;
-        footprint(A.x, A.y, A.z, A.w, cop[g].x, support_span(qsup[g]), tiles_y, fp);
+        footprint(r0.x, r0.y, r0.z, r0.w, r1.x, support_span(r1.y), tiles_y, fp);
         uint32_t pos = off;
         for (int ty = fp.ty0; ty <= fp.ty1; ++ty) {
           int tx0, tx1;
@@ -434,9 +440,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
         const uint32_t cs = __shfl(c, src, 64);
         if (!win.meets(os, os + cs)) continue;
         const uint32_t gs = __shfl(g, src, 64);
-        const float4 A = xyab[gs];
         Footprint fp;
-        footprint(A.x, A.y, A.z, A.w, cop[gs].x, support_span(qsup[gs]), tiles_y, fp);
+        footprint(__shfl(r0.x, src, 64), __shfl(r0.y, src, 64), __shfl(r0.z, src, 64), __shfl(r0.w, src, 64),
+                  __shfl(r1.x, src, 64), support_span(__shfl(r1.y, src, 64)), tiles_y, fp);
         const int nrows = fp.ty1 - fp.ty0 + 1;
         uint32_t base = os;
         for (int rb = 0; rb < nrows; rb += 64) {
@@ -468,12 +474,11 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
 }
 
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const uint32_t *k_ptr, int64_t n_max,
-                       const uint32_t *tiles, const float4 *xyab, const float4 *cop, const uint2 *rect,
-                       const float *qsup, const unsigned long long *prefix, int tiles_x, int tiles_y,
-                       uint32_t *tile_ids, uint32_t *values, hipStream_t s) {
+                       const uint32_t *sorted_tiles, const float4 *bin, const unsigned long long *prefix,
+                       int tiles_x, int tiles_y, uint32_t *tile_ids, uint32_t *values, hipStream_t s) {
   if (n_max <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_max + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, sorted_ids,
-                     n_ptr, k_ptr, tiles, xyab, cop, rect, qsup, prefix, tiles_x, tiles_y, tile_ids, values);
+                     n_ptr, k_ptr, sorted_tiles, bin, prefix, tiles_x, tiles_y, tile_ids, values);
   return hipGetLastError();
 }
 

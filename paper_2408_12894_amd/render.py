@@ -321,7 +321,8 @@ class Renderer:
         return dict(tile_ids=get(v.tile_ids, K, np.uint32), values=get(v.values, K, np.uint32),
                     ranges=get(v.ranges, 2 * tiles, np.uint32).reshape(tiles, 2),
                     depth_bits=get(v.depth_bits, N, np.uint32),
-                    rect=get(v.rect, 2 * N, np.uint32).reshape(N, 2),
+                    rect=get(v.bin, 8 * N, np.uint32).reshape(N, 8)[:, 6:8].copy(),
+                    bin=get(v.bin, 8 * N, np.float32).reshape(N, 8),
                     tiles_touched=get(v.tiles_touched, N, np.uint32),
                     xy_conic=get(v.xy_conic, 4 * N, np.float32).reshape(N, 4),
                     cop=get(v.conic_c_opacity_rg, 4 * N, np.float32).reshape(N, 4),

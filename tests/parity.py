@@ -29,7 +29,7 @@ def check_keys(view, k, idx=None):
     vis = k["visible"].astype(bool)
     if idx is not None:
         vis = vis[idx]
-        sub = {n: k[n][idx] for n in ("depth_bits", "rect", "tiles", "mxy", "conic", "mu_lo")}
+        sub = {n: k[n][idx] for n in ("depth_bits", "rect", "tiles", "mxy", "conic", "mu_lo", "qsup")}
     else:
         sub = k
     g_vis = view["tiles_touched"] > 0
@@ -42,6 +42,14 @@ def check_keys(view, k, idx=None):
     g_conic = np.stack([view["xy_conic"][vis, 2], view["xy_conic"][vis, 3], view["cop"][vis, 0]], 1)
     np.testing.assert_array_equal(g_conic.view(np.uint32), sub["conic"][vis].view(np.uint32), err_msg="conic bits")
     np.testing.assert_array_equal(view["mu_lo_bits"][vis], sub["mu_lo"][vis], err_msg="mu' residual bits")
+    # the binning record repeats mu' and the conic, and carries the support bound Q_g
+    rec = view["bin"][vis]
+    np.testing.assert_array_equal(rec[:, :4].view(np.uint32), view["xy_conic"][vis].view(np.uint32),
+                                  err_msg="record mu', conic a, b")
+    np.testing.assert_array_equal(rec[:, 4].view(np.uint32), view["cop"][vis, 0].view(np.uint32),
+                                  err_msg="record conic c")
+    np.testing.assert_array_equal(rec[:, 5].view(np.uint32), np.asarray(sub["qsup"], np.float32)[vis].view(np.uint32),
+                                  err_msg="record support bound")
 
 
 def check_instances(view, k, index_offset=0):
