@@ -100,16 +100,16 @@ def timed(fn, n, warm, sync):
 def algorithmic_bytes(stage, N, n_vis, K, P, tiles):
     """Bytes a stage must move (one launch), per its definition in the design doc."""
     return {
-        "preprocess": (236 + 56) * N,
+        "preprocess": (236 + 80) * N,
         "compact": 8 * N + 8 * n_vis,
         "depth_sort": 4 * 2 * 8 * n_vis,
         "offsets": 8 * n_vis,
-        "emit": 32 * n_vis + 8 * K,
+        "emit": 40 * n_vis + 8 * K,
         "tile_sort": 2 * (4 + 16) * K,
         "ranges": 4 * K + 8 * tiles,
         "blend": 44 * K + 20 * P,
         "blend_bwd": 44 * K + 20 * P + 12 * P + 36 * K,
-        "preprocess_bwd": (236 + 56 + 36 + 236) * N,
+        "preprocess_bwd": (236 + 4 + 36 + 236) * N,
     }[stage]
 
 
