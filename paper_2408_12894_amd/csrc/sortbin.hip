@@ -52,24 +52,44 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
 // total32 receives the total when it is at most cap32 and 0 otherwise: kernels sized for
 // cap32 items read it as their item count and then do nothing.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_scan_blocks(const uint32_t *in, const uint32_t *n_items,
-                                                        int items_per_block, unsigned long long *prefix,
-                                                        uint32_t *total32, unsigned long long *total64,
-                                                        unsigned long long cap32, int max_blocks) {
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const uint32_t *in, const uint32_t *n_items,
+                                                              int items_per_block, unsigned long long *prefix,
+                                                              uint32_t *total32, unsigned long long *total64,
+                                                              unsigned long long cap32, int max_blocks) {
+  __shared__ unsigned long long s_w[kScanThreads / 64];
   int nb = max_blocks;
   if (n_items) nb = (int)(((unsigned long long)*n_items + items_per_block - 1) / items_per_block);
-  unsigned long long run = 0;
-  for (int base = 0; base < nb; base += kBlock) {
-    const int k = base + threadIdx.x;
-    uint32_t v = (k < nb) ? in[k] : 0u;
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(v, &tot);
-    if (k < nb) prefix[k] = run + ex;
-    run += tot;
+  // thread t owns the contiguous counts [t per, (t + 1) per): its sum, a workgroup scan of the
+  // sums, then its exclusive prefixes (a second read of its counts, from cache)
+  const int per = (nb + kScanThreads - 1) / kScanThreads;
+  const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
+  unsigned long long mine = 0;
+  for (int k = lo; k < hi; ++k) mine += in[k];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned long long inc = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) s_w[w] = inc;
+  __syncthreads();
+  unsigned long long run = inc - mine, total = 0;
+#pragma unroll
+  for (int k = 0; k < kScanThreads / 64; ++k) {
+    const unsigned long long t = s_w[k];
+    run += (k < w) ? t : 0ull;
+    total += t;
+  }
+  for (int k = lo; k < hi; ++k) {
+    prefix[k] = run;
+    run += in[k];
   }
   if (threadIdx.x == 0) {
-    if (total64) *total64 = run;
-    if (total32) *total32 = run > cap32 ? 0u : (uint32_t)run;
+    if (total64) *total64 = total;
+    if (total32) *total32 = total > cap32 ? 0u : (uint32_t)total;
   }
 }
 
@@ -77,7 +97,7 @@ hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int i
                               unsigned long long *prefix, uint32_t *total32, unsigned long long *total64,
                               int max_blocks, hipStream_t s, unsigned long long cap32) {
   if (cap32 > 0xFFFFFFFFull) cap32 = 0xFFFFFFFFull;
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, s, in, n_items, items_per_block, prefix,
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, in, n_items, items_per_block, prefix,
                      total32, total64, cap32, max_blocks);
   return hipGetLastError();
 }
@@ -486,13 +506,31 @@ hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const 
 // Tile ranges from the sorted tile ids (ranges zeroed beforehand); the id count is read on
 // the device, the grid covers k_max ids.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, uint2 *ranges) {
+__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *__restrict__ tile_ids, const uint32_t *k_ptr,
+                                                   uint2 *__restrict__ ranges) {
   const uint32_t K = *k_ptr;
-  const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= K) return;
-  const uint32_t t = tile_ids[k];
-  if (k == 0 || tile_ids[k - 1] != t) ranges[t].x = k;
-  if (k == K - 1 || tile_ids[k + 1] != t) ranges[t].y = k + 1;
+  const uint32_t k0 = 4u * (blockIdx.x * kBlock + threadIdx.x);   // four ids per thread
+  if (k0 >= K) return;
+  uint32_t t[4];
+  if (k0 + 4u <= K) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(tile_ids + k0);
+    t[0] = v.x; t[1] = v.y; t[2] = v.z; t[3] = v.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[i] = (k0 + i < K) ? tile_ids[k0 + i] : 0u;
+  }
+  uint32_t prev = (k0 > 0u) ? tile_ids[k0 - 1u] : 0xFFFFFFFFu;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t k = k0 + i;
+    if (k >= K) break;
+    if (t[i] != prev) {
+      ranges[t[i]].x = k;
+      if (k > 0u) ranges[prev].y = k;
+    }
+    prev = t[i];
+  }
+  if (k0 + 4u >= K) ranges[prev].y = K;   // the last id closes its tile
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
@@ -510,7 +548,8 @@ hipError_t launch_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, int64_
                          uint2 *ranges, hipStream_t s) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * (int64_t)n_tiles, s);
   if (e != hipSuccess || k_max <= 0) return e;
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)((k_max + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tile_ids,
+  const int64_t threads = (k_max + 3) / 4;
+  hipLaunchKernelGGL(k_ranges, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tile_ids,
                      k_ptr, ranges);
   return hipGetLastError();
 }
