@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       for (int k = 0; k < PPT; ++k) {
         dyv[k] = (fy[k] - A.y) - loy;
         const float q = conic_q(A.z, A.w, B.x, dx, dyv[k]);
-        Gv[k] = __expf(-0.5f * q);
+        Gv[k] = gauss_weight(q);
         a0v[k] = B.y * Gv[k];
         alv[k] = fminf(kAlphaMax, a0v[k]);
         okv[k] = jpos < last[k] && q <= kQCut && alv[k] >= kAlphaMin;

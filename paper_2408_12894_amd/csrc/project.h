@@ -290,10 +290,16 @@ __device__ __forceinline__ float dist2(float m0, float m1, float m2, const float
   return (dx * dx + dy * dy) + dz * dz;
 }
 
+// exp(-q/2) as one hardware exp2 of a scaled q, shared by both blend kernels (the same
+// bits on both sides; within a few ulp of exp).
+__device__ __forceinline__ float gauss_weight(float q) { return __builtin_amdgcn_exp2f(q * -0.72134752044448170f); }
+
 // q = d^T conic d, shared by the forward and backward blend so both take the same
 // decisions (support cut, alpha floor) on the same bits.
 __device__ __forceinline__ float conic_q(float a, float b, float c, float dx, float dy) {
-  return fmaf(a * dx, dx, fmaf(c * dy, dy, 2.0f * b * dx * dy));
+  const float ax2 = (a * dx) * dx;      // depend on the column only: a lane's pixels of one
+  const float b2x = (2.0f * b) * dx;    // column share them
+  return fmaf(dy, fmaf(c, dy, b2x), ax2);
 }
 
 }  // namespace flod
