@@ -60,6 +60,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   __shared__ int s_max[WAVES];
   const int tile = (int)order[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, lane16 = tid & 15;
+  const int comp = row_sum9_component(lane16);   // gradient component this lane adds
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
   const int px = x0 + (tid & (kTile - 1));
   const float fx = (float)px + 0.5f;
@@ -186,18 +187,13 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       gr[0] = -2.0f * (A.z * dx * S0 + A.w * S1);
       gr[1] = -2.0f * (A.w * dx * S0 + B.x * S1);
       {
-        // nine in-row DPP reductions (interleaved, no control flow between them) leave each
-        // row's sums in all its lanes; lane 16 r + c keeps component c, two cross-row
-        // exchanges complete the sums, and lanes 0..8 add them with one atomic instruction
-        float x = 0.0f;
-#pragma unroll
-        for (int c = 0; c < kG2d; ++c) {
-          const float rs = row_sum16(gr[c]);
-          x = (lane16 == c) ? rs : x;
-        }
+        // the nine components summed within each DPP row (transposed: one component per
+        // lane), two cross-row exchanges complete the sums, and the nine lanes of row 0 that
+        // hold a component add it with one atomic instruction
+        float x = row_sum9(gr, lane16);
         x += __shfl_xor(x, 16, 64);
         x += __shfl_xor(x, 32, 64);
-        if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[(size_t)s_id[jl] * kG2d + lane], x);
+        if (lane < 16 && comp >= 0 && x != 0.0f) atomicAdd(&g2d[(size_t)s_id[jl] * kG2d + comp], x);
       }
       }
     }
