@@ -32,7 +32,7 @@ constexpr int kBwdPix = FLOD_BWD_PIX;   // pixels per thread: 4 = one wave64 per
 #ifndef FLOD_BWD_BATCH
 #define FLOD_BWD_BATCH 128
 #endif
-// List entries staged in LDS per batch: 128 x 44 B = 5.6 KB per one-wave workgroup, so LDS
+// List entries staged in LDS per batch: 128 x 56 B = 7 KB per one-wave workgroup, so LDS
 // does not cap the waves a CU holds below what the registers allow.
 constexpr int kBwdBatch = FLOD_BWD_BATCH;
 
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   constexpr int WAVES = NT / 64;
   __shared__ float4 s_a[kBwdBatch];
   __shared__ float4 s_b[kBwdBatch];
-  __shared__ float2 s_c[kBwdBatch];
+  __shared__ float4 s_c[kBwdBatch];
   __shared__ uint32_t s_id[kBwdBatch];
   __shared__ int s_pos[kBwdBatch];
   __shared__ int s_max[WAVES];
@@ -118,9 +118,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         const uint32_t g = values[rg.x + start + e];
         s_id[idx] = g;
         s_pos[idx] = start + e;
-        s_a[idx] = xyab[g];
-        s_b[idx] = cop[g];
-        s_c[idx] = blue[g];
+        stage_entry(xyab, cop, blue, g, s_a[idx], s_b[idx], s_c[idx]);
       }
     }
     __syncthreads();
@@ -128,11 +126,10 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       const int jpos = s_pos[jl];
       const float4 A = s_a[jl];
       const float4 B = s_b[jl];
-      const float2 BL = s_c[jl];
+      const float4 BL = s_c[jl];
       const float c2 = BL.x;
-      const uint32_t lo = __float_as_uint(BL.y);
-      const float loy = mu_lo_y(lo);
-      const float dx = (fx - A.x) - mu_lo_x(lo);
+      const float loy = BL.z;
+      const float dx = (fx - A.x) - BL.y;
       // first only what decides whether a pixel takes part; the transmittance recovery and
       // the gradient run when some pixel of the wave does (predicated per pixel: a pixel
       // that does not take part adds exact zeros and keeps its T and V)
@@ -184,8 +181,9 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       gr[2] = dx * dx * S0;
       gr[3] = 2.0f * dx * S1;
       gr[4] = S2;
-      gr[0] = -2.0f * (A.z * dx * S0 + A.w * S1);
-      gr[1] = -2.0f * (A.w * dx * S0 + B.x * S1);
+      // A.w = 2 b: dL/dmu' = -2 (a dx S0 + b S1, b dx S0 + c S1)
+      gr[0] = -(2.0f * A.z * dx * S0 + A.w * S1);
+      gr[1] = -(A.w * dx * S0 + 2.0f * B.x * S1);
       {
         // the nine components summed within each DPP row (transposed: one component per
         // lane), two cross-row exchanges complete the sums, and the nine lanes of row 0 that

@@ -3,8 +3,8 @@
 // One workgroup per 16x16 tile with PPT pixels per thread: thread t owns the pixels
 // (t % 16, t / 16 + (256 / PPT / 16) k), k < PPT, so each list entry staged in LDS is read
 // once per thread and applied to PPT pixels. The tile's
-// sorted list is consumed in batches of 256 entries (40 bytes each: mu' and its residual,
-// conic, opacity, colour). Per pixel:
+// sorted list is consumed in batches of 256 entries (48 bytes each in LDS: mu' and its
+// residual, conic, opacity, colour, decoded once per entry). Per pixel:
 //   q = d^T conic d (d = pixel centre - mu', formed as (centre - hi) - lo); skip if q > 9
 //   alpha = min(0.99, o exp(-q/2)); skip if alpha < 1/255
 //   stop (without blending) once T (1 - alpha) < 1e-4
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
   constexpr int ROWS = NT / kTile;          // pixel rows covered by one pass of the threads
   __shared__ float4 s_a[kBatch];
   __shared__ float4 s_b[kBatch];
-  __shared__ float2 s_c[kBatch];
+  __shared__ float4 s_c[kBatch];
   __shared__ uint8_t s_taken[kBatch];
   __shared__ int s_count[NT / 64];
   const int tile = (int)order[blockIdx.x];
@@ -90,9 +90,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
     for (int e = tid; e < kBatch; e += NT) {
       if (start + e < n) {
         const uint32_t g = values[rg.x + start + e];
-        s_a[e] = xyab[g];
-        s_b[e] = cop[g];
-        s_c[e] = blue[g];
+        stage_entry(xyab, cop, blue, g, s_a[e], s_b[e], s_c[e]);
       }
     }
     __syncthreads();
@@ -107,11 +105,10 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
       if (!any_live) break;
       const float4 A = s_a[j];
       const float4 B = s_b[j];
-      const float2 BL = s_c[j];
+      const float4 BL = s_c[j];
       const float c2 = BL.x;
-      const uint32_t lo = __float_as_uint(BL.y);
-      const float loy = mu_lo_y(lo);
-      const float dx = (fx - A.x) - mu_lo_x(lo);
+      const float loy = BL.z;
+      const float dx = (fx - A.x) - BL.y;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         if (done[k]) continue;

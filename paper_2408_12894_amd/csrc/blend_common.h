@@ -8,6 +8,19 @@ namespace flod {
 
 constexpr int kBatch = 256;                                // list entries staged in LDS at once
 
+// A list entry as both blend kernels stage it in LDS, decoded once per entry instead of in
+// every lane: (mu'x, mu'y, conic a, 2 conic b), (conic c, opacity, red, green) and (blue,
+// the bf16 residuals of mu' as floats, unused).
+__device__ __forceinline__ void stage_entry(const float4 *xyab, const float4 *cop, const float2 *blue, uint32_t g,
+                                            float4 &a, float4 &b, float4 &c) {
+  const float4 A = xyab[g];
+  const float2 BL = blue[g];
+  const uint32_t lo = __float_as_uint(BL.y);
+  a = make_float4(A.x, A.y, A.z, 2.0f * A.w);
+  b = cop[g];
+  c = make_float4(BL.x, mu_lo_x(lo), mu_lo_y(lo), 0.0f);
+}
+
 // Tile orders, longest first (LPT order). The blend kernels' cost per tile varies by orders of
 // magnitude between tiles; dispatched in frame order, tiles with much work often started last
 // and a kernel ended in a long ramp with most wave slots idle. The forward orders its tiles by

@@ -296,9 +296,10 @@ __device__ __forceinline__ float gauss_weight(float q) { return __builtin_amdgcn
 
 // q = d^T conic d, shared by the forward and backward blend so both take the same
 // decisions (support cut, alpha floor) on the same bits.
-__device__ __forceinline__ float conic_q(float a, float b, float c, float dx, float dy) {
-  const float ax2 = (a * dx) * dx;      // depend on the column only: a lane's pixels of one
-  const float b2x = (2.0f * b) * dx;    // column share them
+// b2 = 2 b (exact), as the blend kernels stage it.
+__device__ __forceinline__ float conic_q(float a, float b2, float c, float dx, float dy) {
+  const float ax2 = (a * dx) * dx;   // depend on the column only: a lane's pixels of one
+  const float b2x = b2 * dx;         // column share them
   return fmaf(dy, fmaf(c, dy, b2x), ax2);
 }
 
