@@ -122,6 +122,19 @@ def test_training_size_sampled(renderer):
     print(worst, nz)
 
 
+def test_4k_sampled(renderer):
+    """The 1M cluster scene at 3840x2160 (the largest serving resolution) with the loss on 256
+    sampled pixels: the backward's tile order, ranges and atomics at 32,400 tiles."""
+    _say("1M Gaussians, 3840x2160, 256 sampled pixels")
+    scene, _, bg = synth.hd_forward_case()
+    cam = synth.orbit_cameras(2, 1, 4.0, 3840, 2160)[0]
+    rng = np.random.default_rng(62)
+    pix = np.stack([rng.integers(0, 3840, 256), rng.integers(0, 2160, 256)], 1).astype(np.int32)
+    pix = np.unique(pix, axis=0)
+    worst, nz = grad_parity(renderer, scene, cam, bg, pix=pix, seed=4)
+    print(worst, nz)
+
+
 def test_autograd_l1_step(renderer):
     """rasterize() under an L1 loss: torch autograd reaches the HIP backward, and its
     gradients equal Renderer.backward with dL/dimage = sign(I - I_target) / P."""

@@ -183,3 +183,17 @@ def test_instance_capacity_growth():
         if step < 2:
             full_parity(shared, scene, cam, bg)
     assert k_seen[1] > 2 * k_seen[0]   # the second frame outgrows the first frame's buffers
+
+
+def test_4k_full_size_sampled(renderer):
+    """The same 1M cluster scene at 3840x2160, the largest serving resolution (32,400 tiles,
+    15-bit tile ids, about four times the 1080p instance count): the whole key path and
+    instance list bit-exact, the image on 256 sampled pixels."""
+    _say("1M Gaussians, 3840x2160")
+    scene, _, bg = synth.hd_forward_case()
+    cam = synth.orbit_cameras(2, 1, 4.0, 3840, 2160)[0]
+    rng = np.random.default_rng(51)
+    pix = np.stack([rng.integers(0, 3840, 256), rng.integers(0, 2160, 256)], 1).astype(np.int32)
+    err, frac, view = full_parity(renderer, scene, cam, bg, pix=pix, frac_max=0.02)
+    assert view["stats"]["tiles_x"] * view["stats"]["tiles_y"] == 32400
+    print(f"K={view['stats']['n_instances']} visible={view['stats']['n_visible']} err={err:.2e}")
