@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
         if (done[k]) continue;
         const float dy = (fy[k] - A.y) - loy;
         const float q = conic_q(A.z, A.w, B.x, dx, dy);
-        if (q > kQCut) continue;
+        if (q > BL.w) continue;
         const float alpha = fminf(kAlphaMax, B.y * gauss_weight(q));
         if (alpha < kAlphaMin) continue;
         const float Tn = T[k] * (1.0f - alpha);

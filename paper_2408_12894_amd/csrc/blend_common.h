@@ -18,7 +18,11 @@ __device__ __forceinline__ void stage_entry(const float4 *xyab, const float4 *co
   const uint32_t lo = __float_as_uint(BL.y);
   a = make_float4(A.x, A.y, A.z, 2.0f * A.w);
   b = cop[g];
-  c = make_float4(BL.x, mu_lo_x(lo), mu_lo_y(lo), 0.0f);
+  // support cut of this entry: q beyond min(9, Q_g (1 + 1e-3) + 1e-3), Q_g = 2 ln(255 o), has
+  // alpha below 1/255 by a relative 5e-4 (the binning's margin), so cutting there takes the
+  // same decisions as q <= 9 and alpha >= 1/255 while whole waves skip the exp more often
+  const float qcut = fminf(kQCut, fmaf(2.0f * logf(255.0f * b.y), 1.001f, 1e-3f));
+  c = make_float4(BL.x, mu_lo_x(lo), mu_lo_y(lo), qcut);
 }
 
 // Tile orders, longest first (LPT order). The blend kernels' cost per tile varies by orders of
