@@ -55,22 +55,47 @@ struct CountCost {        // backward: entries the forward blended somewhere in 
 
 template <class Cost>
 __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, uint32_t *__restrict__ order) {
-  __shared__ uint32_t s_hist[kOrderBuckets];
-  __shared__ uint32_t s_pos[kOrderBuckets];
-  const int tid = threadIdx.x;
-  if (tid < kOrderBuckets) s_hist[tid] = 0;
+  constexpr int W = kOrderThreads / 64;
+  // per-wave bucket counts (contention only inside a wave), then per (bucket, wave) offsets
+  __shared__ uint32_t s_cnt[W][kOrderBuckets];
+  __shared__ uint32_t s_wsum[kOrderBuckets / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int k = tid; k < W * kOrderBuckets; k += kOrderThreads) (&s_cnt[0][0])[k] = 0u;
   __syncthreads();
-  for (int t = tid; t < n; t += kOrderThreads) atomicAdd(&s_hist[cost_bucket(cost(t))], 1u);
+  const int chunk = (n + W - 1) / W;
+  const int t0 = w * chunk, t1 = min(n, t0 + chunk);
+  for (int t = t0 + lane; t < t1; t += 64) atomicAdd(&s_cnt[w][cost_bucket(cost(t))], 1u);
   __syncthreads();
-  if (tid == 0) {
-    uint32_t run = 0;
-    for (int b = kOrderBuckets - 1; b >= 0; --b) {
-      s_pos[b] = run;
-      run += s_hist[b];
+  // thread d < 256 takes bucket b = 255 - d (descending cost): its count over the waves, with
+  // each wave's count replaced by the running sum before it
+  uint32_t tot = 0u;
+  if (tid < kOrderBuckets) {
+    const int b = kOrderBuckets - 1 - tid;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const uint32_t c = s_cnt[k][b];
+      s_cnt[k][b] = tot;
+      tot += c;
     }
   }
+  // exclusive scan of the bucket totals in descending bucket order (threads 0..255)
+  uint32_t inc = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t x = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += x;
+  }
+  if (tid < kOrderBuckets && lane == 63) s_wsum[w] = inc;
   __syncthreads();
-  for (int t = tid; t < n; t += kOrderThreads) order[atomicAdd(&s_pos[cost_bucket(cost(t))], 1u)] = (uint32_t)t;
+  if (tid < kOrderBuckets) {
+    uint32_t base = inc - tot;
+    for (int k = 0; k < w; ++k) base += s_wsum[k];
+    const int b = kOrderBuckets - 1 - tid;
+#pragma unroll
+    for (int k = 0; k < W; ++k) s_cnt[k][b] += base;
+  }
+  __syncthreads();
+  for (int t = t0 + lane; t < t1; t += 64) order[atomicAdd(&s_cnt[w][cost_bucket(cost(t))], 1u)] = (uint32_t)t;
 }
 
 template <int CTRL, int ROW_MASK = 0xF>
