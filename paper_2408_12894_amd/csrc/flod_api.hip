@@ -328,7 +328,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     if (k_max > 0) {
       uint32_t *dv = dres ? P<uint32_t>(c, B_DVAL1) : P<uint32_t>(c, B_DVAL0);
       tm.begin(FLOD_STAGE_EMIT);
-      if (launch_emit(dv, counters + kCntVisible, counters + kCntInstances, N, sorted_tiles, P<float4>(c, B_BIN),
+      if (launch_emit(dv, counters + kCntVisible, counters + kCntInstances, N, k_max, sorted_tiles, P<float4>(c, B_BIN),
                       P<unsigned long long>(c, B_TPREFIX), cam.tiles_x, cam.tiles_y, tk[0], tv[0], s) != hipSuccess)
         return FLOD_ERR_DEVICE;
       tm.end();

@@ -115,7 +115,7 @@ hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
                               const uint32_t *tiles, uint32_t *block_sum, uint32_t *sorted_tiles,
                               hipStream_t s);
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const uint32_t *k_ptr,
-                       int64_t n_max, const uint32_t *sorted_tiles, const float4 *bin,
+                       int64_t n_max, int64_t k_max, const uint32_t *sorted_tiles, const float4 *bin,
                        const unsigned long long *prefix, int tiles_x, int tiles_y, uint32_t *tile_ids,
                        uint32_t *values, hipStream_t s);
 hipError_t launch_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, int64_t k_max, int n_tiles,

@@ -14,6 +14,8 @@
 // workgroups, then a scatter in which each workgroup ranks its 4096 (or 1024) keys stably in LDS
 // (wave64 ballots over the digit bits), reorders them by digit in LDS and writes each
 // digit run contiguously.
+#include <algorithm>
+
 #include "project.h"
 
 namespace flod {
@@ -25,6 +27,12 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     uint32_t t = __shfl_up(v, o, 64);
     if (lane >= o) v += t;
   }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
@@ -352,6 +360,7 @@ hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
 // ---------------------------------------------------------------------------------------
 constexpr uint32_t kEmitSolo = 64;
 constexpr uint32_t kEmitCap = 4096;   // instances staged per window (32 KB of LDS)
+constexpr uint32_t kEmitSplit = 8;    // at most this many workgroups share one block's windows
 
 struct RectSpan {
   int x0, y0, x1, y1;
@@ -401,7 +410,14 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
   __shared__ uint32_t s_val[kEmitCap];
   const uint32_t n = *n_ptr;
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  if (blockIdx.x * kBlock >= n || *k_ptr == 0u) return;   // no instances, or more than the buffers hold
+  const uint32_t K = *k_ptr;
+  if (blockIdx.x * kBlock >= n || K == 0u) return;   // no instances, or more than the buffers hold
+  // workgroup (block, split) takes the block's windows split, split + gridDim.y, ...: a block
+  // of huge footprints fills hundreds of windows, most blocks fill one
+  const uint32_t split = blockIdx.y;
+  const uint32_t nblk = (n + kBlock - 1) / kBlock;
+  const unsigned long long block_end = (blockIdx.x + 1 < nblk) ? prefix[blockIdx.x + 1] : (unsigned long long)K;
+  if ((unsigned long long)split * kEmitCap >= block_end - prefix[blockIdx.x]) return;
   const bool valid = j < n;
   const uint32_t g = valid ? sorted_ids[j] : 0u;
   const uint32_t c = valid ? sorted_tiles[j] : 0u;
@@ -425,12 +441,17 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
   const uint32_t wave_lo = __shfl(off, 0, 64), wave_hi = __shfl(off + c, 63, 64);
   const unsigned long long big_all = __ballot(c > kEmitSolo && !rs.full);
 
-  for (uint32_t w0 = 0; w0 < tot; w0 += kEmitCap) {
+  for (uint32_t w0 = split * kEmitCap; w0 < tot; w0 += gridDim.y * kEmitCap) {
     const EmitWindow win{w0, min(w0 + kEmitCap, tot), s_tile, s_val};
     if (win.meets(wave_lo, wave_hi)) {
-      // full rectangles, the whole wave at once
-      for (uint32_t v0 = 0; v0 < total_f; v0 += 64) {
-        const uint32_t v = min(v0 + (uint32_t)lane, total_f - 1u);
+      // full rectangles, the whole wave at once. A lane's full slots take consecutive
+      // positions, and positions grow with the slot index v over the wave, so the slots that
+      // land in this window are the range [va, vb): the slots before each window edge, summed
+      // over the lanes. (Walking every slot in every window made huge footprints quadratic.)
+      const uint32_t va = wave_sum_u32(cf ? min(cf, (uint32_t)max(0ll, (long long)win.w0 - (long long)off)) : 0u);
+      const uint32_t vb = wave_sum_u32(cf ? min(cf, (uint32_t)max(0ll, (long long)win.w1 - (long long)off)) : 0u);
+      for (uint32_t v0 = va; v0 < vb; v0 += 64) {
+        const uint32_t v = min(v0 + (uint32_t)lane, vb - 1u);
         const int o = owner_lane(incl_f, v);
         const uint32_t t = v - (__shfl(incl_f, o, 64) - __shfl(cf, o, 64));
         const uint32_t wo = __shfl(wf, o, 64);
@@ -438,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
         const uint32_t tile = __shfl(first_f, o, 64) + row * (uint32_t)tiles_x + (t - row * wo);
         const uint32_t pos = __shfl(off, o, 64) + t;
         const uint32_t go = __shfl(g, o, 64);
-        if (v0 + (uint32_t)lane < total_f) win.put(pos, tile, go);
+        if (v0 + (uint32_t)lane < vb) win.put(pos, tile, go);
       }
       // small footprints that do not fill their rectangle, one thread each
       if (c > 0 && c <= kEmitSolo && !rs.full && win.meets(off, off + c)) {
@@ -473,14 +494,18 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
           const uint32_t incl = wave_incl_scan(wr);
           const uint32_t total = __shfl(incl, 63, 64);
           const uint32_t first = (uint32_t)(ty * tiles_x + tx0);
-          for (uint32_t v0 = 0; v0 < total; v0 += 64) {
-            const uint32_t v = min(v0 + (uint32_t)lane, total - 1u);
+          // only the slots of these rows whose positions fall in the window
+          const uint32_t va = (uint32_t)min((long long)total, max(0ll, (long long)win.w0 - (long long)base));
+          const uint32_t vb = (uint32_t)min((long long)total, max(0ll, (long long)win.w1 - (long long)base));
+          for (uint32_t v0 = va; v0 < vb; v0 += 64) {
+            const uint32_t v = min(v0 + (uint32_t)lane, vb - 1u);
             const int o = owner_lane(incl, v);
             const uint32_t t = v - (__shfl(incl, o, 64) - __shfl(wr, o, 64));
             const uint32_t tile = __shfl(first, o, 64) + t;
-            if (v0 + (uint32_t)lane < total) win.put(base + v, tile, gs);
+            if (v0 + (uint32_t)lane < vb) win.put(base + v, tile, gs);
           }
           base += total;
+          if (base >= win.w1) break;   // later rows land past the window
         }
       }
     }
@@ -494,11 +519,17 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
 }
 
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const uint32_t *k_ptr, int64_t n_max,
-                       const uint32_t *sorted_tiles, const float4 *bin, const unsigned long long *prefix,
-                       int tiles_x, int tiles_y, uint32_t *tile_ids, uint32_t *values, hipStream_t s) {
+                       int64_t k_max, const uint32_t *sorted_tiles, const float4 *bin,
+                       const unsigned long long *prefix, int tiles_x, int tiles_y, uint32_t *tile_ids,
+                       uint32_t *values, hipStream_t s) {
   if (n_max <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_max + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, sorted_ids,
-                     n_ptr, k_ptr, sorted_tiles, bin, prefix, tiles_x, tiles_y, tile_ids, values);
+  // workgroups per block: enough for the windows an average block of up to k_max instances
+  // fills (1 when blocks fit a window, as they do for small footprints)
+  const int64_t blocks = (n_max + kBlock - 1) / kBlock;
+  const int64_t windows = (k_max + blocks * (int64_t)kEmitCap - 1) / (blocks * (int64_t)kEmitCap);
+  const unsigned split = (unsigned)std::min<int64_t>(kEmitSplit, std::max<int64_t>(1, windows));
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks, split), dim3(kBlock), 0, s, sorted_ids, n_ptr, k_ptr,
+                     sorted_tiles, bin, prefix, tiles_x, tiles_y, tile_ids, values);
   return hipGetLastError();
 }
 

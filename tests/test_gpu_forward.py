@@ -197,3 +197,20 @@ def test_4k_full_size_sampled(renderer):
     err, frac, view = full_parity(renderer, scene, cam, bg, pix=pix, frac_max=0.02)
     assert view["stats"]["tiles_x"] * view["stats"]["tiles_y"] == 32400
     print(f"K={view['stats']['n_instances']} visible={view['stats']['n_visible']} err={err:.2e}")
+
+
+def test_huge_footprints_many_windows(renderer):
+    """Coarse-level Gaussians (scale floor 0.2, as level 1 of the stack) at 3840x2160: single
+    footprints of thousands of tiles, so one emission workgroup fills hundreds of 4096-instance
+    windows. Key path and instance list bit-exact, image on 256 sampled pixels."""
+    _say("3k level-1 Gaussians, 3840x2160")
+    scene = synth.cluster_scene(3000, seed=11, layout_seed=1, s_min=0.2)
+    cam = synth.orbit_cameras(2, 1, 4.0, 3840, 2160)[0]
+    rng = np.random.default_rng(52)
+    pix = np.stack([rng.integers(0, 3840, 256), rng.integers(0, 2160, 256)], 1).astype(np.int32)
+    err, frac, view = full_parity(renderer, scene, cam, np.zeros(3, np.float32), pix=pix, frac_max=0.05)
+    tt = view["tiles_touched"].astype(np.int64)
+    n_wg = -(-int((tt > 0).sum()) // 256)  # emission workgroups (256 Gaussians each)
+    assert tt.max() > 4096                 # one footprint alone spans more than one window
+    assert tt.sum() / n_wg > 50 * 4096     # a workgroup fills over 50 windows on average
+    print(f"K={view['stats']['n_instances']} max footprint {tt.max()} tiles, err={err:.2e}")
