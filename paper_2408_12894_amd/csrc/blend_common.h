@@ -137,4 +137,15 @@ __host__ __device__ constexpr int row_sum9_component(int t) {
              : (t & 1) + 2 * ((t >> 1) & 1) + 3 * ((t >> 2) & 1) + 5 * ((t >> 3) & 1);
 }
 
+// every component 0..8 is held by exactly one lane of a row
+constexpr bool row_sum9_covers_all() {
+  for (int c = 0; c < 9; ++c) {
+    int n = 0;
+    for (int t = 0; t < 16; ++t) n += row_sum9_component(t) == c ? 1 : 0;
+    if (n != 1) return false;
+  }
+  return true;
+}
+static_assert(row_sum9_covers_all(), "row_sum9 must leave each component in exactly one lane");
+
 }  // namespace flod
