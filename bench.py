@@ -98,7 +98,7 @@ def timed(fn, n, warm, sync):
 
 
 def algorithmic_bytes(stage, N, n_vis, K, P, tiles):
-    """Bytes a stage must move (one launch), per its definition in the design doc."""
+    """Bytes a stage cannot avoid moving in one launch (its reads and writes of each item once)."""
     return {
         "preprocess": (236 + 80) * N,
         "compact": 8 * N + 8 * n_vis,
