@@ -12,9 +12,9 @@ constexpr int kTile = FLOD_TILE;          // 16x16 pixel tiles
 constexpr int kBlock = 256;               // threads per workgroup (4 wave64)
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;   // 256 buckets per radix pass
-constexpr int kSortItems = 16;            // keys per thread in a radix pass
-constexpr int kSortTile = kBlock * kSortItems;   // 4096 keys per workgroup
-constexpr int kSortItemsSmall = 4;        // 1024-key workgroups for sorts below kRadixBigSort
+constexpr int kSortItems = 12;            // keys per thread in a radix pass (measured 8 / 12 / 16)
+constexpr int kSortTile = kBlock * kSortItems;   // 3072 keys per workgroup
+constexpr int kSortItemsSmall = 8;        // 2048-key workgroups for sorts below kRadixBigSort (2 / 4 / 8)
 constexpr int64_t kRadixBigSort = 4 << 20;
 constexpr size_t kGaussianBytes = (3 + 3 + 4 + 1 + FLOD_SH_COEFFS * 3) * 4;   // 236 B per stored Gaussian
 constexpr unsigned long long kPruneMaxScan = 1ull << 36;   // overlap-pruning neighbour-scan limit

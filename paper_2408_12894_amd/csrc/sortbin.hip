@@ -11,7 +11,7 @@
 //
 // The radix pass is a reduce-then-scan design (no inter-workgroup spinning, which would
 // need cross-XCD coherent flags): per-workgroup digit histograms, a per-digit scan over
-// workgroups, then a scatter in which each workgroup ranks its 4096 (or 1024) keys stably in LDS
+// workgroups, then a scatter in which each workgroup ranks its 3072 (or 2048) keys stably in LDS
 // (wave64 ballots over the digit bits), reorders them by digit in LDS and writes each
 // digit run contiguously.
 #include <algorithm>
@@ -289,7 +289,7 @@ int radix_items(int64_t n_max) { return n_max >= kRadixBigSort ? kSortItems : kS
 
 // Sort (keys, vals) by the low `bits` bits of the keys; stable. Ping-pongs between
 // buffers [0] and [1]; *result_buf receives the index holding the result. Sorts of fewer
-// than kRadixBigSort keys use 1024-key workgroups so that the grid still fills the chip.
+// than kRadixBigSort keys use 2048-key workgroups, more of them for the same keys.
 template <int ITEMS>
 static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr, int64_t n_max, int bits,
                          uint32_t *hist, uint32_t *scan, uint32_t *tot, int *cur_out, hipStream_t s) {
