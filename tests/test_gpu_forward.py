@@ -214,3 +214,19 @@ def test_huge_footprints_many_windows(renderer):
     assert tt.max() > 4096                 # one footprint alone spans more than one window
     assert tt.sum() / n_wg > 50 * 4096     # a workgroup fills over 50 windows on average
     print(f"K={view['stats']['n_instances']} max footprint {tt.max()} tiles, err={err:.2e}")
+
+
+def test_max_frame_16384(renderer):
+    """The largest frame the API accepts, 16384 x 16384: 1,048,576 tiles, so tile ids take 20
+    bits (a third radix pass) and the tile-order kernel spans a million tiles. Key path and
+    instance list bit-exact, the image on 256 sampled pixels."""
+    _say("2k Gaussians, 16384x16384")
+    scene = synth.uniform_scene(2000, seed=53, s_mu=-4.0, s_sigma=0.5)
+    cam = synth.look_at_camera((0.4, -0.3, -3.8), (0, 0, 0), 16384, 16384)
+    rng = np.random.default_rng(54)
+    pix = np.stack([rng.integers(0, 16384, 256), rng.integers(0, 16384, 256)], 1).astype(np.int32)
+    err, frac, view = full_parity(renderer, scene, cam, np.array([0.2, 0.1, 0.4], np.float32), pix=pix,
+                                  frac_max=0.05)
+    assert view["stats"]["tiles_x"] * view["stats"]["tiles_y"] == 1 << 20
+    assert int(view["tile_ids"].max()) >= 1 << 16       # ids beyond two radix digits
+    print(f"K={view['stats']['n_instances']} err={err:.2e}")
