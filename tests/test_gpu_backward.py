@@ -135,6 +135,19 @@ def test_4k_sampled(renderer):
     print(worst, nz)
 
 
+def test_max_frame_16384(renderer):
+    """The largest frame the API accepts (16384 x 16384, 2^20 tiles) with the loss on 128
+    sampled pixels: the backward's million-tile order and its atomics."""
+    _say("2k Gaussians, 16384x16384, 128 sampled pixels")
+    scene = synth.uniform_scene(2000, seed=53, s_mu=-4.0, s_sigma=0.5)
+    cam = synth.look_at_camera((0.4, -0.3, -3.8), (0, 0, 0), 16384, 16384)
+    rng = np.random.default_rng(63)
+    pix = np.stack([rng.integers(0, 16384, 128), rng.integers(0, 16384, 128)], 1).astype(np.int32)
+    pix = np.unique(pix, axis=0)
+    worst, nz = grad_parity(renderer, scene, cam, np.array([0.2, 0.1, 0.4], np.float32), pix=pix, seed=5)
+    print(worst, nz)
+
+
 def test_autograd_l1_step(renderer):
     """rasterize() under an L1 loss: torch autograd reaches the HIP backward, and its
     gradients equal Renderer.backward with dL/dimage = sign(I - I_target) / P."""
