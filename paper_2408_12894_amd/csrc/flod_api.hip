@@ -209,10 +209,7 @@ int64_t instance_capacity(const flod_ctx *c) {
   return k > 0 ? k : 0;
 }
 
-size_t hist_bytes(int64_t n_max) {
-  const int64_t tile = (int64_t)kBlock * radix_items(n_max);
-  return 4 * (size_t)kRadix * (size_t)((n_max + tile - 1) / tile);
-}
+size_t hist_bytes(int64_t n_max) { return radix_hist_bytes(n_max); }
 
 // The forward pipeline over the candidate set described by p.
 //
@@ -709,8 +706,6 @@ flod_status flod_overlap_prune(flod_ctx *ctx, const flod_level *level, float d_o
   if (n == 0) return FLOD_OK;
   const int bits = prune_table_bits(n);
   const int64_t buckets = (int64_t)1 << bits;
-  const int64_t sort_tile_n = (int64_t)kBlock * radix_items(n);
-  const int nbs = (int)((n + sort_tile_n - 1) / sort_tile_n);
   size_t extra = 0;
   auto need = [&](BufId id, size_t bytes) {
     if (ensure(ctx, id, bytes, s, &extra) != FLOD_OK) st = FLOD_ERR_WORKSPACE;
@@ -722,8 +717,8 @@ flod_status flod_overlap_prune(flod_ctx *ctx, const flod_level *level, float d_o
     need(B_DVAL1, 4 * (size_t)n);
     need(B_XYAB, 16 * (size_t)n);
     need(B_RANGES, 8 * (size_t)buckets);
-    need(B_HIST, 4 * (size_t)kRadix * nbs);
-    need(B_SCAN, 4 * (size_t)kRadix * nbs);
+    need(B_HIST, radix_hist_bytes(n));
+    need(B_SCAN, radix_hist_bytes(n));
     need(B_TOT, 4 * (size_t)kRadix);
   }
   need(B_COUNTERS, 8 * (size_t)kCntSlots);

@@ -107,7 +107,8 @@ hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int i
 hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
                           const unsigned long long *prefix, uint32_t *keys, uint32_t *vals,
                           hipStream_t s);
-int radix_items(int64_t n_max);   // keys per thread the radix sort of n_max keys uses
+int radix_items(int64_t n_max);        // keys per thread the radix sort of n_max keys uses
+size_t radix_hist_bytes(int64_t n_max);  // bytes of each of its hist and scan arrays
 hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr,
                              int64_t n_max, int bits, uint32_t *hist, uint32_t *scan,
                              uint32_t *tot, int *result_buf, hipStream_t s);

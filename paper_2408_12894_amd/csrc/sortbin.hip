@@ -137,7 +137,8 @@ hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t 
 
 // ---------------------------------------------------------------------------------------
 // Radix pass: histogram, per-digit scan, stable scatter.
-// hist[d * nb_max + b] = count of digit d in block b; scan = exclusive prefix over b.
+// hist[d * stride + b] = count of digit d in block b; scan = exclusive prefix over b. The row
+// stride is the block count rounded up to a multiple of 8 (32-byte aligned rows).
 //
 // Block of a histogram or scatter workgroup: workgroups go to the 8 XCDs round-robin, and
 // each XCD takes runs of kXcdRun consecutive blocks. The counts of adjacent blocks share
@@ -155,9 +156,11 @@ static unsigned radix_grid(int nb_max) {
   const int g = 8 * (int)kXcdRun;
   return (unsigned)(((nb_max + g - 1) / g) * g);
 }
+// All of a workgroup's keys are loaded before the first LDS update, so its loads are in
+// flight together.
 template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const uint32_t *n_ptr, int shift,
-                                                    uint32_t *hist, int nb_max) {
+                                                    uint32_t *hist, int stride) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   __shared__ uint32_t h[kRadix];
   const uint32_t n = *n_ptr;
@@ -165,31 +168,60 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const 
   const uint32_t b = radix_block(blockIdx.x);
   if (b >= nb) return;
   h[threadIdx.x] = 0;
-  __syncthreads();
   const uint32_t base = b * TILE;
-#pragma unroll 4
+  uint32_t kr[ITEMS];
+#pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     const uint32_t idx = base + r * kBlock + threadIdx.x;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (kRadix - 1)], 1u);
+    kr[r] = idx < n ? keys[idx] : 0u;
   }
   __syncthreads();
-  hist[(size_t)threadIdx.x * nb_max + b] = h[threadIdx.x];
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r)
+    if (base + r * kBlock + threadIdx.x < n) atomicAdd(&h[(kr[r] >> shift) & (kRadix - 1)], 1u);
+  __syncthreads();
+  hist[(size_t)threadIdx.x * stride + b] = h[threadIdx.x];
 }
 
+// One workgroup per digit. Rounds of 2048 counts: each thread takes 8 consecutive ones (two
+// 16-byte loads), the next round's loads are issued before this round's scan.
 __global__ __launch_bounds__(kBlock) void k_rs_scan(const uint32_t *n_ptr, const uint32_t *hist, uint32_t *scan,
-                                                    uint32_t *tot, int nb_max, int tile) {
+                                                    uint32_t *tot, int stride, int tile) {
+  constexpr uint32_t kPer = 8, kRound = kBlock * kPer;
   const uint32_t n = *n_ptr;
-  const int nb = (int)((n + tile - 1) / tile);
+  const uint32_t nb = (n + tile - 1) / tile;
   const int d = blockIdx.x;
-  const uint32_t *row = hist + (size_t)d * nb_max;
-  uint32_t *out = scan + (size_t)d * nb_max;
+  const uint32_t *row = hist + (size_t)d * stride;
+  uint32_t *out = scan + (size_t)d * stride;
+  // k < nb implies k + 3 < stride: a 16-byte group that starts below nb lies inside the row
+  auto load = [&](uint32_t k, uint4 &lo, uint4 &hi) {
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    lo = k < nb ? *reinterpret_cast<const uint4 *>(row + k) : z;
+    hi = k + 4 < nb ? *reinterpret_cast<const uint4 *>(row + k + 4) : z;
+  };
   uint32_t run = 0;
-  for (int base = 0; base < nb; base += kBlock) {
-    const int k = base + threadIdx.x;
-    uint32_t v = (k < nb) ? row[k] : 0u;
+  uint32_t k = threadIdx.x * kPer;
+  uint4 lo, hi;
+  load(k, lo, hi);
+  for (uint32_t base = 0; base < nb; base += kRound, k += kRound) {
+    uint32_t v[kPer] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    load(k + kRound, lo, hi);
+    uint32_t sum = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; ++i) {
+      if (k + i >= nb) v[i] = 0u;
+      sum += v[i];
+    }
     uint32_t t;
-    uint32_t ex = block_excl_scan(v, &t);
-    if (k < nb) out[k] = run + ex;
+    uint32_t e = run + block_excl_scan(sum, &t);
+    uint32_t o[kPer];
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; ++i) {
+      o[i] = e;
+      e += v[i];
+    }
+    if (k < nb) *reinterpret_cast<uint4 *>(out + k) = make_uint4(o[0], o[1], o[2], o[3]);
+    if (k + 4 < nb) *reinterpret_cast<uint4 *>(out + k + 4) = make_uint4(o[4], o[5], o[6], o[7]);
     run += t;
   }
   if (threadIdx.x == 0) tot[d] = run;
@@ -208,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
                                                        uint32_t *__restrict__ keys_out,
                                                        uint32_t *__restrict__ vals_out, const uint32_t *n_ptr,
                                                        int shift, const uint32_t *hist, const uint32_t *scan,
-                                                       const uint32_t *tot, int nb_max) {
+                                                       const uint32_t *tot, int stride) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   constexpr int WAVES = kBlock / 64;
   constexpr uint32_t WTILE = 64 * ITEMS;
@@ -224,10 +256,10 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
   // digit bases over the whole array and this workgroup's local digit bases
   uint32_t t_all;
   uint32_t dbase = block_excl_scan(tot[tid], &t_all);
-  const uint32_t cnt = hist[(size_t)tid * nb_max + b];
+  const uint32_t cnt = hist[(size_t)tid * stride + b];
   uint32_t t_loc;
   const uint32_t lbase = block_excl_scan(cnt, &t_loc);
-  s_goff[tid] = dbase + scan[(size_t)tid * nb_max + b] - lbase;
+  s_goff[tid] = dbase + scan[(size_t)tid * stride + b] - lbase;
 #pragma unroll
   for (int k = 0; k < WAVES; ++k) s_wcnt[k][tid] = 0;
   __syncthreads();
@@ -287,21 +319,30 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
 
 int radix_items(int64_t n_max) { return n_max >= kRadixBigSort ? kSortItems : kSortItemsSmall; }
 
+static int64_t radix_stride(int64_t n_max) {
+  const int64_t tile = (int64_t)kBlock * radix_items(n_max);
+  return ((n_max + tile - 1) / tile + 7) & ~(int64_t)7;
+}
+
+size_t radix_hist_bytes(int64_t n_max) { return 4 * (size_t)kRadix * (size_t)radix_stride(n_max); }
+
 // Sort (keys, vals) by the low `bits` bits of the keys; stable. Ping-pongs between
-// buffers [0] and [1]; *result_buf receives the index holding the result. Sorts of fewer
+// buffers [0] and [1]; *result_buf receives the index holding the result. hist and scan
+// hold radix_hist_bytes(n_max) each (16-byte aligned). Sorts of fewer
 // than kRadixBigSort keys use 2048-key workgroups, more of them for the same keys.
 template <int ITEMS>
 static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr, int64_t n_max, int bits,
                          uint32_t *hist, uint32_t *scan, uint32_t *tot, int *cur_out, hipStream_t s) {
   constexpr int TILE = kBlock * ITEMS;
   const int nb_max = (int)((n_max + TILE - 1) / TILE);
+  const int stride = (int)radix_stride(n_max);
   int cur = 0;
   for (int shift = 0; shift < bits; shift += kRadixBits) {
     hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], n_ptr, shift, hist,
-                       nb_max);
-    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, s, n_ptr, hist, scan, tot, nb_max, TILE);
+                       stride);
+    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, s, n_ptr, hist, scan, tot, stride, TILE);
     hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
-                       vals[cur ^ 1], n_ptr, shift, hist, scan, tot, nb_max);
+                       vals[cur ^ 1], n_ptr, shift, hist, scan, tot, stride);
     cur ^= 1;
   }
   *cur_out = cur;
