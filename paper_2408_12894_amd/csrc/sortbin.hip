@@ -61,20 +61,37 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
 // cap32 items read it as their item count and then do nothing.
 // ---------------------------------------------------------------------------------------
 constexpr int kScanThreads = 1024;
+constexpr int kScanRegs = 16;   // counts per thread held in registers (up to 16384 counts)
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const uint32_t *in, const uint32_t *n_items,
                                                               int items_per_block, unsigned long long *prefix,
                                                               uint32_t *total32, unsigned long long *total64,
                                                               unsigned long long cap32, int max_blocks) {
   __shared__ unsigned long long s_w[kScanThreads / 64];
+  // thread t owns the contiguous counts [t per, (t + 1) per), per from the buffer's
+  // max_blocks, so its loads need not wait for the count n_items: its sum, a workgroup scan of
+  // the sums, then its exclusive prefixes. Up to kScanRegs counts stay in registers (loaded
+  // together); beyond that they are read twice, the second time from cache.
+  const int per = (max_blocks + kScanThreads - 1) / kScanThreads;
+  const int lo = min(max_blocks, (int)threadIdx.x * per);
+  const bool in_regs = per <= kScanRegs;
+  uint32_t v[kScanRegs];
+  if (in_regs) {
+#pragma unroll
+    for (int i = 0; i < kScanRegs; ++i) v[i] = (i < per && lo + i < max_blocks) ? in[lo + i] : 0u;
+  }
   int nb = max_blocks;
-  if (n_items) nb = (int)(((unsigned long long)*n_items + items_per_block - 1) / items_per_block);
-  // thread t owns the contiguous counts [t per, (t + 1) per): its sum, a workgroup scan of the
-  // sums, then its exclusive prefixes (a second read of its counts, from cache)
-  const int per = (nb + kScanThreads - 1) / kScanThreads;
-  const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
+  if (n_items) nb = (int)min((unsigned long long)max_blocks,
+                             ((unsigned long long)*n_items + items_per_block - 1) / items_per_block);
+  const int hi = max(lo, min(nb, lo + per));
   unsigned long long mine = 0;
-  for (int k = lo; k < hi; ++k) mine += in[k];
+  if (in_regs) {
+#pragma unroll
+    for (int i = 0; i < kScanRegs; ++i)
+      if (lo + i < hi) mine += v[i];
+  } else {
+    for (int k = lo; k < hi; ++k) mine += in[k];
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   unsigned long long inc = mine;
 #pragma unroll
@@ -91,9 +108,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const uint32_t *in
     run += (k < w) ? t : 0ull;
     total += t;
   }
-  for (int k = lo; k < hi; ++k) {
-    prefix[k] = run;
-    run += in[k];
+  if (in_regs) {
+#pragma unroll
+    for (int i = 0; i < kScanRegs; ++i)
+      if (lo + i < hi) {
+        prefix[lo + i] = run;
+        run += v[i];
+      }
+  } else {
+    for (int k = lo; k < hi; ++k) {
+      prefix[k] = run;
+      run += in[k];
+    }
   }
   if (threadIdx.x == 0) {
     if (total64) *total64 = total;
@@ -157,24 +183,25 @@ static unsigned radix_grid(int nb_max) {
   return (unsigned)(((nb_max + g - 1) / g) * g);
 }
 // All of a workgroup's keys are loaded before the first LDS update, so its loads are in
-// flight together.
+// flight together; they are bounded by the buffer's n_max keys and issued before the count
+// n is known (keys at n and beyond are loaded but not counted).
 template <int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const uint32_t *n_ptr, int shift,
-                                                    uint32_t *hist, int stride) {
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const uint32_t *n_ptr, uint32_t n_max,
+                                                    int shift, uint32_t *hist, int stride) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   __shared__ uint32_t h[kRadix];
-  const uint32_t n = *n_ptr;
-  const uint32_t nb = (n + TILE - 1) / TILE;
   const uint32_t b = radix_block(blockIdx.x);
-  if (b >= nb) return;
-  h[threadIdx.x] = 0;
   const uint32_t base = b * TILE;
   uint32_t kr[ITEMS];
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     const uint32_t idx = base + r * kBlock + threadIdx.x;
-    kr[r] = idx < n ? keys[idx] : 0u;
+    kr[r] = idx < n_max ? keys[idx] : 0u;
   }
+  const uint32_t n = *n_ptr;
+  const uint32_t nb = (n + TILE - 1) / TILE;
+  if (b >= nb) return;
+  h[threadIdx.x] = 0;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r)
@@ -239,8 +266,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
                                                        const uint32_t *__restrict__ vals_in,
                                                        uint32_t *__restrict__ keys_out,
                                                        uint32_t *__restrict__ vals_out, const uint32_t *n_ptr,
-                                                       int shift, const uint32_t *hist, const uint32_t *scan,
-                                                       const uint32_t *tot, int stride) {
+                                                       uint32_t n_max, int shift, const uint32_t *hist,
+                                                       const uint32_t *scan, const uint32_t *tot, int stride) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   constexpr int WAVES = kBlock / 64;
   constexpr uint32_t WTILE = 64 * ITEMS;
@@ -248,32 +275,41 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
   __shared__ uint32_t s_vals[TILE];
   __shared__ uint32_t s_goff[kRadix];
   __shared__ uint32_t s_wcnt[WAVES][kRadix];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t b = radix_block(blockIdx.x);
+  const uint32_t base = b * TILE;
+  // the tile's keys and values, bounded by the buffer's n_max and loaded before the count n
+  // is known, so that their latency overlaps the count's and the digit offsets'
+  uint32_t kr[ITEMS], vr[ITEMS], rr[ITEMS];
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const uint32_t idx = base + (uint32_t)w * WTILE + (uint32_t)r * 64u + (uint32_t)lane;
+    kr[r] = idx < n_max ? keys_in[idx] : 0u;
+    vr[r] = idx < n_max ? vals_in[idx] : 0u;
+  }
   const uint32_t n = *n_ptr;
   const uint32_t nb = (n + TILE - 1) / TILE;
-  const uint32_t b = radix_block(blockIdx.x);
   if (b >= nb) return;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  // digit bases over the whole array and this workgroup's local digit bases
-  uint32_t t_all;
-  uint32_t dbase = block_excl_scan(tot[tid], &t_all);
+  // digit bases over the whole array and this workgroup's local digit bases (the three
+  // loads issued together, ahead of the scans' barriers)
+  const uint32_t tot_d = tot[tid];
   const uint32_t cnt = hist[(size_t)tid * stride + b];
+  const uint32_t sc = scan[(size_t)tid * stride + b];
+  uint32_t t_all;
+  const uint32_t dbase = block_excl_scan(tot_d, &t_all);
   uint32_t t_loc;
   const uint32_t lbase = block_excl_scan(cnt, &t_loc);
-  s_goff[tid] = dbase + scan[(size_t)tid * stride + b] - lbase;
+  s_goff[tid] = dbase + sc - lbase;
 #pragma unroll
   for (int k = 0; k < WAVES; ++k) s_wcnt[k][tid] = 0;
   __syncthreads();
-  const uint32_t base = b * TILE;
   const uint32_t count = min(TILE, n - base);
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t kr[ITEMS], vr[ITEMS], rr[ITEMS];
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     const uint32_t li = (uint32_t)w * WTILE + (uint32_t)r * 64u + (uint32_t)lane;
     const bool valid = li < count;
-    const uint32_t key = valid ? keys_in[base + li] : 0u;
-    kr[r] = key;
-    vr[r] = valid ? vals_in[base + li] : 0u;
+    const uint32_t key = kr[r];
     const uint32_t d = (key >> shift) & (kRadix - 1);
     unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -338,11 +374,11 @@ static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n
   const int stride = (int)radix_stride(n_max);
   int cur = 0;
   for (int shift = 0; shift < bits; shift += kRadixBits) {
-    hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], n_ptr, shift, hist,
-                       stride);
+    hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], n_ptr,
+                       (uint32_t)n_max, shift, hist, stride);
     hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, s, n_ptr, hist, scan, tot, stride, TILE);
     hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
-                       vals[cur ^ 1], n_ptr, shift, hist, scan, tot, stride);
+                       vals[cur ^ 1], n_ptr, (uint32_t)n_max, shift, hist, scan, tot, stride);
     cur ^= 1;
   }
   *cur_out = cur;
