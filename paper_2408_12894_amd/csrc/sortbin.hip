@@ -399,13 +399,15 @@ hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_
 // ---------------------------------------------------------------------------------------
 // Tiles touched in depth order: per-workgroup sums over the sorted visible Gaussians.
 // ---------------------------------------------------------------------------------------
+// The sorted id is loaded (bounded by the buffer's n_max) before the count n is known.
 __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
-                                                        const uint32_t *tiles, uint32_t *block_sum,
+                                                        uint32_t n_max, const uint32_t *tiles, uint32_t *block_sum,
                                                         uint32_t *sorted_tiles) {
-  const uint32_t n = *n_ptr;
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t id = j < n_max ? sorted_ids[j] : 0u;
+  const uint32_t n = *n_ptr;
   if (blockIdx.x * kBlock >= n) return;
-  const uint32_t c = (j < n) ? tiles[sorted_ids[j]] : 0u;
+  const uint32_t c = (j < n) ? tiles[id] : 0u;
   if (j < n) sorted_tiles[j] = c;
   uint32_t tot;
   block_excl_scan(c, &tot);
@@ -417,7 +419,7 @@ hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
                               hipStream_t s) {
   if (n_max <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)((n_max + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     sorted_ids, n_ptr, tiles, block_sum, sorted_tiles);
+                     sorted_ids, n_ptr, (uint32_t)n_max, tiles, block_sum, sorted_tiles);
   return hipGetLastError();
 }
 
@@ -479,28 +481,35 @@ struct EmitWindow {
 };
 
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr,
-                                                 const uint32_t *k_ptr, const uint32_t *sorted_tiles,
+                                                 const uint32_t *k_ptr, uint32_t n_max, const uint32_t *sorted_tiles,
                                                  const float4 *bin, const unsigned long long *prefix,
                                                  int tiles_x, int tiles_y, uint32_t *__restrict__ tile_ids,
                                                  uint32_t *__restrict__ values) {
   __shared__ uint32_t s_tile[kEmitCap];
   __shared__ uint32_t s_val[kEmitCap];
-  const uint32_t n = *n_ptr;
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  // the Gaussian, its tile count and the block's offsets are loaded (bounded by the buffers'
+  // n_max entries; the grid has one block per kBlock of them) before the counts n and K are
+  // known, so that their latencies overlap
+  const uint32_t nblk_max = (n_max + kBlock - 1) / kBlock;
+  const uint32_t g_ld = j < n_max ? sorted_ids[j] : 0u;
+  const uint32_t c_ld = j < n_max ? sorted_tiles[j] : 0u;
+  const unsigned long long obase = prefix[blockIdx.x];
+  const unsigned long long p_next = (blockIdx.x + 1 < nblk_max) ? prefix[blockIdx.x + 1] : 0ull;
+  const uint32_t n = *n_ptr;
   const uint32_t K = *k_ptr;
   if (blockIdx.x * kBlock >= n || K == 0u) return;   // no instances, or more than the buffers hold
   // workgroup (block, split) takes the block's windows split, split + gridDim.y, ...: a block
   // of huge footprints fills hundreds of windows, most blocks fill one
   const uint32_t split = blockIdx.y;
   const uint32_t nblk = (n + kBlock - 1) / kBlock;
-  const unsigned long long block_end = (blockIdx.x + 1 < nblk) ? prefix[blockIdx.x + 1] : (unsigned long long)K;
-  if ((unsigned long long)split * kEmitCap >= block_end - prefix[blockIdx.x]) return;
+  const unsigned long long block_end = (blockIdx.x + 1 < nblk) ? p_next : (unsigned long long)K;
+  if ((unsigned long long)split * kEmitCap >= block_end - obase) return;
   const bool valid = j < n;
-  const uint32_t g = valid ? sorted_ids[j] : 0u;
-  const uint32_t c = valid ? sorted_tiles[j] : 0u;
+  const uint32_t g = valid ? g_ld : 0u;
+  const uint32_t c = valid ? c_ld : 0u;
   uint32_t tot;
   const uint32_t off = block_excl_scan(c, &tot);     // local position of this Gaussian's first instance
-  const unsigned long long obase = prefix[blockIdx.x];
   const int lane = threadIdx.x & 63;
   // the Gaussian's binning record: one 32-byte gather (mu', conic, support bound, rectangle)
   float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
@@ -606,7 +615,7 @@ hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const 
   const int64_t windows = (k_max + blocks * (int64_t)kEmitCap - 1) / (blocks * (int64_t)kEmitCap);
   const unsigned split = (unsigned)std::min<int64_t>(kEmitSplit, std::max<int64_t>(1, windows));
   hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks, split), dim3(kBlock), 0, s, sorted_ids, n_ptr, k_ptr,
-                     sorted_tiles, bin, prefix, tiles_x, tiles_y, tile_ids, values);
+                     (uint32_t)n_max, sorted_tiles, bin, prefix, tiles_x, tiles_y, tile_ids, values);
   return hipGetLastError();
 }
 
@@ -614,20 +623,22 @@ hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const 
 // Tile ranges from the sorted tile ids (ranges zeroed beforehand); the id count is read on
 // the device, the grid covers k_max ids.
 // ---------------------------------------------------------------------------------------
+// The ids are loaded (bounded by the buffer's k_max) before the count K is known.
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *__restrict__ tile_ids, const uint32_t *k_ptr,
-                                                   uint2 *__restrict__ ranges) {
-  const uint32_t K = *k_ptr;
+                                                   uint32_t k_max, uint2 *__restrict__ ranges) {
   const uint32_t k0 = 4u * (blockIdx.x * kBlock + threadIdx.x);   // four ids per thread
-  if (k0 >= K) return;
+  if (k0 >= k_max) return;
   uint32_t t[4];
-  if (k0 + 4u <= K) {
+  if (k0 + 4u <= k_max) {
     const uint4 v = *reinterpret_cast<const uint4 *>(tile_ids + k0);
     t[0] = v.x; t[1] = v.y; t[2] = v.z; t[3] = v.w;
   } else {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) t[i] = (k0 + i < K) ? tile_ids[k0 + i] : 0u;
+    for (int i = 0; i < 4; ++i) t[i] = (k0 + i < k_max) ? tile_ids[k0 + i] : 0u;
   }
   uint32_t prev = (k0 > 0u) ? tile_ids[k0 - 1u] : 0xFFFFFFFFu;
+  const uint32_t K = *k_ptr;
+  if (k0 >= K) return;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const uint32_t k = k0 + i;
@@ -641,14 +652,26 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *__restrict__ 
   if (k0 + 4u >= K) ranges[prev].y = K;   // the last id closes its tile
 }
 
-__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+// 16-byte stores over the aligned body (grid-stride), single words before and after it.
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+  const int64_t lead = min(n, (int64_t)(((16u - (uint32_t)(reinterpret_cast<uintptr_t>(p) & 15u)) & 15u) / 4u));
+  const int64_t n4 = (n - lead) / 4;
+  uint4 *q = reinterpret_cast<uint4 *>(p + lead);
+  const uint4 vv = make_uint4(v, v, v, v);
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += stride) q[i] = vv;
+  if (blockIdx.x == 0) {
+    const int64_t tail = lead + 4 * n4;
+    if ((int64_t)threadIdx.x < lead) p[threadIdx.x] = v;
+    if ((int64_t)threadIdx.x < n - tail) p[tail + threadIdx.x] = v;
+  }
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, v, n);
+  const int64_t groups = (n / 4 + kBlock - 1) / kBlock;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 4096));
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(kBlock), 0, s, p, v, n);
   return hipGetLastError();
 }
 
@@ -658,7 +681,7 @@ hipError_t launch_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, int64_
   if (e != hipSuccess || k_max <= 0) return e;
   const int64_t threads = (k_max + 3) / 4;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tile_ids,
-                     k_ptr, ranges);
+                     k_ptr, (uint32_t)k_max, ranges);
   return hipGetLastError();
 }
 
