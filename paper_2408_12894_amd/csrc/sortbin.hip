@@ -183,24 +183,24 @@ static unsigned radix_grid(int nb_max) {
   return (unsigned)(((nb_max + g - 1) / g) * g);
 }
 // All of a workgroup's keys are loaded before the first LDS update, so its loads are in
-// flight together; they are bounded by the buffer's n_max keys and issued before the count
-// n is known (keys at n and beyond are loaded but not counted).
+// flight together. The count n is read first: grids are sized for the buffers' capacity,
+// which can far exceed n, and workgroups past n must not read their keys.
 template <int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const uint32_t *n_ptr, uint32_t n_max,
-                                                    int shift, uint32_t *hist, int stride) {
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const uint32_t *n_ptr, int shift,
+                                                    uint32_t *hist, int stride) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   __shared__ uint32_t h[kRadix];
+  const uint32_t n = *n_ptr;
+  const uint32_t nb = (n + TILE - 1) / TILE;
   const uint32_t b = radix_block(blockIdx.x);
+  if (b >= nb) return;
   const uint32_t base = b * TILE;
   uint32_t kr[ITEMS];
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     const uint32_t idx = base + r * kBlock + threadIdx.x;
-    kr[r] = idx < n_max ? keys[idx] : 0u;
+    kr[r] = idx < n ? keys[idx] : 0u;
   }
-  const uint32_t n = *n_ptr;
-  const uint32_t nb = (n + TILE - 1) / TILE;
-  if (b >= nb) return;
   h[threadIdx.x] = 0;
   __syncthreads();
 #pragma unroll
@@ -266,8 +266,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
                                                        const uint32_t *__restrict__ vals_in,
                                                        uint32_t *__restrict__ keys_out,
                                                        uint32_t *__restrict__ vals_out, const uint32_t *n_ptr,
-                                                       uint32_t n_max, int shift, const uint32_t *hist,
-                                                       const uint32_t *scan, const uint32_t *tot, int stride) {
+                                                       int shift, const uint32_t *hist, const uint32_t *scan,
+                                                       const uint32_t *tot, int stride) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   constexpr int WAVES = kBlock / 64;
   constexpr uint32_t WTILE = 64 * ITEMS;
@@ -276,20 +276,21 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
   __shared__ uint32_t s_goff[kRadix];
   __shared__ uint32_t s_wcnt[WAVES][kRadix];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // the count first (grids are sized for the capacity); then the tile's keys and values,
+  // loaded together with the digit offsets below, so that their latencies overlap
+  const uint32_t n = *n_ptr;
+  const uint32_t nb = (n + TILE - 1) / TILE;
   const uint32_t b = radix_block(blockIdx.x);
+  if (b >= nb) return;
   const uint32_t base = b * TILE;
-  // the tile's keys and values, bounded by the buffer's n_max and loaded before the count n
-  // is known, so that their latency overlaps the count's and the digit offsets'
+  const uint32_t count = min(TILE, n - base);
   uint32_t kr[ITEMS], vr[ITEMS], rr[ITEMS];
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
-    const uint32_t idx = base + (uint32_t)w * WTILE + (uint32_t)r * 64u + (uint32_t)lane;
-    kr[r] = idx < n_max ? keys_in[idx] : 0u;
-    vr[r] = idx < n_max ? vals_in[idx] : 0u;
+    const uint32_t li = (uint32_t)w * WTILE + (uint32_t)r * 64u + (uint32_t)lane;
+    kr[r] = li < count ? keys_in[base + li] : 0u;
+    vr[r] = li < count ? vals_in[base + li] : 0u;
   }
-  const uint32_t n = *n_ptr;
-  const uint32_t nb = (n + TILE - 1) / TILE;
-  if (b >= nb) return;
   // digit bases over the whole array and this workgroup's local digit bases (the three
   // loads issued together, ahead of the scans' barriers)
   const uint32_t tot_d = tot[tid];
@@ -303,7 +304,6 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
 #pragma unroll
   for (int k = 0; k < WAVES; ++k) s_wcnt[k][tid] = 0;
   __syncthreads();
-  const uint32_t count = min(TILE, n - base);
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
@@ -374,11 +374,11 @@ static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n
   const int stride = (int)radix_stride(n_max);
   int cur = 0;
   for (int shift = 0; shift < bits; shift += kRadixBits) {
-    hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], n_ptr,
-                       (uint32_t)n_max, shift, hist, stride);
+    hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], n_ptr, shift, hist,
+                       stride);
     hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, s, n_ptr, hist, scan, tot, stride, TILE);
     hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
-                       vals[cur ^ 1], n_ptr, (uint32_t)n_max, shift, hist, scan, tot, stride);
+                       vals[cur ^ 1], n_ptr, shift, hist, scan, tot, stride);
     cur ^= 1;
   }
   *cur_out = cur;
@@ -399,15 +399,13 @@ hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_
 // ---------------------------------------------------------------------------------------
 // Tiles touched in depth order: per-workgroup sums over the sorted visible Gaussians.
 // ---------------------------------------------------------------------------------------
-// The sorted id is loaded (bounded by the buffer's n_max) before the count n is known.
 __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
-                                                        uint32_t n_max, const uint32_t *tiles, uint32_t *block_sum,
+                                                        const uint32_t *tiles, uint32_t *block_sum,
                                                         uint32_t *sorted_tiles) {
-  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  const uint32_t id = j < n_max ? sorted_ids[j] : 0u;
   const uint32_t n = *n_ptr;
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
   if (blockIdx.x * kBlock >= n) return;
-  const uint32_t c = (j < n) ? tiles[id] : 0u;
+  const uint32_t c = (j < n) ? tiles[sorted_ids[j]] : 0u;
   if (j < n) sorted_tiles[j] = c;
   uint32_t tot;
   block_excl_scan(c, &tot);
@@ -419,7 +417,7 @@ hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
                               hipStream_t s) {
   if (n_max <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)((n_max + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     sorted_ids, n_ptr, (uint32_t)n_max, tiles, block_sum, sorted_tiles);
+                     sorted_ids, n_ptr, tiles, block_sum, sorted_tiles);
   return hipGetLastError();
 }
 
@@ -481,33 +479,28 @@ struct EmitWindow {
 };
 
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr,
-                                                 const uint32_t *k_ptr, uint32_t n_max, const uint32_t *sorted_tiles,
+                                                 const uint32_t *k_ptr, const uint32_t *sorted_tiles,
                                                  const float4 *bin, const unsigned long long *prefix,
                                                  int tiles_x, int tiles_y, uint32_t *__restrict__ tile_ids,
                                                  uint32_t *__restrict__ values) {
   __shared__ uint32_t s_tile[kEmitCap];
   __shared__ uint32_t s_val[kEmitCap];
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  // the Gaussian, its tile count and the block's offsets are loaded (bounded by the buffers'
-  // n_max entries; the grid has one block per kBlock of them) before the counts n and K are
-  // known, so that their latencies overlap
-  const uint32_t nblk_max = (n_max + kBlock - 1) / kBlock;
-  const uint32_t g_ld = j < n_max ? sorted_ids[j] : 0u;
-  const uint32_t c_ld = j < n_max ? sorted_tiles[j] : 0u;
-  const unsigned long long obase = prefix[blockIdx.x];
-  const unsigned long long p_next = (blockIdx.x + 1 < nblk_max) ? prefix[blockIdx.x + 1] : 0ull;
+  // the counts first (the grid covers every candidate, of which n are visible); then the
+  // Gaussian, its tile count and the block's offsets, loaded together
   const uint32_t n = *n_ptr;
   const uint32_t K = *k_ptr;
   if (blockIdx.x * kBlock >= n || K == 0u) return;   // no instances, or more than the buffers hold
+  const bool valid = j < n;
+  const uint32_t nblk = (n + kBlock - 1) / kBlock;
+  const uint32_t g = valid ? sorted_ids[j] : 0u;
+  const uint32_t c = valid ? sorted_tiles[j] : 0u;
+  const unsigned long long obase = prefix[blockIdx.x];
+  const unsigned long long block_end = (blockIdx.x + 1 < nblk) ? prefix[blockIdx.x + 1] : (unsigned long long)K;
   // workgroup (block, split) takes the block's windows split, split + gridDim.y, ...: a block
   // of huge footprints fills hundreds of windows, most blocks fill one
   const uint32_t split = blockIdx.y;
-  const uint32_t nblk = (n + kBlock - 1) / kBlock;
-  const unsigned long long block_end = (blockIdx.x + 1 < nblk) ? p_next : (unsigned long long)K;
   if ((unsigned long long)split * kEmitCap >= block_end - obase) return;
-  const bool valid = j < n;
-  const uint32_t g = valid ? g_ld : 0u;
-  const uint32_t c = valid ? c_ld : 0u;
   uint32_t tot;
   const uint32_t off = block_excl_scan(c, &tot);     // local position of this Gaussian's first instance
   const int lane = threadIdx.x & 63;
@@ -615,7 +608,7 @@ hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const 
   const int64_t windows = (k_max + blocks * (int64_t)kEmitCap - 1) / (blocks * (int64_t)kEmitCap);
   const unsigned split = (unsigned)std::min<int64_t>(kEmitSplit, std::max<int64_t>(1, windows));
   hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks, split), dim3(kBlock), 0, s, sorted_ids, n_ptr, k_ptr,
-                     (uint32_t)n_max, sorted_tiles, bin, prefix, tiles_x, tiles_y, tile_ids, values);
+                     sorted_tiles, bin, prefix, tiles_x, tiles_y, tile_ids, values);
   return hipGetLastError();
 }
 
@@ -623,22 +616,20 @@ hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const 
 // Tile ranges from the sorted tile ids (ranges zeroed beforehand); the id count is read on
 // the device, the grid covers k_max ids.
 // ---------------------------------------------------------------------------------------
-// The ids are loaded (bounded by the buffer's k_max) before the count K is known.
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *__restrict__ tile_ids, const uint32_t *k_ptr,
-                                                   uint32_t k_max, uint2 *__restrict__ ranges) {
+                                                   uint2 *__restrict__ ranges) {
+  const uint32_t K = *k_ptr;
   const uint32_t k0 = 4u * (blockIdx.x * kBlock + threadIdx.x);   // four ids per thread
-  if (k0 >= k_max) return;
+  if (k0 >= K) return;
   uint32_t t[4];
-  if (k0 + 4u <= k_max) {
+  if (k0 + 4u <= K) {
     const uint4 v = *reinterpret_cast<const uint4 *>(tile_ids + k0);
     t[0] = v.x; t[1] = v.y; t[2] = v.z; t[3] = v.w;
   } else {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) t[i] = (k0 + i < k_max) ? tile_ids[k0 + i] : 0u;
+    for (int i = 0; i < 4; ++i) t[i] = (k0 + i < K) ? tile_ids[k0 + i] : 0u;
   }
   uint32_t prev = (k0 > 0u) ? tile_ids[k0 - 1u] : 0xFFFFFFFFu;
-  const uint32_t K = *k_ptr;
-  if (k0 >= K) return;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const uint32_t k = k0 + i;
@@ -681,7 +672,7 @@ hipError_t launch_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, int64_
   if (e != hipSuccess || k_max <= 0) return e;
   const int64_t threads = (k_max + 3) / 4;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tile_ids,
-                     k_ptr, (uint32_t)k_max, ranges);
+                     k_ptr, ranges);
   return hipGetLastError();
 }
 
