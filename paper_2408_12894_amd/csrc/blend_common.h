@@ -35,7 +35,6 @@ __device__ __forceinline__ void stage_entry(const float4 *xyab, const float4 *co
 // workgroups go to different XCDs (round-robin), so every XCD receives an even share.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 256;
-constexpr int kOrderRegs = 32;   // tiles per lane held in registers (frames up to 32768 tiles)
 
 __device__ __forceinline__ int cost_bucket(uint32_t c) {
   if (c < 8u) return (int)c;
@@ -61,28 +60,11 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, 
   __shared__ uint32_t s_cnt[W][kOrderBuckets];
   __shared__ uint32_t s_wsum[kOrderBuckets / 64];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int chunk = (n + W - 1) / W;
-  const int t0 = w * chunk, t1 = min(n, t0 + chunk);
-  // a lane's tiles t0 + lane + 64 r: when the wave's chunk fits, their buckets are computed
-  // once into registers with all cost loads in flight together
-  const bool in_regs = chunk <= 64 * kOrderRegs;
-  int bk[kOrderRegs];
-  if (in_regs) {
-#pragma unroll
-    for (int r = 0; r < kOrderRegs; ++r) {
-      const int t = t0 + lane + 64 * r;
-      bk[r] = t < t1 ? cost_bucket(cost(t)) : -1;
-    }
-  }
   for (int k = tid; k < W * kOrderBuckets; k += kOrderThreads) (&s_cnt[0][0])[k] = 0u;
   __syncthreads();
-  if (in_regs) {
-#pragma unroll
-    for (int r = 0; r < kOrderRegs; ++r)
-      if (bk[r] >= 0) atomicAdd(&s_cnt[w][bk[r]], 1u);
-  } else {
-    for (int t = t0 + lane; t < t1; t += 64) atomicAdd(&s_cnt[w][cost_bucket(cost(t))], 1u);
-  }
+  const int chunk = (n + W - 1) / W;
+  const int t0 = w * chunk, t1 = min(n, t0 + chunk);
+  for (int t = t0 + lane; t < t1; t += 64) atomicAdd(&s_cnt[w][cost_bucket(cost(t))], 1u);
   __syncthreads();
   // thread d < 256 takes bucket b = 255 - d (descending cost): its count over the waves, with
   // each wave's count replaced by the running sum before it
@@ -113,13 +95,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, 
     for (int k = 0; k < W; ++k) s_cnt[k][b] += base;
   }
   __syncthreads();
-  if (in_regs) {
-#pragma unroll
-    for (int r = 0; r < kOrderRegs; ++r)
-      if (bk[r] >= 0) order[atomicAdd(&s_cnt[w][bk[r]], 1u)] = (uint32_t)(t0 + lane + 64 * r);
-  } else {
-    for (int t = t0 + lane; t < t1; t += 64) order[atomicAdd(&s_cnt[w][cost_bucket(cost(t))], 1u)] = (uint32_t)t;
-  }
+  for (int t = t0 + lane; t < t1; t += 64) order[atomicAdd(&s_cnt[w][cost_bucket(cost(t))], 1u)] = (uint32_t)t;
 }
 
 template <int CTRL, int ROW_MASK = 0xF>

@@ -61,37 +61,20 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
 // cap32 items read it as their item count and then do nothing.
 // ---------------------------------------------------------------------------------------
 constexpr int kScanThreads = 1024;
-constexpr int kScanRegs = 16;   // counts per thread held in registers (up to 16384 counts)
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const uint32_t *in, const uint32_t *n_items,
                                                               int items_per_block, unsigned long long *prefix,
                                                               uint32_t *total32, unsigned long long *total64,
                                                               unsigned long long cap32, int max_blocks) {
   __shared__ unsigned long long s_w[kScanThreads / 64];
-  // thread t owns the contiguous counts [t per, (t + 1) per), per from the buffer's
-  // max_blocks, so its loads need not wait for the count n_items: its sum, a workgroup scan of
-  // the sums, then its exclusive prefixes. Up to kScanRegs counts stay in registers (loaded
-  // together); beyond that they are read twice, the second time from cache.
-  const int per = (max_blocks + kScanThreads - 1) / kScanThreads;
-  const int lo = min(max_blocks, (int)threadIdx.x * per);
-  const bool in_regs = per <= kScanRegs;
-  uint32_t v[kScanRegs];
-  if (in_regs) {
-#pragma unroll
-    for (int i = 0; i < kScanRegs; ++i) v[i] = (i < per && lo + i < max_blocks) ? in[lo + i] : 0u;
-  }
   int nb = max_blocks;
-  if (n_items) nb = (int)min((unsigned long long)max_blocks,
-                             ((unsigned long long)*n_items + items_per_block - 1) / items_per_block);
-  const int hi = max(lo, min(nb, lo + per));
+  if (n_items) nb = (int)(((unsigned long long)*n_items + items_per_block - 1) / items_per_block);
+  // thread t owns the contiguous counts [t per, (t + 1) per): its sum, a workgroup scan of the
+  // sums, then its exclusive prefixes (a second read of its counts, from cache)
+  const int per = (nb + kScanThreads - 1) / kScanThreads;
+  const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
   unsigned long long mine = 0;
-  if (in_regs) {
-#pragma unroll
-    for (int i = 0; i < kScanRegs; ++i)
-      if (lo + i < hi) mine += v[i];
-  } else {
-    for (int k = lo; k < hi; ++k) mine += in[k];
-  }
+  for (int k = lo; k < hi; ++k) mine += in[k];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   unsigned long long inc = mine;
 #pragma unroll
@@ -108,18 +91,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const uint32_t *in
     run += (k < w) ? t : 0ull;
     total += t;
   }
-  if (in_regs) {
-#pragma unroll
-    for (int i = 0; i < kScanRegs; ++i)
-      if (lo + i < hi) {
-        prefix[lo + i] = run;
-        run += v[i];
-      }
-  } else {
-    for (int k = lo; k < hi; ++k) {
-      prefix[k] = run;
-      run += in[k];
-    }
+  for (int k = lo; k < hi; ++k) {
+    prefix[k] = run;
+    run += in[k];
   }
   if (threadIdx.x == 0) {
     if (total64) *total64 = total;
