@@ -51,7 +51,7 @@ FLOPS_BLEND_BWD = 46
 # step_1080p_1M_hbm_counters.md). A figure holds only for the kernel sources it was taken
 # with: the sha256 over the listed files must match, else the traffic is reported as null.
 PROFILED_TRAFFIC = {
-    "blend_bwd": {"bytes": 319244277, "sha256": "028723a4791a8f59730ac617896de42aebd071d4ab5ca2d3c8d290699c2e5a20",
+    "blend_bwd": {"bytes": 319463363, "sha256": "50f33f2ec4fa7f40011cbcc9154d33373edaff13e52073e4353cf0706bc0f52e",
                   "sources": ['paper_2408_12894_amd/csrc/backward.hip', 'paper_2408_12894_amd/csrc/blend_common.h', 'paper_2408_12894_amd/csrc/project.h', 'paper_2408_12894_amd/csrc/flod_internal.h']},
 }
 
