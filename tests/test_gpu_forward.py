@@ -185,6 +185,32 @@ def test_instance_capacity_growth():
     assert k_seen[1] > 2 * k_seen[0]   # the second frame outgrows the first frame's buffers
 
 
+def test_small_frame_after_large_frame():
+    """A context keeps the instance capacity of its largest frame, and the sort, emission and
+    range kernels launch grids sized for that capacity: after a 1080p / 1M frame (about 8.5M
+    instances, so the tile sort takes its large-workgroup path), a 128x128 frame of 2k
+    Gaussians on the same context runs with almost every workgroup past the frame's counts.
+    It is bit-identical to the same frame on a fresh context and matches the oracle."""
+    from paper_2408_12894_amd import render
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    shared = render.Renderer(0)
+    big, cams, bg_big = synth.hd_forward_case()
+    _say("capacity set by 1M Gaussians, 1920x1080")
+    k_big = gpu_render(shared, big, cams[0], bg_big)[3]["stats"]["n_instances"]
+    assert k_big > 4 << 20
+    scene, cam, bg = synth.small_forward_case()
+    _say("2k Gaussians, 128x128 on the grown context")
+    got = gpu_render(shared, scene, cam, bg)
+    ref = gpu_render(render.Renderer(0), scene, cam, bg)
+    for a, b in zip(got[:3], ref[:3]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(got[3]["values"], ref[3]["values"])
+    np.testing.assert_array_equal(got[3]["tile_ids"], ref[3]["tile_ids"])
+    assert got[3]["stats"]["n_instances"] * 1000 < k_big
+    full_parity(shared, scene, cam, bg)
+
+
 def test_4k_full_size_sampled(renderer):
     """The same 1M cluster scene at 3840x2160, the largest serving resolution (32,400 tiles,
     15-bit tile ids, about four times the 1080p instance count): the whole key path and
