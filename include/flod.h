@@ -24,8 +24,10 @@
  * enqueued on it. A render enqueues the whole frame before it waits for anything: the
  * emission, tile sort and blend are sized for the instances the context's buffers hold and
  * read the instance count K on the device, doing nothing when K exceeds that capacity. The
- * host then waits for a stream-ordered 16-byte read of the counts (it completes once the
- * binning offsets are known, while the rest of the frame is still queued), fills the
+ * host then waits for the 16 bytes of counts, which the kernel that computes them writes to
+ * pinned host memory (or a stream-ordered copy, where coherent pinned memory is not
+ * available); they are there once the binning offsets are known, while the rest of the
+ * frame is still queued. It then fills the
  * statistics and, when K exceeded the capacity, grows the buffers and enqueues the frame's
  * tail again. A context's first render, with no buffers yet, waits for K before the tail.
  *
@@ -314,14 +316,15 @@ enum {
   FLOD_STAGE_TILE_SORT,       /* stable radix sort of instances by tile              */
   FLOD_STAGE_RANGES,          /* per-tile [start, end)                               */
   FLOD_STAGE_BLEND,           /* front-to-back compositing (eq. 2)                   */
-  FLOD_STAGE_BLEND_BWD,       /* reverse compositing                                 */
+  FLOD_STAGE_BLEND_BWD,       /* reverse compositing kernel (its tile order excluded) */
   FLOD_STAGE_PREPROCESS_BWD,  /* chain rule to the 3D attributes                     */
   FLOD_NUM_STAGES
 };
 /* enable != 0 records every stage. */
 flod_status flod_ctx_set_timing(flod_ctx *ctx, int enable);
 /* Record only the stages whose bit (1 << FLOD_STAGE_...) is set; 0 turns timing off. Each
-   recorded stage adds two event records to the stream. */
+   recorded stage adds two event records to the stream, except FLOD_STAGE_BLEND_BWD, which is
+   timed from its kernel's own dispatch (no packets between it and its neighbours). */
 flod_status flod_ctx_set_timing_stages(flod_ctx *ctx, unsigned int stage_mask);
 /* Accumulated milliseconds and call counts per stage since the last reset; synchronises
    on the last recorded events. ms and calls: host arrays of FLOD_NUM_STAGES. */

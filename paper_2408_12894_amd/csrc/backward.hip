@@ -20,6 +20,8 @@
 // and applying the chain rule in FP64 to the mean (through mu', the EWA Jacobian and the SH view
 // direction), log-scales (eq. 4: times exp(s_opt); s_min gets no gradient), quaternion
 // (through the normalisation), opacity logit (times o (1 - o)) and SH coefficients.
+#include <hip/hip_ext.h>
+
 #include "blend_common.h"
 
 namespace flod {
@@ -201,11 +203,18 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
 hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
                             const float2 *blue, const DevCamera &cam, const float bg[3], const float *final_T,
                             const int32_t *n_contrib, const float *dL_dimage, float *g2d, const uint8_t *taken,
-                            const uint32_t *order, hipStream_t s) {
+                            const uint32_t *order, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
-  hipLaunchKernelGGL(k_blend_bwd<kBwdPix>, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s, ranges, values,
-                     xyab, cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib,
-                     dL_dimage, g2d, taken, order);
+  if (ev_start || ev_stop) {
+    // timed from the kernel's own dispatch: no event packets between it and its neighbours
+    hipExtLaunchKernelGGL(k_blend_bwd<kBwdPix>, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s, ev_start,
+                          ev_stop, 0, ranges, values, xyab, cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0],
+                          bg[1], bg[2], final_T, n_contrib, dL_dimage, g2d, taken, order);
+  } else {
+    hipLaunchKernelGGL(k_blend_bwd<kBwdPix>, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s, ranges, values,
+                       xyab, cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib,
+                       dL_dimage, g2d, taken, order);
+  }
   return hipGetLastError();
 }
 

@@ -49,6 +49,11 @@ struct flod_ctx {
   hipStream_t last_stream = nullptr;
   size_t required = 0;
   unsigned long long *host_counters = nullptr;   // pinned: [visible u32 | K u32], [K u64]
+  // coherent pinned memory the offsets scan writes the same counts into (null: copy instead),
+  // its device address, and the event that completes with that kernel
+  uint32_t *host_counts = nullptr;
+  uint32_t *host_counts_dev = nullptr;
+  hipEvent_t ev_counts = nullptr;
   Saved saved;
   flod_stats stats{};
   // timing
@@ -136,6 +141,15 @@ struct StageTimer {
     c->ev_pending[stage] = true;
     stage = -1;
   }
+  // A one-kernel stage timed by its kernel's dispatch: the stage's events for the launch (null
+  // when the stage is not recorded), so that no event packet sits between it and its neighbours.
+  void dispatch(int k, hipEvent_t *start, hipEvent_t *stop) {
+    *start = *stop = nullptr;
+    if (!c->timing || !((c->timing_mask >> k) & 1u)) return;
+    *start = c->ev[k][0];
+    *stop = c->ev[k][1];
+    c->ev_pending[k] = true;
+  }
 };
 
 // Mark the work enqueued on s so far; wait_marked() returns once it has finished.
@@ -147,16 +161,18 @@ hipError_t mark_stream(flod_ctx *c, hipStream_t s) {
   return hipEventRecord(c->ev_sync, s);
 }
 
-// Poll the mark (a few microseconds of wake-up instead of a blocking wait's), falling back to
+// Poll an event (a few microseconds of wake-up instead of a blocking wait's), falling back to
 // a blocking wait after ~20000 polls.
-hipError_t wait_marked(flod_ctx *c) {
+hipError_t wait_event(hipEvent_t ev) {
   hipError_t e = hipSuccess;
   for (int spin = 0; spin < 20000; ++spin) {
-    e = hipEventQuery(c->ev_sync);
+    e = hipEventQuery(ev);
     if (e != hipErrorNotReady) return e;
   }
-  return hipEventSynchronize(c->ev_sync);
+  return hipEventSynchronize(ev);
 }
+
+hipError_t wait_marked(flod_ctx *c) { return wait_event(c->ev_sync); }
 
 int ceil_log2(int64_t v) {
   int b = 0;
@@ -269,11 +285,14 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   int dres = 0;
   uint32_t *sorted_tiles = nullptr;
   // tile counts in depth order and their scan; K (guarded by `guard`) to counters[kCntInstances]
-  auto offsets = [&](int64_t guard) -> hipError_t {
+  // and, when `to_host`, the counts straight to the host (completing c->ev_counts)
+  const bool direct = c->host_counts_dev != nullptr;
+  auto offsets = [&](int64_t guard, bool to_host) -> hipError_t {
     return launch_scan_blocks(P<uint32_t>(c, B_TBSUM), counters + kCntVisible, kBlock,
                               P<unsigned long long>(c, B_TPREFIX), counters + kCntInstances,
                               reinterpret_cast<unsigned long long *>(counters + kCntTotal64), nb, s,
-                              (unsigned long long)guard);
+                              (unsigned long long)guard, to_host ? c->host_counts_dev : nullptr,
+                              to_host ? c->ev_counts : nullptr);
   };
   if (N > 0) {
     PreOut o;
@@ -308,11 +327,12 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     sorted_tiles = dk[dres ^ 1];
     if (launch_tile_counts(dv[dres], counters + kCntVisible, N, o.tiles, P<uint32_t>(c, B_TBSUM), sorted_tiles,
                            s) != hipSuccess ||
-        offsets(speculate ? cap : 0xFFFFFFFEll) != hipSuccess)
+        offsets(speculate ? cap : 0xFFFFFFFEll, direct) != hipSuccess)
       return FLOD_ERR_DEVICE;
-    // the count read-back: [visible u32 | guarded K u32], [K u64]
-    if (hipMemcpyAsync(c->host_counters, counters, 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        mark_stream(c, s) != hipSuccess)
+    // the count read-back, [visible u32 | guarded K u32], [K u64]: written by the scan itself
+    // (direct), else copied
+    if (!direct && (hipMemcpyAsync(c->host_counters, counters, 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    mark_stream(c, s) != hipSuccess))
       return FLOD_ERR_DEVICE;
     tm.end();
   }
@@ -354,9 +374,11 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   int64_t n_vis = 0;
   unsigned long long K = 0;
   if (N > 0) {
-    if (wait_marked(c) != hipSuccess) return FLOD_ERR_DEVICE;
-    n_vis = reinterpret_cast<const uint32_t *>(c->host_counters)[kCntVisible];
-    K = c->host_counters[1];
+    if ((direct ? wait_event(c->ev_counts) : wait_marked(c)) != hipSuccess) return FLOD_ERR_DEVICE;
+    const volatile uint32_t *hc =
+        direct ? c->host_counts : reinterpret_cast<const volatile uint32_t *>(c->host_counters);
+    n_vis = hc[kCntVisible];
+    K = (unsigned long long)hc[2] | ((unsigned long long)hc[3] << 32);
   }
   c->stats.n_candidates = N;
   c->stats.n_visible = n_vis;
@@ -383,7 +405,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
         c->required = ws_bytes(c) + extra;
         return st;
       }
-      if (speculate && offsets(cap) != hipSuccess) return FLOD_ERR_DEVICE;
+      if (speculate && offsets(cap, false) != hipSuccess) return FLOD_ERR_DEVICE;
     }
     if ((st = tail(N > 0 ? cap : 0)) != FLOD_OK) return st;
   }
@@ -430,6 +452,22 @@ flod_status flod_ctx_create(flod_ctx **ctx, int device, flod_alloc_fn alloc, flo
     delete c;
     return FLOD_ERR_DEVICE;
   }
+  // counts written by a kernel straight into coherent host memory; without it the render
+  // copies them
+  if (hipHostMalloc((void **)&c->host_counts, 64, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess &&
+      (hipHostGetDevicePointer((void **)&c->host_counts_dev, c->host_counts, 0) != hipSuccess ||
+       hipEventCreate(&c->ev_counts) != hipSuccess)) {
+    if (c->ev_counts) (void)hipEventDestroy(c->ev_counts);
+    (void)hipHostFree(c->host_counts);
+    c->host_counts = nullptr;
+    c->host_counts_dev = nullptr;
+    c->ev_counts = nullptr;
+    (void)hipGetLastError();
+  }
+  if (!c->host_counts) {
+    c->host_counts_dev = nullptr;
+    (void)hipGetLastError();
+  }
   memset(c->ms, 0, sizeof(c->ms));
   memset(c->calls, 0, sizeof(c->calls));
   memset(c->ev_pending, 0, sizeof(c->ev_pending));
@@ -451,6 +489,8 @@ void flod_ctx_destroy(flod_ctx *ctx) {
     }
   if (ctx->ev_sync) (void)hipEventDestroy(ctx->ev_sync);
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+  if (ctx->ev_counts) (void)hipEventDestroy(ctx->ev_counts);
+  if (ctx->host_counts) (void)hipHostFree(ctx->host_counts);
   delete ctx;
 }
 
@@ -899,15 +939,15 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   }
   float *g2d = P<float>(ctx, B_G2D);
   if (launch_fill_u32(reinterpret_cast<uint32_t *>(g2d), 0u, 9 * N, s) != hipSuccess) return FLOD_ERR_DEVICE;
-  tm.begin(FLOD_STAGE_BLEND_BWD);
   const uint32_t *vals = sv.sorted_vals ? P<uint32_t>(ctx, B_TVAL1) : P<uint32_t>(ctx, B_TVAL0);
   uint32_t *order = P<uint32_t>(ctx, B_TILE_ORDER);
+  hipEvent_t ev_a, ev_b;
+  tm.dispatch(FLOD_STAGE_BLEND_BWD, &ev_a, &ev_b);
   if (launch_tile_order_by_count(P<uint32_t>(ctx, B_TILE_TAKEN), n_tiles, order, s) != hipSuccess ||
       launch_blend_bwd(P<uint2>(ctx, B_RANGES), vals, P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
                        P<float2>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d,
-                       P<uint8_t>(ctx, B_TAKEN), order, s) != hipSuccess)
+                       P<uint8_t>(ctx, B_TAKEN), order, s, ev_a, ev_b) != hipSuccess)
     return FLOD_ERR_DEVICE;
-  tm.end();
   tm.begin(FLOD_STAGE_PREPROCESS_BWD);
   PreParams p = base_params(sv.cam, sv.sh_degree);
   p.n_levels = 1;

@@ -103,7 +103,8 @@ hipError_t launch_preprocess(const PreParams &p, const PreOut &o, hipStream_t s)
 hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int items_per_block,
                               unsigned long long *prefix, uint32_t *total32,
                               unsigned long long *total64, int max_blocks, hipStream_t s,
-                              unsigned long long cap32 = 0xFFFFFFFFull);
+                              unsigned long long cap32 = 0xFFFFFFFFull, uint32_t *host_out = nullptr,
+                              hipEvent_t ev_done = nullptr);
 hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
                           const unsigned long long *prefix, uint32_t *keys, uint32_t *vals,
                           hipStream_t s);
@@ -130,7 +131,8 @@ hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const f
                             const float4 *cop, const float2 *blue, const DevCamera &cam,
                             const float bg[3], const float *final_T, const int32_t *n_contrib,
                             const float *dL_dimage, float *g2d, const uint8_t *taken,
-                            const uint32_t *order, hipStream_t s);
+                            const uint32_t *order, hipStream_t s, hipEvent_t ev_start = nullptr,
+                            hipEvent_t ev_stop = nullptr);
 hipError_t launch_tile_order_by_length(const uint2 *ranges, int n_tiles, uint32_t *order, hipStream_t s);
 hipError_t launch_tile_order_by_count(const uint32_t *count, int n_tiles, uint32_t *order, hipStream_t s);
 hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, const float *g2d,

@@ -16,6 +16,8 @@
 // digit run contiguously.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "project.h"
 
 namespace flod {
@@ -58,17 +60,21 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
 // ---------------------------------------------------------------------------------------
 // Scan of per-workgroup counts (one workgroup): 64-bit exclusive prefixes and the total.
 // total32 receives the total when it is at most cap32 and 0 otherwise: kernels sized for
-// cap32 items read it as their item count and then do nothing.
+// cap32 items read it as their item count and then do nothing. host_out (coherent host
+// memory, or null) receives [item count u32 | total32 u32], [total u64] by system-scope
+// stores, for a host that waits on the kernel's completion instead of a copy.
 // ---------------------------------------------------------------------------------------
 constexpr int kScanThreads = 1024;
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const uint32_t *in, const uint32_t *n_items,
                                                               int items_per_block, unsigned long long *prefix,
                                                               uint32_t *total32, unsigned long long *total64,
-                                                              unsigned long long cap32, int max_blocks) {
+                                                              unsigned long long cap32, int max_blocks,
+                                                              uint32_t *host_out) {
   __shared__ unsigned long long s_w[kScanThreads / 64];
   int nb = max_blocks;
-  if (n_items) nb = (int)(((unsigned long long)*n_items + items_per_block - 1) / items_per_block);
+  const uint32_t items = n_items ? *n_items : 0u;
+  if (n_items) nb = (int)(((unsigned long long)items + items_per_block - 1) / items_per_block);
   // thread t owns the contiguous counts [t per, (t + 1) per): its sum, a workgroup scan of the
   // sums, then its exclusive prefixes (a second read of its counts, from cache)
   const int per = (nb + kScanThreads - 1) / kScanThreads;
@@ -96,17 +102,29 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const uint32_t *in
     run += in[k];
   }
   if (threadIdx.x == 0) {
+    const uint32_t t32 = total > cap32 ? 0u : (uint32_t)total;
     if (total64) *total64 = total;
-    if (total32) *total32 = total > cap32 ? 0u : (uint32_t)total;
+    if (total32) *total32 = t32;
+    if (host_out) {
+      __hip_atomic_store(&host_out[0], items, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&host_out[1], t32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(reinterpret_cast<unsigned long long *>(host_out + 2), total, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
 hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int items_per_block,
                               unsigned long long *prefix, uint32_t *total32, unsigned long long *total64,
-                              int max_blocks, hipStream_t s, unsigned long long cap32) {
+                              int max_blocks, hipStream_t s, unsigned long long cap32, uint32_t *host_out,
+                              hipEvent_t ev_done) {
   if (cap32 > 0xFFFFFFFFull) cap32 = 0xFFFFFFFFull;
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, in, n_items, items_per_block, prefix,
-                     total32, total64, cap32, max_blocks);
+  if (ev_done)   // ev_done completes with the kernel (no event packet after it)
+    hipExtLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, nullptr, ev_done, 0, in, n_items,
+                          items_per_block, prefix, total32, total64, cap32, max_blocks, host_out);
+  else
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, in, n_items, items_per_block, prefix,
+                       total32, total64, cap32, max_blocks, host_out);
   return hipGetLastError();
 }
 
