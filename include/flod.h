@@ -24,10 +24,10 @@
  * enqueued on it. A render enqueues the whole frame before it waits for anything: the
  * emission, tile sort and blend are sized for the instances the context's buffers hold and
  * read the instance count K on the device, doing nothing when K exceeds that capacity. The
- * host then waits for the 16 bytes of counts, which the kernel that computes them writes to
- * pinned host memory (or a stream-ordered copy, where coherent pinned memory is not
- * available); they are there once the binning offsets are known, while the rest of the
- * frame is still queued. It then fills the
+ * host then waits for the counts, which the kernel that computes them writes to coherent
+ * pinned host memory tagged with the render's sequence number (or a stream-ordered copy,
+ * where coherent pinned memory is not available); they are there once the binning offsets
+ * are known, while the rest of the frame is still queued. It then fills the
  * statistics and, when K exceeded the capacity, grows the buffers and enqueues the frame's
  * tail again. A context's first render, with no buffers yet, waits for K before the tail.
  *

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <chrono>
 #include <new>
 
 #include "flod_internal.h"
@@ -49,11 +50,11 @@ struct flod_ctx {
   hipStream_t last_stream = nullptr;
   size_t required = 0;
   unsigned long long *host_counters = nullptr;   // pinned: [visible u32 | K u32], [K u64]
-  // coherent pinned memory the offsets scan writes the same counts into (null: copy instead),
-  // its device address, and the event that completes with that kernel
-  uint32_t *host_counts = nullptr;
-  uint32_t *host_counts_dev = nullptr;
-  hipEvent_t ev_counts = nullptr;
+  // coherent pinned memory the offsets scan writes the counts into, as four 64-bit words
+  // tagged with the render's sequence number (null: copy instead), and its device address
+  unsigned long long *host_counts = nullptr;
+  unsigned long long *host_counts_dev = nullptr;
+  uint32_t count_seq = 0;
   Saved saved;
   flod_stats stats{};
   // timing
@@ -174,6 +175,25 @@ hipError_t wait_event(hipEvent_t ev) {
 
 hipError_t wait_marked(flod_ctx *c) { return wait_event(c->ev_sync); }
 
+// Wait until all four count words carry `seq` (the scan kernel writes them whole): polling,
+// and after about 2 s a blocking wait for the stream, then one last look.
+hipError_t wait_counts(flod_ctx *c, hipStream_t s, uint32_t seq) {
+  const volatile unsigned long long *w = c->host_counts;
+  auto ready = [&]() {
+    for (int k = 0; k < 4; ++k)
+      if ((uint32_t)(w[k] >> 32) != seq) return false;
+    return true;
+  };
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint64_t spin = 0;; ++spin) {
+    if (ready()) return hipSuccess;
+    if ((spin & 1023u) == 1023u && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) break;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  return ready() ? hipSuccess : hipErrorUnknown;
+}
+
 int ceil_log2(int64_t v) {
   int b = 0;
   while (b < 62 && ((int64_t)1 << b) < v) ++b;
@@ -285,14 +305,15 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   int dres = 0;
   uint32_t *sorted_tiles = nullptr;
   // tile counts in depth order and their scan; K (guarded by `guard`) to counters[kCntInstances]
-  // and, when `to_host`, the counts straight to the host (completing c->ev_counts)
+  // and, when `to_host`, the counts straight to the host, tagged with this render's number
   const bool direct = c->host_counts_dev != nullptr;
+  if (direct && ++c->count_seq == 0u) c->count_seq = 1u;   // 0 is the buffer's initial tag
+  const uint32_t seq = direct ? c->count_seq : 0u;
   auto offsets = [&](int64_t guard, bool to_host) -> hipError_t {
     return launch_scan_blocks(P<uint32_t>(c, B_TBSUM), counters + kCntVisible, kBlock,
                               P<unsigned long long>(c, B_TPREFIX), counters + kCntInstances,
                               reinterpret_cast<unsigned long long *>(counters + kCntTotal64), nb, s,
-                              (unsigned long long)guard, to_host ? c->host_counts_dev : nullptr,
-                              to_host ? c->ev_counts : nullptr);
+                              (unsigned long long)guard, to_host ? c->host_counts_dev : nullptr, seq);
   };
   if (N > 0) {
     PreOut o;
@@ -374,11 +395,16 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   int64_t n_vis = 0;
   unsigned long long K = 0;
   if (N > 0) {
-    if ((direct ? wait_event(c->ev_counts) : wait_marked(c)) != hipSuccess) return FLOD_ERR_DEVICE;
-    const volatile uint32_t *hc =
-        direct ? c->host_counts : reinterpret_cast<const volatile uint32_t *>(c->host_counters);
-    n_vis = hc[kCntVisible];
-    K = (unsigned long long)hc[2] | ((unsigned long long)hc[3] << 32);
+    if (direct) {
+      if (wait_counts(c, s, seq) != hipSuccess) return FLOD_ERR_DEVICE;
+      const volatile unsigned long long *w = c->host_counts;
+      n_vis = (uint32_t)w[0];
+      K = (unsigned long long)(uint32_t)w[2] | ((unsigned long long)(uint32_t)w[3] << 32);
+    } else {
+      if (wait_marked(c) != hipSuccess) return FLOD_ERR_DEVICE;
+      n_vis = reinterpret_cast<const uint32_t *>(c->host_counters)[kCntVisible];
+      K = c->host_counters[1];
+    }
   }
   c->stats.n_candidates = N;
   c->stats.n_visible = n_vis;
@@ -454,15 +480,12 @@ flod_status flod_ctx_create(flod_ctx **ctx, int device, flod_alloc_fn alloc, flo
   }
   // counts written by a kernel straight into coherent host memory; without it the render
   // copies them
-  if (hipHostMalloc((void **)&c->host_counts, 64, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess &&
-      (hipHostGetDevicePointer((void **)&c->host_counts_dev, c->host_counts, 0) != hipSuccess ||
-       hipEventCreate(&c->ev_counts) != hipSuccess)) {
-    if (c->ev_counts) (void)hipEventDestroy(c->ev_counts);
-    (void)hipHostFree(c->host_counts);
-    c->host_counts = nullptr;
-    c->host_counts_dev = nullptr;
-    c->ev_counts = nullptr;
-    (void)hipGetLastError();
+  if (hipHostMalloc((void **)&c->host_counts, 64, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess) {
+    memset(c->host_counts, 0, 64);   // sequence 0 is never a render's
+    if (hipHostGetDevicePointer((void **)&c->host_counts_dev, c->host_counts, 0) != hipSuccess) {
+      (void)hipHostFree(c->host_counts);
+      c->host_counts = nullptr;
+    }
   }
   if (!c->host_counts) {
     c->host_counts_dev = nullptr;
@@ -489,7 +512,6 @@ void flod_ctx_destroy(flod_ctx *ctx) {
     }
   if (ctx->ev_sync) (void)hipEventDestroy(ctx->ev_sync);
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
-  if (ctx->ev_counts) (void)hipEventDestroy(ctx->ev_counts);
   if (ctx->host_counts) (void)hipHostFree(ctx->host_counts);
   delete ctx;
 }

@@ -103,8 +103,8 @@ hipError_t launch_preprocess(const PreParams &p, const PreOut &o, hipStream_t s)
 hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int items_per_block,
                               unsigned long long *prefix, uint32_t *total32,
                               unsigned long long *total64, int max_blocks, hipStream_t s,
-                              unsigned long long cap32 = 0xFFFFFFFFull, uint32_t *host_out = nullptr,
-                              hipEvent_t ev_done = nullptr);
+                              unsigned long long cap32 = 0xFFFFFFFFull, unsigned long long *host_out = nullptr,
+                              uint32_t host_seq = 0);
 hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
                           const unsigned long long *prefix, uint32_t *keys, uint32_t *vals,
                           hipStream_t s);

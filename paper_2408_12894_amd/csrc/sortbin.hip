@@ -16,8 +16,6 @@
 // digit run contiguously.
 #include <algorithm>
 
-#include <hip/hip_ext.h>
-
 #include "project.h"
 
 namespace flod {
@@ -61,8 +59,10 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
 // Scan of per-workgroup counts (one workgroup): 64-bit exclusive prefixes and the total.
 // total32 receives the total when it is at most cap32 and 0 otherwise: kernels sized for
 // cap32 items read it as their item count and then do nothing. host_out (coherent host
-// memory, or null) receives [item count u32 | total32 u32], [total u64] by system-scope
-// stores, for a host that waits on the kernel's completion instead of a copy.
+// memory, or null) receives four 64-bit words, each host_seq in its high half and in its low
+// half the item count, total32, and the low and high halves of the total: system-scope
+// stores of whole words, so a host that polls them sees every word either old or complete
+// and needs neither a copy nor an event.
 // ---------------------------------------------------------------------------------------
 constexpr int kScanThreads = 1024;
 
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const uint32_t *in
                                                               int items_per_block, unsigned long long *prefix,
                                                               uint32_t *total32, unsigned long long *total64,
                                                               unsigned long long cap32, int max_blocks,
-                                                              uint32_t *host_out) {
+                                                              unsigned long long *host_out, uint32_t host_seq) {
   __shared__ unsigned long long s_w[kScanThreads / 64];
   int nb = max_blocks;
   const uint32_t items = n_items ? *n_items : 0u;
@@ -106,25 +106,21 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const uint32_t *in
     if (total64) *total64 = total;
     if (total32) *total32 = t32;
     if (host_out) {
-      __hip_atomic_store(&host_out[0], items, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(&host_out[1], t32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(reinterpret_cast<unsigned long long *>(host_out + 2), total, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_SYSTEM);
+      const unsigned long long tag = (unsigned long long)host_seq << 32;
+      const unsigned long long w[4] = {tag | items, tag | t32, tag | (total & 0xFFFFFFFFull), tag | (total >> 32)};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) __hip_atomic_store(&host_out[k], w[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
 }
 
 hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int items_per_block,
                               unsigned long long *prefix, uint32_t *total32, unsigned long long *total64,
-                              int max_blocks, hipStream_t s, unsigned long long cap32, uint32_t *host_out,
-                              hipEvent_t ev_done) {
+                              int max_blocks, hipStream_t s, unsigned long long cap32,
+                              unsigned long long *host_out, uint32_t host_seq) {
   if (cap32 > 0xFFFFFFFFull) cap32 = 0xFFFFFFFFull;
-  if (ev_done)   // ev_done completes with the kernel (no event packet after it)
-    hipExtLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, nullptr, ev_done, 0, in, n_items,
-                          items_per_block, prefix, total32, total64, cap32, max_blocks, host_out);
-  else
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, in, n_items, items_per_block, prefix,
-                       total32, total64, cap32, max_blocks, host_out);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, in, n_items, items_per_block, prefix,
+                     total32, total64, cap32, max_blocks, host_out, host_seq);
   return hipGetLastError();
 }
 
