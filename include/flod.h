@@ -27,7 +27,8 @@
  * host then waits for the counts, which the kernel that computes them writes to coherent
  * pinned host memory tagged with the render's sequence number (or a stream-ordered copy,
  * where coherent pinned memory is not available); they are there once the binning offsets
- * are known, while the rest of the frame is still queued. It then fills the
+ * are known, while the rest of the frame is still queued (FLOD_COUNT_COPY=1 in the
+ * environment when a context is created selects the copy). It then fills the
  * statistics and, when K exceeded the capacity, grows the buffers and enqueues the frame's
  * tail again. A context's first render, with no buffers yet, waits for K before the tail.
  *

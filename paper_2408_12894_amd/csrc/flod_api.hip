@@ -1,6 +1,7 @@
 // C ABI of libflod: argument validation, workspace management and stage orchestration on
 // the caller's stream. Every arithmetic step runs in the kernels of this library.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <chrono>
@@ -478,9 +479,11 @@ flod_status flod_ctx_create(flod_ctx **ctx, int device, flod_alloc_fn alloc, flo
     delete c;
     return FLOD_ERR_DEVICE;
   }
-  // counts written by a kernel straight into coherent host memory; without it the render
-  // copies them
-  if (hipHostMalloc((void **)&c->host_counts, 64, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess) {
+  // counts written by a kernel straight into coherent host memory; without it (or with
+  // FLOD_COUNT_COPY=1 in the environment) the render copies them
+  const char *force_copy = getenv("FLOD_COUNT_COPY");
+  if (!(force_copy && force_copy[0] == '1') &&
+      hipHostMalloc((void **)&c->host_counts, 64, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess) {
     memset(c->host_counts, 0, 64);   // sequence 0 is never a render's
     if (hipHostGetDevicePointer((void **)&c->host_counts_dev, c->host_counts, 0) != hipSuccess) {
       (void)hipHostFree(c->host_counts);

@@ -211,6 +211,32 @@ def test_small_frame_after_large_frame():
     full_parity(shared, scene, cam, bg)
 
 
+def test_count_copy_fallback(monkeypatch):
+    """The instance counts reach the host through coherent pinned memory the scan kernel writes,
+    or, where that memory is unavailable, through a copy (forced here by FLOD_COUNT_COPY=1 at
+    context creation). A small -> large -> small sequence gives bit-identical frames and
+    counts both ways."""
+    from paper_2408_12894_amd import render
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    small = synth.uniform_scene(300, seed=70, s_mu=-3.5, s_sigma=0.5)
+    large = synth.uniform_scene(4000, seed=71, s_mu=-2.5, s_sigma=0.7)
+    cam = synth.look_at_camera((0.3, -0.2, -3.8), (0, 0, 0), 144, 112)
+    bg = np.array([0.2, 0.1, 0.3], np.float32)
+    direct = render.Renderer(0)
+    monkeypatch.setenv("FLOD_COUNT_COPY", "1")
+    copied = render.Renderer(0)
+    for step, scene in enumerate([small, large, small]):
+        _say(f"count read-back both ways, frame {step} (n={scene.n})")
+        a = gpu_render(direct, scene, cam, bg)
+        b = gpu_render(copied, scene, cam, bg)
+        for x, y in zip(a[:3], b[:3]):
+            np.testing.assert_array_equal(x, y)
+        for key in ("n_instances", "n_visible"):
+            assert a[3]["stats"][key] == b[3]["stats"][key]
+        np.testing.assert_array_equal(a[3]["values"], b[3]["values"])
+
+
 def test_4k_full_size_sampled(renderer):
     """The same 1M cluster scene at 3840x2160, the largest serving resolution (32,400 tiles,
     15-bit tile ids, about four times the 1080p instance count): the whole key path and
