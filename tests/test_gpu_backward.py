@@ -182,3 +182,46 @@ def test_backward_after_selective_is_unsupported(renderer):
     with pytest.raises(_lib.FlodError) as e:
         renderer.backward(lv, torch.zeros((3, cam.height, cam.width), device="cuda"))
     assert e.value.status == _lib.FLOD_ERR_UNSUPPORTED
+
+
+def test_stage_timing_records_and_changes_nothing():
+    """Per-stage device timing (HIP events; the backward blend timed from its own kernel
+    dispatch): with every stage timed, a first forward and backward on a context record each
+    stage once with a positive time; with only the backward blend timed, only it is recorded.
+    Images are bit-identical with and without timing, gradients equal up to the order of the
+    atomic sums."""
+    from paper_2408_12894_amd import render
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _say("stage timing on a forward and backward")
+    scene, cam, _ = synth.small_forward_case()
+    bg = (0.1, 0.2, 0.3)
+    lv = render.GaussianLevel.from_scene(scene)
+    rng = np.random.default_rng(90)
+    dimg = torch.from_numpy(rng.standard_normal((3, cam.height, cam.width)).astype(np.float32)).cuda()
+
+    def run(r):
+        img, T, nc = r.render_level(lv, cam, bg)
+        g = r.backward(lv, dimg)
+        torch.cuda.synchronize()
+        return [img.cpu().numpy(), T.cpu().numpy(), nc.cpu().numpy()], [g[k].cpu().numpy() for k in NAMES]
+
+    plain = run(render.Renderer(0))
+    r = render.Renderer(0)
+    r.set_timing(True)
+    r.stage_times(reset=True)
+    timed = run(r)
+    st = r.stage_times(reset=True)
+    for name, (ms, calls) in st.items():
+        assert calls == 1 and ms > 0.0, (name, ms, calls)
+    r.set_timing(True, stages=["blend_bwd"])
+    only = run(r)
+    st = r.stage_times(reset=True)
+    for name, (ms, calls) in st.items():
+        assert calls == (1 if name == "blend_bwd" else 0), (name, calls)
+    assert st["blend_bwd"][0] > 0.0
+    for other in (timed, only):
+        for a, b in zip(plain[0], other[0]):
+            np.testing.assert_array_equal(a, b)
+        for a, b in zip(plain[1], other[1]):
+            np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-6)
