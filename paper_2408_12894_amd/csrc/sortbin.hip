@@ -425,7 +425,9 @@ hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
 // ---------------------------------------------------------------------------------------
 constexpr uint32_t kEmitSolo = 256;  // measured: 64 -> 256 halves emission of 75-tile footprints (4K)
 constexpr uint32_t kEmitCap = 4096;   // instances staged per window (32 KB of LDS)
-constexpr uint32_t kEmitSplit = 8;    // at most this many workgroups share one block's windows
+constexpr uint32_t kEmitSplit = 8;    // at most this many workgroups share one block's windows,
+constexpr uint32_t kEmitSplitHuge = 64;  // or this many when a block may fill kEmitHugeWindows or more
+constexpr uint32_t kEmitHugeWindows = 32;
 
 struct RectSpan {
   int x0, y0, x1, y1;
@@ -591,10 +593,14 @@ hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const 
                        uint32_t *values, hipStream_t s) {
   if (n_max <= 0) return hipSuccess;
   // workgroups per block: enough for the windows an average block of up to k_max instances
-  // fills (1 when blocks fit a window, as they do for small footprints)
+  // fills (1 when blocks fit a window, as they do for small footprints). Coarse levels, whose
+  // few blocks each fill hundreds of windows, get up to 64 (level 1 at 3840x2160: 1.42 ->
+  // 1.04 ms); others at most 8, since the surplus workgroups of a small frame on a context
+  // whose capacity a large frame set still cost their launch.
   const int64_t blocks = (n_max + kBlock - 1) / kBlock;
   const int64_t windows = (k_max + blocks * (int64_t)kEmitCap - 1) / (blocks * (int64_t)kEmitCap);
-  const unsigned split = (unsigned)std::min<int64_t>(kEmitSplit, std::max<int64_t>(1, windows));
+  const int64_t cap_split = windows >= (int64_t)kEmitHugeWindows ? kEmitSplitHuge : kEmitSplit;
+  const unsigned split = (unsigned)std::min<int64_t>(cap_split, std::max<int64_t>(1, windows));
   hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks, split), dim3(kBlock), 0, s, sorted_ids, n_ptr, k_ptr,
                      sorted_tiles, bin, prefix, tiles_x, tiles_y, tile_ids, values);
   return hipGetLastError();
