@@ -16,6 +16,8 @@ constexpr int kSortItems = 12;            // keys per thread in a radix pass (me
 constexpr int kSortTile = kBlock * kSortItems;   // 3072 keys per workgroup
 constexpr int kSortItemsSmall = 8;        // 2048-key workgroups for sorts below kRadixBigSort (2 / 4 / 8)
 constexpr int64_t kRadixBigSort = 4 << 20;
+constexpr int kSortItemsHuge = 16;        // 4096-key workgroups for sorts of kRadixHugeSort keys or more
+constexpr int64_t kRadixHugeSort = 32 << 20;
 constexpr size_t kGaussianBytes = (3 + 3 + 4 + 1 + FLOD_SH_COEFFS * 3) * 4;   // 236 B per stored Gaussian
 constexpr unsigned long long kPruneMaxScan = 1ull << 36;   // overlap-pruning neighbour-scan limit
 
