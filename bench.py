@@ -51,7 +51,7 @@ FLOPS_BLEND_BWD = 46
 # step_1080p_1M_hbm_counters.md). A figure holds only for the kernel sources it was taken
 # with: the sha256 over the listed files must match, else the traffic is reported as null.
 PROFILED_TRAFFIC = {
-    "blend_bwd": {"bytes": 319116200, "sha256": "f631a77c4c89cc740d3f00207b3e4d5086f3fea29b98daf242af7526394307ad",
+    "blend_bwd": {"bytes": 319119367, "sha256": "17d6024965aa7389acd53ff94b484008d182eaa5b04c943c55a4ab56e915284f",
                   "sources": ['paper_2408_12894_amd/csrc/backward.hip', 'paper_2408_12894_amd/csrc/blend_common.h', 'paper_2408_12894_amd/csrc/project.h', 'paper_2408_12894_amd/csrc/flod_internal.h']},
 }
 
