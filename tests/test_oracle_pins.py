@@ -184,6 +184,95 @@ def test_ewa_off_axis_matches_numerical_jacobian(oracle_mod):
         np.testing.assert_allclose(out[i, :2], pix(t), rtol=1e-12)
 
 
+def _ewa_clamped_expect(cam, t, Sig_view):
+    """Sigma' = J W J^T + 0.3 I with J = [[f/z, 0, -f xc/z], [0, f/z, -f yc/z]] taken at the
+    image-plane coordinates (x/z, y/z) clamped to 1.3 times the half field of view on each
+    axis (the 3DGS framework's guard against huge footprints far outside the frustum)."""
+    fx, fy = float(np.float32(cam.fx)), float(np.float32(cam.fy))
+    limx = 1.3 * (0.5 * cam.width) / fx
+    limy = 1.3 * (0.5 * cam.height) / fy
+    xc = min(max(t[0] / t[2], -limx), limx)
+    yc = min(max(t[1] / t[2], -limy), limy)
+    J = np.array([[fx / t[2], 0.0, -fx * xc / t[2]], [0.0, fy / t[2], -fy * yc / t[2]]])
+    return J @ Sig_view @ J.T + 0.3 * np.eye(2)
+
+
+def test_ewa_fov_clamp_closed_form(oracle_mod):
+    """Gaussians whose centres lie beyond 1.3x the half field of view (either side, either
+    axis): the Jacobian is taken at the clamped image-plane coordinate, not at the centre's
+    own. The FP64 projection and the FP32 key mirror's stored conic both follow it; an
+    unclamped or differently clamped Jacobian changes Sigma' by far more than the tolerance."""
+    cam = axis_camera(64, 48)
+    rng = np.random.default_rng(31)
+    limx = 1.3 * 32.0 / cam.fx
+    cases = [(1.0, 0.1), (-1.2, 0.05), (0.2, 1.1), (-0.3, -0.9), (0.95, -1.05)]
+    for u, v in cases:
+        z = 4.0 + rng.uniform(-0.5, 0.5)
+        mu = np.array([u * z, v * z, z - 4.0], np.float32)
+        g = rng.normal(size=4)
+        q = (g / np.linalg.norm(g)).astype(np.float32)
+        ls = rng.normal(-1.0, 0.3, size=3).astype(np.float32)
+        arr = one_gaussian(mu, ls, q, 2.0)
+        out = oracle_mod.project64([0], *arr[:4], 0.0, arr[4], 0, cam)[0]
+        t = mu.astype(np.float64) + np.array([0.0, 0.0, 4.0])
+        qd = q.astype(np.float64)
+        Rm = Rotation.from_quat([qd[1], qd[2], qd[3], qd[0]]).as_matrix()
+        Sig = Rm @ np.diag(np.exp(ls.astype(np.float64)) ** 2) @ Rm.T
+        expect = _ewa_clamped_expect(cam, t, Sig)
+        np.testing.assert_allclose(_sigma2d_from_conic(out[2:5]), expect, rtol=1e-9, atol=1e-12)
+        # the mean itself is projected without any clamp
+        np.testing.assert_allclose(out[:2], [cam.fx * t[0] / t[2] + cam.cx, cam.fy * t[1] / t[2] + cam.cy],
+                                   rtol=1e-12)
+        k = oracle_mod.keys(*arr[:4], 0.0, cam)
+        np.testing.assert_allclose(k["conic"][0], np.linalg.inv(expect)[[0, 0, 1], [0, 1, 1]], rtol=2e-6)
+    assert abs(cases[0][0]) > limx
+
+
+def test_ewa_fov_clamp_gradient_by_differences(oracle_mod):
+    """Beyond the clamp the projected covariance no longer depends on the clamped coordinate:
+    with the camera on the axis, Sigma' is constant in mu_x, and the analytic gradient of a
+    pixel loss with respect to mu_x is the mean's own term dL/dmu'_x f/z only; both are
+    checked against FP64 central differences of the brute-force image."""
+    cam = axis_camera(64, 64)
+    z = 4.0
+    mu = np.array([0.95 * z, 0.1, 0.0], np.float32)       # x/z = 0.95 > 1.3 tan 30deg = 0.75
+    ls = np.log(np.array([0.6, 0.5, 0.4], np.float32))
+    arr = one_gaussian(mu, ls, (1, 0, 0, 0), 1.5, sh0=sh0_for_colour([0.9, 0.4, 0.2]))
+    arrs = [a.astype(np.float64) for a in arr]
+    h = 1e-4
+    p0 = oracle_mod.project64([0], *arrs[:4], 0.0, arrs[4], 0, cam)[0]
+    for d in (-h, h):
+        a2 = [x.copy() for x in arrs]
+        a2[0][0, 0] += d
+        p1 = oracle_mod.project64([0], *a2[:4], 0.0, a2[4], 0, cam)[0]
+        np.testing.assert_array_equal(p1[2:5], p0[2:5])
+    bg = np.array([0.1, 0.2, 0.3], np.float32)
+    k = oracle_mod.keys(*arr[:4], 0.0, cam)
+    assert k["visible"][0]
+    order = oracle_mod.depth_order(k)
+    pix = oracle_mod.all_pixels(64, 64)
+    base = oracle_mod.image(order, *arrs[:4], 0.0, arrs[4], 0, cam, bg, pix)
+    assert (base["nblend"] > 0).sum() > 50             # the Gaussian reaches into the frame
+    rng = np.random.default_rng(32)
+    w = rng.normal(size=(pix.shape[0], 3))
+    w[base["flag"] == 1] = 0.0
+    g = oracle_mod.grad(order, *arrs[:4], 0.0, arrs[4], 0, cam, bg, pix, w)
+    np.testing.assert_allclose(g["means"][0, 0], g["g2d"][0, 0] * np.float32(cam.fx) / z, rtol=1e-10)
+
+    def loss(a):
+        return float(np.sum(w * oracle_mod.image(order, *a[:4], 0.0, a[4], 0, cam, bg, pix)["rgb"]))
+
+    for j in range(3):
+        hh = 1e-6
+        a2 = [x.copy() for x in arrs]
+        a2[0][0, j] += hh
+        lp = loss(a2)
+        a2[0][0, j] -= 2 * hh
+        lm = loss(a2)
+        fd = (lp - lm) / (2 * hh)
+        assert abs(g["means"][0, j] - fd) <= 1e-6 * max(1.0, abs(fd)), (j, g["means"][0, j], fd)
+
+
 # --------------------------------------------------------------------------------------
 # Spherical-harmonic colour (Preliminary: SH coefficients; degree 3 per the workloads)
 # --------------------------------------------------------------------------------------
@@ -236,6 +325,47 @@ def test_sh_degree_truncation(oracle_mod):
     assert abs(Y3[0] - Y00) < 1e-16
 
 
+def test_sh_view_direction_degree1_closed_form(oracle_mod):
+    """Colour is evaluated at the unit direction from the camera centre to the Gaussian's
+    mean, dir = (mu - eye) / |mu - eye|: with one degree-1 coefficient k per channel,
+    c = max(0, k sqrt(3 / (4 pi)) dir_j + 0.5) with dir_j = x, y, z for m = 1, -1, 0.
+    Cameras on opposite sides see opposite directions, and the SH gradient is the same basis
+    value times dL/dc."""
+    y1 = math.sqrt(3.0 / (4.0 * math.pi))
+    mu = np.array([0.7, -0.4, 0.3], np.float32)
+    kcoef = float(np.float32(0.8))
+    sh = np.zeros((1, 16, 3), np.float32)
+    sh[0, 3, 0] = kcoef      # Y_1^1  ~ x  -> red
+    sh[0, 1, 1] = kcoef      # Y_1^-1 ~ y  -> green
+    sh[0, 2, 2] = -kcoef     # Y_1^0  ~ z  -> blue
+    for eye in ((0.0, 0.0, -4.0), (0.0, 0.0, 4.0), (3.0, 1.0, -2.0)):
+        cam = synth.look_at_camera(eye, (0.0, 0.0, 0.0), 64, 64)
+        e = np.asarray(cam.campos, np.float64)
+        d = mu.astype(np.float64) - e
+        d /= np.linalg.norm(d)
+        expect = np.maximum(0.0, np.array([kcoef * y1 * d[0], kcoef * y1 * d[1], -kcoef * y1 * d[2]]) + 0.5)
+        arr = one_gaussian(mu, (-2.0, -2.0, -2.0), (1, 0, 0, 0), 2.0)
+        out = oracle_mod.project64([0], *arr[:4], 0.0, sh, 1, cam)[0]
+        np.testing.assert_allclose(out[6:9], expect, rtol=1e-12, atol=1e-14)
+        # the gradient with respect to each coefficient carries the same basis value
+        k = oracle_mod.keys(*arr[:4], 0.0, cam)
+        assert k["visible"][0]
+        order = oracle_mod.depth_order(k)
+        pix = np.array([[32, 32], [33, 31], [30, 34]], np.int32)
+        w = np.ones((3, 3))
+        g = oracle_mod.grad(order, *[a.astype(np.float64) for a in arr[:4]], 0.0, sh.astype(np.float64), 1,
+                            cam, np.zeros(3, np.float32), pix, w)
+        dc = g["g2d"][0, 6:9]
+        Y = np.array([y1 * d[1], y1 * d[2], y1 * d[0]])          # basis rows 1, 2, 3
+        for ch in range(3):
+            if expect[ch] > 0:
+                np.testing.assert_allclose(g["sh"][0, 1:4, ch], dc[ch] * Y, rtol=1e-12, atol=1e-15)
+    # the two on-axis cameras see the mean from opposite sides: blue flips about 0.5
+    a = [oracle_mod.project64([0], *one_gaussian(mu, (-2.0,) * 3, (1, 0, 0, 0), 2.0)[:4], 0.0, sh, 1,
+                              synth.look_at_camera(e, (0.0, 0.0, 0.0), 64, 64))[0][8] for e in ((0, 0, -4.0), (0, 0, 4.0))]
+    assert a[0] < 0.5 < a[1]
+
+
 # --------------------------------------------------------------------------------------
 # eq. 2 and depth-ordered blending (Preliminary): closed-form images
 # --------------------------------------------------------------------------------------
@@ -252,22 +382,34 @@ def _closed_alpha(px, py, cam, s, z, o):
 
 
 def test_single_gaussian_image_closed_form(oracle_mod):
+    """One Gaussian on the optical axis: every pixel is alpha c + (1 - alpha) bg with
+    alpha = min(0.99, o exp(-q/2)), zero where q > 9 or alpha < 1/255. Three opacities: a
+    middle one, an opaque one whose alpha saturates at 0.99 near the centre, and a faint one
+    whose alpha crosses 1/128 and 1/255 inside the 3-sigma support."""
     cam = axis_camera(64, 64)
-    ls = np.log(np.array([0.04, 0.07, 0.05], np.float32))
-    s = np.exp(ls.astype(np.float64))
-    logit = 1.3
-    o = 1.0 / (1.0 + math.exp(-np.float32(logit)))
     col = np.array([0.8, 0.3, 0.55])
-    arr = one_gaussian((0, 0, 0), ls, (1, 0, 0, 0), logit, sh0=sh0_for_colour(col))
     bg = np.array([0.1, 0.2, 0.3], np.float32)
-    r = oracle_mod.render(arr, 0.0, cam, bg, deg=0)
-    img = r["rgb"].reshape(64, 64, 3)
-    T = r["T"].reshape(64, 64)
-    for py in range(64):
-        for px in range(64):
-            a = _closed_alpha(px, py, cam, s, 4.0, o)
-            np.testing.assert_allclose(img[py, px], a * col + (1 - a) * bg.astype(np.float64), atol=1e-12)
-            assert abs(T[py, px] - (1 - a)) < 1e-12
+    cases = [((0.04, 0.07, 0.05), 1.3), ((0.5, 0.45, 0.5), 8.0), ((0.1, 0.12, 0.1), -2.9)]
+    for scales, logit in cases:
+        ls = np.log(np.array(scales, np.float32))
+        s = np.exp(ls.astype(np.float64))
+        o = 1.0 / (1.0 + math.exp(-np.float32(logit)))
+        arr = one_gaussian((0, 0, 0), ls, (1, 0, 0, 0), logit, sh0=sh0_for_colour(col))
+        r = oracle_mod.render(arr, 0.0, cam, bg, deg=0)
+        img = r["rgb"].reshape(64, 64, 3)
+        T = r["T"].reshape(64, 64)
+        alphas = []
+        for py in range(64):
+            for px in range(64):
+                a = _closed_alpha(px, py, cam, s, 4.0, o)
+                alphas.append(a)
+                np.testing.assert_allclose(img[py, px], a * col + (1 - a) * bg.astype(np.float64), atol=1e-12)
+                assert abs(T[py, px] - (1 - a)) < 1e-12
+        alphas = np.array(alphas)
+        if logit > 5:
+            assert (alphas == 0.99).sum() >= 4
+        if logit < 0:
+            assert ((alphas > 1 / 255) & (alphas < 1 / 128)).sum() >= 8
 
 
 def test_two_coaxial_gaussians_order(oracle_mod):
@@ -481,6 +623,10 @@ def test_culls(oracle_mod):
         (dict(base, mu=(0, 0, -3.7)), True),
         (dict(base, logit=-5.6), False),                  # opacity below 1/255
         (dict(base, logit=-5.5), True),
+        # centred on a pixel centre, so that the support of a faint Gaussian still meets a
+        # tile: o = 1/255 at logit = -ln 254 = -5.53733 (compared in FP32)
+        (dict(base, mu=(0.5 * 4 / 55.42562484741211, 0.5 * 4 / 55.42562484741211, 0), logit=-5.5374), False),
+        (dict(base, mu=(0.5 * 4 / 55.42562484741211, 0.5 * 4 / 55.42562484741211, 0), logit=-5.5373), True),
         (dict(base, quat=(0, 0, 0, 0)), False),           # zero-norm quaternion
         (dict(base, mu=(50, 0, 0)), False),               # far outside the frame
     ]
