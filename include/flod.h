@@ -54,7 +54,8 @@ typedef enum {
   FLOD_ERR_WORKSPACE = -2,    /* the allocator callback refused; see flod_ctx_required_bytes */
   FLOD_ERR_OVERFLOW = -3,     /* more than 2^32 - 1 tile instances */
   FLOD_ERR_DEVICE = -4,       /* a HIP runtime call failed */
-  FLOD_ERR_UNSUPPORTED = -5   /* e.g. backward after a selective render */
+  FLOD_ERR_UNSUPPORTED = -5,  /* e.g. backward after a selective render */
+  FLOD_ERR_TOO_LARGE = -6     /* input beyond an allocation-free entry point's fixed scratch */
 } flod_status;
 
 #define FLOD_MAX_LEVELS 8
@@ -202,6 +203,22 @@ flod_status flod_compact_level(flod_ctx *ctx, const flod_level *in, const uint8_
    fixed order (deterministic). 0 <= lambda <= 1; 1 <= channels <= 64, sizes <= 65536. */
 flod_status flod_l1_ssim_forward(flod_ctx *ctx, const float *image, const float *target, int channels, int height,
                                  int width, float lambda, double *loss, float *dmaps, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+   serving or training loops, harnesses that forbid hipMalloc): flod_l1_ssim_forward with
+   the same arguments, results and determinism, but its per-workgroup partial sums live in a
+   fixed scratch array of 4 MiB inside the library (one per device, held until the process
+   ends) instead of the context's workspace, so the call allocates nothing, not even on its
+   first use. ctx only names the device; it must have been created on that device (creation
+   looks up the scratch's device address). Limit: channels * ceil(height/16) * ceil(width/16)
+   <= 262144 workgroups (3 channels: 87381 tiles of 16x16, so 3840x2160 with 32400 tiles
+   fits and 7680x4320 with 129600 does not), else FLOD_ERR_TOO_LARGE before any launch. All calls on one device share the
+   scratch: calls that overlap in time on one device (different streams, or different host
+   threads) race and give wrong losses; calls ordered on one stream are safe. Nothing is
+   read from an earlier call's scratch contents, so nothing needs clearing. */
+flod_status flod_l1_ssim_forward_noalloc(flod_ctx *ctx, const float *image, const float *target, int channels,
+                                         int height, int width, float lambda, double *loss, float *dmaps,
+                                         void *stream);
 
 /* Gradient of the loss above with respect to image, times *dloss (device double[1], NULL
    for 1): d_image, device float[channels, height, width]. dmaps from flod_l1_ssim_forward on

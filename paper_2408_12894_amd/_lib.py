@@ -17,6 +17,7 @@ FLOD_ERR_WORKSPACE = -2
 FLOD_ERR_OVERFLOW = -3
 FLOD_ERR_DEVICE = -4
 FLOD_ERR_UNSUPPORTED = -5
+FLOD_ERR_TOO_LARGE = -6
 MAX_LEVELS = 8
 NUM_STAGES = 10
 STAGES = ("preprocess", "compact", "depth_sort", "offsets", "emit", "tile_sort", "ranges", "blend",
@@ -28,7 +29,7 @@ EXPORTS = ("flod_ctx_create", "flod_ctx_destroy", "flod_ctx_workspace_bytes", "f
            "flod_stage_name", "flod_smin", "flod_dproj", "flod_status_str", "flod_copy_to_host",
            "flod_render_merged", "flod_select_compact", "flod_overlap_prune", "flod_compact_level",
            "flod_level_transition", "flod_adam_step", "flod_l1_ssim_forward", "flod_l1_ssim_backward",
-           "flod_l1_loss_forward", "flod_l1_loss_backward")
+           "flod_l1_loss_forward", "flod_l1_loss_backward", "flod_l1_ssim_forward_noalloc")
 
 
 class FlodError(RuntimeError):
@@ -132,6 +133,8 @@ def load():
     ci = C.c_int
     L.flod_l1_ssim_forward.argtypes = [vp, vp, vp, ci, ci, ci, C.c_float, vp, vp, vp]
     L.flod_l1_ssim_forward.restype = C.c_int
+    L.flod_l1_ssim_forward_noalloc.argtypes = [vp, vp, vp, ci, ci, ci, C.c_float, vp, vp, vp]
+    L.flod_l1_ssim_forward_noalloc.restype = C.c_int
     L.flod_l1_ssim_backward.argtypes = [vp, vp, vp, ci, ci, ci, C.c_float, vp, vp, vp, vp]
     L.flod_l1_ssim_backward.restype = C.c_int
     L.flod_l1_loss_forward.argtypes = [vp, vp, vp, C.c_int64, vp, vp]

@@ -5,11 +5,46 @@
 #include <string.h>
 
 #include <chrono>
+#include <mutex>
 #include <new>
 
 #include "flod_internal.h"
 
 using namespace flod;
+
+// Fixed scratch of flod_l1_ssim_forward_noalloc: the SSIM forward's per-workgroup partial
+// sums (one double2 per workgroup). Each device holds its own copy until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is only a stand-in
+// for the symbol): the device address is looked up once per device, with that device
+// current, when a context is created on it, and kept in g_scratch_dev.
+constexpr size_t kNoAllocScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void *g_scratch_dev[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// Look up the device address of `scratch` on `device`, which must be current.
+bool resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return false;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return true;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return false;
+  }
+  g_scratch_dev[device] = ptr;
+  return true;
+}
+
+void *scratch_on(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+}  // namespace
 
 namespace {
 
@@ -469,6 +504,8 @@ flod_status flod_ctx_create(flod_ctx **ctx, int device, flod_alloc_fn alloc, flo
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return FLOD_ERR_DEVICE;
   if (hipSetDevice(device) != hipSuccess) return FLOD_ERR_DEVICE;
+  // the allocation-free entry point's scratch on this device (failure only disables it)
+  (void)resolve_scratch(device);
   flod_ctx *c = new (std::nothrow) flod_ctx();
   if (!c) return FLOD_ERR_WORKSPACE;
   c->device = device;
@@ -837,6 +874,24 @@ flod_status flod_l1_ssim_forward(flod_ctx *ctx, const float *image, const float 
                                  P<double2>(ctx, B_SSIM), s));
 }
 
+flod_status flod_l1_ssim_forward_noalloc(flod_ctx *ctx, const float *image, const float *target, int channels,
+                                         int height, int width, float lambda, double *loss, float *dmaps,
+                                         void *stream) {
+  if (!ctx || !image || !target || !loss) return FLOD_ERR_INVALID_ARG;
+  if (channels < 1 || height < 1 || width < 1 || height > 65536 || width > 65536 || channels > 64)
+    return FLOD_ERR_INVALID_ARG;
+  if (!(lambda >= 0.0f && lambda <= 1.0f) || !aligned(loss, 8)) return FLOD_ERR_INVALID_ARG;
+  if ((size_t)ssim_blocks(channels, height, width) * sizeof(double2) > kNoAllocScratchBytes)
+    return FLOD_ERR_TOO_LARGE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
+  double2 *partials = reinterpret_cast<double2 *>(scratch_on(ctx->device));
+  if (!partials) return FLOD_ERR_DEVICE;
+  // every workgroup writes its own partial and the reduction reads exactly those: nothing
+  // left in the scratch by an earlier call is read, so nothing is cleared
+  return dev(launch_ssim_forward(image, target, channels, height, width, lambda, loss, dmaps, partials,
+                                 (hipStream_t)stream));
+}
+
 flod_status flod_l1_ssim_backward(flod_ctx *ctx, const float *image, const float *target, int channels, int height,
                                   int width, float lambda, const float *dmaps, const double *dloss, float *d_image,
                                   void *stream) {
@@ -1063,6 +1118,7 @@ const char *flod_status_str(flod_status status) {
     case FLOD_OK: return "ok";
     case FLOD_ERR_INVALID_ARG: return "invalid argument";
     case FLOD_ERR_WORKSPACE: return "workspace allocation refused";
+    case FLOD_ERR_TOO_LARGE: return "input exceeds the fixed scratch of the allocation-free entry point";
     case FLOD_ERR_OVERFLOW: return "instance count overflow (more than 2^32-1 tile instances)";
     case FLOD_ERR_DEVICE: return "HIP device error";
     case FLOD_ERR_UNSUPPORTED: return "unsupported operation";
