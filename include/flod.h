@@ -321,6 +321,11 @@ typedef struct {
                                    Gaussian dL/d(mu'x, mu'y, conic a, b, c, opacity, red,
                                    green, blue), with b the off-diagonal conic entry; NULL
                                    before a backward                                       */
+  const uint8_t *taken;         /* [n_instances] 1 where the forward blended the sorted
+                                   instance into some pixel of its tile (state the backward
+                                   reads: it walks only these entries)                     */
+  const uint32_t *tile_taken;   /* [tiles] count of such instances per tile (the backward's
+                                   tile order)                                             */
 } flod_view;
 flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out);
 

@@ -12,9 +12,8 @@
 //   Shat_{i-1} = alpha_i c_i + (1 - alpha_i) Shat_i,  Shat_last = bg,
 // which avoids the cancellation between T_i c_i and S_i / (1 - alpha_i) in FP32.
 // Then alpha -> (opacity, q) unless the 0.99 clamp is active, q -> (conic, mu').
-// Per entry the 9 gradient components are reduced across the wave (DPP within rows, then
-// two cross-row exchanges of one packed register) and lanes 0..8 issue one FP32 atomic each
-// per (tile, Gaussian).
+// Per entry the 9 gradient components are reduced across the wave through LDS and nine lanes
+// issue one FP32 atomic each per (tile, Gaussian).
 //
 // Preprocess backward: one thread per Gaussian, recomputing the forward projection (FP64)
 // and applying the chain rule in FP64 to the mean (through mu', the EWA Jacobian and the SH view
@@ -32,10 +31,12 @@ constexpr int kG2d = 9;   // mu'x, mu'y, conic a, b, c, opacity, red, green, blu
 #endif
 constexpr int kBwdPix = FLOD_BWD_PIX;   // pixels per thread: 4 = one wave64 per tile
 #ifndef FLOD_BWD_BATCH
-#define FLOD_BWD_BATCH 128
+#define FLOD_BWD_BATCH 64
 #endif
-// List entries staged in LDS per batch: 128 x 56 B = 7 KB per one-wave workgroup, so LDS
-// does not cap the waves a CU holds below what the registers allow.
+// List entries staged in LDS per batch: 64 x 72 B = 4.5 KB per one-wave workgroup, plus the
+// 2.3 KB of the per-entry reduction, so LDS does not cap the waves a CU holds below what the
+// registers allow (82 VGPRs: 5 waves per SIMD). At 1080p / 1M, 128-entry batches (9.3 KB per
+// wave) took 0.268 ms, 96 0.241 ms and 64 0.232 ms.
 constexpr int kBwdBatch = FLOD_BWD_BATCH;
 
 // One workgroup per tile with PPT pixels per thread (the forward's geometry). Per pixel
@@ -57,12 +58,16 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   __shared__ float4 s_a[kBwdBatch];
   __shared__ float4 s_b[kBwdBatch];
   __shared__ float4 s_c[kBwdBatch];
+  __shared__ float4 s_d[kBwdBatch];
   __shared__ uint32_t s_id[kBwdBatch];
   __shared__ int s_pos[kBwdBatch];
   __shared__ int s_max[WAVES];
+  __shared__ __align__(16) float s_red[kG2d * 64];   // the per-entry reduction
   const int tile = (int)order[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, lane16 = tid & 15;
-  const int comp = row_sum9_component(lane16);   // gradient component this lane adds
+  const int tid = threadIdx.x, lane = tid & 63;
+  // float4 slots each lane reads in the reduction's rounds (clamped: lanes past the last
+  // slot read a valid one and discard it)
+  const int red_hi = min(lane + 128, kG2d * 16 - 1), red_lo36 = min(lane, 35), red_lo9 = min(lane, kG2d - 1);
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
   const int px = x0 + (tid & (kTile - 1));
   const float fx = (float)px + 0.5f;
@@ -121,6 +126,8 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         s_id[idx] = g;
         s_pos[idx] = start + e;
         stage_entry(xyab, cop, blue, g, s_a[idx], s_b[idx], s_c[idx]);
+        const float4 A = xyab[g];
+        s_d[idx] = make_float4(2.0f * A.z, 2.0f * A.w, 2.0f * cop[g].x, -0.5f * cop[g].y);
       }
     }
     __syncthreads();
@@ -133,20 +140,23 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       const float loy = BL.z;
       const float dx = (fx - A.x) - BL.y;
       // first only what decides whether a pixel takes part; the transmittance recovery and
-      // the gradient run when some pixel of the wave does (predicated per pixel: a pixel
-      // that does not take part adds exact zeros and keeps its T and V)
-      float dyv[PPT], Gv[PPT], a0v[PPT], alv[PPT];
-      bool okv[PPT];
+      // the gradient run when some pixel of the wave does
+      float dyv[PPT], aev[PPT], gmv[PPT];
       bool contrib = false;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         dyv[k] = (fy[k] - A.y) - loy;
-        const float q = conic_q(A.z, A.w, B.x, dx, dyv[k]);
-        Gv[k] = gauss_weight(q);
-        a0v[k] = B.y * Gv[k];
-        alv[k] = fminf(kAlphaMax, a0v[k]);
-        okv[k] = jpos < last[k] && q <= kQCut && alv[k] >= kAlphaMin;
-        contrib = contrib || okv[k];
+        const float kq = conic_q(A.z, A.w, B.x, dx, dyv[k]);   // k q (scaled conic)
+        const float G = gauss_weight_scaled(kq);
+        const float a0 = B.y * G;
+        const float al = fminf(kAlphaMax, a0);
+        const bool ok = jpos < last[k] && kq >= kQCutScaled && al >= kAlphaMin;
+        // a pixel that does not take part gets alpha 0 and G 0: it then adds exact zeros, keeps
+        // its T (T / (1 - 0) = T) and its V; G is also 0 where the 0.99 clamp is active (alpha
+        // does not depend on opacity or q there)
+        aev[k] = ok ? al : 0.0f;
+        gmv[k] = (ok && a0 <= kAlphaMax) ? G : 0.0f;
+        contrib = contrib || ok;
       }
       if (!__any(contrib)) continue;
       {
@@ -154,46 +164,69 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       // repeats the forward's, bit for bit)
 #pragma clang fp contract(fast)
       float gr[kG2d];
-#pragma unroll
-      for (int c = 0; c < kG2d; ++c) gr[c] = 0.0f;
-      // a lane's pixels share their column, so the q-derivatives need only the sums of dq,
-      // dq dy and dq dy^2 over them: dL/d(a, b, c) = (dx^2 S0, 2 dx S1, S2) and
-      // dL/dmu' = -2 (a dx S0 + b S1, b dx S0 + c S1)
-      float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
+      gr[6] = gr[7] = gr[8] = 0.0f;
+      // with alpha = o G below the clamp, dalpha/do = G and dalpha/dq = -o G / 2, so one sum
+      // e = dL/dalpha G per pixel serves both: dL/do = sum e and dL/dq = -(o / 2) e. A lane's
+      // pixels share their column, so the q-derivatives need only E0 = sum e, E1 = sum e dy
+      // and E2 = sum e dy^2 over them: with S = -(o / 2) E, dL/d(a, b, c) = (dx^2 S0, 2 dx S1,
+      // S2) and dL/dmu' = -2 (a dx S0 + b S1, b dx S0 + c S1)
+      float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
-        const bool ok = okv[k];
-        const float alpha = alv[k], G = Gv[k], dy = dyv[k];
+        const float alpha = aev[k], dy = dyv[k];
         const float Ti = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
-        const float wT = ok ? alpha * Ti : 0.0f;
+        const float wT = alpha * Ti;
         const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * c2;   // dL/dC . c
-        const float dalpha = (ok && a0v[k] <= kAlphaMax) ? Ti * (dcc - V[k]) : 0.0f;
+        const float diff = dcc - V[k];
+        const float e = (Ti * diff) * gmv[k];                       // dL/dalpha G
         gr[6] = fmaf(wT, d0[k], gr[6]);
         gr[7] = fmaf(wT, d1[k], gr[7]);
         gr[8] = fmaf(wT, d2[k], gr[8]);
-        V[k] = ok ? fmaf(alpha, dcc - V[k], V[k]) : V[k];   // alpha dcc + (1 - alpha) V
-        T[k] = ok ? Ti : T[k];
-        gr[5] = fmaf(dalpha, G, gr[5]);
-        const float dq = -0.5f * alpha * dalpha;
-        const float dqy = dq * dy;
-        S0 += dq;
-        S1 += dqy;
-        S2 = fmaf(dqy, dy, S2);
+        V[k] = fmaf(alpha, diff, V[k]);                             // alpha dcc + (1 - alpha) V
+        T[k] = Ti;
+        const float ey = e * dy;
+        E0 += e;
+        E1 += ey;
+        E2 = fmaf(ey, dy, E2);
       }
+      const float4 D = s_d[jl];   // 2a, 2b, 2c, -o/2 (the unscaled conic)
+      const float S0 = D.w * E0, S1 = D.w * E1;
+      gr[5] = E0;
       gr[2] = dx * dx * S0;
       gr[3] = 2.0f * dx * S1;
-      gr[4] = S2;
-      // A.w = 2 b: dL/dmu' = -2 (a dx S0 + b S1, b dx S0 + c S1)
-      gr[0] = -(2.0f * A.z * dx * S0 + A.w * S1);
-      gr[1] = -(A.w * dx * S0 + 2.0f * B.x * S1);
+      gr[4] = D.w * E2;
+      // dL/dmu' = -2 (a dx S0 + b S1, b dx S0 + c S1)
+      gr[0] = -(D.x * dx * S0 + D.y * S1);
+      gr[1] = -(D.y * dx * S0 + D.z * S1);
       {
-        // the nine components summed within each DPP row (transposed: one component per
-        // lane), two cross-row exchanges complete the sums, and the nine lanes of row 0 that
-        // hold a component add it with one atomic instruction
-        float x = row_sum9(gr, lane16);
-        x += __shfl_xor(x, 16, 64);
-        x += __shfl_xor(x, 32, 64);
-        if (lane < 16 && comp >= 0 && x != 0.0f) atomicAdd(&g2d[(size_t)s_id[jl] * kG2d + comp], x);
+        // the nine components summed over the wave through LDS (no DPP: a DPP operation costs
+        // about two VALU issue slots, LDS traffic is idle here): each lane writes its nine
+        // values component-major, then three rounds of float4 reads and adds leave 16, 4 and
+        // finally 1 partial per component; lane c < 9 then holds component c and the nine
+        // lanes add their sums to the Gaussian's 36-byte row with one atomic instruction. The
+        // workgroup is one wave, so its barriers only order the LDS accesses.
+        static_assert(NT == 64, "the LDS reduction assumes one wave per tile");
+#pragma unroll
+        for (int c = 0; c < kG2d; ++c) s_red[c * 64 + lane] = gr[c];
+        __syncthreads();
+        const float4 *r4 = reinterpret_cast<const float4 *>(s_red);
+        const float4 ra = r4[lane], rb = r4[lane + 64], rc = r4[red_hi];
+        const float p0 = (ra.x + ra.y) + (ra.z + ra.w);   // component lane / 16
+        const float p1 = (rb.x + rb.y) + (rb.z + rb.w);   // component 4 + lane / 16
+        const float p2 = (rc.x + rc.y) + (rc.z + rc.w);   // component 8 (lanes 0..15)
+        __syncthreads();
+        s_red[lane] = p0;
+        s_red[64 + lane] = p1;
+        if (lane < 16) s_red[128 + lane] = p2;
+        __syncthreads();
+        const float4 rd = r4[red_lo36];                      // component lane / 4 (lanes 0..35)
+        const float p3 = (rd.x + rd.y) + (rd.z + rd.w);
+        __syncthreads();
+        if (lane < 36) s_red[lane] = p3;
+        __syncthreads();
+        const float4 re = r4[red_lo9];                       // component lane (lanes 0..8)
+        const float x = (re.x + re.y) + (re.z + re.w);
+        if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[(size_t)s_id[jl] * kG2d + lane], x);
       }
       }
     }

@@ -1,5 +1,5 @@
-// Shared by the forward and backward blend kernels: tile geometry, the longest-first tile
-// orders and wave64 reductions through DPP (no LDS crossbar traffic).
+// Shared by the forward and backward blend kernels: the staged list entry and the
+// longest-first tile orders.
 #pragma once
 
 #include "project.h"
@@ -9,20 +9,21 @@ namespace flod {
 constexpr int kBatch = 256;                                // list entries staged in LDS at once
 
 // A list entry as both blend kernels stage it in LDS, decoded once per entry instead of in
-// every lane: (mu'x, mu'y, conic a, 2 conic b), (conic c, opacity, red, green) and (blue,
-// the bf16 residuals of mu' as floats, unused).
+// every lane: (mu'x, mu'y, k a, 2 k b), (k c, opacity, red, green) and (blue, the bf16
+// residuals of mu' as floats, the scaled support cut), with k = kExpScale.
 __device__ __forceinline__ void stage_entry(const float4 *xyab, const float4 *cop, const float2 *blue, uint32_t g,
                                             float4 &a, float4 &b, float4 &c) {
   const float4 A = xyab[g];
   const float2 BL = blue[g];
   const uint32_t lo = __float_as_uint(BL.y);
-  a = make_float4(A.x, A.y, A.z, 2.0f * A.w);
   b = cop[g];
   // support cut of this entry: q beyond min(9, Q_g (1 + 1e-3) + 1e-3), Q_g = 2 ln(255 o), has
   // alpha below 1/255 by a relative 5e-4 (the binning's margin), so cutting there takes the
   // same decisions as q <= 9 and alpha >= 1/255 while whole waves skip the exp more often
   const float qcut = fminf(kQCut, fmaf(2.0f * logf(255.0f * b.y), 1.001f, 1e-3f));
-  c = make_float4(BL.x, mu_lo_x(lo), mu_lo_y(lo), qcut);
+  a = make_float4(A.x, A.y, kExpScale * A.z, kExpScale * (2.0f * A.w));
+  b.x *= kExpScale;
+  c = make_float4(BL.x, mu_lo_x(lo), mu_lo_y(lo), kExpScale * qcut);
 }
 
 // Tile orders, longest first (LPT order). The blend kernels' cost per tile varies by orders of
@@ -97,55 +98,5 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, 
   __syncthreads();
   for (int t = t0 + lane; t < t1; t += 64) order[atomicAdd(&s_cnt[w][cost_bucket(cost(t))], 1u)] = (uint32_t)t;
 }
-
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ __forceinline__ float dpp_or_zero(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, true));
-}
-
-// Sums of nine values over the 16 lanes of each DPP row, transposed: at each of four
-// exchanges a lane keeps one half of its values and adds the other half of its partner's
-// (partners lane ^ 8, lane ^ 7, lane ^ 3, lane ^ 1 inside the row, all involutions), so
-// 9 -> 5 -> 3 -> 2 -> 1 values per lane and 33 VALU operations instead of 45 for nine
-// separate row sums. Lane t of a row then holds that row's sum of component
-// row_sum9_component(t) (-1: none; t = 0, 1, 2, 4, 5, 8, 9, 10, 12 hold 0..8).
-template <int CTRL>
-__device__ __forceinline__ void keep_half(const float *v, int n, bool upper, float *out) {
-  const int h = (n + 1) / 2;
-#pragma unroll
-  for (int i = 0; i < h; ++i) {
-    const float lo = v[i], hi = (i + h < n) ? v[i + h] : 0.0f;
-    const float keep = upper ? hi : lo, send = upper ? lo : hi;
-    out[i] = keep + dpp_or_zero<CTRL>(send);
-  }
-}
-
-__device__ __forceinline__ float row_sum9(const float v[9], int lane16) {
-  float u[5], w[3], x[2], y[1];
-  keep_half<0x128>(v, 9, (lane16 & 8) != 0, u);   // row_ror:8 (lane ^ 8)
-  keep_half<0x141>(u, 5, (lane16 & 4) != 0, w);   // row_half_mirror (lane ^ 7)
-  keep_half<0x1B>(w, 3, (lane16 & 2) != 0, x);    // quad_perm [3,2,1,0] (lane ^ 3)
-  keep_half<0xB1>(x, 2, (lane16 & 1) != 0, y);    // quad_perm [1,0,3,2] (lane ^ 1)
-  return y[0];
-}
-
-__host__ __device__ constexpr int row_sum9_component(int t) {
-  // slot in x: bit 0; in w: + 2 bit 1 (< 3); in u: + 3 bit 2 (< 5); in v: + 5 bit 3 (< 9)
-  return ((t & 1) + 2 * ((t >> 1) & 1) >= 3 || (t & 1) + 2 * ((t >> 1) & 1) + 3 * ((t >> 2) & 1) >= 5 ||
-          (t & 1) + 2 * ((t >> 1) & 1) + 3 * ((t >> 2) & 1) + 5 * ((t >> 3) & 1) >= 9)
-             ? -1
-             : (t & 1) + 2 * ((t >> 1) & 1) + 3 * ((t >> 2) & 1) + 5 * ((t >> 3) & 1);
-}
-
-// every component 0..8 is held by exactly one lane of a row
-constexpr bool row_sum9_covers_all() {
-  for (int c = 0; c < 9; ++c) {
-    int n = 0;
-    for (int t = 0; t < 16; ++t) n += row_sum9_component(t) == c ? 1 : 0;
-    if (n != 1) return false;
-  }
-  return true;
-}
-static_assert(row_sum9_covers_all(), "row_sum9 must leave each component in exactly one lane");
 
 }  // namespace flod

@@ -1064,6 +1064,8 @@ flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out) {
   out->conic_c_opacity_rg = P<float>(c, B_COP);
   out->blue = P<float>(c, B_BLUE);
   out->grad2d = sv.has_grad2d ? P<float>(c, B_G2D) : nullptr;
+  out->taken = P<uint8_t>(c, B_TAKEN);
+  out->tile_taken = P<uint32_t>(c, B_TILE_TAKEN);
   return FLOD_OK;
 }
 

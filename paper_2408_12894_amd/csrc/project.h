@@ -290,12 +290,16 @@ __device__ __forceinline__ float dist2(float m0, float m1, float m2, const float
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-// exp(-q/2) as one hardware exp2 of a scaled q, shared by both blend kernels (the same
-// bits on both sides; within a few ulp of exp).
-__device__ __forceinline__ float gauss_weight(float q) { return __builtin_amdgcn_exp2f(q * -0.72134752044448170f); }
+// The blend kernels evaluate exp(-q/2) as 2^(k q), k = -log2(e) / 2, with the scale folded
+// into the staged conic (k a, 2 k b, k c), so that each (pixel, entry) pair forms k q directly
+// and takes one hardware exp2: within a few ulp of exp. The support cut q <= 9 becomes
+// k q >= 9 k. Both kernels stage entries the same way and take their decisions on the same bits.
+constexpr float kExpScale = -0.72134752044448170f;
+constexpr float kQCutScaled = kQCut * kExpScale;
+__device__ __forceinline__ float gauss_weight_scaled(float kq) { return __builtin_amdgcn_exp2f(kq); }
 
-// q = d^T conic d, shared by the forward and backward blend so both take the same
-// decisions (support cut, alpha floor) on the same bits.
+// q = d^T conic d (with the scaled conic: k q), shared by the forward and backward blend so
+// both take the same decisions (support cut, alpha floor) on the same bits.
 // b2 = 2 b (exact), as the blend kernels stage it.
 __device__ __forceinline__ float conic_q(float a, float b2, float c, float dx, float dy) {
   const float ax2 = (a * dx) * dx;   // depend on the column only: a lane's pixels of one
