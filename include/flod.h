@@ -284,7 +284,12 @@ flod_status flod_level_transition(flod_ctx *ctx, const flod_level *in, float s_m
 
 /* Backward of the last flod_render_level on ctx: given dL/dimage [3,H,W] (device), write
    dL/d(inputs) into grads. Per-pixel transmittance is recovered from the saved final_T
-   and n_contrib (no per-pixel contributor lists are stored). Returns
+   and n_contrib (no per-pixel contributor lists are stored): the forward's output buffers,
+   which must still hold its values (the walk of each pixel is clamped to its tile's list, so
+   changed n_contrib values give wrong gradients but no access outside the context's
+   buffers). Besides them the backward reads the O(K) state the forward left in ctx: the
+   sorted list, the per-instance flags of the entries blended somewhere in their tile, and the
+   per-tile counts of those entries (flod_view: taken, tile_taken). Returns
    FLOD_ERR_UNSUPPORTED after a selective render or when no render preceded it. FP32
    atomic accumulation: results are deterministic up to summation order. */
 flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_grads *grads,

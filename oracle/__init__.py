@@ -9,7 +9,9 @@ Parts (see oracle.cpp for the arithmetic):
                   bounding rectangle, stored FP32 mu' with its bf16 residual and conic)
   instances()     O1 instance list sorted by (tile, depth bits, index) and tile ranges
   depth_order()   surviving ids in (depth bits, index) order: the compositing order
-  image()         O2 FP64 brute-force image at chosen pixels, with ambiguity flags
+  image()         O2 FP64 brute-force image at chosen pixels, with ambiguity flags (bit 1: a
+                  decision that changes the image is near its threshold; bit 2: the alpha clamp's
+                  kink, which changes only the gradient)
   grad()          O3 FP64 gradient of sum(dL_dimage * image) over chosen pixels
   select()        eq. 6 band selection over a level range, FP32 squared distances
   ssim, adam      the training loss (L1 + SSIM) and the optimiser step (numpy modules)

@@ -440,6 +440,11 @@ void project64_all(int64_t nv, const int64_t* order, const double* means, const 
 // One pixel, front to back over all Gaussians in O1 order (preliminary section: alpha
 // by eq. 2, blending in depth order). Steps: support cut q <= 9, alpha = min(0.99, o e^{-q/2}),
 // skip alpha < 1/255, stop before blending when T(1 - alpha) < 1e-4.
+// Flags (bits): 1 = a decision that changes the image lies within a relative 1e-4 of its
+// threshold, where FP32 arithmetic may take it the other way: the support cut (only when the
+// alpha test would pass at q = 9, else the Gaussian is skipped either way), the alpha floor or
+// the stop; 2 = the unclamped alpha lies within a relative 1e-4 of the 0.99 clamp, whose kink
+// changes the gradient but not the image (alpha is continuous there).
 struct Contrib { int64_t k; double alpha, G, T; bool clamp; double dx, dy; };
 
 template <bool RECORD>
@@ -449,20 +454,21 @@ void composite_pixel(double px, double py, const std::vector<Gauss64>& G, const 
   double T = 1.0, C[3] = {0, 0, 0};
   last = -1; flag = 0; nblend = 0;
   const double a_min = 1.0 / 255.0, t_min = 1e-4, a_max = 0.99, q_cut = 9.0;
+  const double g_cut = std::exp(-0.5 * q_cut);
   for (size_t k = 0; k < G.size(); ++k) {
     const Gauss64& g = G[k];
     double dx = px - g.mx, dy = py - g.my;
     double q = g.ca * dx * dx + 2.0 * g.cb * dx * dy + g.cc * dy * dy;
-    if (near_rel(q, q_cut)) flag = 1;
+    if (near_rel(q, q_cut) && g.opac * g_cut >= a_min * (1.0 - 1e-4)) flag |= 1;
     if (q > q_cut) continue;
     double Gv = std::exp(-0.5 * q);
     double a0 = g.opac * Gv;
     double alpha = std::min(a_max, a0);
-    if (near_rel(a0, a_max)) flag = 1;     // the clamp's kink: gradients differ on each side
-    if (near_rel(alpha, a_min)) flag = 1;
+    if (near_rel(a0, a_max)) flag |= 2;    // the clamp's kink: gradients differ on each side
+    if (near_rel(alpha, a_min)) flag |= 1;
     if (alpha < a_min) continue;
     double Tn = T * (1.0 - alpha);
-    if (near_rel(Tn, t_min)) flag = 1;
+    if (near_rel(Tn, t_min)) flag |= 1;
     if (Tn < t_min) break;
     if (RECORD) rec->push_back(Contrib{(int64_t)k, alpha, Gv, T, a0 > a_max, dx, dy});
     for (int ch = 0; ch < 3; ++ch) C[ch] += alpha * T * g.rgb[ch];

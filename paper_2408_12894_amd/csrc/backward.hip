@@ -72,6 +72,10 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   const int px = x0 + (tid & (kTile - 1));
   const float fx = (float)px + 0.5f;
   const size_t plane = (size_t)W * H;
+  const uint2 rg = ranges[tile];
+  // a pixel's walk starts at its n_contrib, clamped to the tile's list so that no value of that
+  // input (it comes from the caller's buffer) can take the walk outside the list
+  const int list_len = (int)(rg.y - rg.x);
   float fy[PPT], d0[PPT], d1[PPT], d2[PPT];
   float T[PPT], V[PPT];
   int last[PPT];
@@ -85,7 +89,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
     if (px < W && py < H) {
       const size_t pix = (size_t)py * W + px;
       T[k] = final_T[pix];
-      last[k] = n_contrib[pix];
+      last[k] = min(max(n_contrib[pix], 0), list_len);
       d0[k] = dimg[pix];
       d1[k] = dimg[plane + pix];
       d2[k] = dimg[2 * plane + pix];
@@ -101,7 +105,6 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
 #pragma unroll
     for (int w = 0; w < WAVES; ++w) mylast = max(mylast, s_max[w]);
   }
-  const uint2 rg = ranges[tile];
   const unsigned long long lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int end = mylast; end > 0; end -= kBwdBatch) {
     const int start = max(0, end - kBwdBatch);
@@ -139,14 +142,17 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       const float c2 = BL.x;
       const float loy = BL.z;
       const float dx = (fx - A.x) - BL.y;
+      float off, t;
+      conic_column(A.z, A.w, loy, dx, off, t);
       // first only what decides whether a pixel takes part; the transmittance recovery and
       // the gradient run when some pixel of the wave does
       float dyv[PPT], aev[PPT], gmv[PPT];
       bool contrib = false;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
-        dyv[k] = (fy[k] - A.y) - loy;
-        const float kq = conic_q(A.z, A.w, B.x, dx, dyv[k]);   // k q (scaled conic)
+        const float t1 = fy[k] - A.y;
+        dyv[k] = t1 - loy;
+        const float kq = conic_kq(B.x, off, t, t1);   // k q
         const float G = gauss_weight_scaled(kq);
         const float a0 = B.y * G;
         const float al = fminf(kAlphaMax, a0);

@@ -5,8 +5,8 @@
 // once per thread and applied to PPT pixels. The tile's
 // sorted list is consumed in batches of 256 entries (48 bytes each in LDS: mu' and its
 // residual, conic, opacity, colour, decoded once per entry). Per pixel:
-//   q = d^T conic d (d = pixel centre - mu', formed as (centre - hi) - lo); skip if q > 9
-//   (evaluated as k q with the scale k of exp2 folded into the staged conic)
+//   q = d^T conic d (d = pixel centre - mu', mu' = hi + lo); skip if q > 9 (evaluated as
+//   k q in the completed-square form of conic_stage, k the scale of exp2)
 //   alpha = min(0.99, o exp(-q/2)); skip if alpha < 1/255
 //   stop (without blending) once T (1 - alpha) < 1e-4
 //   C += alpha T c; T *= 1 - alpha
@@ -108,14 +108,14 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
       const float4 B = s_b[j];
       const float4 BL = s_c[j];
       const float c2 = BL.x;
-      const float loy = BL.z;
       const float dx = (fx - A.x) - BL.y;
+      float off, t;
+      conic_column(A.z, A.w, BL.z, dx, off, t);
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         if (done[k]) continue;
-        const float dy = (fy[k] - A.y) - loy;
-        const float kq = conic_q(A.z, A.w, B.x, dx, dy);   // k q (scaled conic)
-        if (kq < BL.w) continue;                            // q beyond the support cut
+        const float kq = conic_kq(B.x, off, t, fy[k] - A.y);   // k q
+        if (kq < BL.w) continue;                               // q beyond the support cut
         const float alpha = fminf(kAlphaMax, B.y * gauss_weight_scaled(kq));
         if (alpha < kAlphaMin) continue;
         const float Tn = T[k] * (1.0f - alpha);

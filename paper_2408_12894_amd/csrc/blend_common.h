@@ -9,8 +9,9 @@ namespace flod {
 constexpr int kBatch = 256;                                // list entries staged in LDS at once
 
 // A list entry as both blend kernels stage it in LDS, decoded once per entry instead of in
-// every lane: (mu'x, mu'y, k a, 2 k b), (k c, opacity, red, green) and (blue, the bf16
-// residuals of mu' as floats, the scaled support cut), with k = kExpScale.
+// every lane: (mu'x, mu'y, r = b / c, k det / c), (k c, opacity, red, green) and (blue, the
+// bf16 residuals of mu' as floats, the scaled support cut), with k = kExpScale (the completed
+// square of q, see conic_stage).
 __device__ __forceinline__ void stage_entry(const float4 *xyab, const float4 *cop, const float2 *blue, uint32_t g,
                                             float4 &a, float4 &b, float4 &c) {
   const float4 A = xyab[g];
@@ -21,8 +22,10 @@ __device__ __forceinline__ void stage_entry(const float4 *xyab, const float4 *co
   // alpha below 1/255 by a relative 5e-4 (the binning's margin), so cutting there takes the
   // same decisions as q <= 9 and alpha >= 1/255 while whole waves skip the exp more often
   const float qcut = fminf(kQCut, fmaf(2.0f * logf(255.0f * b.y), 1.001f, 1e-3f));
-  a = make_float4(A.x, A.y, kExpScale * A.z, kExpScale * (2.0f * A.w));
-  b.x *= kExpScale;
+  float r, ek, ck;
+  conic_stage(A.z, A.w, b.x, r, ek, ck);
+  a = make_float4(A.x, A.y, r, ek);
+  b.x = ck;
   c = make_float4(BL.x, mu_lo_x(lo), mu_lo_y(lo), kExpScale * qcut);
 }
 

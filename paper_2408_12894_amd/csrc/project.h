@@ -291,20 +291,39 @@ __device__ __forceinline__ float dist2(float m0, float m1, float m2, const float
 }
 
 // The blend kernels evaluate exp(-q/2) as 2^(k q), k = -log2(e) / 2, with the scale folded
-// into the staged conic (k a, 2 k b, k c), so that each (pixel, entry) pair forms k q directly
-// and takes one hardware exp2: within a few ulp of exp. The support cut q <= 9 becomes
-// k q >= 9 k. Both kernels stage entries the same way and take their decisions on the same bits.
+// into the staged terms below, so that each (pixel, entry) pair forms k q directly and takes
+// one hardware exp2: within a few ulp of exp. The support cut q <= 9 becomes k q >= 9 k.
 constexpr float kExpScale = -0.72134752044448170f;
 constexpr float kQCutScaled = kQCut * kExpScale;
 __device__ __forceinline__ float gauss_weight_scaled(float kq) { return __builtin_amdgcn_exp2f(kq); }
 
-// q = d^T conic d (with the scaled conic: k q), shared by the forward and backward blend so
-// both take the same decisions (support cut, alpha floor) on the same bits.
-// b2 = 2 b (exact), as the blend kernels stage it.
-__device__ __forceinline__ float conic_q(float a, float b2, float c, float dx, float dy) {
-  const float ax2 = (a * dx) * dx;   // depend on the column only: a lane's pixels of one
-  const float b2x = b2 * dx;         // column share them
-  return fmaf(dy, fmaf(c, dy, b2x), ax2);
+// q = a dx^2 + 2 b dx dy + c dy^2 completed to a square in dy:
+//   q = c v^2 + (det / c) dx^2,  v = dy + (b / c) dx,  det = a c - b^2 > 0, c > 0,
+// a sum of two non-negative terms. The expanded form cancels for elongated footprints far
+// from the centre (terms of thousands summing to a q of a few units: about 1e-4 relative
+// error in FP32); here the only cancellation is in v, whose error stays near an ulp of dy.
+// An entry is staged as r = b / c, e = k det / c (det by Kahan's two-product method, from the
+// stored FP32 conic) and c_k = k c. Per column (a lane's pixels share dx): off = loy - r dx and
+// t = e dx^2; per pixel, with t1 = (pixel centre y - mu'y hi): v = t1 - off, k q = c_k v^2 + t.
+// Shared by both blend kernels so that they take the same decisions on the same bits.
+__device__ __forceinline__ void conic_stage(float a, float b, float c, float &r, float &ek, float &ck) {
+  const float p = b * b;
+  const float perr = fmaf(b, b, -p);              // b^2 = p + perr exactly
+  const float det = fmaf(a, c, -p) - perr;
+  const float ic = 1.0f / c;
+  r = b * ic;
+  ek = kExpScale * (det * ic);
+  ck = kExpScale * c;
+}
+
+__device__ __forceinline__ void conic_column(float r, float ek, float loy, float dx, float &off, float &t) {
+  off = loy - r * dx;
+  t = (ek * dx) * dx;
+}
+
+__device__ __forceinline__ float conic_kq(float ck, float off, float t, float t1) {
+  const float v = t1 - off;
+  return fmaf(ck * v, v, t);
 }
 
 }  // namespace flod

@@ -138,6 +138,9 @@ class Renderer:
         _lib.check(st, "flod_render_level")
         self.generation += 1
         self._last_level_forward = self.generation
+        # the library keeps pointers to final_T and n_contrib for the matching backward: hold
+        # the tensors until the next render, so a caller that drops them cannot free them
+        self._saved_frame = (final_T, n_contrib)
         return image, final_T, n_contrib
 
     def render_selective(self, levels, l_start: int, l_end: int, d_proj, centre, cam, bg=(0.0, 0.0, 0.0),
@@ -312,8 +315,8 @@ class Renderer:
         tiles = s["tiles_x"] * s["tiles_y"]
 
         def get(ptr, count, dtype):
-            out = np.empty(count, dtype=dtype)
-            if count:
+            out = np.empty(count if ptr else 0, dtype=dtype)
+            if out.size:
                 _lib.check(self.L.flod_copy_to_host(out.ctypes.data_as(C.c_void_p), C.c_void_p(ptr),
                                                     out.nbytes), "flod_copy_to_host")
             return out

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2408_12894_amd import synth
-from parity import check_fp64_fields, check_image, check_instances, check_keys
+from parity import FLAG_FRAC_MAX, check_fp64_fields, check_image, check_instances, check_keys, sample_pixels
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -37,14 +37,19 @@ def gpu_render(renderer, scene, cam, bg, deg=3):
     return image.cpu().numpy(), final_T.cpu().numpy(), n_contrib.cpu().numpy(), view
 
 
-def full_parity(renderer, scene, cam, bg, deg=3, pix=None, frac_max=2e-2):
+def full_parity(renderer, scene, cam, bg, deg=3, pix=None, frac_max=FLAG_FRAC_MAX, sample=None, label=""):
+    """sample = (n uniform pixels, n pixels in the 1% longest tile lists of the oracle's own
+    list, seed) replaces pix."""
     image, T, nc, view = gpu_render(renderer, scene, cam, bg, deg)
     k = oracle.keys(*scene.arrays()[:4], scene.s_min, cam)
     check_keys(view, k)
-    check_instances(view, k)
+    _, _, oranges = check_instances(view, k)
+    if sample is not None:
+        pix = sample_pixels(cam.width, cam.height, sample[0], sample[2], oranges, sample[1], (cam.width + 15) // 16)
     order = oracle.depth_order(k)
     ref = oracle.image(order, *scene.arrays()[:4], scene.s_min, scene.sh, deg, cam, bg, pix)
-    err, frac = check_image(image, T, nc, ref, view, cam, frac_max=frac_max, n_blended=view["n_blended"])
+    err, frac = check_image(image, T, nc, ref, view, cam, frac_max=frac_max, n_blended=view["n_blended"],
+                            label=label or f"{scene.n} Gaussians {cam.width}x{cam.height}")
     vis = np.nonzero(k["visible"])[0]
     if vis.size:
         p64 = oracle.project64(vis, *scene.arrays()[:4], scene.s_min, scene.sh, deg, cam)
@@ -145,13 +150,12 @@ def test_repeat_bit_identical(renderer):
 
 def test_hd_full_size_sampled(renderer):
     """1M cluster Gaussians at 1920x1080 (the benchmark configuration): the whole key path
-    and instance list bit-exact, the image on 384 sampled pixels."""
+    and instance list bit-exact, the image on 4096 uniform pixels plus 512 in the 1% of tiles
+    with the longest lists."""
     _say("1M Gaussians, 1920x1080, camera 0")
     scene, cams, bg = synth.hd_forward_case()
     cam = cams[0]
-    rng = np.random.default_rng(50)
-    pix = np.stack([rng.integers(0, 1920, 384), rng.integers(0, 1080, 384)], 1).astype(np.int32)
-    err, frac, view = full_parity(renderer, scene, cam, bg, pix=pix, frac_max=0.02)
+    err, frac, view = full_parity(renderer, scene, cam, bg, sample=(4096, 512, 50), label="1080p / 1M")
     print(f"K={view['stats']['n_instances']} visible={view['stats']['n_visible']} err={err:.2e}")
 
 
@@ -240,13 +244,12 @@ def test_count_copy_fallback(monkeypatch):
 def test_4k_full_size_sampled(renderer):
     """The same 1M cluster scene at 3840x2160, the largest serving resolution (32,400 tiles,
     15-bit tile ids, about four times the 1080p instance count): the whole key path and
-    instance list bit-exact, the image on 256 sampled pixels."""
+    instance list bit-exact, the image on 4096 uniform pixels plus 512 in the 1% of tiles with
+    the longest lists."""
     _say("1M Gaussians, 3840x2160")
     scene, _, bg = synth.hd_forward_case()
     cam = synth.orbit_cameras(2, 1, 4.0, 3840, 2160)[0]
-    rng = np.random.default_rng(51)
-    pix = np.stack([rng.integers(0, 3840, 256), rng.integers(0, 2160, 256)], 1).astype(np.int32)
-    err, frac, view = full_parity(renderer, scene, cam, bg, pix=pix, frac_max=0.02)
+    err, frac, view = full_parity(renderer, scene, cam, bg, sample=(4096, 512, 51), label="4K / 1M")
     assert view["stats"]["tiles_x"] * view["stats"]["tiles_y"] == 32400
     print(f"K={view['stats']['n_instances']} visible={view['stats']['n_visible']} err={err:.2e}")
 
@@ -254,13 +257,13 @@ def test_4k_full_size_sampled(renderer):
 def test_huge_footprints_many_windows(renderer):
     """Coarse-level Gaussians (scale floor 0.2, as level 1 of the stack) at 3840x2160: single
     footprints of thousands of tiles, so one emission workgroup fills hundreds of 4096-instance
-    windows. Key path and instance list bit-exact, image on 256 sampled pixels."""
+    windows. Key path and instance list bit-exact, image on 4096 uniform pixels plus 512 in the
+    longest lists."""
     _say("3k level-1 Gaussians, 3840x2160")
     scene = synth.cluster_scene(3000, seed=11, layout_seed=1, s_min=0.2)
     cam = synth.orbit_cameras(2, 1, 4.0, 3840, 2160)[0]
-    rng = np.random.default_rng(52)
-    pix = np.stack([rng.integers(0, 3840, 256), rng.integers(0, 2160, 256)], 1).astype(np.int32)
-    err, frac, view = full_parity(renderer, scene, cam, np.zeros(3, np.float32), pix=pix, frac_max=0.05)
+    err, frac, view = full_parity(renderer, scene, cam, np.zeros(3, np.float32), sample=(4096, 512, 52),
+                                  label="4K / 3k level-1")
     tt = view["tiles_touched"].astype(np.int64)
     n_wg = -(-int((tt > 0).sum()) // 256)  # emission workgroups (256 Gaussians each)
     assert tt.max() > 4096                 # one footprint alone spans more than one window
@@ -271,14 +274,12 @@ def test_huge_footprints_many_windows(renderer):
 def test_max_frame_16384(renderer):
     """The largest frame the API accepts, 16384 x 16384: 1,048,576 tiles, so tile ids take 20
     bits (a third radix pass) and the tile-order kernel spans a million tiles. Key path and
-    instance list bit-exact, the image on 256 sampled pixels."""
+    instance list bit-exact, the image on 4096 uniform pixels plus 512 in the longest lists."""
     _say("2k Gaussians, 16384x16384")
     scene = synth.uniform_scene(2000, seed=53, s_mu=-4.0, s_sigma=0.5)
     cam = synth.look_at_camera((0.4, -0.3, -3.8), (0, 0, 0), 16384, 16384)
-    rng = np.random.default_rng(54)
-    pix = np.stack([rng.integers(0, 16384, 256), rng.integers(0, 16384, 256)], 1).astype(np.int32)
-    err, frac, view = full_parity(renderer, scene, cam, np.array([0.2, 0.1, 0.4], np.float32), pix=pix,
-                                  frac_max=0.05)
+    err, frac, view = full_parity(renderer, scene, cam, np.array([0.2, 0.1, 0.4], np.float32),
+                                  sample=(4096, 512, 54), label="16384^2 / 2k")
     assert view["stats"]["tiles_x"] * view["stats"]["tiles_y"] == 1 << 20
     assert int(view["tile_ids"].max()) >= 1 << 16       # ids beyond two radix digits
     print(f"K={view['stats']['n_instances']} err={err:.2e}")

@@ -164,13 +164,28 @@ def test_level_transition(r, level):
     s_l = np.exp(sc.log_scales.astype(np.float64)).astype(np.float32).astype(np.float64) + float(np.float32(sl))
     s_n = np.exp(got.astype(np.float64)).astype(np.float32).astype(np.float64) + float(np.float32(sn))
     np.testing.assert_allclose(s_n, s_l, rtol=1e-6)
-    # and the next level renders as the trained one did, except where a support-cut or
-    # alpha-floor decision sits on its threshold (one Gaussian's contribution)
+    # and the next level renders as the trained one did: within 1e-4 on every pixel where
+    # neither level has a decision the oracle flags (eq. 5 keeps each scale up to the FP32
+    # rounding of the stored parameter, which moves alpha by about 1e-6 relative and can flip
+    # only decisions sitting on their thresholds), and within one flipped decision elsewhere
     cam = synth.look_at_camera((0.0, 1.0, 9.0), (0, 0, 0), 320, 240)
     a = r.render_level(lv, cam)[0].cpu().numpy()
     b = r.render_level(nxt, cam)[0].cpu().numpy()
     diff = np.abs(a - b).max(axis=0)
-    assert (diff > 1e-4).mean() <= 1e-2 and diff.mean() <= 1e-5
+    nsc = sc.copy()
+    nsc.log_scales = ref
+    nsc.s_min = np.float32(sn)
+    pix = np.unique(np.stack([np.random.default_rng(level).integers(0, 320, 4096),
+                              np.random.default_rng(level + 10).integers(0, 240, 4096)], 1).astype(np.int32), axis=0)
+    fa = oracle.render(sc.arrays(), sc.s_min, cam, np.zeros(3, np.float32), pix=pix)["flag"]
+    fb = oracle.render(nsc.arrays(), nsc.s_min, cam, np.zeros(3, np.float32), pix=pix)["flag"]
+    flagged = ((fa | fb) & 1) != 0
+    d = diff[pix[:, 1], pix[:, 0]]
+    print(f"[transition] level {level}: {pix.shape[0]} pixels, flagged {flagged.mean():.3%}, over 1e-4: "
+          f"{int((d > 1e-4).sum())} ({int((d[flagged] > 1e-4).sum())} flagged); whole frame over 1e-4: "
+          f"{(diff > 1e-4).mean():.3%}, max {diff.max():.2e}", flush=True)
+    assert d[~flagged].max() <= 1e-4
+    assert (diff > 1e-4).mean() <= 1e-3 and diff.max() <= 0.05
 
 
 def test_level_transition_rejects_rising_floor(r):

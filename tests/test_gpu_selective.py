@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2408_12894_amd import synth
-from parity import check_image, check_instances, check_keys
+from parity import FLAG_FRAC_MAX, check_image, check_instances, check_keys, sample_pixels
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -38,7 +38,9 @@ def concat(levels):
     return arrs, smin
 
 
-def selective_parity(renderer, levels, l_start, l_end, d_proj, centre, cam, bg, pix=None, frac_max=2e-2):
+def selective_parity(renderer, levels, l_start, l_end, d_proj, centre, cam, bg, pix=None, frac_max=FLAG_FRAC_MAX,
+                     sample=None, label=""):
+    """sample = (n uniform pixels, n in the 1% longest tile lists of the oracle's list, seed)."""
     from paper_2408_12894_amd import render
     dev = [render.GaussianLevel.from_scene(lv) for lv in levels]
     image, T, nc, counts = renderer.render_selective(dev, l_start, l_end, d_proj, centre, cam, bg, with_counts=True)
@@ -58,10 +60,13 @@ def selective_parity(renderer, levels, l_start, l_end, d_proj, centre, cam, bg, 
     arrs, smin = concat(in_range)
     k = oracle.keys(*arrs[:4], smin, cam, keep=keep)
     check_keys(view, k)
-    check_instances(view, k)
+    _, _, oranges = check_instances(view, k)
+    if sample is not None:
+        pix = sample_pixels(cam.width, cam.height, sample[0], sample[2], oranges, sample[1], (cam.width + 15) // 16)
     order = oracle.depth_order(k)
     ref = oracle.image(order, *arrs[:4], smin, arrs[4], 3, cam, bg, pix)
-    check_image(image.cpu().numpy(), T.cpu().numpy(), nc.cpu().numpy(), ref, view, cam, frac_max=frac_max)
+    check_image(image.cpu().numpy(), T.cpu().numpy(), nc.cpu().numpy(), ref, view, cam, frac_max=frac_max,
+                label=label or f"selective [{l_start},{l_end}] {cam.width}x{cam.height}")
     return view, got_counts
 
 
@@ -140,16 +145,15 @@ def test_invalid_ranges_rejected(renderer):
 def test_full_stack_1080p(renderer):
     """The 5-level stack (40k..2.5M, 4.39M resident) at 1920x1080: selective [1,5] with the
     2/4/8/16 bands around the eye, and the top level alone; key path and instance list
-    bit-exact over every candidate, image on 256 sampled pixels."""
+    bit-exact over every candidate, image on 4096 uniform pixels plus 512 in the 1% of tiles
+    with the longest lists."""
     _say("5-level stack, 1920x1080, selective [1,5] and level 5 alone")
     levels = synth.level_stack()
     cam = synth.orbit_cameras(2, 1, 4.0, 1920, 1080)[0]
-    rng = np.random.default_rng(71)
-    pix = np.stack([rng.integers(0, 1920, 256), rng.integers(0, 1080, 256)], 1).astype(np.int32)
     bg = np.zeros(3, np.float32)
-    view, counts = selective_parity(renderer, levels, 1, 5, synth.LEVEL_BANDS, cam.campos, cam, bg, pix=pix,
-                                    frac_max=0.05)
+    view, counts = selective_parity(renderer, levels, 1, 5, synth.LEVEL_BANDS, cam.campos, cam, bg,
+                                    sample=(4096, 512, 71), label="stack selective [1,5] 1080p")
     print(f"selected per level {counts.tolist()}, K={view['stats']['n_instances']}")
-    view, counts = selective_parity(renderer, levels, 5, 5, synth.LEVEL_BANDS, cam.campos, cam, bg, pix=pix,
-                                    frac_max=0.05)
+    view, counts = selective_parity(renderer, levels, 5, 5, synth.LEVEL_BANDS, cam.campos, cam, bg,
+                                    sample=(4096, 512, 72), label="stack level 5 1080p")
     print(f"level 5 alone: K={view['stats']['n_instances']}")

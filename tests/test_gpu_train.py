@@ -173,4 +173,6 @@ def test_level_by_level_training(r):
         a = r.render_level(levels[l], cams[0])[0].cpu().numpy()
         b = r.render_level(nxt, cams[0])[0].cpu().numpy()
         diff = np.abs(a - b).max(axis=0)
-        assert (diff > 1e-4).mean() <= 1e-2 and diff.mean() <= 1e-5
+        print(f"[hand-over] level {l + 1} -> {l + 2}: pixels over 1e-4 {(diff > 1e-4).mean():.3%}, "
+              f"max {diff.max():.2e}, mean {diff.mean():.2e}", flush=True)
+        assert (diff > 1e-4).mean() <= 1e-3 and diff.max() <= 0.05
