@@ -31,6 +31,10 @@
  * environment when a context is created selects the copy). It then fills the
  * statistics and, when K exceeded the capacity, grows the buffers and enqueues the frame's
  * tail again. A context's first render, with no buffers yet, waits for K before the tail.
+ * A context may be used on different streams from one call to the next: a call on a stream
+ * other than the one the context last used first makes its stream wait (an event, no host
+ * wait) for the work already enqueued on the previous one, so no buffer is reused, grown or
+ * released under an earlier call's kernels.
  *
  * Errors: no function throws or aborts. Arguments are validated before any launch; on
  * FLOD_ERR_INVALID_ARG the outputs are untouched. flod_status_str() describes a code.

@@ -83,7 +83,9 @@ struct flod_ctx {
   flod_free_fn release = nullptr;
   void *user = nullptr;
   Buf buf[B_COUNT];
-  hipStream_t last_stream = nullptr;
+  hipStream_t last_stream = nullptr;   // stream of the last call that used the workspace
+  bool has_stream = false;
+  hipEvent_t ev_switch = nullptr;       // orders a call on a new stream after the last one
   size_t required = 0;
   unsigned long long *host_counters = nullptr;   // pinned: [visible u32 | K u32], [K u64]
   // coherent pinned memory the offsets scan writes the counts into, as four 64-bit words
@@ -188,6 +190,25 @@ struct StageTimer {
     c->ev_pending[k] = true;
   }
 };
+
+// Every call that uses the context's workspace runs on its caller's stream. When that stream
+// differs from the one the context last used, the new stream first waits for the work already
+// enqueued on the old one (an event, no host wait), so buffers are never reused, grown or
+// released while an earlier call may still read or write them.
+hipError_t use_stream(flod_ctx *c, hipStream_t s) {
+  if (c->has_stream && s != c->last_stream) {
+    if (!c->ev_switch && hipEventCreateWithFlags(&c->ev_switch, hipEventDisableTiming) != hipSuccess) {
+      c->ev_switch = nullptr;
+      return hipErrorOutOfMemory;
+    }
+    hipError_t e = hipEventRecord(c->ev_switch, c->last_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_switch, 0);
+    if (e != hipSuccess) return e;
+  }
+  c->last_stream = s;
+  c->has_stream = true;
+  return hipSuccess;
+}
 
 // Mark the work enqueued on s so far; wait_marked() returns once it has finished.
 hipError_t mark_stream(flod_ctx *c, hipStream_t s) {
@@ -294,7 +315,7 @@ size_t hist_bytes(int64_t n_max) { return radix_hist_bytes(n_max); }
 flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const float bg[3],
                           flod_frame *out, hipStream_t s) {
   c->required = 0;
-  c->last_stream = s;
+  if (use_stream(c, s) != hipSuccess) return FLOD_ERR_DEVICE;
   c->saved.valid = false;
   c->saved.has_grad2d = false;
   timing_flush(c);
@@ -551,6 +572,7 @@ void flod_ctx_destroy(flod_ctx *ctx) {
       (void)hipEventDestroy(ctx->ev[k][1]);
     }
   if (ctx->ev_sync) (void)hipEventDestroy(ctx->ev_sync);
+  if (ctx->ev_switch) (void)hipEventDestroy(ctx->ev_switch);
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
   if (ctx->host_counts) (void)hipHostFree(ctx->host_counts);
   delete ctx;
@@ -564,6 +586,7 @@ flod_status flod_ctx_trim(flod_ctx *ctx, void *stream) {
   if (!ctx) return FLOD_ERR_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
   hipStream_t s = (hipStream_t)stream;
+  if (use_stream(ctx, s) != hipSuccess) return FLOD_ERR_DEVICE;
   for (int i = 0; i < B_COUNT; ++i) release_buf(ctx, ctx->buf[i], s);
   ctx->saved.valid = false;
   return FLOD_OK;
@@ -726,7 +749,7 @@ flod_status compact_pass(flod_ctx *ctx, int64_t n, hipStream_t s, CountFn count,
 
 flod_status begin_level_op(flod_ctx *ctx, hipStream_t s) {
   if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
-  ctx->last_stream = s;
+  if (use_stream(ctx, s) != hipSuccess) return FLOD_ERR_DEVICE;
   ctx->required = 0;
   ctx->saved.valid = false;
   return FLOD_OK;
@@ -863,7 +886,7 @@ flod_status flod_l1_ssim_forward(flod_ctx *ctx, const float *image, const float 
   if (!(lambda >= 0.0f && lambda <= 1.0f) || !aligned(loss, 8)) return FLOD_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
   if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
-  ctx->last_stream = s;
+  if (use_stream(ctx, s) != hipSuccess) return FLOD_ERR_DEVICE;
   ctx->required = 0;
   size_t extra = 0;
   if (ensure(ctx, B_SSIM, 16 * (size_t)ssim_blocks(channels, height, width), s, &extra) != FLOD_OK) {
@@ -901,7 +924,7 @@ flod_status flod_l1_ssim_backward(flod_ctx *ctx, const float *image, const float
   if (!(lambda >= 0.0f && lambda <= 1.0f) || (dloss && !aligned(dloss, 8))) return FLOD_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
   if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
-  ctx->last_stream = s;
+  if (use_stream(ctx, s) != hipSuccess) return FLOD_ERR_DEVICE;
   ctx->required = 0;
   return dev(launch_ssim_backward(image, target, channels, height, width, lambda, dmaps, dloss, d_image, s));
 }
@@ -911,7 +934,7 @@ flod_status flod_l1_loss_forward(flod_ctx *ctx, const float *image, const float 
   if (!ctx || !image || !target || !loss || count < 1 || !aligned(loss, 8)) return FLOD_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
   if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
-  ctx->last_stream = s;
+  if (use_stream(ctx, s) != hipSuccess) return FLOD_ERR_DEVICE;
   ctx->required = 0;
   size_t extra = 0;
   if (ensure(ctx, B_SSIM, 16 * (size_t)l1_blocks(), s, &extra) != FLOD_OK) {
@@ -927,7 +950,7 @@ flod_status flod_l1_loss_backward(flod_ctx *ctx, const float *image, const float
     return FLOD_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
   if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
-  ctx->last_stream = s;
+  if (use_stream(ctx, s) != hipSuccess) return FLOD_ERR_DEVICE;
   ctx->required = 0;
   return dev(launch_l1_backward(image, target, count, dloss, d_image, s));
 }
@@ -1005,7 +1028,7 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
     return FLOD_ERR_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return FLOD_ERR_DEVICE;
   hipStream_t s = (hipStream_t)stream;
-  ctx->last_stream = s;
+  if (use_stream(ctx, s) != hipSuccess) return FLOD_ERR_DEVICE;
   ctx->required = 0;
   timing_flush(ctx);
   StageTimer tm(ctx, s);

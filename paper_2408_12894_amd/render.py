@@ -117,20 +117,28 @@ class Renderer:
             pass
 
     # ------------------------------------------------------------------ forward
-    def _frame(self, cam, device, n_blended=None):
+    def _frame(self, cam, device, n_blended=None, out=None):
         H, W = int(cam.height), int(cam.width)
-        image = torch.empty((3, H, W), dtype=torch.float32, device=device)
-        final_T = torch.empty((H, W), dtype=torch.float32, device=device)
-        n_contrib = torch.empty((H, W), dtype=torch.int32, device=device)
+        if out is not None:
+            image, final_T, n_contrib = out
+            if (tuple(image.shape) != (3, H, W) or image.dtype != torch.float32 or tuple(final_T.shape) != (H, W)
+                    or final_T.dtype != torch.float32 or tuple(n_contrib.shape) != (H, W)
+                    or n_contrib.dtype != torch.int32 or not all(t.is_contiguous() for t in out)):
+                raise ValueError("out must be contiguous (image f32 [3,H,W], final_T f32 [H,W], n_contrib i32 [H,W])")
+        else:
+            image = torch.empty((3, H, W), dtype=torch.float32, device=device)
+            final_T = torch.empty((H, W), dtype=torch.float32, device=device)
+            n_contrib = torch.empty((H, W), dtype=torch.int32, device=device)
         fr = _lib.Frame(image.data_ptr(), final_T.data_ptr(), n_contrib.data_ptr(),
                         n_blended.data_ptr() if n_blended is not None else None)
         return image, final_T, n_contrib, fr
 
     def render_level(self, level: GaussianLevel, cam, bg=(0.0, 0.0, 0.0), sh_degree: int = 3, stream=None,
-                     n_blended: torch.Tensor | None = None):
-        """Single-level render. Returns (image [3,H,W], final_T [H,W], n_contrib [H,W]); the
-        optional int32 [H,W] tensor n_blended receives the per-pixel blended count."""
-        image, final_T, n_contrib, fr = self._frame(cam, level.means.device, n_blended)
+                     n_blended: torch.Tensor | None = None, out=None):
+        """Single-level render. Returns (image [3,H,W], final_T [H,W], n_contrib [H,W]), written
+        into `out` when given; the optional int32 [H,W] tensor n_blended receives the per-pixel
+        blended count."""
+        image, final_T, n_contrib, fr = self._frame(cam, level.means.device, n_blended, out)
         lv = level.c_struct()
         cs = camera_struct(cam)
         st = self.L.flod_render_level(self.ctx, C.byref(lv), int(sh_degree), C.byref(cs), _floats(bg, 3),
@@ -144,7 +152,7 @@ class Renderer:
         return image, final_T, n_contrib
 
     def render_selective(self, levels, l_start: int, l_end: int, d_proj, centre, cam, bg=(0.0, 0.0, 0.0),
-                         sh_degree: int = 3, stream=None, with_counts: bool = False):
+                         sh_degree: int = 3, stream=None, with_counts: bool = False, out=None):
         """Selective render over levels l_start..l_end (1-based) with distance bands d_proj
         (d_proj[l-1] = d_proj^(l)) around `centre`. Returns (image, final_T, n_contrib) and,
         with with_counts, the per-level selected counts (int64 tensor on the device)."""
@@ -153,7 +161,7 @@ class Renderer:
         for i, lv in enumerate(levels):
             arr[i] = lv.c_struct()
         dev = levels[l_start - 1].means.device
-        image, final_T, n_contrib, fr = self._frame(cam, dev)
+        image, final_T, n_contrib, fr = self._frame(cam, dev, out=out)
         counts = torch.empty(n_levels, dtype=torch.int64, device=dev) if with_counts else None
         cs = camera_struct(cam)
         st = self.L.flod_render_selective(self.ctx, arr, n_levels, int(l_start), int(l_end),

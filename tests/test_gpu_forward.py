@@ -283,3 +283,25 @@ def test_max_frame_16384(renderer):
     assert view["stats"]["tiles_x"] * view["stats"]["tiles_y"] == 1 << 20
     assert int(view["tile_ids"].max()) >= 1 << 16       # ids beyond two radix digits
     print(f"K={view['stats']['n_instances']} err={err:.2e}")
+
+
+def test_context_used_on_two_streams():
+    """A context's render on a second stream waits for the first render's frame, still queued on
+    the first stream when the call returns, before reusing the buffers: both frames equal the
+    same frames rendered on one stream."""
+    from paper_2408_12894_amd import render
+    _say("one context, two streams back to back")
+    scene = synth.cluster_scene(200_000, seed=41, layout_seed=1)
+    cams = synth.orbit_cameras(2, 2, 4.0, 1280, 720)
+    lv = render.GaussianLevel.from_scene(scene)
+    ref_r = render.Renderer(0)
+    ref = [ref_r.render_level(lv, c)[0].cpu().numpy() for c in cams]
+    r = render.Renderer(0)
+    r.render_level(lv, cams[0])          # buffers sized for this frame
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    a = r.render_level(lv, cams[0], stream=sa)[0]
+    b = r.render_level(lv, cams[1], stream=sb)[0]
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a.cpu().numpy(), ref[0])
+    np.testing.assert_array_equal(b.cpu().numpy(), ref[1])

@@ -43,7 +43,7 @@ class FakeExecutor:
             self.ledger.give(self.held[slot])
             self.held[slot] = 0
 
-    def run(self, slot, req):
+    def run(self, slot, req, promise=None):
         if self.held[slot] < req.ws:
             self.trim(slot)
             if not self.ledger.try_take(req.ws):
@@ -139,3 +139,96 @@ def test_trace_generator():
     assert all((r.l_start, r.l_end) in synth.SELECTIVE_RANGES for r in multi)
     for r in tr[:20]:
         assert abs(np.linalg.norm(r.camera.campos) - 4.0) < 1e-5
+
+
+class FakePending(serving.Pending):
+    def __init__(self, t_start, work_s):
+        self.t0, self.t1 = t_start, t_start + work_s
+
+    def ready(self):
+        return time.perf_counter() >= self.t1
+
+    def finish(self, rec, keep):
+        rec.dev_start_ms, rec.dev_end_ms = 1e3 * self.t0, 1e3 * self.t1
+        return {"done_at": self.t1} if keep else None
+
+
+class FakeAsyncExecutor(FakeExecutor):
+    """Returns at once with a pending result that is ready work_s later (as the GPU executor
+    returns once a request's work is enqueued): the scheduler's reaper completes it."""
+
+    def run(self, slot, req, promise=None):
+        with self.lock:
+            self.running += 1
+            self.max_running = max(self.max_running, self.running)
+        p = FakePending(time.perf_counter(), req.work_s)
+        orig = p.finish
+
+        def finish(rec, keep, _orig=orig):
+            with self.lock:
+                self.running -= 1
+            return _orig(rec, keep)
+        p.finish = finish
+        return p
+
+
+def test_pending_results_are_completed_by_the_reaper():
+    reqs = [FakeReq(i, 0.001 * i, 0.03, 500) for i in range(12)]
+    ledger = serving.BudgetLedger(10_000, 1_000)
+    ex = FakeAsyncExecutor(4, ledger)
+    recs = serving.Scheduler(ex, 4, ledger, keep_results=True).serve(reqs)
+    assert all(r.status == "ok" for r in recs)
+    assert ex.max_running == 4 and ex.running == 0
+    for r in recs:
+        assert r.done - r.admitted >= 0.03 - 1e-3 and r.result["done_at"] > 0
+    st = serving.latency_stats(recs)
+    assert st["completed"] == 12
+    assert st["device_overlapping"] == 12 and st["device_max_in_flight"] == 4
+    assert st["device_concurrency"] > 2.0
+    assert ledger.held == 1_000 + sum(ex.held)      # every admission reserve was given back
+
+
+def test_device_overlap_statistics():
+    mk = lambda a, b: serving.Completed(0, 0.0, dev_start_ms=a, dev_end_ms=b)
+    st = serving.device_overlap([mk(0, 10), mk(5, 15), mk(20, 30), mk(22, 24), mk(40, 41)])
+    assert st["device_overlapping"] == 4 and st["device_max_in_flight"] == 2
+    assert st["device_busy_ms"] == 26 and st["device_sum_ms"] == 33
+    assert st["device_concurrency"] == 33 / 26
+    assert serving.device_overlap([]) == {}
+
+
+class FakeCachingExecutor(FakeExecutor):
+    """Like a caching allocator: a finished request's frame stays charged (cached) until
+    release_cached() returns it, so an idle server may hold memory that only a release frees."""
+
+    def __init__(self, n_slots, ledger):
+        super().__init__(n_slots, ledger)
+        self.cached = 0
+        self.releases = 0
+
+    def run(self, slot, req, promise=None):
+        out = super().run(slot, req, promise)
+        with self.lock:
+            if self.ledger.try_take(req.frame):   # the frame, cached after use
+                self.cached += req.frame
+        return out
+
+    def release_cached(self):
+        with self.lock:
+            self.ledger.give(self.cached)
+            self.cached = 0
+            self.releases += 1
+
+
+@pytest.mark.timeout(60)
+def test_head_waits_for_cached_memory_to_be_released():
+    """Memory held only in a cache must not stall the queue: when the head does not fit, the
+    scheduler trims idle slots and releases the cache."""
+    # one slot, workspace growing with every request: once a finished request's frame sits in
+    # the cache, the next request's larger workspace fits only after the cache is released
+    reqs = [FakeReq(i, 0.0005 * i, 0.005, 1500 + 100 * i, frame=600) for i in range(6)]
+    ledger = serving.BudgetLedger(3_700, 1_000)
+    ex = FakeCachingExecutor(1, ledger)
+    recs = serving.Scheduler(ex, 1, ledger).serve(reqs)
+    assert all(r.status == "ok" for r in recs)
+    assert ex.releases > 0 and ledger.peak <= ledger.budget
