@@ -34,12 +34,51 @@ sys.path.insert(0, ROOT)
 import hashlib
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X fp32 vector, TFLOP/s
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X fp32 vector, TFLOP/s (FMA = 2 FLOP, packed FP32 issue)
+# FP32 lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation per lane
+# per clock (an FMA counts once); the published 157.3 TFLOP/s is this x 2 (FMA) x 2 (packed
+# FP32), and this build does not issue packed FP32
+LANE_OP_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Algorithmic FP32 operations per (pixel, list entry) pair of the blend kernels (an FMA
-# counts 2): every evaluated pair recomputes d, q = d^T conic d, exp, o*G and the clamp (15);
-# a blended pair adds 9 in the forward (T update, weight, 3 colour FMAs) and 46 in the
-# backward (transmittance recovery, dL/dalpha, 9 gradient components, the suffix update).
+# Algorithmic work of the hot path's steps (the survey's measurement table), per launch, from the
+# frame's own counts: N candidates, K instances, P pixels, Pi pairs walked (sum of n_contrib),
+# Pi_bl pairs blended. The blend steps are VALU-bound: 20 lane operations per walked pair
+# (offset, q, exp, alpha, tests: about 16 VALU and one exp), and in the backward about 51 per pair,
+# read here as the walk's 20 for every walked pair plus 31 (transmittance recovery, dL/dalpha, the
+# nine components, the suffix update) for every blended one.
+OPS_WALK = 20
+OPS_BWD_BLENDED = 31
+SURVEY_STEPS = {           # step -> the library's timed stages that implement it
+    "S2 preprocess": ["preprocess"],
+    "S3 scan": ["compact", "offsets"],
+    "S4 duplicate": ["emit"],
+    "S5 sort": ["depth_sort", "tile_sort"],
+    "S6 ranges": ["ranges"],
+    "S7 blend": ["blend"],
+    "S8 blend backward": ["blend_bwd"],
+    "S9 preprocess backward": ["preprocess_bwd"],
+}
+
+
+def survey_work(step, N, K, P, tiles, pi_walk, pi_blend):
+    """(bytes, lane operations) the step must move / execute at minimum."""
+    return {
+        "S2 preprocess": ((236 + 48) * N, 0.0),
+        "S3 scan": (8 * N, 0.0),
+        "S4 duplicate": (16 * N + 12 * K, 0.0),
+        "S5 sort": (24 * K, 0.0),
+        "S6 ranges": (8 * K + 8 * tiles, 0.0),
+        "S7 blend": (40 * K + 20 * P, OPS_WALK * pi_walk),
+        "S8 blend backward": (40 * K + 20 * P + 12 * P + 36 * K, OPS_WALK * pi_walk + OPS_BWD_BLENDED * pi_blend),
+        "S9 preprocess backward": ((236 + 52 + 236) * N, 0.0),
+    }[step]
+
+
+# FP32 operations per (pixel, list entry) pair of the blend kernels counted as FLOPs (an FMA
+# counts 2), for the published FP32 peak: every evaluated pair recomputes d, q, exp, o*G and
+# the clamp (15); a blended pair adds 9 in the forward (T update, weight, 3 colour FMAs) and
+# 46 in the backward (transmittance recovery, dL/dalpha, 9 gradient components, the suffix
+# update).
 FLOPS_EVAL = 15
 FLOPS_BLEND_FWD = 9
 FLOPS_BLEND_BWD = 46
@@ -51,7 +90,7 @@ FLOPS_BLEND_BWD = 46
 # step_1080p_1M_hbm_counters.md). A figure holds only for the kernel sources it was taken
 # with: the sha256 over the listed files must match, else the traffic is reported as null.
 PROFILED_TRAFFIC = {
-    "blend_bwd": {"bytes": 319197769, "sha256": "17d6024965aa7389acd53ff94b484008d182eaa5b04c943c55a4ab56e915284f",
+    "blend_bwd": {"bytes": 313268431, "sha256": "06b8a4071679f3bfbcc04c26b1fa6358547993575e2ebb554ab6868cf4a4a660",
                   "sources": ['paper_2408_12894_amd/csrc/backward.hip', 'paper_2408_12894_amd/csrc/blend_common.h', 'paper_2408_12894_amd/csrc/project.h', 'paper_2408_12894_amd/csrc/flod_internal.h']},
 }
 
@@ -79,6 +118,8 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-only", action="store_true",
                     help="only the serving runs over the 5-level stack (for kernel traces of serving)")
+    ap.add_argument("--trace-overlap", metavar="CSV", default=None,
+                    help="only summarise a rocprofv3 kernel-trace CSV: how much kernel time overlaps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device-to-device 10 times (reference for HBM byte counters)")
     return ap.parse_args()
@@ -113,6 +154,36 @@ def algorithmic_bytes(stage, N, n_vis, K, P, tiles):
         "blend_bwd": 44 * K + 20 * P + 12 * P + 36 * K,
         "preprocess_bwd": (236 + 4 + 36 + 236) * N,
     }[stage]
+
+
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Device-to-device copy rate in GB/s (bytes read plus bytes written per second) over a
+    `mib` MiB buffer, HIP events around `reps` copies."""
+    n = mib << 18
+    src = torch.ones(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2 * n * 4 / t / 1e9
+
+
+def cpu_model() -> str:
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return "unknown"
 
 
 def serving_bench(stack, count):
@@ -153,8 +224,46 @@ def serving_bench(stack, count):
     return out
 
 
+def trace_overlap(path, include=None):
+    """Kernel concurrency in a rocprofv3 kernel trace (CSV): the union of the kernels'
+    [start, end) intervals against their sum, the share of that union with two or more kernels
+    running, and the most kernels running at once, per queue and overall."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    iv = []
+    queues = {}
+    for r in rows:
+        name = r.get("Kernel_Name", "")
+        if include and include not in name:
+            continue
+        a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        q = r.get("Queue_Id") or r.get("Stream_Id") or "?"
+        iv.append((a, b))
+        queues[q] = queues.get(q, 0) + 1
+    ev = sorted([(a, 1) for a, _ in iv] + [(b, -1) for _, b in iv], key=lambda e: (e[0], e[1]))
+    cur = best = 0
+    union = multi = 0
+    last = None
+    for t, d in ev:
+        if last is not None:
+            if cur > 0:
+                union += t - last
+            if cur > 1:
+                multi += t - last
+        cur += d
+        best = max(best, cur)
+        last = t
+    total = sum(b - a for a, b in iv)
+    return {"kernels": len(iv), "queues": len(queues), "kernel_time_ms": total / 1e6,
+            "busy_ms": union / 1e6, "concurrency": total / union if union else float("nan"),
+            "share_of_busy_with_2plus": multi / union if union else float("nan"), "max_concurrent": best}
+
+
 def main():
     args = parse()
+    if args.trace_overlap:
+        print(json.dumps(trace_overlap(args.trace_overlap)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}); this build runs on a single "
               "MI355X and its multi-GPU sharding is a design only", file=sys.stderr)
@@ -251,40 +360,59 @@ def main():
     for k, v in per_stage.items():
         v["GBs_algorithmic"] = algorithmic_bytes(k, N, n_vis, K, P, tiles) / (v["ms"] * 1e-3) / 1e9
     dom_ms = dom_live[0] / dom_live[1]        # live, inside the timed steps
+    # the measured device-to-device copy rate: the HBM rate a stream of reads and writes reaches
+    copy_gbs = copy_bandwidth(torch)
+    step_of = {st_: name for name, sts in SURVEY_STEPS.items() for st_ in sts}
     if dom in ("blend", "blend_bwd"):
+        b_, ops = survey_work(step_of[dom], N, K, P, tiles, Pi_walk, Pi_blend)
+        ach = ops / (dom_ms * 1e-3) / 1e12
         per_pair = FLOPS_BLEND_BWD if dom == "blend_bwd" else FLOPS_BLEND_FWD
         flops = FLOPS_EVAL * Pi_walk + per_pair * Pi_blend
-        ach = flops / (dom_ms * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": profiled_traffic(dom), "algorithmic_flops_per_launch": flops,
-                "pairs_walked": Pi_walk, "pairs_blended": Pi_blend}
+        roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": LANE_OP_PEAK_TOPS, "unit": "Top/s",
+                "frac": ach / LANE_OP_PEAK_TOPS, "traffic": profiled_traffic(dom),
+                "algorithmic_ops_per_launch": ops, "pairs_walked": Pi_walk, "pairs_blended": Pi_blend,
+                "fp32_flops_per_launch": flops,
+                "frac_of_published_fp32": flops / (dom_ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS}
     else:
-        byts = algorithmic_bytes(dom, N, n_vis, K, P, tiles)
+        byts, _ = survey_work(step_of[dom], N, K, P, tiles, Pi_walk, Pi_blend)
         ach = byts / (dom_ms * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": profiled_traffic(dom), "algorithmic_bytes_per_launch": byts}
+                "frac": ach / HBM_PEAK_GBS, "traffic": profiled_traffic(dom), "algorithmic_bytes_per_launch": byts,
+                "frac_of_copy": ach / copy_gbs}
     roof["avg_launch_ms"] = dom_ms
-    # whole-step roofline: sum over stages of the larger of the HBM time and the ALU time
+    # whole-step roofline over the survey's steps: the larger of the HBM time and the ALU time
+    steps = {}
     t_roof = 0.0
-    for k, v in per_stage.items():
-        t_b = algorithmic_bytes(k, N, n_vis, K, P, tiles) / (HBM_PEAK_GBS * 1e9)
-        t_a = 0.0
-        if k == "blend":
-            t_a = (FLOPS_EVAL * Pi_walk + FLOPS_BLEND_FWD * Pi_blend) / (FP32_VALU_PEAK_TFLOPS * 1e12)
-        elif k == "blend_bwd":
-            t_a = (FLOPS_EVAL * Pi_walk + FLOPS_BLEND_BWD * Pi_blend) / (FP32_VALU_PEAK_TFLOPS * 1e12)
-        v["roofline_ms"] = 1e3 * max(t_b, t_a)
-        v["frac"] = v["roofline_ms"] / v["ms"]
+    for name, sts in SURVEY_STEPS.items():
+        if not all(x in per_stage for x in sts):
+            continue
+        ms = sum(per_stage[x]["ms"] for x in sts)
+        byts, ops = survey_work(name, N, K, P, tiles, Pi_walk, Pi_blend)
+        t_b, t_a = byts / (HBM_PEAK_GBS * 1e9), ops / (LANE_OP_PEAK_TOPS * 1e12)
         t_roof += max(t_b, t_a)
+        steps[name] = {"ms": round(ms, 4), "bytes": byts, "ops": ops, "GBs": round(byts / (ms * 1e-3) / 1e9, 1),
+                       "frac_hbm": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+                       "frac_copy": round(byts / (ms * 1e-3) / 1e9 / copy_gbs, 3),
+                       "roofline_ms": round(1e3 * max(t_b, t_a), 4), "frac": round(1e3 * max(t_b, t_a) / ms, 3)}
+        if ops:
+            steps[name]["Tops"] = round(ops / (ms * 1e-3) / 1e12, 2)
+            steps[name]["frac_alu"] = round(ops / (ms * 1e-3) / 1e12 / LANE_OP_PEAK_TOPS, 3)
     stage_sum_ms = sum(v["ms"] for v in per_stage.values())
     out_extra["step_roofline"] = {"roofline_ms": 1e3 * t_roof, "stages_ms": stage_sum_ms,
-                                  "frac_of_stages": 1e3 * t_roof / stage_sum_ms, "frac_of_step": 1e3 * t_roof / ms_step}
+                                  "frac_of_stages": 1e3 * t_roof / stage_sum_ms, "frac_of_step": 1e3 * t_roof / ms_step,
+                                  "hbm_peak_GBs": HBM_PEAK_GBS, "hbm_copy_GBs": copy_gbs,
+                                  "lane_op_peak_Tops": LANE_OP_PEAK_TOPS, "steps": steps}
     log(f"step {ms_step:.3f} ms ({iters_s:.1f} it/s); K={K:.0f} visible={n_vis:.0f} "
-        f"pairs walked {Pi_walk:.3g} blended {Pi_blend:.3g}")
+        f"pairs walked {Pi_walk:.3g} blended {Pi_blend:.3g}; device copy {copy_gbs:.0f} GB/s")
     log(f"tile list length mean {lens.mean():.0f} p50 {np.median(lens):.0f} p99 {np.percentile(lens, 99):.0f} "
         f"max {lens.max()}")
     for k, v in per_stage.items():
-        log(f"  {k:15s} {v['ms']:.3f} ms  {v['GBs_algorithmic']:.0f} GB/s algorithmic")
+        log(f"  {k:15s} {v['ms']:.3f} ms  {v['GBs_algorithmic']:.0f} GB/s of this design's bytes")
+    for name, v in steps.items():
+        extra = f", {v['Tops']:.1f} Top/s = {v['frac_alu']:.2f} of {LANE_OP_PEAK_TOPS:.1f}" if "Tops" in v else ""
+        log(f"  {name:24s} {v['ms']:.3f} ms  {v['GBs']:.0f} GB/s of the survey's bytes = {v['frac_hbm']:.2f} of "
+            f"8 TB/s, {v['frac_copy']:.2f} of the copy rate{extra}; roofline {v['roofline_ms']:.3f} ms "
+            f"({v['frac']:.2f})")
 
     if not args.no_extras:
         # -------------------------------------------------------------- forward FPS
@@ -442,8 +570,9 @@ def main():
         order = oracle.depth_order(k)
         t_keys = time.perf_counter() - t0
         rng = np.random.default_rng(7)
-        npx = 512
-        pix = np.stack([rng.integers(0, 1920, npx), rng.integers(0, 1080, npx)], 1).astype(np.int32)
+        npx = 4096
+        pix = np.unique(np.stack([rng.integers(0, 1920, npx), rng.integers(0, 1080, npx)], 1).astype(np.int32), axis=0)
+        npx = pix.shape[0]
         t0 = time.perf_counter()
         ref = oracle.image(order, *scene.arrays()[:4], scene.s_min, scene.sh, 3, cam, bg, pix)
         t_img = time.perf_counter() - t0
@@ -452,12 +581,24 @@ def main():
         oracle.grad(order, *scene.arrays()[:4], scene.s_min, scene.sh, 3, cam, bg, pix, w)
         t_grad = time.perf_counter() - t0
         t_frame = t_keys + (t_img + t_grad) * P / npx
+        # the 2,000-Gaussian 128x128 frame in full: O1 and O2 over every pixel, median of 3
+        from paper_2408_12894_amd import synth as _synth
+        s1, c1, b1 = _synth.small_forward_case()
+        t1 = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.render(s1.arrays(), s1.s_min, c1, b1)
+            t1.append(time.perf_counter() - t0)
         out["cpu_baseline"] = {"value": 1.0 / t_frame, "unit": "iters/s", "cores": oracle.get_threads(),
-                               "kind": "oracle",
+                               "kind": "oracle", "cpu_model": cpu_model(),
                                "sample": f"fwd+bwd step at 1920x1080/1M, camera 0: O1 keys and sorted instance list "
-                                         f"in full ({t_keys:.2f} s), O2 image and O3 gradient on {npx} of {P} pixels "
-                                         f"({t_img + t_grad:.2f} s), extrapolated per pixel to the frame"}
-        log(f"cpu oracle: {t_frame:.1f} s per step extrapolated ({oracle.get_threads()} threads)")
+                                         f"in full ({t_keys:.2f} s), O2 image ({t_img:.2f} s) and O3 gradient "
+                                         f"({t_grad:.2f} s) on {npx} of {P} pixels, extrapolated per pixel to the "
+                                         f"frame",
+                               "extrapolated": True,
+                               "small_frame_128x128_2k_s": float(np.median(t1))}
+        log(f"cpu oracle: {t_frame:.1f} s per step extrapolated ({oracle.get_threads()} threads, {cpu_model()}); "
+            f"128x128 / 2k frame {np.median(t1):.3f} s")
     print(json.dumps(out), flush=True)
 
 
