@@ -39,13 +39,26 @@ constexpr int kBwdPix = FLOD_BWD_PIX;   // pixels per thread: 4 = one wave64 per
 // wave) took 0.268 ms, 96 0.241 ms and 64 0.232 ms.
 constexpr int kBwdBatch = FLOD_BWD_BATCH;
 
+// Sum over the 16 lanes of each DPP row, in every lane of the row (rotations by 8, 4, 2, 1).
+template <int N>
+__device__ __forceinline__ float add_row_ror(float v) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + N, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float row_sum16(float v) {
+  return add_row_ror<1>(add_row_ror<2>(add_row_ror<4>(add_row_ror<8>(v))));
+}
+
+// Frames with at least this many tiles reduce each entry's gradient with a second LDS round,
+// smaller ones with DPP (see the kernel).
+constexpr int kLdsRound2MinTiles = 6144;
+
 // One workgroup per tile with PPT pixels per thread (the forward's geometry). Per pixel
 // the state is T (transmittance after the current entry), V = dL/dC . Shat (the upstream
 // gradient dotted with the normalised colour behind the current entry) and dL/dC, all FP32
 // (V is a convex combination per step, so its error does not grow along the chain). Per entry
 // each thread sums its pixels' 9 gradient components in registers and the wave reduces
 // them (see below) before one atomic instruction adds the nine sums.
-template <int PPT>
+template <int PPT, bool LDS_ROUND2>
 __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ values, const float4 *__restrict__ xyab,
     const float4 *__restrict__ cop, const float2 *__restrict__ blue, int W, int H, int tiles_x, int n_tiles,
@@ -67,7 +80,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   const int tid = threadIdx.x, lane = tid & 63;
   // float4 slots each lane reads in the reduction's rounds (clamped: lanes past the last
   // slot read a valid one and discard it)
-  const int red_hi = min(lane + 128, kG2d * 16 - 1), red_lo36 = min(lane, 35), red_lo9 = min(lane, kG2d - 1);
+  const int red_hi = min(lane + 128, kG2d * 16 - 1), red_lo9 = min(lane, kG2d - 1);
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
   const int px = x0 + (tid & (kTile - 1));
   const float fx = (float)px + 0.5f;
@@ -205,13 +218,17 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       gr[0] = -(D.x * dx * S0 + D.y * S1);
       gr[1] = -(D.y * dx * S0 + D.z * S1);
       {
-        // the nine components summed over the wave through LDS (no DPP: a DPP operation costs
-        // about two VALU issue slots, LDS traffic is idle here): each lane writes its nine
-        // values component-major, then three rounds of float4 reads and adds leave 16, 4 and
-        // finally 1 partial per component; lane c < 9 then holds component c and the nine
-        // lanes add their sums to the Gaussian's 36-byte row with one atomic instruction. The
-        // workgroup is one wave, so its barriers only order the LDS accesses.
-        static_assert(NT == 64, "the LDS reduction assumes one wave per tile");
+        // the nine components summed over the wave: each lane writes its nine values to LDS
+        // component-major and reads three float4 back (lane l: 4 lanes' values of component
+        // l / 16, 4 + l / 16 and, lanes below 16, 8). Then either a second LDS round (the 16
+        // partials of component c read by lane c, which adds them to the Gaussian's 36-byte row;
+        // one atomic instruction), or DPP sums over each row of 16 lanes (lanes 0, 16, 32, 48
+        // then hold the sums; three atomic instructions). DPP costs about two VALU issue slots
+        // per operation, an LDS round a wait: the LDS form for frames with enough tiles to hide
+        // the wait (8 waves per SIMD at 1080p: 0.233 against 0.254 ms), DPP for small ones (720p,
+        // 3.5 waves per SIMD: 0.238 against 0.248 ms). The workgroup is one wave, so its barriers
+        // only order the LDS accesses.
+        static_assert(NT == 64, "the per-entry reduction assumes one wave per tile");
 #pragma unroll
         for (int c = 0; c < kG2d; ++c) s_red[c * 64 + lane] = gr[c];
         __syncthreads();
@@ -220,22 +237,48 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         const float p0 = (ra.x + ra.y) + (ra.z + ra.w);   // component lane / 16
         const float p1 = (rb.x + rb.y) + (rb.z + rb.w);   // component 4 + lane / 16
         const float p2 = (rc.x + rc.y) + (rc.z + rc.w);   // component 8 (lanes 0..15)
-        __syncthreads();
-        s_red[lane] = p0;
-        s_red[64 + lane] = p1;
-        if (lane < 16) s_red[128 + lane] = p2;
-        __syncthreads();
-        const float4 rd = r4[red_lo36];                      // component lane / 4 (lanes 0..35)
-        const float p3 = (rd.x + rd.y) + (rd.z + rd.w);
-        __syncthreads();
-        if (lane < 36) s_red[lane] = p3;
-        __syncthreads();
-        const float4 re = r4[red_lo9];                       // component lane (lanes 0..8)
-        const float x = (re.x + re.y) + (re.z + re.w);
-        if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[(size_t)s_id[jl] * kG2d + lane], x);
+        const size_t row = (size_t)s_id[jl] * kG2d;
+        if (LDS_ROUND2) {
+          __syncthreads();
+          s_red[lane] = p0;
+          s_red[64 + lane] = p1;
+          if (lane < 16) s_red[128 + lane] = p2;
+          __syncthreads();
+          const int c4 = 4 * red_lo9;                        // component lane (lanes 0..8)
+          const float4 q0 = r4[c4], q1 = r4[c4 + 1], q2 = r4[c4 + 2], q3 = r4[c4 + 3];
+          const float x = (((q0.x + q0.y) + (q0.z + q0.w)) + ((q1.x + q1.y) + (q1.z + q1.w))) +
+                          (((q2.x + q2.y) + (q2.z + q2.w)) + ((q3.x + q3.y) + (q3.z + q3.w)));
+          if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[row + lane], x);
+        } else {
+          const float s0 = row_sum16(p0), s1 = row_sum16(p1), s2 = row_sum16(p2);
+          if ((lane & 15) == 0) {
+            if (s0 != 0.0f) atomicAdd(&g2d[row + (lane >> 4)], s0);
+            if (s1 != 0.0f) atomicAdd(&g2d[row + 4 + (lane >> 4)], s1);
+            if (lane == 0 && s2 != 0.0f) atomicAdd(&g2d[row + 8], s2);
+          }
+        }
       }
       }
     }
+  }
+}
+
+template <bool LDS_ROUND2>
+static void launch_blend_bwd_t(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
+                               const float2 *blue, const DevCamera &cam, const float bg[3], const float *final_T,
+                               const int32_t *n_contrib, const float *dL_dimage, float *g2d, const uint8_t *taken,
+                               const uint32_t *order, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  const int n_tiles = cam.tiles_x * cam.tiles_y;
+  auto kernel = k_blend_bwd<kBwdPix, LDS_ROUND2>;
+  if (ev_start || ev_stop) {
+    // timed from the kernel's own dispatch: no event packets between it and its neighbours
+    hipExtLaunchKernelGGL(kernel, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s,
+                          ev_start, ev_stop, 0, ranges, values, xyab, cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles,
+                          bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimage, g2d, taken, order);
+  } else {
+    hipLaunchKernelGGL(kernel, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s, ranges,
+                       values, xyab, cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T,
+                       n_contrib, dL_dimage, g2d, taken, order);
   }
 }
 
@@ -243,17 +286,12 @@ hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const f
                             const float2 *blue, const DevCamera &cam, const float bg[3], const float *final_T,
                             const int32_t *n_contrib, const float *dL_dimage, float *g2d, const uint8_t *taken,
                             const uint32_t *order, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  const int n_tiles = cam.tiles_x * cam.tiles_y;
-  if (ev_start || ev_stop) {
-    // timed from the kernel's own dispatch: no event packets between it and its neighbours
-    hipExtLaunchKernelGGL(k_blend_bwd<kBwdPix>, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s, ev_start,
-                          ev_stop, 0, ranges, values, xyab, cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0],
-                          bg[1], bg[2], final_T, n_contrib, dL_dimage, g2d, taken, order);
-  } else {
-    hipLaunchKernelGGL(k_blend_bwd<kBwdPix>, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s, ranges, values,
-                       xyab, cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib,
-                       dL_dimage, g2d, taken, order);
-  }
+  if (cam.tiles_x * cam.tiles_y >= kLdsRound2MinTiles)
+    launch_blend_bwd_t<true>(ranges, values, xyab, cop, blue, cam, bg, final_T, n_contrib, dL_dimage, g2d, taken,
+                             order, s, ev_start, ev_stop);
+  else
+    launch_blend_bwd_t<false>(ranges, values, xyab, cop, blue, cam, bg, final_T, n_contrib, dL_dimage, g2d, taken,
+                              order, s, ev_start, ev_stop);
   return hipGetLastError();
 }
 
