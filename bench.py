@@ -90,7 +90,7 @@ FLOPS_BLEND_BWD = 46
 # step_1080p_1M_hbm_counters.md). A figure holds only for the kernel sources it was taken
 # with: the sha256 over the listed files must match, else the traffic is reported as null.
 PROFILED_TRAFFIC = {
-    "blend_bwd": {"bytes": 313268431, "sha256": "06b8a4071679f3bfbcc04c26b1fa6358547993575e2ebb554ab6868cf4a4a660",
+    "blend_bwd": {"bytes": 313034147, "sha256": "d97d19d6d1da7a7a10835ab95c751aeec26f471a5006a6bfd6699bea0949c2fc",
                   "sources": ['paper_2408_12894_amd/csrc/backward.hip', 'paper_2408_12894_amd/csrc/blend_common.h', 'paper_2408_12894_amd/csrc/project.h', 'paper_2408_12894_amd/csrc/flod_internal.h']},
 }
 

@@ -305,3 +305,91 @@ def test_context_used_on_two_streams():
     torch.cuda.synchronize()
     np.testing.assert_array_equal(a.cpu().numpy(), ref[0])
     np.testing.assert_array_equal(b.cpu().numpy(), ref[1])
+
+
+
+def _min_q_over_boxes(dxa, dxb, dya, dyb, a, b, c):
+    """Smallest q = a dx^2 + 2 b dx dy + c dy^2 (positive definite) over the boxes
+    [dxa, dxb] x [dya, dyb] of offsets from the mean, FP64, elementwise."""
+    def edge_x(dx, lo, hi):      # dx fixed, dy free in [lo, hi]
+        dy = np.clip(-b * dx / c, lo, hi)
+        return a * dx * dx + 2 * b * dx * dy + c * dy * dy
+
+    def edge_y(dy, lo, hi):
+        dx = np.clip(-b * dy / a, lo, hi)
+        return a * dx * dx + 2 * b * dx * dy + c * dy * dy
+
+    q = np.minimum(np.minimum(edge_x(dxa, dya, dyb), edge_x(dxb, dya, dyb)),
+                   np.minimum(edge_y(dya, dxa, dxb), edge_y(dyb, dxa, dxb)))
+    inside = (dxa <= 0) & (dxb >= 0) & (dya <= 0) & (dyb >= 0)
+    return np.where(inside, 0.0, q)
+
+
+@pytest.mark.parametrize("case", ["small", "cluster"])
+def test_instance_list_against_fp64_geometry(renderer, case):
+    """The GPU's tile lists checked against the FP64 projection directly, not against the FP32
+    key mirror. Completeness: for every Gaussian in front of the near plane, every tile holding
+    a pixel centre where it blends with a margin (q <= 9 (1 - 1e-4) and o e^{-q/2} >=
+    (1 + 1e-4) / 255) lists it. Soundness: a listed tile meets the support, i.e. its band of
+    pixel-centre rows (columns over the whole tile) holds a point with q <= Q_g (1 + 1e-2) +
+    1e-2, Q_g = min(9, 2 ln(255 o)). Order: along each tile's list the FP64 view depth never
+    falls by more than FP32 rounding of it."""
+    _say(f"instance list against FP64 geometry ({case})")
+    if case == "small":
+        scene, cam, bg = synth.small_forward_case()
+    else:
+        scene = synth.cluster_scene(20_000, seed=44, layout_seed=1)
+        cam = synth.orbit_cameras(2, 1, 4.0, 480, 272)[0]
+        bg = np.zeros(3, np.float32)
+    image, T, nc, view = gpu_render(renderer, scene, cam, bg)
+    W, H = cam.width, cam.height
+    tx_n = (W + 15) // 16
+    tiles, vals = view["tile_ids"].astype(np.int64), view["values"].astype(np.int64)
+    assert tiles.size == view["stats"]["n_instances"] > 0
+    R = np.asarray(cam.R, np.float64).reshape(3, 3)
+    tz = scene.means.astype(np.float64) @ R[2] + float(np.asarray(cam.t, np.float64)[2])
+    front = np.nonzero(tz > 0.2 * (1 + 1e-6))[0]
+    p64 = oracle.project64(front, *scene.arrays()[:4], scene.s_min, scene.sh, 3, cam)
+    row = np.full(scene.n, -1, np.int64)
+    row[front] = np.arange(front.size)
+    listed = {}
+    for t, v in zip(tiles.tolist(), vals.tolist()):
+        listed.setdefault(v, set()).add(t)
+    # completeness over each Gaussian's q <= 9 window of pixel centres
+    n_need = 0
+    for j, i in enumerate(front):
+        mx, my, a, b, c, o = p64[j, :6]
+        det = a * c - b * b
+        if not (det > 0) or o * 255.0 < 1 + 1e-4:
+            continue
+        hx, hy = np.sqrt(9 * c / det), np.sqrt(9 * a / det)
+        x0, x1 = max(0, int(np.floor(mx - hx - 1))), min(W, int(np.ceil(mx + hx + 1)))
+        y0, y1 = max(0, int(np.floor(my - hy - 1))), min(H, int(np.ceil(my + hy + 1)))
+        if x0 >= x1 or y0 >= y1:
+            continue
+        ys, xs = np.mgrid[y0:y1, x0:x1]
+        dx, dy = xs + 0.5 - mx, ys + 0.5 - my
+        q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+        must = (q <= 9.0 * (1 - 1e-4)) & (o * np.exp(-0.5 * q) >= (1 + 1e-4) / 255.0)
+        if not must.any():
+            continue
+        need = set(((ys[must] // 16) * tx_n + xs[must] // 16).tolist())
+        n_need += len(need)
+        have = listed.get(int(i), set())
+        assert need <= have, f"Gaussian {i}: tiles {sorted(need - have)[:5]} missing from its list"
+    # soundness of every listed (tile, Gaussian) pair
+    j = row[vals]
+    assert (j >= 0).all(), "a Gaussian behind the near plane is listed"
+    mx, my, a, b, c, o = (p64[j, k] for k in range(6))
+    txs, tys = tiles % tx_n, tiles // tx_n
+    qmin = _min_q_over_boxes(16.0 * txs - mx, 16.0 * txs + 16 - mx, 16.0 * tys + 0.5 - my,
+                             16.0 * tys + 15.5 - my, a, b, c)
+    qg = np.minimum(9.0, 2 * np.log(255.0 * o))
+    far = qmin > qg * (1 + 1e-2) + 1e-2
+    assert not far.any(), f"{int(far.sum())} listed pairs away from the support, e.g. value {vals[far][:3]}"
+    # depth order inside every tile
+    same = tiles[1:] == tiles[:-1]
+    da, db = tz[vals[:-1][same]], tz[vals[1:][same]]
+    bad = da > db + 2e-7 * np.abs(db)
+    assert not bad.any(), f"{int(bad.sum())} adjacent entries out of depth order"
+    print(f"K={tiles.size}, front {front.size}, required pairs {n_need}", flush=True)
