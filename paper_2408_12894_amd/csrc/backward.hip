@@ -52,6 +52,51 @@ __device__ __forceinline__ float row_sum16(float v) {
 // smaller ones with DPP (see the kernel).
 constexpr int kLdsRound2MinTiles = 6144;
 
+// The per-pixel decision of one entry, repeating the forward's bit for bit: the pixel takes
+// part when its walk has reached the entry, q is inside the support cut and alpha reaches the
+// floor. A pixel that does not take part gets alpha 0 and G 0: it then adds exact zeros, keeps
+// its T (T / (1 - 0) = T) and its V. G is also 0 where the 0.99 clamp is active (alpha does not
+// depend on opacity or q there). The clamp can act only for opacities near 0.99: q >= 0 gives
+// kq <= 0 and G = 2^kq <= 1 (to within an ulp of the hardware exp2), so for o <= 0.98 the
+// product o G stays below 0.99 and alpha is o G itself.
+template <int PPT, bool CLAMP>
+__device__ __forceinline__ bool decide(const float (&fy)[PPT], const int (&last)[PPT], int jpos, float ay, float loy,
+                                       float ck, float op, float off, float t, float (&dyv)[PPT],
+                                       float (&aev)[PPT], float (&gmv)[PPT]) {
+  bool contrib = false;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const float t1 = fy[k] - ay;
+    dyv[k] = t1 - loy;
+    const float kq = conic_kq(ck, off, t, t1);   // k q
+    const float G = gauss_weight_scaled(kq);
+    const float a0 = op * G;
+    if (CLAMP) {
+      const float al = fminf(kAlphaMax, a0);
+      const bool ok = jpos < last[k] && kq >= kQCutScaled && al >= kAlphaMin;
+      aev[k] = ok ? al : 0.0f;
+      gmv[k] = (ok && a0 <= kAlphaMax) ? G : 0.0f;
+      contrib = contrib || ok;
+    } else {
+      const bool ok = jpos < last[k] && kq >= kQCutScaled && a0 >= kAlphaMin;
+      aev[k] = ok ? a0 : 0.0f;
+      gmv[k] = ok ? G : 0.0f;
+      contrib = contrib || ok;
+    }
+  }
+  return contrib;
+}
+
+// Opacity above which an entry takes the decision with the clamp (bits of a positive float,
+// compared as integers on the scalar unit).
+constexpr float kClampOpacity = 0.98f;
+constexpr int kClampOpacityBits = __builtin_bit_cast(int, kClampOpacity);
+
+// Per-entry reduction through LDS: component c of lane l at s_red[c * kRedStride + l]. The
+// stride of 80 floats puts the four components a read instruction of the first round touches
+// at once on four different 64-byte bank groups.
+constexpr int kRedStride = 80;
+
 // One workgroup per tile with PPT pixels per thread (the forward's geometry). Per pixel
 // the state is T (transmittance after the current entry), V = dL/dC . Shat (the upstream
 // gradient dotted with the normalised colour behind the current entry) and dL/dC, all FP32
@@ -75,11 +120,17 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   __shared__ uint32_t s_id[kBwdBatch];
   __shared__ int s_pos[kBwdBatch];
   __shared__ int s_max[WAVES];
-  __shared__ __align__(16) float s_red[kG2d * 64];   // the per-entry reduction
+  constexpr int RS = LDS_ROUND2 ? kRedStride : 64;   // component stride of the reduction
+  __shared__ __align__(16) float s_red[kG2d * RS];   // the per-entry reduction
+  __shared__ __align__(16) float s_red2[4 * kG2d];   // its first round's partials (LDS form)
   const int tile = (int)order[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63;
   // float4 slots each lane reads in the reduction's rounds (clamped: lanes past the last
-  // slot read a valid one and discard it)
+  // slot read a valid one and discard it). LDS form: lane 4 c + h (c < 9, h < 4) sums the
+  // float4 slots h, h + 4, h + 8, h + 12 of component c in the first round, lane c < 9 the
+  // four partials of component c in the second; DPP form: slots lane, lane + 64, lane + 128
+  const int red_l36 = min(lane, 4 * kG2d - 1);
+  const int red_r1 = (red_l36 >> 2) * (kRedStride / 4) + (red_l36 & 3);
   const int red_hi = min(lane + 128, kG2d * 16 - 1), red_lo9 = min(lane, kG2d - 1);
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
   const int px = x0 + (tid & (kTile - 1));
@@ -158,25 +209,13 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       float off, t;
       conic_column(A.z, A.w, loy, dx, off, t);
       // first only what decides whether a pixel takes part; the transmittance recovery and
-      // the gradient run when some pixel of the wave does
+      // the gradient run when some pixel of the wave does. The opacity is the same in every
+      // lane, so the branch is uniform
       float dyv[PPT], aev[PPT], gmv[PPT];
-      bool contrib = false;
-#pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        const float t1 = fy[k] - A.y;
-        dyv[k] = t1 - loy;
-        const float kq = conic_kq(B.x, off, t, t1);   // k q
-        const float G = gauss_weight_scaled(kq);
-        const float a0 = B.y * G;
-        const float al = fminf(kAlphaMax, a0);
-        const bool ok = jpos < last[k] && kq >= kQCutScaled && al >= kAlphaMin;
-        // a pixel that does not take part gets alpha 0 and G 0: it then adds exact zeros, keeps
-        // its T (T / (1 - 0) = T) and its V; G is also 0 where the 0.99 clamp is active (alpha
-        // does not depend on opacity or q there)
-        aev[k] = ok ? al : 0.0f;
-        gmv[k] = (ok && a0 <= kAlphaMax) ? G : 0.0f;
-        contrib = contrib || ok;
-      }
+      const bool contrib =
+          __builtin_amdgcn_readfirstlane(__float_as_int(B.y)) > kClampOpacityBits
+              ? decide<PPT, true>(fy, last, jpos, A.y, loy, B.x, B.y, off, t, dyv, aev, gmv)
+              : decide<PPT, false>(fy, last, jpos, A.y, loy, B.x, B.y, off, t, dyv, aev, gmv);
       if (!__any(contrib)) continue;
       {
       // the gradient arithmetic may contract into FMAs (the decision above must not: it
@@ -219,37 +258,37 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       gr[1] = -(D.y * dx * S0 + D.z * S1);
       {
         // the nine components summed over the wave: each lane writes its nine values to LDS
-        // component-major and reads three float4 back (lane l: 4 lanes' values of component
-        // l / 16, 4 + l / 16 and, lanes below 16, 8). Then either a second LDS round (the 16
-        // partials of component c read by lane c, which adds them to the Gaussian's 36-byte row;
-        // one atomic instruction), or DPP sums over each row of 16 lanes (lanes 0, 16, 32, 48
-        // then hold the sums; three atomic instructions). DPP costs about two VALU issue slots
-        // per operation, an LDS round a wait: the LDS form for frames with enough tiles to hide
-        // the wait (8 waves per SIMD at 1080p: 0.233 against 0.254 ms), DPP for small ones (720p,
-        // 3.5 waves per SIMD: 0.238 against 0.248 ms). The workgroup is one wave, so its barriers
-        // only order the LDS accesses.
+        // component-major. LDS form: 36 lanes each add 16 values of one component (four float4
+        // reads), then lane c < 9 adds the four partials of component c to the Gaussian's 36-byte
+        // row (one atomic instruction). DPP form: each lane adds three float4 (4 lanes' values of
+        // components l / 16, 4 + l / 16 and, lanes below 16, 8), DPP sums over each row of 16 lanes
+        // follow (lanes 0, 16, 32, 48 then hold the sums; three atomic instructions). DPP costs
+        // about two VALU issue slots per operation, an LDS round a wait: the LDS form for frames
+        // with enough tiles to hide the wait (8 waves per SIMD at 1080p: 0.233 against 0.254 ms
+        // with a three-float4 first round), DPP for small ones (720p, 3.5 waves per SIMD: 0.238
+        // against 0.248 ms). The workgroup is one wave, so its barriers only order the LDS
+        // accesses.
         static_assert(NT == 64, "the per-entry reduction assumes one wave per tile");
 #pragma unroll
-        for (int c = 0; c < kG2d; ++c) s_red[c * 64 + lane] = gr[c];
+        for (int c = 0; c < kG2d; ++c) s_red[c * RS + lane] = gr[c];
         __syncthreads();
         const float4 *r4 = reinterpret_cast<const float4 *>(s_red);
-        const float4 ra = r4[lane], rb = r4[lane + 64], rc = r4[red_hi];
-        const float p0 = (ra.x + ra.y) + (ra.z + ra.w);   // component lane / 16
-        const float p1 = (rb.x + rb.y) + (rb.z + rb.w);   // component 4 + lane / 16
-        const float p2 = (rc.x + rc.y) + (rc.z + rc.w);   // component 8 (lanes 0..15)
         const size_t row = (size_t)s_id[jl] * kG2d;
         if (LDS_ROUND2) {
-          __syncthreads();
-          s_red[lane] = p0;
-          s_red[64 + lane] = p1;
-          if (lane < 16) s_red[128 + lane] = p2;
-          __syncthreads();
-          const int c4 = 4 * red_lo9;                        // component lane (lanes 0..8)
-          const float4 q0 = r4[c4], q1 = r4[c4 + 1], q2 = r4[c4 + 2], q3 = r4[c4 + 3];
-          const float x = (((q0.x + q0.y) + (q0.z + q0.w)) + ((q1.x + q1.y) + (q1.z + q1.w))) +
+          // lane 4 c + h: 16 values of component c (lanes 4 h .. 4 h + 3 of each group of 16)
+          const float4 q0 = r4[red_r1], q1 = r4[red_r1 + 4], q2 = r4[red_r1 + 8], q3 = r4[red_r1 + 12];
+          const float p = (((q0.x + q0.y) + (q0.z + q0.w)) + ((q1.x + q1.y) + (q1.z + q1.w))) +
                           (((q2.x + q2.y) + (q2.z + q2.w)) + ((q3.x + q3.y) + (q3.z + q3.w)));
+          if (lane < 4 * kG2d) s_red2[lane] = p;
+          __syncthreads();
+          const float4 q = reinterpret_cast<const float4 *>(s_red2)[red_lo9];   // component lane (lanes 0..8)
+          const float x = (q.x + q.y) + (q.z + q.w);
           if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[row + lane], x);
         } else {
+          const float4 ra = r4[lane], rb = r4[lane + 64], rc = r4[red_hi];
+          const float p0 = (ra.x + ra.y) + (ra.z + ra.w);   // component lane / 16
+          const float p1 = (rb.x + rb.y) + (rb.z + rb.w);   // component 4 + lane / 16
+          const float p2 = (rc.x + rc.y) + (rc.z + rc.w);   // component 8 (lanes 0..15)
           const float s0 = row_sum16(p0), s1 = row_sum16(p1), s2 = row_sum16(p2);
           if ((lane & 15) == 0) {
             if (s0 != 0.0f) atomicAdd(&g2d[row + (lane >> 4)], s0);

@@ -122,6 +122,22 @@ def test_ragged_with_scale_floor(renderer):
     grad_parity(renderer, scene, cam, np.zeros(3, np.float32), seed=2)
 
 
+def test_opaque_scene_with_active_clamp(renderer):
+    """Opacities from 0.88 to 0.9999 (logits U[2, 9.2]): entries above opacity 0.98 take the
+    decision with the 0.99 alpha clamp, and near the centres of those above 0.99 the clamp is
+    active (no opacity or q gradient there); the rest take the decision without it."""
+    _say("300 opaque Gaussians, 96x80")
+    scene = synth.uniform_scene(300, seed=62, s_mu=-1.0, s_sigma=0.3)
+    rng = np.random.default_rng(62)
+    scene.opacity_logits[:] = rng.uniform(2.0, 9.2, scene.n).astype(np.float32)
+    o = 1.0 / (1.0 + np.exp(-scene.opacity_logits.astype(np.float64)))
+    assert (o > 0.99).mean() > 0.3 and (o < 0.98).mean() > 0.2
+    cam = synth.look_at_camera((0.2, -0.1, -3.8), (0, 0, 0), 96, 80)
+    worst, nz = grad_parity(renderer, scene, cam, np.array([0.3, 0.2, 0.1], np.float32), seed=5)
+    assert nz > 1000
+    print(worst)
+
+
 def test_training_size_sampled(renderer):
     """500k Gaussians at 1280x720 (the training-step configuration) with the loss restricted
     to 1024 sampled pixels, so the oracle's FP64 gradient stays cheap."""
