@@ -60,15 +60,15 @@ constexpr int kLdsRound2MinTiles = 6144;
 // kq <= 0 and G = 2^kq <= 1 (to within an ulp of the hardware exp2), so for o <= 0.98 the
 // product o G stays below 0.99 and alpha is o G itself.
 template <int PPT, bool CLAMP>
-__device__ __forceinline__ bool decide(const float (&fy)[PPT], const int (&last)[PPT], int jpos, float ay, float loy,
-                                       float ck, float op, float off, float t, float (&dyv)[PPT],
+__device__ __forceinline__ bool decide(const float (&fy)[PPT], const int (&last)[PPT], int jpos, float my, float r,
+                                       float dx, float ck, float op, float t, float (&dyv)[PPT],
                                        float (&aev)[PPT], float (&gmv)[PPT]) {
   bool contrib = false;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const float t1 = fy[k] - ay;
-    dyv[k] = t1 - loy;
-    const float kq = conic_kq(ck, off, t, t1);   // k q
+    const float dy = fy[k] - my;
+    dyv[k] = dy;
+    const float kq = conic_kq(ck, r, dx, dy, t);   // k q
     const float G = gauss_weight_scaled(kq);
     const float a0 = op * G;
     if (CLAMP) {
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   const int red_hi = min(lane + 128, kG2d * 16 - 1), red_lo9 = min(lane, kG2d - 1);
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
   const int px = x0 + (tid & (kTile - 1));
-  const float fx = (float)px + 0.5f;
+  const float fx = (float)(tid & (kTile - 1)) + 0.5f;   // pixel centres relative to the tile's corner
   const size_t plane = (size_t)W * H;
   const uint2 rg = ranges[tile];
   // a pixel's walk starts at its n_contrib, clamped to the tile's list so that no value of that
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int py = y0 + (tid >> 4) + ROWS * k;
-    fy[k] = (float)py + 0.5f;
+    fy[k] = (float)(py - y0) + 0.5f;
     T[k] = 1.0f; V[k] = 0.0f; d0[k] = 0.0f; d1[k] = 0.0f; d2[k] = 0.0f;
     last[k] = 0;
     if (px < W && py < H) {
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         const uint32_t g = values[rg.x + start + e];
         s_id[idx] = g;
         s_pos[idx] = start + e;
-        stage_entry(xyab, cop, blue, g, s_a[idx], s_b[idx], s_c[idx]);
+        stage_entry(xyab, cop, blue, g, x0, y0, s_a[idx], s_b[idx], s_c[idx]);
         const float4 A = xyab[g];
         s_d[idx] = make_float4(2.0f * A.z, 2.0f * A.w, 2.0f * cop[g].x, -0.5f * cop[g].y);
       }
@@ -202,20 +202,17 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       const int jpos = s_pos[jl];
       const float4 A = s_a[jl];
       const float4 B = s_b[jl];
-      const float4 BL = s_c[jl];
-      const float c2 = BL.x;
-      const float loy = BL.z;
-      const float dx = (fx - A.x) - BL.y;
-      float off, t;
-      conic_column(A.z, A.w, loy, dx, off, t);
+      const float blue = s_c[jl].y;
+      const float dx = fx - A.x;
+      const float t = conic_column(A.w, dx);
       // first only what decides whether a pixel takes part; the transmittance recovery and
       // the gradient run when some pixel of the wave does. The opacity is the same in every
       // lane, so the branch is uniform
       float dyv[PPT], aev[PPT], gmv[PPT];
       const bool contrib =
           __builtin_amdgcn_readfirstlane(__float_as_int(B.y)) > kClampOpacityBits
-              ? decide<PPT, true>(fy, last, jpos, A.y, loy, B.x, B.y, off, t, dyv, aev, gmv)
-              : decide<PPT, false>(fy, last, jpos, A.y, loy, B.x, B.y, off, t, dyv, aev, gmv);
+              ? decide<PPT, true>(fy, last, jpos, A.y, A.z, dx, B.x, B.y, t, dyv, aev, gmv)
+              : decide<PPT, false>(fy, last, jpos, A.y, A.z, dx, B.x, B.y, t, dyv, aev, gmv);
       if (!__any(contrib)) continue;
       {
       // the gradient arithmetic may contract into FMAs (the decision above must not: it
@@ -234,7 +231,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         const float alpha = aev[k], dy = dyv[k];
         const float Ti = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
         const float wT = alpha * Ti;
-        const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * c2;   // dL/dC . c
+        const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * blue;   // dL/dC . c
         const float diff = dcc - V[k];
         const float e = (Ti * diff) * gmv[k];                       // dL/dalpha G
         gr[6] = fmaf(wT, d0[k], gr[6]);

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
   const int tid = threadIdx.x;
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
   const int px = x0 + (tid & (kTile - 1));
-  const float fx = (float)px + 0.5f;
+  const float fx = (float)(tid & (kTile - 1)) + 0.5f;   // pixel centres relative to the tile's corner
   float fy[PPT];
   bool inside[PPT];
   float T[PPT];
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int py = y0 + (tid >> 4) + ROWS * k;
-    fy[k] = (float)py + 0.5f;
+    fy[k] = (float)(py - y0) + 0.5f;
     inside[k] = px < W && py < H;
     T[k] = 1.0f; C0[k] = 0.0f; C1[k] = 0.0f; C2[k] = 0.0f;
     last[k] = 0;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
     for (int e = tid; e < kBatch; e += NT) {
       if (start + e < n) {
         const uint32_t g = values[rg.x + start + e];
-        stage_entry(xyab, cop, blue, g, s_a[e], s_b[e], s_c[e]);
+        stage_entry(xyab, cop, blue, g, x0, y0, s_a[e], s_b[e], s_c[e]);
       }
     }
     __syncthreads();
@@ -106,16 +106,14 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
       if (!any_live) break;
       const float4 A = s_a[j];
       const float4 B = s_b[j];
-      const float4 BL = s_c[j];
-      const float c2 = BL.x;
-      const float dx = (fx - A.x) - BL.y;
-      float off, t;
-      conic_column(A.z, A.w, BL.z, dx, off, t);
+      const float2 BL = *reinterpret_cast<const float2 *>(&s_c[j]);   // support cut, blue
+      const float dx = fx - A.x;
+      const float t = conic_column(A.w, dx);
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         if (done[k]) continue;
-        const float kq = conic_kq(B.x, off, t, fy[k] - A.y);   // k q
-        if (kq < BL.w) continue;                               // q beyond the support cut
+        const float kq = conic_kq(B.x, A.z, dx, fy[k] - A.y, t);   // k q
+        if (kq < BL.x) continue;                               // q beyond the support cut
         const float alpha = fminf(kAlphaMax, B.y * gauss_weight_scaled(kq));
         if (alpha < kAlphaMin) continue;
         const float Tn = T[k] * (1.0f - alpha);
@@ -126,7 +124,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
         const float wgt = alpha * T[k];
         C0[k] = fmaf(wgt, B.z, C0[k]);
         C1[k] = fmaf(wgt, B.w, C1[k]);
-        C2[k] = fmaf(wgt, c2, C2[k]);
+        C2[k] = fmaf(wgt, BL.y, C2[k]);
         T[k] = Tn;
         last[k] = start + j + 1;
         ++nbl[k];

@@ -9,24 +9,29 @@ namespace flod {
 constexpr int kBatch = 256;                                // list entries staged in LDS at once
 
 // A list entry as both blend kernels stage it in LDS, decoded once per entry instead of in
-// every lane: (mu'x, mu'y, r = b / c, k det / c), (k c, opacity, red, green) and (blue, the
-// bf16 residuals of mu' as floats, the scaled support cut), with k = kExpScale (the completed
-// square of q, see conic_stage).
+// every lane: (mu'x - x0, mu'y - y0, r = b / c, k det / c), (k c, opacity, red, green) and
+// (the scaled support cut, blue, 0, 0), with k = kExpScale (the completed square of q, see
+// conic_stage) and (x0, y0) the tile's corner. The mean relative to the corner is the FP32 mean
+// minus the corner (exact while the two are within a factor of two, otherwise rounded to the
+// difference's ulp) plus the bf16 residual of mu': a pixel's offsets from the mean are then
+// one subtraction from its tile-local centre, (px - x0) + 1/2. Every float4 holds values the
+// decision needs, so that each is read whole before it and a blending pixel finds its colour in
+// registers (a colour read only by blending pixels would make each of them wait for LDS).
 __device__ __forceinline__ void stage_entry(const float4 *xyab, const float4 *cop, const float2 *blue, uint32_t g,
-                                            float4 &a, float4 &b, float4 &c) {
+                                            int x0, int y0, float4 &a, float4 &b, float4 &c) {
   const float4 A = xyab[g];
   const float2 BL = blue[g];
   const uint32_t lo = __float_as_uint(BL.y);
-  b = cop[g];
+  const float4 C = cop[g];
   // support cut of this entry: q beyond min(9, Q_g (1 + 1e-3) + 1e-3), Q_g = 2 ln(255 o), has
   // alpha below 1/255 by a relative 5e-4 (the binning's margin), so cutting there takes the
   // same decisions as q <= 9 and alpha >= 1/255 while whole waves skip the exp more often
-  const float qcut = fminf(kQCut, fmaf(2.0f * logf(255.0f * b.y), 1.001f, 1e-3f));
+  const float qcut = fminf(kQCut, fmaf(2.0f * logf(255.0f * C.y), 1.001f, 1e-3f));
   float r, ek, ck;
-  conic_stage(A.z, A.w, b.x, r, ek, ck);
-  a = make_float4(A.x, A.y, r, ek);
-  b.x = ck;
-  c = make_float4(BL.x, mu_lo_x(lo), mu_lo_y(lo), kExpScale * qcut);
+  conic_stage(A.z, A.w, C.x, r, ek, ck);
+  a = make_float4((A.x - (float)x0) + mu_lo_x(lo), (A.y - (float)y0) + mu_lo_y(lo), r, ek);
+  b = make_float4(ck, C.y, C.z, C.w);
+  c = make_float4(kExpScale * qcut, BL.x, 0.0f, 0.0f);
 }
 
 // Tile orders, longest first (LPT order). The blend kernels' cost per tile varies by orders of

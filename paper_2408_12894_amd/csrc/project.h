@@ -303,8 +303,9 @@ __device__ __forceinline__ float gauss_weight_scaled(float kq) { return __builti
 // from the centre (terms of thousands summing to a q of a few units: about 1e-4 relative
 // error in FP32); here the only cancellation is in v, whose error stays near an ulp of dy.
 // An entry is staged as r = b / c, e = k det / c (det by Kahan's two-product method, from the
-// stored FP32 conic) and c_k = k c. Per column (a lane's pixels share dx): off = loy - r dx and
-// t = e dx^2; per pixel, with t1 = (pixel centre y - mu'y hi): v = t1 - off, k q = c_k v^2 + t.
+// stored FP32 conic) and c_k = k c, with mu' relative to the tile's corner (see stage_entry).
+// Per column (a lane's pixels share dx = x - mu'x): t = e dx^2; per pixel, with dy = y - mu'y:
+// v = dy + r dx (one FMA), k q = c_k v^2 + t.
 // Shared by both blend kernels so that they take the same decisions on the same bits.
 __device__ __forceinline__ void conic_stage(float a, float b, float c, float &r, float &ek, float &ck) {
   const float p = b * b;
@@ -316,13 +317,10 @@ __device__ __forceinline__ void conic_stage(float a, float b, float c, float &r,
   ck = kExpScale * c;
 }
 
-__device__ __forceinline__ void conic_column(float r, float ek, float loy, float dx, float &off, float &t) {
-  off = loy - r * dx;
-  t = (ek * dx) * dx;
-}
+__device__ __forceinline__ float conic_column(float ek, float dx) { return (ek * dx) * dx; }
 
-__device__ __forceinline__ float conic_kq(float ck, float off, float t, float t1) {
-  const float v = t1 - off;
+__device__ __forceinline__ float conic_kq(float ck, float r, float dx, float dy, float t) {
+  const float v = fmaf(r, dx, dy);
   return fmaf(ck * v, v, t);
 }
 
