@@ -13,7 +13,10 @@ Structure
                  is free and its estimated memory fits; requests that arrive while others are on
                  the GPU join as soon as a slot and memory free up (continuous batching). A request
                  whose allocation is refused mid-render is deferred with its exact need; one that
-                 cannot fit even in an empty server is rejected. An executor may return a pending
+                 cannot fit even in an empty server is rejected, and so is a head that does not
+                 fit when nothing is in flight and the server has released what it holds (memory
+                 held outside it, such as results the caller keeps, then leaves no room that any
+                 event could free). An executor may return a pending
                  result; one reaper thread completes those when their device work has finished.
   GpuExecutor    one libflod Renderer and one HIP stream per slot (slots' kernels overlap on the
                  device); workspace memory comes from torch's caching allocator through the
@@ -324,7 +327,18 @@ class Scheduler:
                         release_cached()
                     room = self.ledger.free() + self.ex.slot_bytes(slot)
                     if room < job.need or not self.ledger.try_take(job.reserve):
-                        return
+                        if busy:
+                            return          # a request in flight will free memory
+                        # nothing in flight, and what the server holds has been released: memory
+                        # held outside it (results the caller keeps) leaves the head no room,
+                        # and no event here will make room; waiting would never end
+                        waiting.popleft()
+                        rec = out[job.req.rid]
+                        rec.status = "rejected"
+                        rec.deferrals = job.deferrals
+                        rec.done = time.perf_counter() - t0
+                        state["finished"] += 1
+                        continue
                 job.promise[0] = job.reserve
                 free_slots.pop()
                 waiting.popleft()

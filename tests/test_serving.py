@@ -232,3 +232,36 @@ def test_head_waits_for_cached_memory_to_be_released():
     recs = serving.Scheduler(ex, 1, ledger).serve(reqs)
     assert all(r.status == "ok" for r in recs)
     assert ex.releases > 0 and ledger.peak <= ledger.budget
+
+
+class FakeKeepingExecutor(FakeExecutor):
+    """A finished request's result keeps `keep` bytes on the device for as long as the caller
+    holds it (the caller allocated it, so the budget check does not apply to it): memory that
+    nothing inside the server will free."""
+
+    def __init__(self, n_slots, ledger, keep):
+        super().__init__(n_slots, ledger)
+        self.keep = keep
+
+    def run(self, slot, req, promise=None):
+        out = super().run(slot, req, promise)
+        with self.ledger.lock:
+            self.ledger.held += self.keep
+        return out
+
+
+@pytest.mark.timeout(60)
+def test_head_that_cannot_fit_with_nothing_in_flight_is_rejected():
+    """Memory held outside the server can leave a deferred head no room even though it fit an
+    idle server when serving began: with nothing in flight nothing will make room, so the head
+    is rejected instead of waited for (waiting would never end)."""
+    # budget 5000, resident 1000: 4000 for requests. Workspaces 1500, 2000, 2500, 3000, ... and
+    # 600 kept per finished request: the fourth request's 3000 + 100 cannot fit beside the
+    # 1800 kept, though it would fit an idle server
+    reqs = [FakeReq(i, 0.001 * i, 0.002, 1500 + 500 * i, frame=100) for i in range(6)]
+    ledger = serving.BudgetLedger(5_000, 1_000)
+    ex = FakeKeepingExecutor(1, ledger, keep=600)
+    recs = serving.Scheduler(ex, 1, ledger).serve(reqs)
+    assert [r.status for r in recs[:3]] == ["ok", "ok", "ok"]
+    assert all(r.status == "rejected" for r in recs[3:])
+    assert recs[3].deferrals >= 1
