@@ -57,7 +57,7 @@ enum BufId {
   B_XYAB, B_COP, B_BLUE, B_DEPTH, B_BIN, B_TILES, B_BLOCKVIS, B_PREFIX,
   B_DKEY0, B_DKEY1, B_DVAL0, B_DVAL1, B_TBSUM, B_TPREFIX,
   B_TKEY0, B_TKEY1, B_TVAL0, B_TVAL1, B_HIST, B_SCAN, B_TOT, B_RANGES, B_COUNTERS,
-  B_G2D, B_SSIM, B_TAKEN, B_TILE_TAKEN, B_TILE_ORDER, B_COUNT
+  B_G2D, B_SSIM, B_TAKEN, B_TILE_TAKEN, B_TILE_ORDER, B_STILES, B_COUNT
 };
 
 struct Saved {
@@ -346,6 +346,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   need(B_DVAL1, 4 * (size_t)N);
   need(B_TBSUM, 4 * (size_t)nb);
   need(B_TPREFIX, 8 * (size_t)nb);
+  need(B_STILES, 4 * (size_t)N);
   need(B_HIST, hist);
   need(B_SCAN, hist);
   need(B_TOT, 4 * (size_t)kRadix);
@@ -390,23 +391,22 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
                            nullptr, nb, s) != hipSuccess)
       return FLOD_ERR_DEVICE;
     if (launch_compact(o.tiles, o.depth, N, P<unsigned long long>(c, B_PREFIX), P<uint32_t>(c, B_DKEY0),
-                       P<uint32_t>(c, B_DVAL0), s) != hipSuccess)
+                       P<uint32_t>(c, B_DVAL0), P<uint32_t>(c, B_TBSUM), s) != hipSuccess)
       return FLOD_ERR_DEVICE;
     tm.end();
     tm.begin(FLOD_STAGE_DEPTH_SORT);
     uint32_t *dk[2] = {P<uint32_t>(c, B_DKEY0), P<uint32_t>(c, B_DKEY1)};
     uint32_t *dv[2] = {P<uint32_t>(c, B_DVAL0), P<uint32_t>(c, B_DVAL1)};
+    // the last pass also writes the tile counts in depth order and their sums per workgroup of
+    // the emission (zeroed by the compaction)
+    sorted_tiles = P<uint32_t>(c, B_STILES);
     if (launch_radix_sort(dk, dv, counters + kCntVisible, N, 32, P<uint32_t>(c, B_HIST), P<uint32_t>(c, B_SCAN),
-                          P<uint32_t>(c, B_TOT), &dres, s) != hipSuccess)
+                          P<uint32_t>(c, B_TOT), &dres, s, o.tiles, sorted_tiles, P<uint32_t>(c, B_TBSUM)) !=
+        hipSuccess)
       return FLOD_ERR_DEVICE;
     tm.end();
     tm.begin(FLOD_STAGE_OFFSETS);
-    // tile counts in depth order go to the depth sort's spare key buffer, for the emission
-    sorted_tiles = dk[dres ^ 1];
-    if (launch_tile_counts(dv[dres], counters + kCntVisible, N, o.tiles, P<uint32_t>(c, B_TBSUM), sorted_tiles,
-                           s) != hipSuccess ||
-        offsets(speculate ? cap : 0xFFFFFFFEll, direct) != hipSuccess)
-      return FLOD_ERR_DEVICE;
+    if (offsets(speculate ? cap : 0xFFFFFFFEll, direct) != hipSuccess) return FLOD_ERR_DEVICE;
     // the count read-back, [visible u32 | guarded K u32], [K u64]: written by the scan itself
     // (direct), else copied
     if (!direct && (hipMemcpyAsync(c->host_counters, counters, 16, hipMemcpyDeviceToHost, s) != hipSuccess ||

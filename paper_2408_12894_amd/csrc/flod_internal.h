@@ -107,17 +107,19 @@ hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int i
                               unsigned long long *total64, int max_blocks, hipStream_t s,
                               unsigned long long cap32 = 0xFFFFFFFFull, unsigned long long *host_out = nullptr,
                               uint32_t host_seq = 0);
+// zero_sums (or null): one word per workgroup of 256 candidates, zeroed for the depth sort's
+// tile-count sums
 hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
                           const unsigned long long *prefix, uint32_t *keys, uint32_t *vals,
-                          hipStream_t s);
+                          uint32_t *zero_sums, hipStream_t s);
 int radix_items(int64_t n_max);        // keys per thread the radix sort of n_max keys uses
 size_t radix_hist_bytes(int64_t n_max);  // bytes of each of its hist and scan arrays
+// With tiles_of (tile count per value), the last pass also writes tiles_out[pos] =
+// tiles_of[sorted value] and adds the counts into block_sum[pos / 256] (zeroed beforehand).
 hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr,
                              int64_t n_max, int bits, uint32_t *hist, uint32_t *scan,
-                             uint32_t *tot, int *result_buf, hipStream_t s);
-hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_max,
-                              const uint32_t *tiles, uint32_t *block_sum, uint32_t *sorted_tiles,
-                              hipStream_t s);
+                             uint32_t *tot, int *result_buf, hipStream_t s, const uint32_t *tiles_of = nullptr,
+                             uint32_t *tiles_out = nullptr, uint32_t *block_sum = nullptr);
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const uint32_t *k_ptr,
                        int64_t n_max, int64_t k_max, const uint32_t *sorted_tiles, const float4 *bin,
                        const unsigned long long *prefix, int tiles_x, int tiles_y, uint32_t *tile_ids,

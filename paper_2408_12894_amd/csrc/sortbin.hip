@@ -129,8 +129,10 @@ hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int i
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
                                                     const unsigned long long *prefix, uint32_t *keys,
-                                                    uint32_t *vals) {
+                                                    uint32_t *vals, uint32_t *zero_sums) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // one word per workgroup of the sums the depth sort's last pass accumulates (see k_rs_scatter)
+  if (zero_sums && threadIdx.x == 0) zero_sums[blockIdx.x] = 0u;
   const bool v = (i < n) && tiles[i] != 0u;
   uint32_t tot;
   uint32_t ex = block_excl_scan(v ? 1u : 0u, &tot);
@@ -142,10 +144,11 @@ __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t *tiles, const
 }
 
 hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
-                          const unsigned long long *prefix, uint32_t *keys, uint32_t *vals, hipStream_t s) {
+                          const unsigned long long *prefix, uint32_t *keys, uint32_t *vals, uint32_t *zero_sums,
+                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_compact, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tiles, depth,
-                     n, prefix, keys, vals);
+                     n, prefix, keys, vals, zero_sums);
   return hipGetLastError();
 }
 
@@ -172,7 +175,9 @@ static unsigned radix_grid(int nb_max) {
 }
 // All of a workgroup's keys are loaded before the first LDS update, so its loads are in
 // flight together. The count n is read first: grids are sized for the buffers' capacity,
-// which can far exceed n, and workgroups past n must not read their keys.
+// which can far exceed n, and workgroups past n leave without reading their keys (loading
+// keys and values together with n, bounded by the capacity, here and in the scatter made the
+// tile sort at 1080p / 1M 10% slower).
 template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const uint32_t *n_ptr, int shift,
                                                     uint32_t *hist, int stride) {
@@ -249,13 +254,28 @@ __global__ __launch_bounds__(kBlock) void k_rs_scan(const uint32_t *n_ptr, const
 // across rounds (a wave's LDS accesses complete in program order, so no barrier is needed
 // between rounds); one barrier then turns the per-wave counts into offsets, keys are placed
 // in LDS in digit order, and each digit's run is written out contiguously.
-template <int ITEMS>
+//
+// With TILES (the last pass of the depth sort) the scatter also writes, at each output
+// position, the tile count of the Gaussian its value names (tiles_out[pos] = tiles_of[val]),
+// and adds the counts into sums over 256 consecutive output positions (block_sum[pos / 256],
+// zeroed beforehand): the emission's per-workgroup counts, in depth order. Output positions
+// grow with the local index across the workgroup (digit runs in digit order, each at its
+// digit's base), so the lanes of one write round that share a 256-block are consecutive: a
+// segmented sum over the wave leaves one atomic per segment.
+struct TileTail {
+  const uint32_t *tiles_of;   // tile count per Gaussian (indexed by value)
+  uint32_t *tiles_out;        // tile count per sorted position
+  uint32_t *block_sum;        // per 256 sorted positions
+};
+
+template <int ITEMS, bool TILES>
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restrict__ keys_in,
                                                        const uint32_t *__restrict__ vals_in,
                                                        uint32_t *__restrict__ keys_out,
                                                        uint32_t *__restrict__ vals_out, const uint32_t *n_ptr,
-                                                       int shift, const uint32_t *hist, const uint32_t *scan,
-                                                       const uint32_t *tot, int stride) {
+                                                       int shift, const uint32_t *hist,
+                                                       const uint32_t *scan, const uint32_t *tot, int stride,
+                                                       TileTail tail) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   constexpr int WAVES = kBlock / 64;
   constexpr uint32_t WTILE = 64 * ITEMS;
@@ -264,8 +284,11 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
   __shared__ uint32_t s_goff[kRadix];
   __shared__ uint32_t s_wcnt[WAVES][kRadix];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  // the count first (grids are sized for the capacity); then the tile's keys and values,
-  // loaded together with the digit offsets below, so that their latencies overlap
+  // the count first (grids are sized for the capacity, which can far exceed it); then the
+  // tile's keys and values, loaded together with the digit offsets below, so that their
+  // latencies overlap (the offsets issued ahead of the count, with the scan's first counts
+  // likewise, made the tile sort at 1080p / 1M 8% slower: a wait for the count then waits for
+  // the scattered offset rows too)
   const uint32_t n = *n_ptr;
   const uint32_t nb = (n + TILE - 1) / TILE;
   const uint32_t b = radix_block(blockIdx.x);
@@ -332,12 +355,43 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
     }
   }
   __syncthreads();
-  for (uint32_t li = tid; li < count; li += kBlock) {
-    const uint32_t key = s_keys[li];
-    const uint32_t d = (key >> shift) & (kRadix - 1);
-    const uint32_t pos = s_goff[d] + li;
-    keys_out[pos] = key;
-    vals_out[pos] = s_vals[li];
+  if (!TILES) {
+    for (uint32_t li = tid; li < count; li += kBlock) {
+      const uint32_t key = s_keys[li];
+      const uint32_t d = (key >> shift) & (kRadix - 1);
+      const uint32_t pos = s_goff[d] + li;
+      keys_out[pos] = key;
+      vals_out[pos] = s_vals[li];
+    }
+  } else {
+    // whole rounds of the workgroup, so that every lane takes part in the segmented sum (the
+    // tile count gathered in each round: gathering all of a thread's counts before the first
+    // round measured 3.5 us slower at 1080p / 1M)
+    for (uint32_t l0 = 0; l0 < count; l0 += kBlock) {
+      const uint32_t li = l0 + tid;
+      const bool valid = li < count;
+      uint32_t c = 0u, seg = 0xFFFFFFFFu;
+      if (valid) {
+        const uint32_t key = s_keys[li];
+        const uint32_t v = s_vals[li];
+        const uint32_t pos = s_goff[(key >> shift) & (kRadix - 1)] + li;
+        keys_out[pos] = key;
+        vals_out[pos] = v;
+        c = tail.tiles_of[v];
+        tail.tiles_out[pos] = c;
+        seg = pos / (uint32_t)kBlock;
+      }
+      // inclusive sums over runs of equal seg (seg does not decrease over the lanes; invalid
+      // lanes, all past the valid ones, form a run of their own)
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t cu = __shfl_up(c, o, 64);
+        const uint32_t su = __shfl_up(seg, o, 64);
+        if (lane >= o && su == seg) c += cu;
+      }
+      const uint32_t seg_next = __shfl_down(seg, 1, 64);
+      if (valid && (lane == 63 || seg_next != seg) && c != 0u) atomicAdd(&tail.block_sum[seg], c);
+    }
   }
 }
 
@@ -357,20 +411,32 @@ size_t radix_hist_bytes(int64_t n_max) { return 4 * (size_t)kRadix * (size_t)rad
 // Sort (keys, vals) by the low `bits` bits of the keys; stable. Ping-pongs between
 // buffers [0] and [1]; *result_buf receives the index holding the result. hist and scan
 // hold radix_hist_bytes(n_max) each (16-byte aligned). Workgroups take 2048 keys below
-// kRadixBigSort keys of capacity, 3072 up to kRadixHugeSort and 4096 beyond.
+// kRadixBigSort keys of capacity, 3072 up to kRadixHugeSort and 4096 beyond. With a tail, the
+// last pass also writes the values' tile counts in sorted order and their 256-position sums
+// (see k_rs_scatter).
 template <int ITEMS>
 static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr, int64_t n_max, int bits,
-                         uint32_t *hist, uint32_t *scan, uint32_t *tot, int *cur_out, hipStream_t s) {
+                         uint32_t *hist, uint32_t *scan, uint32_t *tot, int *cur_out, const TileTail *tail,
+                         hipStream_t s) {
   constexpr int TILE = kBlock * ITEMS;
   const int nb_max = (int)((n_max + TILE - 1) / TILE);
   const int stride = (int)radix_stride(n_max);
+  const TileTail none{nullptr, nullptr, nullptr};
   int cur = 0;
   for (int shift = 0; shift < bits; shift += kRadixBits) {
+    const bool last = shift + kRadixBits >= bits;
     hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], n_ptr, shift, hist,
                        stride);
     hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, s, n_ptr, hist, scan, tot, stride, TILE);
-    hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
-                       vals[cur ^ 1], n_ptr, shift, hist, scan, tot, stride);
+    if (last && tail) {
+      auto kernel = k_rs_scatter<ITEMS, true>;
+      hipLaunchKernelGGL(kernel, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], vals[cur],
+                         keys[cur ^ 1], vals[cur ^ 1], n_ptr, shift, hist, scan, tot, stride, *tail);
+    } else {
+      auto kernel = k_rs_scatter<ITEMS, false>;
+      hipLaunchKernelGGL(kernel, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], vals[cur],
+                         keys[cur ^ 1], vals[cur ^ 1], n_ptr, shift, hist, scan, tot, stride, none);
+    }
     cur ^= 1;
   }
   *cur_out = cur;
@@ -378,39 +444,16 @@ static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n
 
 hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr, int64_t n_max,
                              int bits, uint32_t *hist, uint32_t *scan, uint32_t *tot, int *result_buf,
-                             hipStream_t s) {
+                             hipStream_t s, const uint32_t *tiles_of, uint32_t *tiles_out, uint32_t *block_sum) {
   *result_buf = 0;
   if (n_max <= 0) return hipSuccess;
+  const TileTail t{tiles_of, tiles_out, block_sum};
+  const TileTail *tail = tiles_of ? &t : nullptr;
   switch (radix_items(n_max)) {
-    case kSortItemsHuge: radix_passes<kSortItemsHuge>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, s); break;
-    case kSortItems: radix_passes<kSortItems>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, s); break;
-    default: radix_passes<kSortItemsSmall>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, s); break;
+    case kSortItemsHuge: radix_passes<kSortItemsHuge>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, tail, s); break;
+    case kSortItems: radix_passes<kSortItems>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, tail, s); break;
+    default: radix_passes<kSortItemsSmall>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, tail, s); break;
   }
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------------------
-// Tiles touched in depth order: per-workgroup sums over the sorted visible Gaussians.
-// ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr,
-                                                        const uint32_t *tiles, uint32_t *block_sum,
-                                                        uint32_t *sorted_tiles) {
-  const uint32_t n = *n_ptr;
-  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  if (blockIdx.x * kBlock >= n) return;
-  const uint32_t c = (j < n) ? tiles[sorted_ids[j]] : 0u;
-  if (j < n) sorted_tiles[j] = c;
-  uint32_t tot;
-  block_excl_scan(c, &tot);
-  if (threadIdx.x == 0) block_sum[blockIdx.x] = tot;
-}
-
-hipError_t launch_tile_counts(const uint32_t *sorted_ids, const uint32_t *n_ptr, int64_t n_max,
-                              const uint32_t *tiles, uint32_t *block_sum, uint32_t *sorted_tiles,
-                              hipStream_t s) {
-  if (n_max <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)((n_max + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     sorted_ids, n_ptr, tiles, block_sum, sorted_tiles);
   return hipGetLastError();
 }
 
