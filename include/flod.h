@@ -310,7 +310,8 @@ typedef struct {
 flod_status flod_ctx_stats(const flod_ctx *ctx, flod_stats *out);
 
 /* Device pointers to the last render's intermediate buffers, owned by ctx, valid until
-   the next call on ctx. For inspection and tests. */
+   the next call on ctx. For inspection and tests. May run one kernel and wait for it (see
+   grad2d); FLOD_ERR_DEVICE if that fails. */
 typedef struct {
   const uint32_t *tile_ids;     /* [n_instances] tile id of each sorted instance          */
   const uint32_t *values;       /* [n_instances] Gaussian (global) index, sorted by
@@ -329,7 +330,11 @@ typedef struct {
   const float *grad2d;          /* [n_candidates, 9] after flod_render_backward: per
                                    Gaussian dL/d(mu'x, mu'y, conic a, b, c, opacity, red,
                                    green, blue), with b the off-diagonal conic entry; NULL
-                                   before a backward                                       */
+                                   before a backward. The backward leaves moment sums there
+                                   (the conic and opacity factors are applied per Gaussian
+                                   in its last step); the first view after it applies them
+                                   in place with the stored FP32 conic and opacity (one
+                                   kernel on the stream of the last call, waited for)      */
   const uint8_t *taken;         /* [n_instances] 1 where the forward blended the sorted
                                    instance into some pixel of its tile (state the backward
                                    reads: it walks only these entries)                     */

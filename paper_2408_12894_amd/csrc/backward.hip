@@ -11,9 +11,11 @@
 // where the normalised colour behind entry i follows the convex update
 //   Shat_{i-1} = alpha_i c_i + (1 - alpha_i) Shat_i,  Shat_last = bg,
 // which avoids the cancellation between T_i c_i and S_i / (1 - alpha_i) in FP32.
-// Then alpha -> (opacity, q) unless the 0.99 clamp is active, q -> (conic, mu').
-// Per entry the 9 gradient components are reduced across the wave through LDS and nine lanes
-// issue one FP32 atomic each per (tile, Gaussian).
+// Then alpha -> (opacity, q) unless the 0.99 clamp is active, q -> (conic, mu'): per entry the
+// wave sums nine per-Gaussian values through LDS (the moments of e = dL/dalpha G over its
+// pixels, e dx, e dy, e dx^2, e dx dy, e dy^2 and e, and the colour gradient) and nine lanes
+// issue one FP32 atomic each per (tile, Gaussian); the conic and opacity factors that turn the
+// moments into dL/d(mu', conic, opacity) are applied per Gaussian in the preprocess backward.
 //
 // Preprocess backward: one thread per Gaussian, recomputing the forward projection (FP64)
 // and applying the chain rule in FP64 to the mean (through mu', the EWA Jacobian and the SH view
@@ -33,9 +35,9 @@ constexpr int kBwdPix = FLOD_BWD_PIX;   // pixels per thread: 4 = one wave64 per
 #ifndef FLOD_BWD_BATCH
 #define FLOD_BWD_BATCH 64
 #endif
-// List entries staged in LDS per batch: 64 x 72 B = 4.5 KB per one-wave workgroup, plus the
-// 2.3 KB of the per-entry reduction, so LDS does not cap the waves a CU holds below what the
-// registers allow (82 VGPRs: 5 waves per SIMD). At 1080p / 1M, 128-entry batches (9.3 KB per
+// List entries staged in LDS per batch: 64 x 56 B = 3.5 KB per one-wave workgroup, plus the
+// 3 KB of the per-entry reduction, so LDS does not cap the waves a CU holds below what the
+// registers allow. At 1080p / 1M (with 72-byte entries then), 128-entry batches (9.3 KB per
 // wave) took 0.268 ms, 96 0.241 ms and 64 0.232 ms.
 constexpr int kBwdBatch = FLOD_BWD_BATCH;
 
@@ -116,7 +118,6 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   __shared__ float4 s_a[kBwdBatch];
   __shared__ float4 s_b[kBwdBatch];
   __shared__ float4 s_c[kBwdBatch];
-  __shared__ float4 s_d[kBwdBatch];
   __shared__ uint32_t s_id[kBwdBatch];
   __shared__ int s_pos[kBwdBatch];
   __shared__ int s_max[WAVES];
@@ -193,8 +194,6 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         s_id[idx] = g;
         s_pos[idx] = start + e;
         stage_entry(xyab, cop, blue, g, x0, y0, s_a[idx], s_b[idx], s_c[idx]);
-        const float4 A = xyab[g];
-        s_d[idx] = make_float4(2.0f * A.z, 2.0f * A.w, 2.0f * cop[g].x, -0.5f * cop[g].y);
       }
     }
     __syncthreads();
@@ -221,10 +220,11 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       float gr[kG2d];
       gr[6] = gr[7] = gr[8] = 0.0f;
       // with alpha = o G below the clamp, dalpha/do = G and dalpha/dq = -o G / 2, so one sum
-      // e = dL/dalpha G per pixel serves both: dL/do = sum e and dL/dq = -(o / 2) e. A lane's
-      // pixels share their column, so the q-derivatives need only E0 = sum e, E1 = sum e dy
-      // and E2 = sum e dy^2 over them: with S = -(o / 2) E, dL/d(a, b, c) = (dx^2 S0, 2 dx S1,
-      // S2) and dL/dmu' = -2 (a dx S0 + b S1, b dx S0 + c S1)
+      // e = dL/dalpha G per pixel serves both: dL/do = sum e and dL/dq = -(o / 2) e. With
+      // q = a dx^2 + 2 b dx dy + c dy^2 every q-derivative is a moment of e times a factor of
+      // the Gaussian: dL/d(a, b, c) = -(o / 2) (sum e dx^2, 2 sum e dx dy, sum e dy^2) and
+      // dL/dmu' = o (a sum e dx + b sum e dy, b sum e dx + c sum e dy). A lane's pixels share
+      // their column, so it needs only E0 = sum e, E1 = sum e dy and E2 = sum e dy^2 over them
       float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
@@ -244,15 +244,15 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
         E1 += ey;
         E2 = fmaf(ey, dy, E2);
       }
-      const float4 D = s_d[jl];   // 2a, 2b, 2c, -o/2 (the unscaled conic)
-      const float S0 = D.w * E0, S1 = D.w * E1;
+      // the moments sum e dx, e dy, e dx^2, e dx dy, e dy^2, e over the lane's pixels (dx is
+      // the column's): the conic and opacity factors are the Gaussian's own and are applied
+      // once per Gaussian after all its tiles (k_preprocess_bwd)
+      gr[0] = dx * E0;
+      gr[1] = E1;
+      gr[2] = dx * gr[0];
+      gr[3] = dx * E1;
+      gr[4] = E2;
       gr[5] = E0;
-      gr[2] = dx * dx * S0;
-      gr[3] = 2.0f * dx * S1;
-      gr[4] = D.w * E2;
-      // dL/dmu' = -2 (a dx S0 + b S1, b dx S0 + c S1)
-      gr[0] = -(D.x * dx * S0 + D.y * S1);
-      gr[1] = -(D.y * dx * S0 + D.z * S1);
       {
         // the nine components summed over the wave: each lane writes its nine values to LDS
         // component-major. LDS form: 36 lanes each add 16 values of one component (four float4
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
     for (int k = 0; k < 12; ++k) reinterpret_cast<float4 *>(dsh)[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     return;
   }
-  double g[kG2d];
+  double g[kG2d];   // the blend backward's sums (moments of e, colour), turned into gradients below
 #pragma unroll
   for (int c = 0; c < kG2d; ++c) g[c] = (double)g2d[i * kG2d + c];
   const float m0 = L.means[i * 3 + 0], m1 = L.means[i * 3 + 1], m2 = L.means[i * 3 + 2];
@@ -367,7 +367,18 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
 
   // conic -> dilated 2D covariance (a, b; b, c); FP64 because det can be far below a c
   const double a = pr.a, b = pr.b, c = pr.c;
-  const double id2 = 1.0 / (pr.det * pr.det);
+  const double idet = 1.0 / pr.det;
+  const double id2 = idet * idet;
+  {
+    // moments -> dL/d(mu', conic a, b, c) with the conic (c, -b, a) / det and the opacity
+    const double od = (double)o, ca = c * idet, cb = -b * idet, cc = a * idet;
+    const double m_dx = g[0], m_dy = g[1];
+    g[0] = od * (ca * m_dx + cb * m_dy);
+    g[1] = od * (cb * m_dx + cc * m_dy);
+    g[2] = -0.5 * od * g[2];
+    g[3] = -od * g[3];
+    g[4] = -0.5 * od * g[4];
+  }
   const double gA = g[2], gB = g[3], gC = g[4];
   const double ga = (-c * c * gA + b * c * gB - b * b * gC) * id2;
   const double gb = (2.0 * b * c * gA - (a * c + b * b) * gB + 2.0 * a * b * gC) * id2;
@@ -519,6 +530,32 @@ hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, cons
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, tiles,
                      g2d, g);
+  return hipGetLastError();
+}
+
+// The blend backward's per-Gaussian moment sums turned into dL/d(mu', conic a, b, c) in place,
+// with the stored FP32 conic and opacity (for inspection: the preprocess backward applies the same
+// factors with its FP64 conic).
+__global__ __launch_bounds__(kBlock) void k_g2d_from_moments(int64_t n, const uint32_t *__restrict__ tiles,
+                                                             const float4 *__restrict__ xyab,
+                                                             const float4 *__restrict__ cop, float *__restrict__ g2d) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n || tiles[i] == 0u) return;   // not rendered: zero sums, and no conic stored
+  float *g = g2d + i * kG2d;
+  const double a = xyab[i].z, b = xyab[i].w, c = cop[i].x, o = cop[i].y;
+  const double m_dx = g[0], m_dy = g[1];
+  g[0] = (float)(o * (a * m_dx + b * m_dy));
+  g[1] = (float)(o * (b * m_dx + c * m_dy));
+  g[2] = (float)(-0.5 * o * (double)g[2]);
+  g[3] = (float)(-o * (double)g[3]);
+  g[4] = (float)(-0.5 * o * (double)g[4]);
+}
+
+hipError_t launch_g2d_from_moments(int64_t n, const uint32_t *tiles, const float4 *xyab, const float4 *cop,
+                                   float *g2d, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_g2d_from_moments, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, tiles,
+                     xyab, cop, g2d);
   return hipGetLastError();
 }
 

@@ -73,6 +73,7 @@ struct Saved {
   int sorted_keys = 0;
   int depth_buf = 0;
   bool has_grad2d = false;
+  bool grad2d_moments = false;   // B_G2D still holds the backward's moment sums (see flod_ctx_view)
 };
 
 }  // namespace
@@ -1062,6 +1063,7 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   if (launch_preprocess_bwd(p, P<uint32_t>(ctx, B_TILES), g2d, *grads, s) != hipSuccess) return FLOD_ERR_DEVICE;
   tm.end();
   ctx->saved.has_grad2d = true;
+  ctx->saved.grad2d_moments = true;
   return FLOD_OK;
 }
 
@@ -1086,6 +1088,15 @@ flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out) {
   out->xy_conic = P<float>(c, B_XYAB);
   out->conic_c_opacity_rg = P<float>(c, B_COP);
   out->blue = P<float>(c, B_BLUE);
+  if (sv.has_grad2d && sv.grad2d_moments) {
+    // the first view after a backward turns its moment sums into the gradient, in place
+    if (hipSetDevice(ctx->device) != hipSuccess ||
+        launch_g2d_from_moments(sv.level.n, P<uint32_t>(c, B_TILES), P<float4>(c, B_XYAB), P<float4>(c, B_COP),
+                                P<float>(c, B_G2D), c->last_stream) != hipSuccess ||
+        hipStreamSynchronize(c->last_stream) != hipSuccess)
+      return FLOD_ERR_DEVICE;
+    c->saved.grad2d_moments = false;
+  }
   out->grad2d = sv.has_grad2d ? P<float>(c, B_G2D) : nullptr;
   out->taken = P<uint8_t>(c, B_TAKEN);
   out->tile_taken = P<uint32_t>(c, B_TILE_TAKEN);

@@ -139,6 +139,9 @@ hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const f
                             hipEvent_t ev_stop = nullptr);
 hipError_t launch_tile_order_by_length(const uint2 *ranges, int n_tiles, uint32_t *order, hipStream_t s);
 hipError_t launch_tile_order_by_count(const uint32_t *count, int n_tiles, uint32_t *order, hipStream_t s);
+// The blend backward's per-Gaussian moment sums into dL/d(mu', conic) in place (inspection).
+hipError_t launch_g2d_from_moments(int64_t n, const uint32_t *tiles, const float4 *xyab, const float4 *cop,
+                                   float *g2d, hipStream_t s);
 hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, const float *g2d,
                                  const flod_grads &g, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
