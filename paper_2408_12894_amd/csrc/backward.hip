@@ -12,7 +12,7 @@
 //   Shat_{i-1} = alpha_i c_i + (1 - alpha_i) Shat_i,  Shat_last = bg,
 // which avoids the cancellation between T_i c_i and S_i / (1 - alpha_i) in FP32.
 // Then alpha -> (opacity, q) unless the 0.99 clamp is active, q -> (conic, mu'): per entry the
-// wave sums nine per-Gaussian values through LDS (the moments of e = dL/dalpha G over its
+// wave sums nine per-Gaussian values through LDS (the moments of e = dL/dalpha alpha over its
 // pixels, e dx, e dy, e dx^2, e dx dy, e dy^2 and e, and the colour gradient) and nine lanes
 // issue one FP32 atomic each per (tile, Gaussian); the conic and opacity factors that turn the
 // moments into dL/d(mu', conic, opacity) are applied per Gaussian in the preprocess backward.
@@ -22,6 +22,8 @@
 // direction), log-scales (eq. 4: times exp(s_opt); s_min gets no gradient), quaternion
 // (through the normalisation), opacity logit (times o (1 - o)) and SH coefficients.
 #include <hip/hip_ext.h>
+
+#include <type_traits>
 
 #include "blend_common.h"
 
@@ -55,44 +57,33 @@ __device__ __forceinline__ float row_sum16(float v) {
 constexpr int kLdsRound2MinTiles = 6144;
 
 // The per-pixel decision of one entry, repeating the forward's bit for bit: the pixel takes
-// part when its walk has reached the entry, q is inside the support cut and alpha reaches the
-// floor. A pixel that does not take part gets alpha 0 and G 0: it then adds exact zeros, keeps
-// its T (T / (1 - 0) = T) and its V. G is also 0 where the 0.99 clamp is active (alpha does not
-// depend on opacity or q there). The clamp can act only for opacities near 0.99: q >= 0 gives
-// kq <= 0 and G = 2^kq <= 1 (to within an ulp of the hardware exp2), so for o <= 0.98 the
-// product o G stays below 0.99 and alpha is o G itself.
+// part when its walk has reached the entry and l = k q + log2 o reaches the entry's threshold
+// (q <= 9 and alpha >= 1/255). A pixel that does not take part gets alpha 0 and a weight of 0:
+// it then adds exact zeros, keeps its T (T / (1 - 0) = T) and its V. The weight gmv is the
+// unclamped alpha o G, and 0 where the 0.99 clamp is active (alpha does not depend on opacity
+// or q there); entries whose opacity cannot reach the clamp (see stage_entry) skip its test.
 template <int PPT, bool CLAMP>
 __device__ __forceinline__ bool decide(const float (&fy)[PPT], const int (&last)[PPT], int jpos, float my, float r,
-                                       float dx, float ck, float op, float t, float (&dyv)[PPT],
+                                       float dx, float ck, float thr, float t, float (&dyv)[PPT],
                                        float (&aev)[PPT], float (&gmv)[PPT]) {
   bool contrib = false;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const float dy = fy[k] - my;
     dyv[k] = dy;
-    const float kq = conic_kq(ck, r, dx, dy, t);   // k q
-    const float G = gauss_weight_scaled(kq);
-    const float a0 = op * G;
+    const float l = conic_kq(ck, r, dx, dy, t);   // k q + log2 o
+    const float a0 = alpha_from_log2(l);          // o G
+    const bool ok = jpos < last[k] && l >= thr;
     if (CLAMP) {
-      const float al = fminf(kAlphaMax, a0);
-      const bool ok = jpos < last[k] && kq >= kQCutScaled && al >= kAlphaMin;
-      aev[k] = ok ? al : 0.0f;
-      gmv[k] = (ok && a0 <= kAlphaMax) ? G : 0.0f;
-      contrib = contrib || ok;
+      aev[k] = ok ? fminf(kAlphaMax, a0) : 0.0f;
+      gmv[k] = (ok && a0 <= kAlphaMax) ? a0 : 0.0f;
     } else {
-      const bool ok = jpos < last[k] && kq >= kQCutScaled && a0 >= kAlphaMin;
-      aev[k] = ok ? a0 : 0.0f;
-      gmv[k] = ok ? G : 0.0f;
-      contrib = contrib || ok;
+      aev[k] = ok ? a0 : 0.0f;   // gmv: alpha itself (the caller reads aev)
     }
+    contrib = contrib || ok;
   }
   return contrib;
 }
-
-// Opacity above which an entry takes the decision with the clamp (bits of a positive float,
-// compared as integers on the scalar unit).
-constexpr float kClampOpacity = 0.98f;
-constexpr int kClampOpacityBits = __builtin_bit_cast(int, kClampOpacity);
 
 // Per-entry reduction through LDS: component c of lane l at s_red[c * kRedStride + l]. The
 // stride of 80 floats puts the four components a read instruction of the first round touches
@@ -201,100 +192,104 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       const int jpos = s_pos[jl];
       const float4 A = s_a[jl];
       const float4 B = s_b[jl];
-      const float blue = s_c[jl].y;
+      const float4 BL = s_c[jl];   // threshold on l, blue, clamp flag
       const float dx = fx - A.x;
-      const float t = conic_column(A.w, dx);
+      const float t = conic_column(A.w, dx, B.y);
       // first only what decides whether a pixel takes part; the transmittance recovery and
-      // the gradient run when some pixel of the wave does. The opacity is the same in every
-      // lane, so the branch is uniform
-      float dyv[PPT], aev[PPT], gmv[PPT];
-      const bool contrib =
-          __builtin_amdgcn_readfirstlane(__float_as_int(B.y)) > kClampOpacityBits
-              ? decide<PPT, true>(fy, last, jpos, A.y, A.z, dx, B.x, B.y, t, dyv, aev, gmv)
-              : decide<PPT, false>(fy, last, jpos, A.y, A.z, dx, B.x, B.y, t, dyv, aev, gmv);
-      if (!__any(contrib)) continue;
-      {
-      // the gradient arithmetic may contract into FMAs (the decision above must not: it
-      // repeats the forward's, bit for bit)
+      // the gradient run when some pixel of the wave does. The whole entry is instantiated with
+      // and without the clamp's test (the flag is the same in every lane: a uniform branch), so
+      // that without it alpha itself is the weight of the gradient
+      auto entry = [&](auto clamp_tag) {
+        constexpr bool CLAMP = decltype(clamp_tag)::value;
+        float dyv[PPT], aev[PPT], gmv[PPT];
+        if (!__any(decide<PPT, CLAMP>(fy, last, jpos, A.y, A.z, dx, B.x, BL.x, t, dyv, aev, gmv))) return;
+        {
+        // the gradient arithmetic may contract into FMAs (the decision above must not: it
+        // repeats the forward's, bit for bit)
 #pragma clang fp contract(fast)
-      float gr[kG2d];
-      gr[6] = gr[7] = gr[8] = 0.0f;
-      // with alpha = o G below the clamp, dalpha/do = G and dalpha/dq = -o G / 2, so one sum
-      // e = dL/dalpha G per pixel serves both: dL/do = sum e and dL/dq = -(o / 2) e. With
-      // q = a dx^2 + 2 b dx dy + c dy^2 every q-derivative is a moment of e times a factor of
-      // the Gaussian: dL/d(a, b, c) = -(o / 2) (sum e dx^2, 2 sum e dx dy, sum e dy^2) and
-      // dL/dmu' = o (a sum e dx + b sum e dy, b sum e dx + c sum e dy). A lane's pixels share
-      // their column, so it needs only E0 = sum e, E1 = sum e dy and E2 = sum e dy^2 over them
-      float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
+        float gr[kG2d];
+        gr[6] = gr[7] = gr[8] = 0.0f;
+        // with alpha = o G below the clamp, dalpha/do = alpha / o and dalpha/dq = -alpha / 2, so one
+        // sum e = dL/dalpha alpha per pixel serves both: dL/do = sum e / o and dL/dq = -e / 2. With
+        // q = a dx^2 + 2 b dx dy + c dy^2 every q-derivative is a moment of e times a factor of
+        // the Gaussian: dL/d(a, b, c) = -(1 / 2) (sum e dx^2, 2 sum e dx dy, sum e dy^2) and
+        // dL/dmu' = (a sum e dx + b sum e dy, b sum e dx + c sum e dy). A lane's pixels share
+        // their column, so it needs only E0 = sum e, E1 = sum e dy and E2 = sum e dy^2 over them
+        float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
 #pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        const float alpha = aev[k], dy = dyv[k];
-        const float Ti = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
-        const float wT = alpha * Ti;
-        const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * blue;   // dL/dC . c
-        const float diff = dcc - V[k];
-        const float e = (Ti * diff) * gmv[k];                       // dL/dalpha G
-        gr[6] = fmaf(wT, d0[k], gr[6]);
-        gr[7] = fmaf(wT, d1[k], gr[7]);
-        gr[8] = fmaf(wT, d2[k], gr[8]);
-        V[k] = fmaf(alpha, diff, V[k]);                             // alpha dcc + (1 - alpha) V
-        T[k] = Ti;
-        const float ey = e * dy;
-        E0 += e;
-        E1 += ey;
-        E2 = fmaf(ey, dy, E2);
-      }
-      // the moments sum e dx, e dy, e dx^2, e dx dy, e dy^2, e over the lane's pixels (dx is
-      // the column's): the conic and opacity factors are the Gaussian's own and are applied
-      // once per Gaussian after all its tiles (k_preprocess_bwd)
-      gr[0] = dx * E0;
-      gr[1] = E1;
-      gr[2] = dx * gr[0];
-      gr[3] = dx * E1;
-      gr[4] = E2;
-      gr[5] = E0;
-      {
-        // the nine components summed over the wave: each lane writes its nine values to LDS
-        // component-major. LDS form: 36 lanes each add 16 values of one component (four float4
-        // reads), then lane c < 9 adds the four partials of component c to the Gaussian's 36-byte
-        // row (one atomic instruction). DPP form: each lane adds three float4 (4 lanes' values of
-        // components l / 16, 4 + l / 16 and, lanes below 16, 8), DPP sums over each row of 16 lanes
-        // follow (lanes 0, 16, 32, 48 then hold the sums; three atomic instructions). DPP costs
-        // about two VALU issue slots per operation, an LDS round a wait: the LDS form for frames
-        // with enough tiles to hide the wait (8 waves per SIMD at 1080p: 0.233 against 0.254 ms
-        // with a three-float4 first round), DPP for small ones (720p, 3.5 waves per SIMD: 0.238
-        // against 0.248 ms). The workgroup is one wave, so its barriers only order the LDS
-        // accesses.
-        static_assert(NT == 64, "the per-entry reduction assumes one wave per tile");
+        for (int k = 0; k < PPT; ++k) {
+          const float alpha = aev[k], dy = dyv[k];
+          const float Ti = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
+          const float wT = alpha * Ti;
+          const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * BL.y;   // dL/dC . c
+          const float diff = dcc - V[k];
+          const float e = (Ti * diff) * (CLAMP ? gmv[k] : alpha);     // dL/dalpha alpha
+          gr[6] = fmaf(wT, d0[k], gr[6]);
+          gr[7] = fmaf(wT, d1[k], gr[7]);
+          gr[8] = fmaf(wT, d2[k], gr[8]);
+          V[k] = fmaf(alpha, diff, V[k]);                             // alpha dcc + (1 - alpha) V
+          T[k] = Ti;
+          const float ey = e * dy;
+          E0 += e;
+          E1 += ey;
+          E2 = fmaf(ey, dy, E2);
+        }
+        // the moments sum e dx, e dy, e dx^2, e dx dy, e dy^2, e over the lane's pixels (dx is
+        // the column's): the conic and opacity factors are the Gaussian's own and are applied
+        // once per Gaussian after all its tiles (k_preprocess_bwd)
+        gr[0] = dx * E0;
+        gr[1] = E1;
+        gr[2] = dx * gr[0];
+        gr[3] = dx * E1;
+        gr[4] = E2;
+        gr[5] = E0;
+        {
+          // the nine components summed over the wave: each lane writes its nine values to LDS
+          // component-major. LDS form: 36 lanes each add 16 values of one component (four float4
+          // reads), then lane c < 9 adds the four partials of component c to the Gaussian's 36-byte
+          // row (one atomic instruction). DPP form: each lane adds three float4 (4 lanes' values of
+          // components l / 16, 4 + l / 16 and, lanes below 16, 8), DPP sums over each row of 16 lanes
+          // follow (lanes 0, 16, 32, 48 then hold the sums; three atomic instructions). DPP costs
+          // about two VALU issue slots per operation, an LDS round a wait: the LDS form for frames
+          // with enough tiles to hide the wait (8 waves per SIMD at 1080p: 0.233 against 0.254 ms
+          // with a three-float4 first round), DPP for small ones (720p, 3.5 waves per SIMD: 0.238
+          // against 0.248 ms). The workgroup is one wave, so its barriers only order the LDS
+          // accesses.
+          static_assert(NT == 64, "the per-entry reduction assumes one wave per tile");
 #pragma unroll
-        for (int c = 0; c < kG2d; ++c) s_red[c * RS + lane] = gr[c];
-        __syncthreads();
-        const float4 *r4 = reinterpret_cast<const float4 *>(s_red);
-        const size_t row = (size_t)s_id[jl] * kG2d;
-        if (LDS_ROUND2) {
-          // lane 4 c + h: 16 values of component c (lanes 4 h .. 4 h + 3 of each group of 16)
-          const float4 q0 = r4[red_r1], q1 = r4[red_r1 + 4], q2 = r4[red_r1 + 8], q3 = r4[red_r1 + 12];
-          const float p = (((q0.x + q0.y) + (q0.z + q0.w)) + ((q1.x + q1.y) + (q1.z + q1.w))) +
-                          (((q2.x + q2.y) + (q2.z + q2.w)) + ((q3.x + q3.y) + (q3.z + q3.w)));
-          if (lane < 4 * kG2d) s_red2[lane] = p;
+          for (int c = 0; c < kG2d; ++c) s_red[c * RS + lane] = gr[c];
           __syncthreads();
-          const float4 q = reinterpret_cast<const float4 *>(s_red2)[red_lo9];   // component lane (lanes 0..8)
-          const float x = (q.x + q.y) + (q.z + q.w);
-          if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[row + lane], x);
-        } else {
-          const float4 ra = r4[lane], rb = r4[lane + 64], rc = r4[red_hi];
-          const float p0 = (ra.x + ra.y) + (ra.z + ra.w);   // component lane / 16
-          const float p1 = (rb.x + rb.y) + (rb.z + rb.w);   // component 4 + lane / 16
-          const float p2 = (rc.x + rc.y) + (rc.z + rc.w);   // component 8 (lanes 0..15)
-          const float s0 = row_sum16(p0), s1 = row_sum16(p1), s2 = row_sum16(p2);
-          if ((lane & 15) == 0) {
-            if (s0 != 0.0f) atomicAdd(&g2d[row + (lane >> 4)], s0);
-            if (s1 != 0.0f) atomicAdd(&g2d[row + 4 + (lane >> 4)], s1);
-            if (lane == 0 && s2 != 0.0f) atomicAdd(&g2d[row + 8], s2);
+          const float4 *r4 = reinterpret_cast<const float4 *>(s_red);
+          const size_t row = (size_t)s_id[jl] * kG2d;
+          if (LDS_ROUND2) {
+            // lane 4 c + h: 16 values of component c (lanes 4 h .. 4 h + 3 of each group of 16)
+            const float4 q0 = r4[red_r1], q1 = r4[red_r1 + 4], q2 = r4[red_r1 + 8], q3 = r4[red_r1 + 12];
+            const float p = (((q0.x + q0.y) + (q0.z + q0.w)) + ((q1.x + q1.y) + (q1.z + q1.w))) +
+                            (((q2.x + q2.y) + (q2.z + q2.w)) + ((q3.x + q3.y) + (q3.z + q3.w)));
+            if (lane < 4 * kG2d) s_red2[lane] = p;
+            __syncthreads();
+            const float4 q = reinterpret_cast<const float4 *>(s_red2)[red_lo9];   // component lane (lanes 0..8)
+            const float x = (q.x + q.y) + (q.z + q.w);
+            if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[row + lane], x);
+          } else {
+            const float4 ra = r4[lane], rb = r4[lane + 64], rc = r4[red_hi];
+            const float p0 = (ra.x + ra.y) + (ra.z + ra.w);   // component lane / 16
+            const float p1 = (rb.x + rb.y) + (rb.z + rb.w);   // component 4 + lane / 16
+            const float p2 = (rc.x + rc.y) + (rc.z + rc.w);   // component 8 (lanes 0..15)
+            const float s0 = row_sum16(p0), s1 = row_sum16(p1), s2 = row_sum16(p2);
+            if ((lane & 15) == 0) {
+              if (s0 != 0.0f) atomicAdd(&g2d[row + (lane >> 4)], s0);
+              if (s1 != 0.0f) atomicAdd(&g2d[row + 4 + (lane >> 4)], s1);
+              if (lane == 0 && s2 != 0.0f) atomicAdd(&g2d[row + 8], s2);
+            }
           }
         }
-      }
-      }
+        }
+      };
+      if (__builtin_amdgcn_readfirstlane(__float_as_int(BL.z)) != 0)
+        entry(std::integral_constant<bool, true>{});
+      else
+        entry(std::integral_constant<bool, false>{});
     }
   }
 }
@@ -363,22 +358,24 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
 
   // opacity
   const float o = 1.0f / (1.0f + __expf(-logit));
-  const float d_logit = (float)g[5] * o * (1.0f - o);
 
   // conic -> dilated 2D covariance (a, b; b, c); FP64 because det can be far below a c
   const double a = pr.a, b = pr.b, c = pr.c;
   const double idet = 1.0 / pr.det;
   const double id2 = idet * idet;
   {
-    // moments -> dL/d(mu', conic a, b, c) with the conic (c, -b, a) / det and the opacity
-    const double od = (double)o, ca = c * idet, cb = -b * idet, cc = a * idet;
+    // moments of e = dL/dalpha alpha -> dL/d(mu', conic a, b, c, opacity), with the conic
+    // (c, -b, a) / det and the opacity
+    const double ca = c * idet, cb = -b * idet, cc = a * idet;
     const double m_dx = g[0], m_dy = g[1];
-    g[0] = od * (ca * m_dx + cb * m_dy);
-    g[1] = od * (cb * m_dx + cc * m_dy);
-    g[2] = -0.5 * od * g[2];
-    g[3] = -od * g[3];
-    g[4] = -0.5 * od * g[4];
+    g[0] = ca * m_dx + cb * m_dy;
+    g[1] = cb * m_dx + cc * m_dy;
+    g[2] = -0.5 * g[2];
+    g[3] = -g[3];
+    g[4] = -0.5 * g[4];
+    g[5] = g[5] / (double)o;
   }
+  const float d_logit = (float)g[5] * o * (1.0f - o);
   const double gA = g[2], gB = g[3], gC = g[4];
   const double ga = (-c * c * gA + b * c * gB - b * b * gC) * id2;
   const double gb = (2.0 * b * c * gA - (a * c + b * b) * gB + 2.0 * a * b * gC) * id2;
@@ -533,9 +530,9 @@ hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, cons
   return hipGetLastError();
 }
 
-// The blend backward's per-Gaussian moment sums turned into dL/d(mu', conic a, b, c) in place,
-// with the stored FP32 conic and opacity (for inspection: the preprocess backward applies the same
-// factors with its FP64 conic).
+// The blend backward's per-Gaussian moment sums turned into dL/d(mu', conic a, b, c, opacity)
+// in place, with the stored FP32 conic and opacity (for inspection: the preprocess backward
+// applies the same factors with its FP64 conic).
 __global__ __launch_bounds__(kBlock) void k_g2d_from_moments(int64_t n, const uint32_t *__restrict__ tiles,
                                                              const float4 *__restrict__ xyab,
                                                              const float4 *__restrict__ cop, float *__restrict__ g2d) {
@@ -544,11 +541,12 @@ __global__ __launch_bounds__(kBlock) void k_g2d_from_moments(int64_t n, const ui
   float *g = g2d + i * kG2d;
   const double a = xyab[i].z, b = xyab[i].w, c = cop[i].x, o = cop[i].y;
   const double m_dx = g[0], m_dy = g[1];
-  g[0] = (float)(o * (a * m_dx + b * m_dy));
-  g[1] = (float)(o * (b * m_dx + c * m_dy));
-  g[2] = (float)(-0.5 * o * (double)g[2]);
-  g[3] = (float)(-o * (double)g[3]);
-  g[4] = (float)(-0.5 * o * (double)g[4]);
+  g[0] = (float)(a * m_dx + b * m_dy);
+  g[1] = (float)(b * m_dx + c * m_dy);
+  g[2] = (float)(-0.5 * (double)g[2]);
+  g[3] = (float)(-(double)g[3]);
+  g[4] = (float)(-0.5 * (double)g[4]);
+  g[5] = (float)((double)g[5] / o);
 }
 
 hipError_t launch_g2d_from_moments(int64_t n, const uint32_t *tiles, const float4 *xyab, const float4 *cop,

@@ -106,16 +106,15 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
       if (!any_live) break;
       const float4 A = s_a[j];
       const float4 B = s_b[j];
-      const float2 BL = *reinterpret_cast<const float2 *>(&s_c[j]);   // support cut, blue
+      const float2 BL = *reinterpret_cast<const float2 *>(&s_c[j]);   // threshold on l, blue
       const float dx = fx - A.x;
-      const float t = conic_column(A.w, dx);
+      const float t = conic_column(A.w, dx, B.y);
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         if (done[k]) continue;
-        const float kq = conic_kq(B.x, A.z, dx, fy[k] - A.y, t);   // k q
-        if (kq < BL.x) continue;                               // q beyond the support cut
-        const float alpha = fminf(kAlphaMax, B.y * gauss_weight_scaled(kq));
-        if (alpha < kAlphaMin) continue;
+        const float l = conic_kq(B.x, A.z, dx, fy[k] - A.y, t);   // k q + log2 o
+        if (l < BL.x) continue;                                   // q > 9 or alpha < 1/255
+        const float alpha = fminf(kAlphaMax, alpha_from_log2(l));
         const float Tn = T[k] * (1.0f - alpha);
         if (Tn < kTMin) {
           done[k] = true;

@@ -9,29 +9,35 @@ namespace flod {
 constexpr int kBatch = 256;                                // list entries staged in LDS at once
 
 // A list entry as both blend kernels stage it in LDS, decoded once per entry instead of in
-// every lane: (mu'x - x0, mu'y - y0, r = b / c, k det / c), (k c, opacity, red, green) and
-// (the scaled support cut, blue, 0, 0), with k = kExpScale (the completed square of q, see
-// conic_stage) and (x0, y0) the tile's corner. The mean relative to the corner is the FP32 mean
-// minus the corner (exact while the two are within a factor of two, otherwise rounded to the
-// difference's ulp) plus the bf16 residual of mu': a pixel's offsets from the mean are then
-// one subtraction from its tile-local centre, (px - x0) + 1/2. Every float4 holds values the
-// decision needs, so that each is read whole before it and a blending pixel finds its colour in
-// registers (a colour read only by blending pixels would make each of them wait for LDS).
+// every lane: (mu'x - x0, mu'y - y0, r = b / c, k det / c), (k c, log2 o, red, green) and
+// (the threshold on l = k q + log2 o, blue, 1 when the opacity exceeds kClampOpacity, 0), with
+// k = kExpScale (the completed square of q, see conic_stage) and (x0, y0) the tile's corner.
+// The mean relative to the corner is the FP32 mean minus the corner (exact while the two are
+// within a factor of two, otherwise rounded to the difference's ulp) plus the bf16 residual of
+// mu': a pixel's offsets from the mean are then one subtraction from its tile-local centre,
+// (px - x0) + 1/2. Every float4 holds values the decision needs, so that each is read whole
+// before it and a blending pixel finds its colour in registers (a colour read only by
+// blending pixels would make each of them wait for LDS).
+//
+// An opacity up to kClampOpacity cannot reach the 0.99 clamp: q >= 0 gives l <= log2 o, so
+// 2^l <= o (1 + a few ulp) < 0.99; such entries take alpha = 2^l without the clamp where that
+// saves work (the backward's decision).
+constexpr float kClampOpacity = 0.98f;
+
 __device__ __forceinline__ void stage_entry(const float4 *xyab, const float4 *cop, const float2 *blue, uint32_t g,
                                             int x0, int y0, float4 &a, float4 &b, float4 &c) {
   const float4 A = xyab[g];
   const float2 BL = blue[g];
   const uint32_t lo = __float_as_uint(BL.y);
   const float4 C = cop[g];
-  // support cut of this entry: q beyond min(9, Q_g (1 + 1e-3) + 1e-3), Q_g = 2 ln(255 o), has
-  // alpha below 1/255 by a relative 5e-4 (the binning's margin), so cutting there takes the
-  // same decisions as q <= 9 and alpha >= 1/255 while whole waves skip the exp more often
-  const float qcut = fminf(kQCut, fmaf(2.0f * logf(255.0f * C.y), 1.001f, 1e-3f));
+  // the decision: q <= 9 and o exp(-q/2) >= 1/255, i.e. l >= max(log2(1/255), 9 k + log2 o)
+  const float l2o = log2f(C.y);
+  const float thr = fmaxf(kLog2AlphaMin, kQCutScaled + l2o);
   float r, ek, ck;
   conic_stage(A.z, A.w, C.x, r, ek, ck);
   a = make_float4((A.x - (float)x0) + mu_lo_x(lo), (A.y - (float)y0) + mu_lo_y(lo), r, ek);
-  b = make_float4(ck, C.y, C.z, C.w);
-  c = make_float4(kExpScale * qcut, BL.x, 0.0f, 0.0f);
+  b = make_float4(ck, l2o, C.z, C.w);
+  c = make_float4(thr, BL.x, C.y > kClampOpacity ? 1.0f : 0.0f, 0.0f);
 }
 
 // Tile orders, longest first (LPT order). The blend kernels' cost per tile varies by orders of

@@ -290,12 +290,16 @@ __device__ __forceinline__ float dist2(float m0, float m1, float m2, const float
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-// The blend kernels evaluate exp(-q/2) as 2^(k q), k = -log2(e) / 2, with the scale folded
-// into the staged terms below, so that each (pixel, entry) pair forms k q directly and takes
-// one hardware exp2: within a few ulp of exp. The support cut q <= 9 becomes k q >= 9 k.
+// The blend kernels evaluate o exp(-q/2) as 2^(k q + log2 o), k = -log2(e) / 2, with the scale
+// and log2 o folded into the staged terms below, so that each (pixel, entry) pair forms
+// l = k q + log2 o (the log2 of the unclamped alpha) directly and takes one hardware exp2:
+// within a few ulp of o exp(-q/2). The support cut q <= 9 becomes k q >= 9 k, the alpha floor
+// o exp(-q/2) >= 1/255 becomes l >= log2(1/255): both are l >= max(log2(1/255), 9 k + log2 o),
+// one threshold per entry.
 constexpr float kExpScale = -0.72134752044448170f;
 constexpr float kQCutScaled = kQCut * kExpScale;
-__device__ __forceinline__ float gauss_weight_scaled(float kq) { return __builtin_amdgcn_exp2f(kq); }
+constexpr float kLog2AlphaMin = -7.99435343685885793f;   // log2(1/255)
+__device__ __forceinline__ float alpha_from_log2(float l) { return __builtin_amdgcn_exp2f(l); }
 
 // q = a dx^2 + 2 b dx dy + c dy^2 completed to a square in dy:
 //   q = c v^2 + (det / c) dx^2,  v = dy + (b / c) dx,  det = a c - b^2 > 0, c > 0,
@@ -304,8 +308,8 @@ __device__ __forceinline__ float gauss_weight_scaled(float kq) { return __builti
 // error in FP32); here the only cancellation is in v, whose error stays near an ulp of dy.
 // An entry is staged as r = b / c, e = k det / c (det by Kahan's two-product method, from the
 // stored FP32 conic) and c_k = k c, with mu' relative to the tile's corner (see stage_entry).
-// Per column (a lane's pixels share dx = x - mu'x): t = e dx^2; per pixel, with dy = y - mu'y:
-// v = dy + r dx (one FMA), k q = c_k v^2 + t.
+// Per column (a lane's pixels share dx = x - mu'x): t = e dx^2 + log2 o; per pixel, with
+// dy = y - mu'y: v = dy + r dx (one FMA), l = c_k v^2 + t = k q + log2 o.
 // Shared by both blend kernels so that they take the same decisions on the same bits.
 __device__ __forceinline__ void conic_stage(float a, float b, float c, float &r, float &ek, float &ck) {
   const float p = b * b;
@@ -317,7 +321,7 @@ __device__ __forceinline__ void conic_stage(float a, float b, float c, float &r,
   ck = kExpScale * c;
 }
 
-__device__ __forceinline__ float conic_column(float ek, float dx) { return (ek * dx) * dx; }
+__device__ __forceinline__ float conic_column(float ek, float dx, float lo) { return fmaf(ek * dx, dx, lo); }
 
 __device__ __forceinline__ float conic_kq(float ck, float r, float dx, float dy, float t) {
   const float v = fmaf(r, dx, dy);
