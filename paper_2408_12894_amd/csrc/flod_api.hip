@@ -425,7 +425,8 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
       uint32_t *dv = dres ? P<uint32_t>(c, B_DVAL1) : P<uint32_t>(c, B_DVAL0);
       tm.begin(FLOD_STAGE_EMIT);
       if (launch_emit(dv, counters + kCntVisible, counters + kCntInstances, N, k_max, sorted_tiles, P<float4>(c, B_BIN),
-                      P<unsigned long long>(c, B_TPREFIX), cam.tiles_x, cam.tiles_y, tk[0], tv[0], s) != hipSuccess)
+                      P<unsigned long long>(c, B_TPREFIX), cam.tiles_x, cam.tiles_y, tk[0], tv[0],
+                      P<uint2>(c, B_RANGES), s) != hipSuccess)
         return FLOD_ERR_DEVICE;
       tm.end();
       tm.begin(FLOD_STAGE_TILE_SORT);
@@ -436,7 +437,9 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
       tm.end();
     }
     tm.begin(FLOD_STAGE_RANGES);
-    if (launch_ranges(tk[tres], counters + kCntInstances, k_max, n_tiles, P<uint2>(c, B_RANGES), s) != hipSuccess)
+    // the emission zeroed the ranges when it ran
+    if (launch_ranges(tk[tres], counters + kCntInstances, k_max, n_tiles, P<uint2>(c, B_RANGES), k_max > 0, s) !=
+        hipSuccess)
       return FLOD_ERR_DEVICE;
     tm.end();
     tm.begin(FLOD_STAGE_BLEND);
@@ -865,7 +868,8 @@ flod_status flod_overlap_prune(flod_ctx *ctx, const flod_level *level, float d_o
         launch_radix_sort(dk, dv, counters + kCntVisible, n, bits, P<uint32_t>(ctx, B_HIST),
                           P<uint32_t>(ctx, B_SCAN), P<uint32_t>(ctx, B_TOT), &res, s) != hipSuccess ||
         launch_prune_gather(level->means, dv[res], n, P<float4>(ctx, B_XYAB), s) != hipSuccess ||
-        launch_ranges(dk[res], counters + kCntVisible, n, (int)buckets, P<uint2>(ctx, B_RANGES), s) != hipSuccess ||
+        launch_ranges(dk[res], counters + kCntVisible, n, (int)buckets, P<uint2>(ctx, B_RANGES), false, s) !=
+            hipSuccess ||
         launch_prune_cost(pts, ranges, n, d_op, reinterpret_cast<unsigned long long *>(counters + kCntTotal64),
                           s) != hipSuccess ||
         hipMemcpyAsync(ctx->host_counters, counters, 16, hipMemcpyDeviceToHost, s) != hipSuccess ||

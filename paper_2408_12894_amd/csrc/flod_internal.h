@@ -123,9 +123,10 @@ hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const uint32_t *k_ptr,
                        int64_t n_max, int64_t k_max, const uint32_t *sorted_tiles, const float4 *bin,
                        const unsigned long long *prefix, int tiles_x, int tiles_y, uint32_t *tile_ids,
-                       uint32_t *values, hipStream_t s);
+                       uint32_t *values, uint2 *ranges, hipStream_t s);   // also zeroes ranges
+// zeroed: ranges already zeroed (by the emission); otherwise zeroed here first
 hipError_t launch_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, int64_t k_max, int n_tiles,
-                         uint2 *ranges, hipStream_t s);
+                         uint2 *ranges, bool zeroed, hipStream_t s);
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
                         const float4 *cop, const float2 *blue, const DevCamera &cam,
                         const float bg[3], float *image, float *final_T, int32_t *n_contrib,

@@ -520,10 +520,17 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
                                                  const uint32_t *k_ptr, const uint32_t *sorted_tiles,
                                                  const float4 *bin, const unsigned long long *prefix,
                                                  int tiles_x, int tiles_y, uint32_t *__restrict__ tile_ids,
-                                                 uint32_t *__restrict__ values) {
+                                                 uint32_t *__restrict__ values, uint2 *__restrict__ ranges) {
   __shared__ uint32_t s_tile[kEmitCap];
   __shared__ uint32_t s_val[kEmitCap];
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  // the tile ranges start empty (k_ranges writes the tiles that have instances): zeroed here,
+  // by the first workgroup of each block, before any workgroup leaves, instead of by a launch
+  // of their own
+  if (blockIdx.y == 0) {
+    const int n_tiles = tiles_x * tiles_y;
+    for (int t = (int)j; t < n_tiles; t += (int)(gridDim.x * kBlock)) ranges[t] = make_uint2(0u, 0u);
+  }
   // the counts first (the grid covers every candidate, of which n are visible); then the
   // Gaussian, its tile count and the block's offsets, loaded together
   const uint32_t n = *n_ptr;
@@ -638,7 +645,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *sorted_ids, con
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const uint32_t *k_ptr, int64_t n_max,
                        int64_t k_max, const uint32_t *sorted_tiles, const float4 *bin,
                        const unsigned long long *prefix, int tiles_x, int tiles_y, uint32_t *tile_ids,
-                       uint32_t *values, hipStream_t s) {
+                       uint32_t *values, uint2 *ranges, hipStream_t s) {
   if (n_max <= 0) return hipSuccess;
   // workgroups per block: enough for the windows an average block of up to k_max instances
   // fills (1 when blocks fit a window, as they do for small footprints). Coarse levels, whose
@@ -650,7 +657,7 @@ hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const 
   const int64_t cap_split = windows >= (int64_t)kEmitHugeWindows ? kEmitSplitHuge : kEmitSplit;
   const unsigned split = (unsigned)std::min<int64_t>(cap_split, std::max<int64_t>(1, windows));
   hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks, split), dim3(kBlock), 0, s, sorted_ids, n_ptr, k_ptr,
-                     sorted_tiles, bin, prefix, tiles_x, tiles_y, tile_ids, values);
+                     sorted_tiles, bin, prefix, tiles_x, tiles_y, tile_ids, values, ranges);
   return hipGetLastError();
 }
 
@@ -709,8 +716,8 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, int64_t k_max, int n_tiles,
-                         uint2 *ranges, hipStream_t s) {
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * (int64_t)n_tiles, s);
+                         uint2 *ranges, bool zeroed, hipStream_t s) {
+  hipError_t e = zeroed ? hipSuccess : launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * (int64_t)n_tiles, s);
   if (e != hipSuccess || k_max <= 0) return e;
   const int64_t threads = (k_max + 3) / 4;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tile_ids,
