@@ -50,7 +50,7 @@ OPS_WALK = 20
 OPS_BWD_BLENDED = 31
 SURVEY_STEPS = {           # step -> the library's timed stages that implement it
     "S2 preprocess": ["preprocess"],
-    "S3 scan": ["compact", "offsets"],
+    "S3 scan": ["offsets"],       # the visible-set compaction is the depth sort's first pass
     "S4 duplicate": ["emit"],
     "S5 sort": ["depth_sort", "tile_sort"],
     "S6 ranges": ["ranges"],
@@ -144,8 +144,7 @@ def algorithmic_bytes(stage, N, n_vis, K, P, tiles):
     """Bytes a stage cannot avoid moving in one launch (its reads and writes of each item once)."""
     return {
         "preprocess": (236 + 80) * N,
-        "compact": 8 * N + 8 * n_vis,
-        "depth_sort": 4 * 2 * 8 * n_vis,
+        "depth_sort": 4 * N + 8 * n_vis + 3 * 2 * 8 * n_vis,   # the first pass reads every candidate's key
         "offsets": 8 * n_vis,
         "emit": 40 * n_vis + 8 * K,
         "tile_sort": 2 * (4 + 16) * K,

@@ -346,9 +346,9 @@ flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out);
 /* Per-stage device timing with HIP events on the render stream (off by default). */
 enum {
   FLOD_STAGE_PREPROCESS = 0,  /* selection (eq. 6), activation (eq. 4), projection, SH */
-  FLOD_STAGE_COMPACT,         /* visible-set compaction                              */
-  FLOD_STAGE_DEPTH_SORT,      /* radix sort of visible Gaussians by depth            */
-  FLOD_STAGE_OFFSETS,         /* tile counts in depth order, scan, count readback    */
+  FLOD_STAGE_DEPTH_SORT,      /* radix sort by depth; its first pass compacts the visible
+                                 set, its last writes the tile counts in depth order   */
+  FLOD_STAGE_OFFSETS,         /* scan of the tile counts, count readback             */
   FLOD_STAGE_EMIT,            /* (tile, Gaussian) instance emission                  */
   FLOD_STAGE_TILE_SORT,       /* stable radix sort of instances by tile              */
   FLOD_STAGE_RANGES,          /* per-tile [start, end)                               */

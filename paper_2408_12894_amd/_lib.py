@@ -19,8 +19,8 @@ FLOD_ERR_DEVICE = -4
 FLOD_ERR_UNSUPPORTED = -5
 FLOD_ERR_TOO_LARGE = -6
 MAX_LEVELS = 8
-NUM_STAGES = 10
-STAGES = ("preprocess", "compact", "depth_sort", "offsets", "emit", "tile_sort", "ranges", "blend",
+NUM_STAGES = 9
+STAGES = ("preprocess", "depth_sort", "offsets", "emit", "tile_sort", "ranges", "blend",
           "blend_bwd", "preprocess_bwd")
 
 EXPORTS = ("flod_ctx_create", "flod_ctx_destroy", "flod_ctx_workspace_bytes", "flod_ctx_required_bytes",

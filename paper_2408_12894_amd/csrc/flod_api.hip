@@ -383,27 +383,22 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     o.bin = P<float4>(c, B_BIN);
     o.tiles = P<uint32_t>(c, B_TILES);
     o.block_vis = P<uint32_t>(c, B_BLOCKVIS);
+    o.zero_sums = P<uint32_t>(c, B_TBSUM);
     o.n_selected = reinterpret_cast<unsigned long long *>(n_selected);
     tm.begin(FLOD_STAGE_PREPROCESS);
     if (launch_preprocess(p, o, s) != hipSuccess) return FLOD_ERR_DEVICE;
     tm.end();
-    tm.begin(FLOD_STAGE_COMPACT);
-    if (launch_scan_blocks(o.block_vis, nullptr, kBlock, P<unsigned long long>(c, B_PREFIX), counters + kCntVisible,
-                           nullptr, nb, s) != hipSuccess)
-      return FLOD_ERR_DEVICE;
-    if (launch_compact(o.tiles, o.depth, N, P<unsigned long long>(c, B_PREFIX), P<uint32_t>(c, B_DKEY0),
-                       P<uint32_t>(c, B_DVAL0), P<uint32_t>(c, B_TBSUM), s) != hipSuccess)
-      return FLOD_ERR_DEVICE;
-    tm.end();
     tm.begin(FLOD_STAGE_DEPTH_SORT);
     uint32_t *dk[2] = {P<uint32_t>(c, B_DKEY0), P<uint32_t>(c, B_DKEY1)};
     uint32_t *dv[2] = {P<uint32_t>(c, B_DVAL0), P<uint32_t>(c, B_DVAL1)};
-    // the last pass also writes the tile counts in depth order and their sums per workgroup of
-    // the emission (zeroed by the compaction)
+    // the first pass reads every candidate's depth key and keeps the rendered ones (the
+    // compaction of the visible set; their count goes to counters[kCntVisible]); the last pass
+    // also writes the tile counts in depth order and their sums per workgroup of the emission
+    // (zeroed by the preprocess)
     sorted_tiles = P<uint32_t>(c, B_STILES);
     if (launch_radix_sort(dk, dv, counters + kCntVisible, N, 32, P<uint32_t>(c, B_HIST), P<uint32_t>(c, B_SCAN),
-                          P<uint32_t>(c, B_TOT), &dres, s, o.tiles, sorted_tiles, P<uint32_t>(c, B_TBSUM)) !=
-        hipSuccess)
+                          P<uint32_t>(c, B_TOT), &dres, s, o.tiles, sorted_tiles, P<uint32_t>(c, B_TBSUM),
+                          o.depth) != hipSuccess)
       return FLOD_ERR_DEVICE;
     tm.end();
     tm.begin(FLOD_STAGE_OFFSETS);
@@ -1139,7 +1134,7 @@ flod_status flod_ctx_stage_times(flod_ctx *ctx, double *ms, int64_t *calls, int 
 }
 
 const char *flod_stage_name(int stage) {
-  static const char *names[FLOD_NUM_STAGES] = {"preprocess", "compact", "depth_sort", "offsets", "emit",
+  static const char *names[FLOD_NUM_STAGES] = {"preprocess", "depth_sort", "offsets", "emit",
                                                "tile_sort", "ranges", "blend", "blend_bwd", "preprocess_bwd"};
   return (stage >= 0 && stage < FLOD_NUM_STAGES) ? names[stage] : "unknown";
 }

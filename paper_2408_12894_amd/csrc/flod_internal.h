@@ -26,6 +26,9 @@ constexpr unsigned long long kPruneMaxScan = 1ull << 36;   // overlap-pruning ne
 constexpr float kNearZ = 0.2f;
 constexpr float kDilate = 0.3f;
 constexpr float kFovClamp = 1.3f;
+// Depth key of a candidate that is not rendered (culled or not selected): above every FP32
+// depth bits of a positive depth, and skipped by the depth sort's first pass.
+constexpr uint32_t kDepthNone = 0xFFFFFFFFu;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
@@ -68,6 +71,7 @@ struct PreOut {
                       // (conic c, support bound Q_g, bits of x0 | y0 << 16, bits of x1 | y1 << 16)
   uint32_t *tiles;    // tiles touched, 0 when culled or not selected
   uint32_t *block_vis;  // per-workgroup count of visible candidates
+  uint32_t *zero_sums;  // one word per workgroup, zeroed (the depth sort's tile-count sums; may be null)
   unsigned long long *n_selected;   // per-level selected counts (may be null)
 };
 
@@ -107,19 +111,18 @@ hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int i
                               unsigned long long *total64, int max_blocks, hipStream_t s,
                               unsigned long long cap32 = 0xFFFFFFFFull, unsigned long long *host_out = nullptr,
                               uint32_t host_seq = 0);
-// zero_sums (or null): one word per workgroup of 256 candidates, zeroed for the depth sort's
-// tile-count sums
-hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
-                          const unsigned long long *prefix, uint32_t *keys, uint32_t *vals,
-                          uint32_t *zero_sums, hipStream_t s);
 int radix_items(int64_t n_max);        // keys per thread the radix sort of n_max keys uses
 size_t radix_hist_bytes(int64_t n_max);  // bytes of each of its hist and scan arrays
 // With tiles_of (tile count per value), the last pass also writes tiles_out[pos] =
 // tiles_of[sorted value] and adds the counts into block_sum[pos / 256] (zeroed beforehand).
-hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr,
+// With first_keys, the first pass reads first_keys[0, n_max) instead of keys[0] and vals[0],
+// takes each key's index as its value and skips keys equal to kDepthNone; it writes the count
+// it kept to *n_ptr, which the later passes read.
+hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *n_ptr,
                              int64_t n_max, int bits, uint32_t *hist, uint32_t *scan,
                              uint32_t *tot, int *result_buf, hipStream_t s, const uint32_t *tiles_of = nullptr,
-                             uint32_t *tiles_out = nullptr, uint32_t *block_sum = nullptr);
+                             uint32_t *tiles_out = nullptr, uint32_t *block_sum = nullptr,
+                             const uint32_t *first_keys = nullptr);
 hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const uint32_t *k_ptr,
                        int64_t n_max, int64_t k_max, const uint32_t *sorted_tiles, const float4 *bin,
                        const unsigned long long *prefix, int tiles_x, int tiles_y, uint32_t *tile_ids,

@@ -92,7 +92,9 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreParams p, PreOut o) {
       }
     }
     o.tiles[i] = tiles;
+    if (!vis) o.depth[i] = kDepthNone;   // the depth sort's first pass skips it
   }
+  if (o.zero_sums && threadIdx.x == 0) o.zero_sums[blockIdx.x] = 0u;
   // per-level selected counts, aggregated per wave
   if (o.n_selected) {
     const int lane = threadIdx.x & 63;

@@ -1,11 +1,12 @@
 // Binning: visible-set compaction, depth sort, instance emission, stable tile sort, ranges.
 //
 // Order of the instance list: ascending (tile, depth bits, Gaussian index). It is built as
-//   1. compact the visible candidates in index order,
-//   2. stable LSD radix sort of (depth bits, index) over the visible Gaussians (N keys),
-//   3. emit each Gaussian's tiles in that depth order (row-major over its footprint),
-//   4. stable LSD radix sort of the K instances by tile id only.
-// Stability makes step 4 keep the (depth, index) order inside each tile, so only the tile
+//   1. stable LSD radix sort of (depth bits, index) over the visible Gaussians (N keys); its
+//      first pass reads every candidate's depth key in index order and drops the candidates
+//      not rendered (key kDepthNone), so it also compacts the visible set,
+//   2. emit each Gaussian's tiles in that depth order (row-major over its footprint),
+//   3. stable LSD radix sort of the K instances by tile id only.
+// Stability makes step 3 keep the (depth, index) order inside each tile, so only the tile
 // digits of the K-long list are sorted: ceil(log2(tiles) / 8) passes instead of a full
 // 64-bit key sort.
 //
@@ -125,34 +126,6 @@ hipError_t launch_scan_blocks(const uint32_t *in, const uint32_t *n_items, int i
 }
 
 // ---------------------------------------------------------------------------------------
-// Compaction of visible candidates into (depth bits, index) pairs, in index order.
-// ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
-                                                    const unsigned long long *prefix, uint32_t *keys,
-                                                    uint32_t *vals, uint32_t *zero_sums) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  // one word per workgroup of the sums the depth sort's last pass accumulates (see k_rs_scatter)
-  if (zero_sums && threadIdx.x == 0) zero_sums[blockIdx.x] = 0u;
-  const bool v = (i < n) && tiles[i] != 0u;
-  uint32_t tot;
-  uint32_t ex = block_excl_scan(v ? 1u : 0u, &tot);
-  if (v) {
-    const uint64_t pos = prefix[blockIdx.x] + ex;
-    keys[pos] = depth[i];
-    vals[pos] = (uint32_t)i;
-  }
-}
-
-hipError_t launch_compact(const uint32_t *tiles, const uint32_t *depth, int64_t n,
-                          const unsigned long long *prefix, uint32_t *keys, uint32_t *vals, uint32_t *zero_sums,
-                          hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compact, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tiles, depth,
-                     n, prefix, keys, vals, zero_sums);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------------------
 // Radix pass: histogram, per-digit scan, stable scatter.
 // hist[d * stride + b] = count of digit d in block b; scan = exclusive prefix over b. The row
 // stride is the block count rounded up to a multiple of 8 (32-byte aligned rows).
@@ -178,12 +151,15 @@ static unsigned radix_grid(int nb_max) {
 // which can far exceed n, and workgroups past n leave without reading their keys (loading
 // keys and values together with n, bounded by the capacity, here and in the scatter made the
 // tile sort at 1080p / 1M 10% slower).
-template <int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const uint32_t *n_ptr, int shift,
-                                                    uint32_t *hist, int stride) {
+//
+// FIRST (the depth sort's first pass): the keys are all n_all candidates' depth keys, read
+// directly, and keys equal to kDepthNone (candidates not rendered) are not counted.
+template <int ITEMS, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const uint32_t *n_ptr, uint32_t n_all,
+                                                    int shift, uint32_t *hist, int stride) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   __shared__ uint32_t h[kRadix];
-  const uint32_t n = *n_ptr;
+  const uint32_t n = FIRST ? n_all : *n_ptr;
   const uint32_t nb = (n + TILE - 1) / TILE;
   const uint32_t b = radix_block(blockIdx.x);
   if (b >= nb) return;
@@ -198,17 +174,18 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const 
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r)
-    if (base + r * kBlock + threadIdx.x < n) atomicAdd(&h[(kr[r] >> shift) & (kRadix - 1)], 1u);
+    if (base + r * kBlock + threadIdx.x < n && (!FIRST || kr[r] != kDepthNone))
+      atomicAdd(&h[(kr[r] >> shift) & (kRadix - 1)], 1u);
   __syncthreads();
   hist[(size_t)threadIdx.x * stride + b] = h[threadIdx.x];
 }
 
 // One workgroup per digit. Rounds of 2048 counts: each thread takes 8 consecutive ones (two
 // 16-byte loads), the next round's loads are issued before this round's scan.
-__global__ __launch_bounds__(kBlock) void k_rs_scan(const uint32_t *n_ptr, const uint32_t *hist, uint32_t *scan,
-                                                    uint32_t *tot, int stride, int tile) {
+__global__ __launch_bounds__(kBlock) void k_rs_scan(const uint32_t *n_ptr, uint32_t n_all, const uint32_t *hist,
+                                                    uint32_t *scan, uint32_t *tot, int stride, int tile) {
   constexpr uint32_t kPer = 8, kRound = kBlock * kPer;
-  const uint32_t n = *n_ptr;
+  const uint32_t n = n_ptr ? *n_ptr : n_all;   // null: the first pass over all candidates
   const uint32_t nb = (n + tile - 1) / tile;
   const int d = blockIdx.x;
   const uint32_t *row = hist + (size_t)d * stride;
@@ -268,14 +245,18 @@ struct TileTail {
   uint32_t *block_sum;        // per 256 sorted positions
 };
 
-template <int ITEMS, bool TILES>
+// With FIRST (the depth sort's first pass) the keys are all n_all candidates' depth keys, each
+// key's value is its index, keys equal to kDepthNone are dropped (the output is the rendered
+// candidates, compacted and ordered by the first digit), and workgroup 0 writes the count kept
+// to *n_out for the later passes.
+template <int ITEMS, bool TILES, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restrict__ keys_in,
                                                        const uint32_t *__restrict__ vals_in,
                                                        uint32_t *__restrict__ keys_out,
                                                        uint32_t *__restrict__ vals_out, const uint32_t *n_ptr,
-                                                       int shift, const uint32_t *hist,
-                                                       const uint32_t *scan, const uint32_t *tot, int stride,
-                                                       TileTail tail) {
+                                                       uint32_t n_all, uint32_t *n_out, int shift,
+                                                       const uint32_t *hist, const uint32_t *scan,
+                                                       const uint32_t *tot, int stride, TileTail tail) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   constexpr int WAVES = kBlock / 64;
   constexpr uint32_t WTILE = 64 * ITEMS;
@@ -289,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
   // latencies overlap (the offsets issued ahead of the count, with the scan's first counts
   // likewise, made the tile sort at 1080p / 1M 8% slower: a wait for the count then waits for
   // the scattered offset rows too)
-  const uint32_t n = *n_ptr;
+  const uint32_t n = FIRST ? n_all : *n_ptr;
   const uint32_t nb = (n + TILE - 1) / TILE;
   const uint32_t b = radix_block(blockIdx.x);
   if (b >= nb) return;
@@ -299,8 +280,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     const uint32_t li = (uint32_t)w * WTILE + (uint32_t)r * 64u + (uint32_t)lane;
-    kr[r] = li < count ? keys_in[base + li] : 0u;
-    vr[r] = li < count ? vals_in[base + li] : 0u;
+    kr[r] = li < count ? keys_in[base + li] : (FIRST ? kDepthNone : 0u);
+    vr[r] = FIRST ? base + li : (li < count ? vals_in[base + li] : 0u);
   }
   // digit bases over the whole array and this workgroup's local digit bases (the three
   // loads issued together, ahead of the scans' barriers)
@@ -309,8 +290,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
   const uint32_t sc = scan[(size_t)tid * stride + b];
   uint32_t t_all;
   const uint32_t dbase = block_excl_scan(tot_d, &t_all);
-  uint32_t t_loc;
+  uint32_t t_loc;   // the keys this workgroup writes (FIRST: the rendered ones)
   const uint32_t lbase = block_excl_scan(cnt, &t_loc);
+  if (FIRST && b == 0 && tid == 0) *n_out = t_all;
   s_goff[tid] = dbase + sc - lbase;
 #pragma unroll
   for (int k = 0; k < WAVES; ++k) s_wcnt[k][tid] = 0;
@@ -319,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     const uint32_t li = (uint32_t)w * WTILE + (uint32_t)r * 64u + (uint32_t)lane;
-    const bool valid = li < count;
+    const bool valid = li < count && (!FIRST || kr[r] != kDepthNone);
     const uint32_t key = kr[r];
     const uint32_t d = (key >> shift) & (kRadix - 1);
     unsigned long long peers = __ballot(valid);
@@ -348,15 +330,16 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     const uint32_t li = (uint32_t)w * WTILE + (uint32_t)r * 64u + (uint32_t)lane;
-    if (li < count) {
+    if (li < count && (!FIRST || kr[r] != kDepthNone)) {
       const uint32_t pos = s_wcnt[w][(kr[r] >> shift) & (kRadix - 1)] + rr[r];
       s_keys[pos] = kr[r];
       s_vals[pos] = vr[r];
     }
   }
   __syncthreads();
+  const uint32_t kept = FIRST ? t_loc : count;
   if (!TILES) {
-    for (uint32_t li = tid; li < count; li += kBlock) {
+    for (uint32_t li = tid; li < kept; li += kBlock) {
       const uint32_t key = s_keys[li];
       const uint32_t d = (key >> shift) & (kRadix - 1);
       const uint32_t pos = s_goff[d] + li;
@@ -367,9 +350,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
     // whole rounds of the workgroup, so that every lane takes part in the segmented sum (the
     // tile count gathered in each round: gathering all of a thread's counts before the first
     // round measured 3.5 us slower at 1080p / 1M)
-    for (uint32_t l0 = 0; l0 < count; l0 += kBlock) {
+    for (uint32_t l0 = 0; l0 < kept; l0 += kBlock) {
       const uint32_t li = l0 + tid;
-      const bool valid = li < count;
+      const bool valid = li < kept;
       uint32_t c = 0u, seg = 0xFFFFFFFFu;
       if (valid) {
         const uint32_t key = s_keys[li];
@@ -415,44 +398,64 @@ size_t radix_hist_bytes(int64_t n_max) { return 4 * (size_t)kRadix * (size_t)rad
 // last pass also writes the values' tile counts in sorted order and their 256-position sums
 // (see k_rs_scatter).
 template <int ITEMS>
-static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr, int64_t n_max, int bits,
+static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], uint32_t *n_ptr, int64_t n_max, int bits,
                          uint32_t *hist, uint32_t *scan, uint32_t *tot, int *cur_out, const TileTail *tail,
-                         hipStream_t s) {
+                         const uint32_t *first_keys, hipStream_t s) {
   constexpr int TILE = kBlock * ITEMS;
   const int nb_max = (int)((n_max + TILE - 1) / TILE);
   const int stride = (int)radix_stride(n_max);
+  const uint32_t n_all = (uint32_t)n_max;
   const TileTail none{nullptr, nullptr, nullptr};
+  const unsigned grid = radix_grid(nb_max);
   int cur = 0;
   for (int shift = 0; shift < bits; shift += kRadixBits) {
+    const bool first = shift == 0 && first_keys;
     const bool last = shift + kRadixBits >= bits;
-    hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], n_ptr, shift, hist,
-                       stride);
-    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, s, n_ptr, hist, scan, tot, stride, TILE);
-    if (last && tail) {
-      auto kernel = k_rs_scatter<ITEMS, true>;
-      hipLaunchKernelGGL(kernel, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], vals[cur],
-                         keys[cur ^ 1], vals[cur ^ 1], n_ptr, shift, hist, scan, tot, stride, *tail);
+    const uint32_t *kin = first ? first_keys : keys[cur];
+    if (first)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_hist<ITEMS, true>), dim3(grid), dim3(kBlock), 0, s, kin, n_ptr, n_all,
+                         shift, hist, stride);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_hist<ITEMS, false>), dim3(grid), dim3(kBlock), 0, s, kin, n_ptr, n_all,
+                         shift, hist, stride);
+    // the first pass's workgroups cover all candidates; the later passes' the count it kept
+    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, s, first ? nullptr : n_ptr, n_all, hist, scan, tot,
+                       stride, TILE);
+    const TileTail &tt = (last && tail) ? *tail : none;
+    if (first && last && tail) {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<ITEMS, true, true>), dim3(grid), dim3(kBlock), 0, s, kin,
+                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, n_all, n_ptr, shift, hist, scan, tot, stride,
+                         tt);
+    } else if (first) {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<ITEMS, false, true>), dim3(grid), dim3(kBlock), 0, s, kin,
+                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, n_all, n_ptr, shift, hist, scan, tot, stride,
+                         tt);
+    } else if (last && tail) {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<ITEMS, true, false>), dim3(grid), dim3(kBlock), 0, s, kin,
+                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, n_all, n_ptr, shift, hist, scan, tot, stride,
+                         tt);
     } else {
-      auto kernel = k_rs_scatter<ITEMS, false>;
-      hipLaunchKernelGGL(kernel, dim3(radix_grid(nb_max)), dim3(kBlock), 0, s, keys[cur], vals[cur],
-                         keys[cur ^ 1], vals[cur ^ 1], n_ptr, shift, hist, scan, tot, stride, none);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<ITEMS, false, false>), dim3(grid), dim3(kBlock), 0, s, kin,
+                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, n_all, n_ptr, shift, hist, scan, tot, stride,
+                         tt);
     }
     cur ^= 1;
   }
   *cur_out = cur;
 }
 
-hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_ptr, int64_t n_max,
+hipError_t launch_radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *n_ptr, int64_t n_max,
                              int bits, uint32_t *hist, uint32_t *scan, uint32_t *tot, int *result_buf,
-                             hipStream_t s, const uint32_t *tiles_of, uint32_t *tiles_out, uint32_t *block_sum) {
+                             hipStream_t s, const uint32_t *tiles_of, uint32_t *tiles_out, uint32_t *block_sum,
+                             const uint32_t *first_keys) {
   *result_buf = 0;
   if (n_max <= 0) return hipSuccess;
   const TileTail t{tiles_of, tiles_out, block_sum};
   const TileTail *tail = tiles_of ? &t : nullptr;
   switch (radix_items(n_max)) {
-    case kSortItemsHuge: radix_passes<kSortItemsHuge>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, tail, s); break;
-    case kSortItems: radix_passes<kSortItems>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, tail, s); break;
-    default: radix_passes<kSortItemsSmall>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, tail, s); break;
+    case kSortItemsHuge: radix_passes<kSortItemsHuge>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, tail, first_keys, s); break;
+    case kSortItems: radix_passes<kSortItems>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, tail, first_keys, s); break;
+    default: radix_passes<kSortItemsSmall>(keys, vals, n_ptr, n_max, bits, hist, scan, tot, result_buf, tail, first_keys, s); break;
   }
   return hipGetLastError();
 }

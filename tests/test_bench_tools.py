@@ -30,4 +30,4 @@ def test_survey_work_model():
     assert abs(bench.LANE_OP_PEAK_TOPS - 39.3216) < 1e-9
     # every library stage belongs to exactly one survey step
     stages = [s for v in bench.SURVEY_STEPS.values() for s in v]
-    assert len(stages) == len(set(stages)) == 10
+    assert len(stages) == len(set(stages)) == 9
