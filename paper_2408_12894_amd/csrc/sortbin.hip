@@ -80,8 +80,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const uint32_t *in
   // sums, then its exclusive prefixes (a second read of its counts, from cache)
   const int per = (nb + kScanThreads - 1) / kScanThreads;
   const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
+  // up to kScanHeld counts per thread are loaded together and kept for the prefixes (one memory
+  // round trip instead of one per count); more (above kScanHeld x 1024 workgroups) are re-read
+  constexpr int kScanHeld = 8;
+  uint32_t held[kScanHeld];
+#pragma unroll
+  for (int i = 0; i < kScanHeld; ++i) held[i] = lo + i < hi ? in[lo + i] : 0u;
   unsigned long long mine = 0;
-  for (int k = lo; k < hi; ++k) mine += in[k];
+#pragma unroll
+  for (int i = 0; i < kScanHeld; ++i) mine += held[i];
+  for (int k = lo + kScanHeld; k < hi; ++k) mine += in[k];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   unsigned long long inc = mine;
 #pragma unroll
@@ -98,7 +106,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const uint32_t *in
     run += (k < w) ? t : 0ull;
     total += t;
   }
-  for (int k = lo; k < hi; ++k) {
+#pragma unroll
+  for (int i = 0; i < kScanHeld; ++i) {
+    if (lo + i < hi) prefix[lo + i] = run;
+    run += held[i];
+  }
+  for (int k = lo + kScanHeld; k < hi; ++k) {
     prefix[k] = run;
     run += in[k];
   }
