@@ -62,10 +62,12 @@ constexpr int kLdsRound2MinTiles = 6144;
 // it then adds exact zeros, keeps its T (T / (1 - 0) = T) and its V. The weight gmv is the
 // unclamped alpha o G, and 0 where the 0.99 clamp is active (alpha does not depend on opacity
 // or q there); entries whose opacity cannot reach the clamp (see stage_entry) skip its test.
-template <int PPT, bool CLAMP>
+// Without CHECK the caller guarantees that the walk has reached the entry in every pixel of the
+// wave.
+template <int PPT, bool CLAMP, bool CHECK>
 __device__ __forceinline__ bool decide(const float (&fy)[PPT], const int (&last)[PPT], int jpos, float my, float r,
-                                       float dx, float ck, float thr, float t, float (&dyv)[PPT],
-                                       float (&aev)[PPT], float (&gmv)[PPT]) {
+                                       float dx, float ck, float thr, float t, float (&dyv)[PPT], float (&aev)[PPT],
+                                       float (&gmv)[PPT]) {
   bool contrib = false;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
@@ -73,7 +75,7 @@ __device__ __forceinline__ bool decide(const float (&fy)[PPT], const int (&last)
     dyv[k] = dy;
     const float l = conic_kq(ck, r, dx, dy, t);   // k q + log2 o
     const float a0 = alpha_from_log2(l);          // o G
-    const bool ok = jpos < last[k] && l >= thr;
+    const bool ok = (!CHECK || jpos < last[k]) && l >= thr;
     if (CLAMP) {
       aev[k] = ok ? fminf(kAlphaMax, a0) : 0.0f;
       gmv[k] = (ok && a0 <= kAlphaMax) ? a0 : 0.0f;
@@ -105,13 +107,12 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
     const uint32_t *__restrict__ order) {
   constexpr int NT = kTile * kTile / PPT;
   constexpr int ROWS = NT / kTile;
-  constexpr int WAVES = NT / 64;
+  static_assert(NT == 64, "one wave per tile");
   __shared__ float4 s_a[kBwdBatch];
   __shared__ float4 s_b[kBwdBatch];
   __shared__ float4 s_c[kBwdBatch];
   __shared__ uint32_t s_id[kBwdBatch];
   __shared__ int s_pos[kBwdBatch];
-  __shared__ int s_max[WAVES];
   constexpr int RS = LDS_ROUND2 ? kRedStride : 64;   // component stride of the reduction
   __shared__ __align__(16) float s_red[kG2d * RS];   // the per-entry reduction
   __shared__ __align__(16) float s_red2[4 * kG2d];   // its first round's partials (LDS form)
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   float fy[PPT], d0[PPT], d1[PPT], d2[PPT];
   float T[PPT], V[PPT];
   int last[PPT];
-  int mylast = 0;
+  int mylast = 0, myfirst = list_len;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int py = y0 + (tid >> 4) + ROWS * k;
@@ -150,16 +151,14 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       d1[k] = dimg[plane + pix];
       d2[k] = dimg[2 * plane + pix];
       V[k] = d0[k] * bg0 + d1[k] * bg1 + d2[k] * bg2;
-      mylast = max(mylast, last[k]);
     }
+    mylast = max(mylast, last[k]);
+    myfirst = min(myfirst, last[k]);   // 0 for a pixel outside the image
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mylast = max(mylast, __shfl_xor(mylast, o, 64));
-  if (WAVES > 1) {
-    if (lane == 0) s_max[tid >> 6] = mylast;
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) mylast = max(mylast, s_max[w]);
+  for (int o = 32; o > 0; o >>= 1) {
+    mylast = max(mylast, __shfl_xor(mylast, o, 64));
+    myfirst = min(myfirst, __shfl_xor(myfirst, o, 64));
   }
   const unsigned long long lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int end = mylast; end > 0; end -= kBwdBatch) {
@@ -167,19 +166,17 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
     const int cnt = end - start;
     __syncthreads();
     // stage only the entries the forward blended into some pixel of the tile (its taken
-    // flags), compacted in list order: the others change no T, no suffix and no gradient
-    int cntc = 0;
+    // flags), compacted in list order: the others change no T, no suffix and no gradient.
+    // The first nlow staged entries lie below every pixel's last entry (myfirst): there the
+    // walk has reached the entry in every pixel and the decision skips that test
+    int cntc = 0, nlow = 0;
     for (int e0 = 0; e0 < cnt; e0 += NT) {
       const int e = e0 + tid;
-      const bool f = e < cnt && (NT != 64 || taken[rg.x + start + e] != 0);
-      int idx = e;
-      if (NT == 64) {
-        const unsigned long long m = __ballot(f);
-        idx = cntc + (int)__popcll(m & lanes_below);
-        cntc += (int)__popcll(m);
-      } else {
-        cntc = cnt;
-      }
+      const bool f = e < cnt && taken[rg.x + start + e] != 0;
+      const unsigned long long m = __ballot(f);
+      const int idx = cntc + (int)__popcll(m & lanes_below);
+      cntc += (int)__popcll(m);
+      nlow += (int)__popcll(__ballot(f && start + e < myfirst));
       if (f) {
         const uint32_t g = values[rg.x + start + e];
         s_id[idx] = g;
@@ -188,109 +185,122 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       }
     }
     __syncthreads();
-    for (int jl = cntc - 1; jl >= 0; --jl) {
-      const int jpos = s_pos[jl];
-      const float4 A = s_a[jl];
-      const float4 B = s_b[jl];
-      const float4 BL = s_c[jl];   // threshold on l, blue, clamp flag
-      const float dx = fx - A.x;
-      const float t = conic_column(A.w, dx, B.y);
-      // first only what decides whether a pixel takes part; the transmittance recovery and
-      // the gradient run when some pixel of the wave does. The whole entry is instantiated with
-      // and without the clamp's test (the flag is the same in every lane: a uniform branch), so
-      // that without it alpha itself is the weight of the gradient
-      auto entry = [&](auto clamp_tag) {
-        constexpr bool CLAMP = decltype(clamp_tag)::value;
-        float dyv[PPT], aev[PPT], gmv[PPT];
-        if (!__any(decide<PPT, CLAMP>(fy, last, jpos, A.y, A.z, dx, B.x, BL.x, t, dyv, aev, gmv))) return;
-        {
-        // the gradient arithmetic may contract into FMAs (the decision above must not: it
-        // repeats the forward's, bit for bit)
+    // back to front over the staged entries: first those that some pixel's walk may not have
+    // reached (with the test of the position), then the rest without it (four compares per
+    // entry fewer: 720p / 500k 0.221 -> 0.217 ms, 1080p / 1M unchanged). The two loops keep
+    // their counters in vector registers: with scalar counters, or without the early return
+    // below, the compiler copied the eight T and V registers on every iteration (8 more VALU
+    // than the test saves)
+    auto walk = [&](auto check_tag, int hi, int lo) {
+      constexpr bool CHECK = decltype(check_tag)::value;
+      for (int jl = hi - 1; jl >= lo; --jl) {
+        const int jpos = CHECK ? s_pos[jl] : 0;
+        const float4 A = s_a[jl];
+        const float4 B = s_b[jl];
+        const float4 BL = s_c[jl];   // threshold on l, blue, clamp flag
+        const float dx = fx - A.x;
+        const float t = conic_column(A.w, dx, B.y);
+        // first only what decides whether a pixel takes part; the transmittance recovery and
+        // the gradient run when some pixel of the wave does (always, in a consistent state: the
+        // entry was staged because the forward blended it into some pixel of the tile, and the
+        // decision repeats the forward's). The whole entry is instantiated with and without the
+        // clamp's test (the flag is the same in every lane: a uniform branch), so that without
+        // it alpha itself is the weight of the gradient
+        auto entry = [&](auto clamp_tag) {
+          constexpr bool CLAMP = decltype(clamp_tag)::value;
+          float dyv[PPT], aev[PPT], gmv[PPT];
+          if (!__any(decide<PPT, CLAMP, CHECK>(fy, last, jpos, A.y, A.z, dx, B.x, BL.x, t, dyv, aev, gmv))) return;
+          {
+          // the gradient arithmetic may contract into FMAs (the decision above must not: it
+          // repeats the forward's, bit for bit)
 #pragma clang fp contract(fast)
-        float gr[kG2d];
-        gr[6] = gr[7] = gr[8] = 0.0f;
-        // with alpha = o G below the clamp, dalpha/do = alpha / o and dalpha/dq = -alpha / 2, so one
-        // sum e = dL/dalpha alpha per pixel serves both: dL/do = sum e / o and dL/dq = -e / 2. With
-        // q = a dx^2 + 2 b dx dy + c dy^2 every q-derivative is a moment of e times a factor of
-        // the Gaussian: dL/d(a, b, c) = -(1 / 2) (sum e dx^2, 2 sum e dx dy, sum e dy^2) and
-        // dL/dmu' = (a sum e dx + b sum e dy, b sum e dx + c sum e dy). A lane's pixels share
-        // their column, so it needs only E0 = sum e, E1 = sum e dy and E2 = sum e dy^2 over them
-        float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
+          float gr[kG2d];
+          gr[6] = gr[7] = gr[8] = 0.0f;
+          // with alpha = o G below the clamp, dalpha/do = alpha / o and dalpha/dq = -alpha / 2, so one
+          // sum e = dL/dalpha alpha per pixel serves both: dL/do = sum e / o and dL/dq = -e / 2. With
+          // q = a dx^2 + 2 b dx dy + c dy^2 every q-derivative is a moment of e times a factor of
+          // the Gaussian: dL/d(a, b, c) = -(1 / 2) (sum e dx^2, 2 sum e dx dy, sum e dy^2) and
+          // dL/dmu' = (a sum e dx + b sum e dy, b sum e dx + c sum e dy). A lane's pixels share
+          // their column, so it needs only E0 = sum e, E1 = sum e dy and E2 = sum e dy^2 over them
+          float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          const float alpha = aev[k], dy = dyv[k];
-          const float Ti = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
-          const float wT = alpha * Ti;
-          const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * BL.y;   // dL/dC . c
-          const float diff = dcc - V[k];
-          const float e = (Ti * diff) * (CLAMP ? gmv[k] : alpha);     // dL/dalpha alpha
-          gr[6] = fmaf(wT, d0[k], gr[6]);
-          gr[7] = fmaf(wT, d1[k], gr[7]);
-          gr[8] = fmaf(wT, d2[k], gr[8]);
-          V[k] = fmaf(alpha, diff, V[k]);                             // alpha dcc + (1 - alpha) V
-          T[k] = Ti;
-          const float ey = e * dy;
-          E0 += e;
-          E1 += ey;
-          E2 = fmaf(ey, dy, E2);
-        }
-        // the moments sum e dx, e dy, e dx^2, e dx dy, e dy^2, e over the lane's pixels (dx is
-        // the column's): the conic and opacity factors are the Gaussian's own and are applied
-        // once per Gaussian after all its tiles (k_preprocess_bwd)
-        gr[0] = dx * E0;
-        gr[1] = E1;
-        gr[2] = dx * gr[0];
-        gr[3] = dx * E1;
-        gr[4] = E2;
-        gr[5] = E0;
-        {
-          // the nine components summed over the wave: each lane writes its nine values to LDS
-          // component-major. LDS form: 36 lanes each add 16 values of one component (four float4
-          // reads), then lane c < 9 adds the four partials of component c to the Gaussian's 36-byte
-          // row (one atomic instruction). DPP form: each lane adds three float4 (4 lanes' values of
-          // components l / 16, 4 + l / 16 and, lanes below 16, 8), DPP sums over each row of 16 lanes
-          // follow (lanes 0, 16, 32, 48 then hold the sums; three atomic instructions). DPP costs
-          // about two VALU issue slots per operation, an LDS round a wait: the LDS form for frames
-          // with enough tiles to hide the wait (8 waves per SIMD at 1080p: 0.233 against 0.254 ms
-          // with a three-float4 first round), DPP for small ones (720p, 3.5 waves per SIMD: 0.238
-          // against 0.248 ms). The workgroup is one wave, so its barriers only order the LDS
-          // accesses.
-          static_assert(NT == 64, "the per-entry reduction assumes one wave per tile");
+          for (int k = 0; k < PPT; ++k) {
+            const float alpha = aev[k], dy = dyv[k];
+            const float Ti = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
+            const float wT = alpha * Ti;
+            const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * BL.y;   // dL/dC . c
+            const float diff = dcc - V[k];
+            const float e = (Ti * diff) * (CLAMP ? gmv[k] : alpha);     // dL/dalpha alpha
+            gr[6] = fmaf(wT, d0[k], gr[6]);
+            gr[7] = fmaf(wT, d1[k], gr[7]);
+            gr[8] = fmaf(wT, d2[k], gr[8]);
+            V[k] = fmaf(alpha, diff, V[k]);                             // alpha dcc + (1 - alpha) V
+            T[k] = Ti;
+            const float ey = e * dy;
+            E0 += e;
+            E1 += ey;
+            E2 = fmaf(ey, dy, E2);
+          }
+          // the moments sum e dx, e dy, e dx^2, e dx dy, e dy^2, e over the lane's pixels (dx is
+          // the column's): the conic and opacity factors are the Gaussian's own and are applied
+          // once per Gaussian after all its tiles (k_preprocess_bwd)
+          gr[0] = dx * E0;
+          gr[1] = E1;
+          gr[2] = dx * gr[0];
+          gr[3] = dx * E1;
+          gr[4] = E2;
+          gr[5] = E0;
+          {
+            // the nine components summed over the wave: each lane writes its nine values to LDS
+            // component-major. LDS form: 36 lanes each add 16 values of one component (four float4
+            // reads), then lane c < 9 adds the four partials of component c to the Gaussian's 36-byte
+            // row (one atomic instruction). DPP form: each lane adds three float4 (4 lanes' values of
+            // components l / 16, 4 + l / 16 and, lanes below 16, 8), DPP sums over each row of 16 lanes
+            // follow (lanes 0, 16, 32, 48 then hold the sums; three atomic instructions). DPP costs
+            // about two VALU issue slots per operation, an LDS round a wait: the LDS form for frames
+            // with enough tiles to hide the wait (8 waves per SIMD at 1080p: 0.233 against 0.254 ms
+            // with a three-float4 first round), DPP for small ones (720p, 3.5 waves per SIMD: 0.238
+            // against 0.248 ms). The workgroup is one wave, so its barriers only order the LDS
+            // accesses.
+            static_assert(NT == 64, "the per-entry reduction assumes one wave per tile");
 #pragma unroll
-          for (int c = 0; c < kG2d; ++c) s_red[c * RS + lane] = gr[c];
-          __syncthreads();
-          const float4 *r4 = reinterpret_cast<const float4 *>(s_red);
-          const size_t row = (size_t)s_id[jl] * kG2d;
-          if (LDS_ROUND2) {
-            // lane 4 c + h: 16 values of component c (lanes 4 h .. 4 h + 3 of each group of 16)
-            const float4 q0 = r4[red_r1], q1 = r4[red_r1 + 4], q2 = r4[red_r1 + 8], q3 = r4[red_r1 + 12];
-            const float p = (((q0.x + q0.y) + (q0.z + q0.w)) + ((q1.x + q1.y) + (q1.z + q1.w))) +
-                            (((q2.x + q2.y) + (q2.z + q2.w)) + ((q3.x + q3.y) + (q3.z + q3.w)));
-            if (lane < 4 * kG2d) s_red2[lane] = p;
+            for (int c = 0; c < kG2d; ++c) s_red[c * RS + lane] = gr[c];
             __syncthreads();
-            const float4 q = reinterpret_cast<const float4 *>(s_red2)[red_lo9];   // component lane (lanes 0..8)
-            const float x = (q.x + q.y) + (q.z + q.w);
-            if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[row + lane], x);
-          } else {
-            const float4 ra = r4[lane], rb = r4[lane + 64], rc = r4[red_hi];
-            const float p0 = (ra.x + ra.y) + (ra.z + ra.w);   // component lane / 16
-            const float p1 = (rb.x + rb.y) + (rb.z + rb.w);   // component 4 + lane / 16
-            const float p2 = (rc.x + rc.y) + (rc.z + rc.w);   // component 8 (lanes 0..15)
-            const float s0 = row_sum16(p0), s1 = row_sum16(p1), s2 = row_sum16(p2);
-            if ((lane & 15) == 0) {
-              if (s0 != 0.0f) atomicAdd(&g2d[row + (lane >> 4)], s0);
-              if (s1 != 0.0f) atomicAdd(&g2d[row + 4 + (lane >> 4)], s1);
-              if (lane == 0 && s2 != 0.0f) atomicAdd(&g2d[row + 8], s2);
+            const float4 *r4 = reinterpret_cast<const float4 *>(s_red);
+            const size_t row = (size_t)s_id[jl] * kG2d;
+            if (LDS_ROUND2) {
+              // lane 4 c + h: 16 values of component c (lanes 4 h .. 4 h + 3 of each group of 16)
+              const float4 q0 = r4[red_r1], q1 = r4[red_r1 + 4], q2 = r4[red_r1 + 8], q3 = r4[red_r1 + 12];
+              const float p = (((q0.x + q0.y) + (q0.z + q0.w)) + ((q1.x + q1.y) + (q1.z + q1.w))) +
+                              (((q2.x + q2.y) + (q2.z + q2.w)) + ((q3.x + q3.y) + (q3.z + q3.w)));
+              if (lane < 4 * kG2d) s_red2[lane] = p;
+              __syncthreads();
+              const float4 q = reinterpret_cast<const float4 *>(s_red2)[red_lo9];   // component lane (lanes 0..8)
+              const float x = (q.x + q.y) + (q.z + q.w);
+              if (lane < kG2d && x != 0.0f) atomicAdd(&g2d[row + lane], x);
+            } else {
+              const float4 ra = r4[lane], rb = r4[lane + 64], rc = r4[red_hi];
+              const float p0 = (ra.x + ra.y) + (ra.z + ra.w);   // component lane / 16
+              const float p1 = (rb.x + rb.y) + (rb.z + rb.w);   // component 4 + lane / 16
+              const float p2 = (rc.x + rc.y) + (rc.z + rc.w);   // component 8 (lanes 0..15)
+              const float s0 = row_sum16(p0), s1 = row_sum16(p1), s2 = row_sum16(p2);
+              if ((lane & 15) == 0) {
+                if (s0 != 0.0f) atomicAdd(&g2d[row + (lane >> 4)], s0);
+                if (s1 != 0.0f) atomicAdd(&g2d[row + 4 + (lane >> 4)], s1);
+                if (lane == 0 && s2 != 0.0f) atomicAdd(&g2d[row + 8], s2);
+              }
             }
           }
-        }
-        }
-      };
-      if (__builtin_amdgcn_readfirstlane(__float_as_int(BL.z)) != 0)
-        entry(std::integral_constant<bool, true>{});
-      else
-        entry(std::integral_constant<bool, false>{});
-    }
+          }
+        };
+        if (__builtin_amdgcn_readfirstlane(__float_as_int(BL.z)) != 0)
+          entry(std::integral_constant<bool, true>{});
+        else
+          entry(std::integral_constant<bool, false>{});
+      }
+    };
+    walk(std::true_type{}, cntc, nlow);
+    walk(std::false_type{}, nlow, 0);
   }
 }
 
