@@ -292,8 +292,8 @@ flod_status flod_level_transition(flod_ctx *ctx, const flod_level *in, float s_m
    which must still hold its values (the walk of each pixel is clamped to its tile's list, so
    changed n_contrib values give wrong gradients but no access outside the context's
    buffers). Besides them the backward reads the O(K) state the forward left in ctx: the
-   sorted list, the per-instance flags of the entries blended somewhere in their tile, and the
-   per-tile counts of those entries (flod_view: taken, tile_taken). Returns
+   tile ranges of the sorted list, per tile the list of the entries blended somewhere in the
+   tile, and the per-tile counts of those entries (flod_view: blended, tile_blended). Returns
    FLOD_ERR_UNSUPPORTED after a selective render or when no render preceded it. FP32
    atomic accumulation: results are deterministic up to summation order. */
 flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_grads *grads,
@@ -335,10 +335,12 @@ typedef struct {
                                    in its last step); the first view after it applies them
                                    in place with the stored FP32 conic and opacity (one
                                    kernel on the stream of the last call, waited for)      */
-  const uint8_t *taken;         /* [n_instances] 1 where the forward blended the sorted
-                                   instance into some pixel of its tile (state the backward
-                                   reads: it walks only these entries)                     */
-  const uint32_t *tile_taken;   /* [tiles] count of such instances per tile (the backward's
+  const uint32_t *blended;      /* [n_instances][2] per tile, the sorted instances the forward
+                                   blended into some pixel of the tile, as (position in the
+                                   tile's list, Gaussian) pairs in list order at the start of
+                                   the tile's range; the rest of the range is unspecified
+                                   (state the backward reads: it walks only these entries)  */
+  const uint32_t *tile_blended; /* [tiles] count of such instances per tile (the backward's
                                    tile order)                                             */
 } flod_view;
 flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out);

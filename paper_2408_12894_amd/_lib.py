@@ -79,7 +79,7 @@ class View(C.Structure):
     _fields_ = [("tile_ids", C.c_void_p), ("values", C.c_void_p), ("ranges", C.c_void_p),
                 ("depth_bits", C.c_void_p), ("bin", C.c_void_p), ("tiles_touched", C.c_void_p),
                 ("xy_conic", C.c_void_p), ("conic_c_opacity_rg", C.c_void_p), ("blue", C.c_void_p),
-                ("grad2d", C.c_void_p), ("taken", C.c_void_p), ("tile_taken", C.c_void_p)]
+                ("grad2d", C.c_void_p), ("blended", C.c_void_p), ("tile_blended", C.c_void_p)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)

@@ -100,14 +100,14 @@ constexpr int kRedStride = 80;
 // them (see below) before one atomic instruction adds the nine sums.
 template <int PPT, bool LDS_ROUND2>
 __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
-    const uint2 *__restrict__ ranges, const uint32_t *__restrict__ values, const float4 *__restrict__ xyab,
-    const float4 *__restrict__ cop, const float2 *__restrict__ blue, int W, int H, int tiles_x, int n_tiles,
-    float bg0, float bg1, float bg2, const float *__restrict__ final_T, const int32_t *__restrict__ n_contrib,
-    const float *__restrict__ dimg, float *__restrict__ g2d, const uint8_t *__restrict__ taken,
+    const uint2 *__restrict__ ranges, const float4 *__restrict__ xyab, const float4 *__restrict__ cop,
+    const float2 *__restrict__ blue, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
+    const float *__restrict__ final_T, const int32_t *__restrict__ n_contrib, const float *__restrict__ dimg,
+    float *__restrict__ g2d, const uint2 *__restrict__ blended, const uint32_t *__restrict__ tile_blended,
     const uint32_t *__restrict__ order) {
   constexpr int NT = kTile * kTile / PPT;
   constexpr int ROWS = NT / kTile;
-  static_assert(NT == 64, "one wave per tile");
+  static_assert(NT == 64 && kBwdBatch == NT, "one wave per tile, one staged entry per lane");
   __shared__ float4 s_a[kBwdBatch];
   __shared__ float4 s_b[kBwdBatch];
   __shared__ float4 s_c[kBwdBatch];
@@ -125,18 +125,26 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   const int red_l36 = min(lane, 4 * kG2d - 1);
   const int red_r1 = (red_l36 >> 2) * (kRedStride / 4) + (red_l36 & 3);
   const int red_hi = min(lane + 128, kG2d * 16 - 1), red_lo9 = min(lane, kG2d - 1);
+  // zero in a vector register, opaque to the compiler: added to the DPP form's lane-0 atomic
+  // address, which the compiler would otherwise see as uniform and send through its atomic
+  // combining path (a lane loop plus a wait for all outstanding memory operations per entry)
+  int vzero = 0;
+  asm volatile("" : "+v"(vzero));
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
   const int px = x0 + (tid & (kTile - 1));
   const float fx = (float)(tid & (kTile - 1)) + 0.5f;   // pixel centres relative to the tile's corner
   const size_t plane = (size_t)W * H;
   const uint2 rg = ranges[tile];
-  // a pixel's walk starts at its n_contrib, clamped to the tile's list so that no value of that
-  // input (it comes from the caller's buffer) can take the walk outside the list
+  // the walk covers the entries the forward blended into some pixel of the tile (the others
+  // change no T, no suffix and no gradient), which it listed at the start of the tile's range;
+  // a pixel takes part in those before its n_contrib (the count is clamped to the list, and
+  // n_contrib, which comes from the caller's buffer, only enters comparisons)
   const int list_len = (int)(rg.y - rg.x);
+  const int n_bl = min((int)tile_blended[tile], list_len);
   float fy[PPT], d0[PPT], d1[PPT], d2[PPT];
   float T[PPT], V[PPT];
   int last[PPT];
-  int mylast = 0, myfirst = list_len;
+  int myfirst = list_len;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int py = y0 + (tid >> 4) + ROWS * k;
@@ -152,38 +160,30 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
       d2[k] = dimg[2 * plane + pix];
       V[k] = d0[k] * bg0 + d1[k] * bg1 + d2[k] * bg2;
     }
-    mylast = max(mylast, last[k]);
     myfirst = min(myfirst, last[k]);   // 0 for a pixel outside the image
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    mylast = max(mylast, __shfl_xor(mylast, o, 64));
-    myfirst = min(myfirst, __shfl_xor(myfirst, o, 64));
-  }
-  const unsigned long long lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int end = mylast; end > 0; end -= kBwdBatch) {
+  for (int o = 32; o > 0; o >>= 1) myfirst = min(myfirst, __shfl_xor(myfirst, o, 64));
+  // batches of 64 listed entries (one per lane), back to front. Listing them in the forward
+  // instead of staging 64 list positions per batch and compacting those it blended: 9% of the
+  // positions are listed at 1080p / 1M (92 of 1040 per tile on average), so a tile took about
+  // 16 batches, each two dependent global loads and two barriers for a handful of entries
+  for (int end = n_bl; end > 0; end -= kBwdBatch) {
     const int start = max(0, end - kBwdBatch);
     const int cnt = end - start;
     __syncthreads();
-    // stage only the entries the forward blended into some pixel of the tile (its taken
-    // flags), compacted in list order: the others change no T, no suffix and no gradient.
-    // The first nlow staged entries lie below every pixel's last entry (myfirst): there the
+    // the first nlow staged entries lie below every pixel's last entry (myfirst): there the
     // walk has reached the entry in every pixel and the decision skips that test
-    int cntc = 0, nlow = 0;
-    for (int e0 = 0; e0 < cnt; e0 += NT) {
-      const int e = e0 + tid;
-      const bool f = e < cnt && taken[rg.x + start + e] != 0;
-      const unsigned long long m = __ballot(f);
-      const int idx = cntc + (int)__popcll(m & lanes_below);
-      cntc += (int)__popcll(m);
-      nlow += (int)__popcll(__ballot(f && start + e < myfirst));
-      if (f) {
-        const uint32_t g = values[rg.x + start + e];
-        s_id[idx] = g;
-        s_pos[idx] = start + e;
-        stage_entry(xyab, cop, blue, g, x0, y0, s_a[idx], s_b[idx], s_c[idx]);
-      }
+    const bool f = tid < cnt;
+    int pos = 0;
+    if (f) {
+      const uint2 pe = blended[rg.x + start + tid];   // (list position, Gaussian)
+      pos = (int)pe.x;
+      s_id[tid] = pe.y;
+      s_pos[tid] = pos;
+      stage_entry(xyab, cop, blue, pe.y, x0, y0, s_a[tid], s_b[tid], s_c[tid]);
     }
+    const int nlow = (int)__popcll(__ballot(f && pos < myfirst));
     __syncthreads();
     // back to front over the staged entries: first those that some pixel's walk may not have
     // reached (with the test of the position), then the rest without it (four compares per
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
               if ((lane & 15) == 0) {
                 if (s0 != 0.0f) atomicAdd(&g2d[row + (lane >> 4)], s0);
                 if (s1 != 0.0f) atomicAdd(&g2d[row + 4 + (lane >> 4)], s1);
-                if (lane == 0 && s2 != 0.0f) atomicAdd(&g2d[row + 8], s2);
+                if (lane == 0 && s2 != 0.0f) atomicAdd(&g2d[row + 8 + vzero], s2);
               }
             }
           }
@@ -299,40 +299,40 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
           entry(std::integral_constant<bool, false>{});
       }
     };
-    walk(std::true_type{}, cntc, nlow);
+    walk(std::true_type{}, cnt, nlow);
     walk(std::false_type{}, nlow, 0);
   }
 }
 
 template <bool LDS_ROUND2>
-static void launch_blend_bwd_t(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
-                               const float2 *blue, const DevCamera &cam, const float bg[3], const float *final_T,
-                               const int32_t *n_contrib, const float *dL_dimage, float *g2d, const uint8_t *taken,
+static void launch_blend_bwd_t(const uint2 *ranges, const float4 *xyab, const float4 *cop, const float2 *blue,
+                               const DevCamera &cam, const float bg[3], const float *final_T, const int32_t *n_contrib,
+                               const float *dL_dimage, float *g2d, const uint2 *blended, const uint32_t *tile_blended,
                                const uint32_t *order, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   auto kernel = k_blend_bwd<kBwdPix, LDS_ROUND2>;
   if (ev_start || ev_stop) {
     // timed from the kernel's own dispatch: no event packets between it and its neighbours
-    hipExtLaunchKernelGGL(kernel, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s,
-                          ev_start, ev_stop, 0, ranges, values, xyab, cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles,
-                          bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimage, g2d, taken, order);
+    hipExtLaunchKernelGGL(kernel, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s, ev_start, ev_stop, 0, ranges,
+                          xyab, cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T,
+                          n_contrib, dL_dimage, g2d, blended, tile_blended, order);
   } else {
-    hipLaunchKernelGGL(kernel, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s, ranges,
-                       values, xyab, cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T,
-                       n_contrib, dL_dimage, g2d, taken, order);
+    hipLaunchKernelGGL(kernel, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s, ranges, xyab, cop, blue, cam.W,
+                       cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimage, g2d, blended,
+                       tile_blended, order);
   }
 }
 
-hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
-                            const float2 *blue, const DevCamera &cam, const float bg[3], const float *final_T,
-                            const int32_t *n_contrib, const float *dL_dimage, float *g2d, const uint8_t *taken,
+hipError_t launch_blend_bwd(const uint2 *ranges, const float4 *xyab, const float4 *cop, const float2 *blue,
+                            const DevCamera &cam, const float bg[3], const float *final_T, const int32_t *n_contrib,
+                            const float *dL_dimage, float *g2d, const uint2 *blended, const uint32_t *tile_blended,
                             const uint32_t *order, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (cam.tiles_x * cam.tiles_y >= kLdsRound2MinTiles)
-    launch_blend_bwd_t<true>(ranges, values, xyab, cop, blue, cam, bg, final_T, n_contrib, dL_dimage, g2d, taken,
-                             order, s, ev_start, ev_stop);
+    launch_blend_bwd_t<true>(ranges, xyab, cop, blue, cam, bg, final_T, n_contrib, dL_dimage, g2d, blended,
+                             tile_blended, order, s, ev_start, ev_stop);
   else
-    launch_blend_bwd_t<false>(ranges, values, xyab, cop, blue, cam, bg, final_T, n_contrib, dL_dimage, g2d, taken,
-                              order, s, ev_start, ev_stop);
+    launch_blend_bwd_t<false>(ranges, xyab, cop, blue, cam, bg, final_T, n_contrib, dL_dimage, g2d, blended,
+                              tile_blended, order, s, ev_start, ev_stop);
   return hipGetLastError();
 }
 

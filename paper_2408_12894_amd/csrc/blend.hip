@@ -16,13 +16,43 @@
 // The workgroup leaves the list as soon as all 256 pixels have stopped.
 //
 // Workgroups take the tiles in order of decreasing list length (k_tile_order). Each tile also
-// records how many of its list entries it blended into some pixel (the entries its backward
-// pass processes), from which the backward orders its tiles.
+// lists the entries it blended into some pixel, the only ones its backward pass processes:
+// (list position, Gaussian) pairs in list order at the start of the tile's range, and their
+// count, from which the backward orders its tiles.
 #include "blend_common.h"
 
 namespace flod {
 
 constexpr int kFwdPix = 1;
+
+// Appends the entries of the staged batch at list position bstart that some pixel blended
+// (s_taken) to the tile's list of blended entries (out, n_bl entries so far; the count is the
+// same in every thread). Called by every thread of the workgroup after a barrier that follows
+// the batch's walk; thread t handles the entries t, t + NT, ...
+template <int NT>
+__device__ __forceinline__ void append_blended(const uint8_t *s_taken, const uint32_t *s_id, uint32_t *s_wcnt,
+                                               int bstart, int n, uint2 *out, uint32_t &n_bl, int tid) {
+  constexpr int W = NT / 64;
+  const int lane = tid & 63, w = tid >> 6;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int e0 = 0; e0 < kBatch; e0 += NT) {
+    const int e = e0 + tid;
+    const bool f = bstart + e < n && s_taken[e] != 0;
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) s_wcnt[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t off = n_bl, tot = 0;
+#pragma unroll
+    for (int v = 0; v < W; ++v) {
+      const uint32_t c = s_wcnt[v];
+      off += v < w ? c : 0u;
+      tot += c;
+    }
+    if (f) out[off + (uint32_t)__popcll(m & below)] = make_uint2((uint32_t)(bstart + e), s_id[e]);
+    n_bl += tot;
+    if (e0 + NT < kBatch) __syncthreads();   // s_wcnt is written again
+  }
+}
 
 template <int PPT>
 __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__restrict__ ranges,
@@ -35,8 +65,8 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
                                                               float *__restrict__ final_T,
                                                               int32_t *__restrict__ n_contrib,
                                                               int32_t *__restrict__ n_blended,
-                                                              uint8_t *__restrict__ taken,
-                                                              uint32_t *__restrict__ tile_taken,
+                                                              uint2 *__restrict__ blended,
+                                                              uint32_t *__restrict__ tile_blended,
                                                               const uint32_t *__restrict__ order) {
   constexpr int NT = kTile * kTile / PPT;   // threads per tile
   constexpr int ROWS = NT / kTile;          // pixel rows covered by one pass of the threads
@@ -44,7 +74,8 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
   __shared__ float4 s_b[kBatch];
   __shared__ float4 s_c[kBatch];
   __shared__ uint8_t s_taken[kBatch];
-  __shared__ int s_count[NT / 64];
+  __shared__ uint32_t s_id[kBatch];
+  __shared__ uint32_t s_wcnt[NT / 64];
   const int tile = (int)order[blockIdx.x];
   const int tid = threadIdx.x;
   const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
@@ -69,7 +100,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
   const uint2 rg = ranges[tile];
   const int n = (int)(rg.y - rg.x);
   int last_start = -1;   // start of the last batch walked
-  int my_taken = 0;      // taken flags this thread wrote out
+  uint32_t n_bl = 0;     // blended entries listed so far
   for (int start = 0; start < n; start += kBatch) {
     bool all_done = true;
 #pragma unroll
@@ -80,17 +111,13 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
     } else {
       if (__syncthreads_and(all_done)) break;
     }
-    // the previous batch's taken flags leave (consecutive bytes), this batch's start at zero
+    // the previous batch's blended entries join the list, this batch's flags start at zero
+    if (start > 0) append_blended<NT>(s_taken, s_id, s_wcnt, start - kBatch, n, blended + rg.x, n_bl, tid);
     for (int e = tid; e < kBatch; e += NT) {
-      if (start > 0) {
-        taken[rg.x + start - kBatch + e] = s_taken[e];
-        my_taken += s_taken[e];
-      }
       s_taken[e] = 0;
-    }
-    for (int e = tid; e < kBatch; e += NT) {
       if (start + e < n) {
         const uint32_t g = values[rg.x + start + e];
+        s_id[e] = g;
         stage_entry(xyab, cop, blue, g, x0, y0, s_a[e], s_b[e], s_c[e]);
       }
     }
@@ -140,24 +167,10 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
     }
     last_start = start;
   }
-  // flags of the last batch walked (entries past the walk are never read by the backward,
-  // which stops at the last blended entry)
+  // the blended entries of the last batch walked (the walk blends nothing after it)
   __syncthreads();
-  if (last_start >= 0)
-    for (int e = tid; e < kBatch && last_start + e < n; e += NT) {
-      taken[rg.x + last_start + e] = s_taken[e];
-      my_taken += s_taken[e];
-    }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) my_taken += __shfl_xor(my_taken, o, 64);
-  if ((tid & 63) == 0) s_count[tid >> 6] = my_taken;
-  __syncthreads();
-  if (tid == 0) {
-    int t = 0;
-#pragma unroll
-    for (int w = 0; w < NT / 64; ++w) t += s_count[w];
-    tile_taken[tile] = (uint32_t)t;
-  }
+  if (last_start >= 0) append_blended<NT>(s_taken, s_id, s_wcnt, last_start, n, blended + rg.x, n_bl, tid);
+  if (tid == 0) tile_blended[tile] = n_bl;
   const size_t plane = (size_t)W * H;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
@@ -175,14 +188,14 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
 
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab, const float4 *cop,
                         const float2 *blue, const DevCamera &cam, const float bg[3], float *image, float *final_T,
-                        int32_t *n_contrib, int32_t *n_blended, uint8_t *taken, uint32_t *tile_taken,
+                        int32_t *n_contrib, int32_t *n_blended, uint2 *blended, uint32_t *tile_blended,
                         const uint32_t *order, hipStream_t s) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   // 1 pixel per thread (4 waves per tile) measured fastest at 1080p / 1M: 0.218 ms against
   // 0.242 ms with 2 and 0.353 ms with 4 (entry loop unrolled by two in that comparison).
   hipLaunchKernelGGL(k_blend<kFwdPix>, dim3(n_tiles), dim3(kTile * kTile / kFwdPix), 0, s, ranges, values, xyab,
                      cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], image, final_T, n_contrib,
-                     n_blended, taken, tile_taken, order);
+                     n_blended, blended, tile_blended, order);
   return hipGetLastError();
 }
 

@@ -57,7 +57,7 @@ enum BufId {
   B_XYAB, B_COP, B_BLUE, B_DEPTH, B_BIN, B_TILES, B_BLOCKVIS, B_PREFIX,
   B_DKEY0, B_DKEY1, B_DVAL0, B_DVAL1, B_TBSUM, B_TPREFIX,
   B_TKEY0, B_TKEY1, B_TVAL0, B_TVAL1, B_HIST, B_SCAN, B_TOT, B_RANGES, B_COUNTERS,
-  B_G2D, B_SSIM, B_TAKEN, B_TILE_TAKEN, B_TILE_ORDER, B_STILES, B_COUNT
+  B_G2D, B_SSIM, B_BLENDED, B_TILE_BLENDED, B_TILE_ORDER, B_STILES, B_COUNT
 };
 
 struct Saved {
@@ -292,12 +292,13 @@ DevCamera dev_camera(const flod_camera *cam) {
 
 float sq32(float d) { return isinf(d) ? INFINITY : (float)((double)d * (double)d); }
 
-// Instances the tail buffers (tile keys and values, both ping-pong halves, taken flags) hold.
+// Instances the tail buffers (tile keys and values, both ping-pong halves, the list of blended
+// entries) hold.
 int64_t instance_capacity(const flod_ctx *c) {
   size_t b = c->buf[B_TKEY0].cap;
   for (BufId id : {B_TKEY1, B_TVAL0, B_TVAL1}) b = b < c->buf[id].cap ? b : c->buf[id].cap;
   int64_t k = (int64_t)(b / 4);
-  const int64_t t = (int64_t)c->buf[B_TAKEN].cap - 4;
+  const int64_t t = (int64_t)(c->buf[B_BLENDED].cap / 8);
   if (t < k) k = t;
   if (k > 0xFFFFFFFEll) k = 0xFFFFFFFEll;
   return k > 0 ? k : 0;
@@ -352,7 +353,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   need(B_SCAN, hist);
   need(B_TOT, 4 * (size_t)kRadix);
   need(B_RANGES, 8 * (size_t)n_tiles);
-  need(B_TILE_TAKEN, 4 * (size_t)n_tiles);
+  need(B_TILE_BLENDED, 4 * (size_t)n_tiles);
   need(B_TILE_ORDER, 4 * (size_t)n_tiles);
   need(B_COUNTERS, 8 * (size_t)kCntSlots);
   if (st != FLOD_OK) {
@@ -442,7 +443,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     if (launch_tile_order_by_length(P<uint2>(c, B_RANGES), n_tiles, order, s) != hipSuccess ||
         launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP),
                      P<float2>(c, B_BLUE), cam, bg, out->image, out->final_T, out->n_contrib, out->n_blended,
-                     P<uint8_t>(c, B_TAKEN), P<uint32_t>(c, B_TILE_TAKEN), order, s) != hipSuccess)
+                     P<uint2>(c, B_BLENDED), P<uint32_t>(c, B_TILE_BLENDED), order, s) != hipSuccess)
       return FLOD_ERR_DEVICE;
     tm.end();
     return FLOD_OK;
@@ -477,7 +478,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
       need(B_TKEY1, 4 * (size_t)Kn);
       need(B_TVAL0, 4 * (size_t)Kn);
       need(B_TVAL1, 4 * (size_t)Kn);
-      need(B_TAKEN, (size_t)Kn + 4);
+      need(B_BLENDED, 8 * (size_t)Kn);
       if (st == FLOD_OK) {
         cap = instance_capacity(c);
         need(B_HIST, hist_bytes(cap));
@@ -1042,14 +1043,14 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   }
   float *g2d = P<float>(ctx, B_G2D);
   if (launch_fill_u32(reinterpret_cast<uint32_t *>(g2d), 0u, 9 * N, s) != hipSuccess) return FLOD_ERR_DEVICE;
-  const uint32_t *vals = sv.sorted_vals ? P<uint32_t>(ctx, B_TVAL1) : P<uint32_t>(ctx, B_TVAL0);
   uint32_t *order = P<uint32_t>(ctx, B_TILE_ORDER);
   hipEvent_t ev_a, ev_b;
   tm.dispatch(FLOD_STAGE_BLEND_BWD, &ev_a, &ev_b);
-  if (launch_tile_order_by_count(P<uint32_t>(ctx, B_TILE_TAKEN), n_tiles, order, s) != hipSuccess ||
-      launch_blend_bwd(P<uint2>(ctx, B_RANGES), vals, P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
+  if (launch_tile_order_by_count(P<uint32_t>(ctx, B_TILE_BLENDED), n_tiles, order, s) != hipSuccess ||
+      launch_blend_bwd(P<uint2>(ctx, B_RANGES), P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
                        P<float2>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d,
-                       P<uint8_t>(ctx, B_TAKEN), order, s, ev_a, ev_b) != hipSuccess)
+                       P<uint2>(ctx, B_BLENDED), P<uint32_t>(ctx, B_TILE_BLENDED), order, s, ev_a, ev_b) !=
+          hipSuccess)
     return FLOD_ERR_DEVICE;
   tm.begin(FLOD_STAGE_PREPROCESS_BWD);
   PreParams p = base_params(sv.cam, sv.sh_degree);
@@ -1097,8 +1098,8 @@ flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out) {
     c->saved.grad2d_moments = false;
   }
   out->grad2d = sv.has_grad2d ? P<float>(c, B_G2D) : nullptr;
-  out->taken = P<uint8_t>(c, B_TAKEN);
-  out->tile_taken = P<uint32_t>(c, B_TILE_TAKEN);
+  out->blended = P<uint32_t>(c, B_BLENDED);
+  out->tile_blended = P<uint32_t>(c, B_TILE_BLENDED);
   return FLOD_OK;
 }
 

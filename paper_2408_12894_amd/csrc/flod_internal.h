@@ -130,17 +130,18 @@ hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *n_ptr, const 
 // zeroed: ranges already zeroed (by the emission); otherwise zeroed here first
 hipError_t launch_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, int64_t k_max, int n_tiles,
                          uint2 *ranges, bool zeroed, hipStream_t s);
+// blended: per tile, the (list position, Gaussian) pairs of the entries the forward blended
+// into some pixel, in list order at the start of the tile's range; tile_blended: their count
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
                         const float4 *cop, const float2 *blue, const DevCamera &cam,
                         const float bg[3], float *image, float *final_T, int32_t *n_contrib,
-                        int32_t *n_blended, uint8_t *taken, uint32_t *tile_taken, const uint32_t *order,
+                        int32_t *n_blended, uint2 *blended, uint32_t *tile_blended, const uint32_t *order,
                         hipStream_t s);
-hipError_t launch_blend_bwd(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
-                            const float4 *cop, const float2 *blue, const DevCamera &cam,
-                            const float bg[3], const float *final_T, const int32_t *n_contrib,
-                            const float *dL_dimage, float *g2d, const uint8_t *taken,
-                            const uint32_t *order, hipStream_t s, hipEvent_t ev_start = nullptr,
-                            hipEvent_t ev_stop = nullptr);
+hipError_t launch_blend_bwd(const uint2 *ranges, const float4 *xyab, const float4 *cop, const float2 *blue,
+                            const DevCamera &cam, const float bg[3], const float *final_T,
+                            const int32_t *n_contrib, const float *dL_dimage, float *g2d,
+                            const uint2 *blended, const uint32_t *tile_blended, const uint32_t *order,
+                            hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_tile_order_by_length(const uint2 *ranges, int n_tiles, uint32_t *order, hipStream_t s);
 hipError_t launch_tile_order_by_count(const uint32_t *count, int n_tiles, uint32_t *order, hipStream_t s);
 // The blend backward's per-Gaussian moment sums into dL/d(mu', conic) in place (inspection).

@@ -340,7 +340,8 @@ class Renderer:
                     blue=get(v.blue, 2 * N, np.float32).reshape(N, 2)[:, 0].copy(),
                     mu_lo_bits=get(v.blue, 2 * N, np.float32).reshape(N, 2)[:, 1].copy().view(np.uint32), stats=s,
                     grad2d=get(v.grad2d, 9 * N, np.float32).reshape(N, 9).T.copy() if v.grad2d else None,
-                    taken=get(v.taken, K, np.uint8), tile_taken=get(v.tile_taken, tiles, np.uint32))
+                    blended=get(v.blended, 2 * K, np.uint32).reshape(K, 2),
+                    tile_blended=get(v.tile_blended, tiles, np.uint32))
 
 
 def _empty_level(n: int, s_min: float, device) -> GaussianLevel:

@@ -393,3 +393,72 @@ def test_instance_list_against_fp64_geometry(renderer, case):
     bad = da > db + 2e-7 * np.abs(db)
     assert not bad.any(), f"{int(bad.sum())} adjacent entries out of depth order"
     print(f"K={tiles.size}, front {front.size}, required pairs {n_need}", flush=True)
+
+
+def check_blended_lists(view, n_contrib, cam, ref=None):
+    """The forward lists, per tile, the entries it blended into some pixel of the tile (the only
+    entries the backward walks): (position in the tile's list, Gaussian) pairs in list order at
+    the start of the tile's range. Positions rise strictly inside the list, each pair carries the
+    list's Gaussian, and every pixel's last blended entry (n_contrib - 1) is listed. With the
+    oracle's per-pixel results (ref, all pixels): every unflagged pixel's last blended Gaussian
+    is listed, and a tile lists at least as many entries as any one of its unflagged pixels
+    blended and at most as many as all its pixels blended together (plus one per flagged pixel,
+    whose decisions may flip)."""
+    tiles_x, tiles_y = (cam.width + 15) // 16, (cam.height + 15) // 16
+    n_tiles = tiles_x * tiles_y
+    rg = view["ranges"].astype(np.int64)
+    vals = view["values"].astype(np.int64)
+    bl = view["blended"].astype(np.int64)
+    m = view["tile_blended"].astype(np.int64)
+    length = rg[:, 1] - rg[:, 0]
+    assert m.shape == (n_tiles,)
+    assert np.all(m <= length), "listed count beyond the tile's list"
+    # every listed entry, with its tile and its index in the tile's range
+    tile_e = np.repeat(np.arange(n_tiles), m)
+    k = np.arange(int(m.sum())) - np.repeat(np.cumsum(m) - m, m)
+    pos, ids = bl[rg[tile_e, 0] + k, 0], bl[rg[tile_e, 0] + k, 1]
+    assert np.all(pos >= 0) and np.all(pos < length[tile_e]), "a position outside its tile's list"
+    same = tile_e[1:] == tile_e[:-1]
+    assert np.all(np.diff(pos)[same] > 0), "positions not rising within a tile"
+    np.testing.assert_array_equal(ids, vals[rg[tile_e, 0] + pos], err_msg="listed Gaussians")
+    listed = rg[tile_e, 0] + pos                       # absolute list index of every listed entry
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    tile_px = ((ys // 16) * tiles_x + xs // 16).ravel()
+    nc = np.asarray(n_contrib).astype(np.int64).ravel()
+    has = nc > 0
+    assert np.isin(rg[tile_px[has], 0] + nc[has] - 1, listed).all(), "a pixel's last blended entry is not listed"
+    if ref is not None:
+        ok = (ref["flag"] & 1) == 0
+        ref_tile = (ref["pix"][:, 1] // 16) * tiles_x + ref["pix"][:, 0] // 16
+        big = int(max(vals.max(initial=0), ref["last"].max(initial=0))) + 1
+        lasts = ok & (ref["last"] >= 0)
+        assert np.isin(ref_tile[lasts] * big + ref["last"][lasts], tile_e * big + ids).all(), \
+            "the oracle's last blended Gaussian of a pixel is not listed"
+        most = np.zeros(n_tiles, np.int64)
+        np.maximum.at(most, ref_tile[ok], ref["nblend"][ok].astype(np.int64))
+        total = np.zeros(n_tiles, np.int64)
+        np.add.at(total, ref_tile, ref["nblend"].astype(np.int64) + (~ok))
+        assert np.all(m >= most), "a tile lists fewer entries than one of its pixels blended"
+        assert np.all(m <= total), "a tile lists more entries than its pixels blended"
+
+
+def test_blended_entry_lists(renderer):
+    _say("2k Gaussians, 128x128: lists of the blended entries against the oracle")
+    scene, cam, bg = synth.small_forward_case()
+    _, _, nc, view = gpu_render(renderer, scene, cam, bg)
+    k = oracle.keys(*scene.arrays()[:4], scene.s_min, cam)
+    ref = oracle.image(oracle.depth_order(k), *scene.arrays()[:4], scene.s_min, scene.sh, 3, cam, bg,
+                       oracle.all_pixels(cam.width, cam.height))
+    check_blended_lists(view, nc, cam, ref)
+    print(f"listed {int(view['tile_blended'].sum())} of K={view['stats']['n_instances']}")
+
+
+def test_blended_entry_lists_hd(renderer):
+    """1080p / 1M: lists spanning several 256-entry batches of the forward."""
+    _say("1M Gaussians, 1920x1080, camera 0: lists of the blended entries")
+    scene, cams, bg = synth.hd_forward_case()
+    _, _, nc, view = gpu_render(renderer, scene, cams[0], bg)
+    n = view["ranges"][:, 1].astype(np.int64) - view["ranges"][:, 0]
+    assert n.max() > 1024
+    check_blended_lists(view, nc, cams[0])
+    print(f"listed {int(view['tile_blended'].sum())} of K={view['stats']['n_instances']}, longest list {n.max()}")
