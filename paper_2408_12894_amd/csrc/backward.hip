@@ -30,10 +30,9 @@
 namespace flod {
 
 constexpr int kG2d = 9;   // mu'x, mu'y, conic a, b, c, opacity, red, green, blue
-#ifndef FLOD_BWD_PIX
-#define FLOD_BWD_PIX 4
+#ifndef FLOD_BWD_SPLIT
+#define FLOD_BWD_SPLIT 2.0f
 #endif
-constexpr int kBwdPix = FLOD_BWD_PIX;   // pixels per thread: 4 = one wave64 per tile
 #ifndef FLOD_BWD_BATCH
 #define FLOD_BWD_BATCH 64
 #endif
@@ -92,31 +91,37 @@ __device__ __forceinline__ bool decide(const float (&fy)[PPT], const int (&last)
 // at once on four different 64-byte bank groups.
 constexpr int kRedStride = 80;
 
-// One workgroup per tile with PPT pixels per thread (the forward's geometry). Per pixel
-// the state is T (transmittance after the current entry), V = dL/dC . Shat (the upstream
-// gradient dotted with the normalised colour behind the current entry) and dL/dC, all FP32
-// (V is a convex combination per step, so its error does not grow along the chain). Per entry
-// each thread sums its pixels' 9 gradient components in registers and the wave reduces
-// them (see below) before one atomic instruction adds the nine sums.
+// The LDS of one backward workgroup (one wave).
+struct __align__(16) BwdShared {
+  float4 a[kBwdBatch], b[kBwdBatch], c[kBwdBatch];   // the staged entries (see stage_entry)
+  uint32_t id[kBwdBatch];                             // their Gaussians
+  int pos[kBwdBatch];                                 // their positions in the tile's list
+  float red[kG2d * kRedStride];                       // the per-entry reduction
+  float red2[4 * kG2d];                               // its first round's partials (LDS form)
+};
+
+// One wave walks one part of a tile: the pixel rows r0 + lane / 16 + 4 k, k < PPT (PPT = 4:
+// the whole tile, 4 pixels per lane; PPT = 2: half of it). Per pixel the state is T
+// (transmittance after the current entry), V = dL/dC . Shat (the upstream gradient dotted with
+// the normalised colour behind the current entry) and dL/dC, all FP32 (V is a convex
+// combination per step, so its error does not grow along the chain). Per entry each lane sums
+// its pixels' 9 gradient components in registers and the wave reduces them (see below) before
+// one atomic instruction adds the nine sums.
 template <int PPT, bool LDS_ROUND2>
-__global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
-    const uint2 *__restrict__ ranges, const float4 *__restrict__ xyab, const float4 *__restrict__ cop,
-    const float2 *__restrict__ blue, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
-    const float *__restrict__ final_T, const int32_t *__restrict__ n_contrib, const float *__restrict__ dimg,
-    float *__restrict__ g2d, const uint2 *__restrict__ blended, const uint32_t *__restrict__ tile_blended,
-    const uint32_t *__restrict__ order) {
-  constexpr int NT = kTile * kTile / PPT;
+__device__ __forceinline__ void bwd_part(
+    BwdShared &sh, int tile, int r0, const uint2 *__restrict__ ranges, const float4 *__restrict__ xyab,
+    const float4 *__restrict__ cop, const float2 *__restrict__ blue, int W, int H, int tiles_x, float bg0,
+    float bg1, float bg2, const float *__restrict__ final_T, const int32_t *__restrict__ n_contrib,
+    const float *__restrict__ dimg, float *__restrict__ g2d, const uint2 *__restrict__ blended,
+    const uint32_t *__restrict__ tile_blended) {
+  constexpr int NT = 64;
   constexpr int ROWS = NT / kTile;
-  static_assert(NT == 64 && kBwdBatch == NT, "one wave per tile, one staged entry per lane");
-  __shared__ float4 s_a[kBwdBatch];
-  __shared__ float4 s_b[kBwdBatch];
-  __shared__ float4 s_c[kBwdBatch];
-  __shared__ uint32_t s_id[kBwdBatch];
-  __shared__ int s_pos[kBwdBatch];
+  static_assert(kBwdBatch == NT, "one staged entry per lane");
+  float4 *s_a = sh.a, *s_b = sh.b, *s_c = sh.c;
+  uint32_t *s_id = sh.id;
+  int *s_pos = sh.pos;
+  float *s_red = sh.red, *s_red2 = sh.red2;
   constexpr int RS = LDS_ROUND2 ? kRedStride : 64;   // component stride of the reduction
-  __shared__ __align__(16) float s_red[kG2d * RS];   // the per-entry reduction
-  __shared__ __align__(16) float s_red2[4 * kG2d];   // its first round's partials (LDS form)
-  const int tile = (int)order[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63;
   // float4 slots each lane reads in the reduction's rounds (clamped: lanes past the last
   // slot read a valid one and discard it). LDS form: lane 4 c + h (c < 9, h < 4) sums the
@@ -147,7 +152,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   int myfirst = list_len;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int py = y0 + (tid >> 4) + ROWS * k;
+    const int py = y0 + r0 + (tid >> 4) + ROWS * k;
     fy[k] = (float)(py - y0) + 0.5f;
     T[k] = 1.0f; V[k] = 0.0f; d0[k] = 0.0f; d1[k] = 0.0f; d2[k] = 0.0f;
     last[k] = 0;
@@ -262,7 +267,6 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
             // with a three-float4 first round), DPP for small ones (720p, 3.5 waves per SIMD: 0.238
             // against 0.248 ms). The workgroup is one wave, so its barriers only order the LDS
             // accesses.
-            static_assert(NT == 64, "the per-entry reduction assumes one wave per tile");
 #pragma unroll
             for (int c = 0; c < kG2d; ++c) s_red[c * RS + lane] = gr[c];
             __syncthreads();
@@ -304,30 +308,67 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend_bwd(
   }
 }
 
+// Tiles whose count of listed entries exceeds this many times the mean (by the tile order's
+// buckets) are walked by two waves, one per half (8 rows each, 2 pixels per lane), at most a
+// quarter of the tiles. One wave per tile leaves the heaviest ones as the kernel's tail: five
+// waves share each SIMD, so a tile with twice the mean work runs about as long as a whole SIMD's
+// share of the frame (1080p / 1M: the last tiles, started at once, ended 70 us after the
+// last dispatch).
+constexpr float kBwdSplitFactor = FLOD_BWD_SPLIT;
+
+// Workgroup b < 2 h (h = order[n_tiles], the split tiles leading the order) walks half b % 2
+// of tile order[b / 2], the others the whole tile order[b - h]; workgroups past n_tiles + h
+// have nothing to do.
+template <bool LDS_ROUND2>
+__global__ __launch_bounds__(64) void k_blend_bwd(
+    const uint2 *__restrict__ ranges, const float4 *__restrict__ xyab, const float4 *__restrict__ cop,
+    const float2 *__restrict__ blue, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
+    const float *__restrict__ final_T, const int32_t *__restrict__ n_contrib, const float *__restrict__ dimg,
+    float *__restrict__ g2d, const uint2 *__restrict__ blended, const uint32_t *__restrict__ tile_blended,
+    const uint32_t *__restrict__ order) {
+  __shared__ BwdShared sh;
+  const int h = (int)order[n_tiles];
+  const int b = (int)blockIdx.x;
+  if (b < 2 * h)
+    bwd_part<2, LDS_ROUND2>(sh, (int)order[b >> 1], (b & 1) * (kTile / 2), ranges, xyab, cop, blue, W, H, tiles_x,
+                            bg0, bg1, bg2, final_T, n_contrib, dimg, g2d, blended, tile_blended);
+  else if (b - h < n_tiles)
+    bwd_part<4, LDS_ROUND2>(sh, (int)order[b - h], 0, ranges, xyab, cop, blue, W, H, tiles_x, bg0, bg1, bg2,
+                            final_T, n_contrib, dimg, g2d, blended, tile_blended);
+}
+
 template <bool LDS_ROUND2>
 static void launch_blend_bwd_t(const uint2 *ranges, const float4 *xyab, const float4 *cop, const float2 *blue,
                                const DevCamera &cam, const float bg[3], const float *final_T, const int32_t *n_contrib,
                                const float *dL_dimage, float *g2d, const uint2 *blended, const uint32_t *tile_blended,
                                const uint32_t *order, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
-  auto kernel = k_blend_bwd<kBwdPix, LDS_ROUND2>;
+  const int grid = n_tiles + bwd_split_cap(n_tiles);
+  auto kernel = k_blend_bwd<LDS_ROUND2>;
   if (ev_start || ev_stop) {
     // timed from the kernel's own dispatch: no event packets between it and its neighbours
-    hipExtLaunchKernelGGL(kernel, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s, ev_start, ev_stop, 0, ranges,
-                          xyab, cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T,
-                          n_contrib, dL_dimage, g2d, blended, tile_blended, order);
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, s, ev_start, ev_stop, 0, ranges, xyab, cop, blue, cam.W,
+                          cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimage, g2d,
+                          blended, tile_blended, order);
   } else {
-    hipLaunchKernelGGL(kernel, dim3(n_tiles), dim3(kTile * kTile / kBwdPix), 0, s, ranges, xyab, cop, blue, cam.W,
-                       cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimage, g2d, blended,
-                       tile_blended, order);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, s, ranges, xyab, cop, blue, cam.W, cam.H, cam.tiles_x,
+                       n_tiles, bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimage, g2d, blended, tile_blended,
+                       order);
   }
 }
+
+int bwd_split_cap(int n_tiles) { return n_tiles / 4; }
 
 hipError_t launch_blend_bwd(const uint2 *ranges, const float4 *xyab, const float4 *cop, const float2 *blue,
                             const DevCamera &cam, const float bg[3], const float *final_T, const int32_t *n_contrib,
                             const float *dL_dimage, float *g2d, const uint2 *blended, const uint32_t *tile_blended,
-                            const uint32_t *order, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  if (cam.tiles_x * cam.tiles_y >= kLdsRound2MinTiles)
+                            uint32_t *order, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  const int n_tiles = cam.tiles_x * cam.tiles_y;
+  if (n_tiles <= 0) return hipSuccess;
+  // tiles in order of decreasing listed-entry count, the ones split in two first
+  hipLaunchKernelGGL(k_tile_order<CountCost>, dim3(1), dim3(kOrderThreads), 0, s, CountCost{tile_blended}, n_tiles,
+                     order, kBwdSplitFactor, bwd_split_cap(n_tiles));
+  if (n_tiles >= kLdsRound2MinTiles)
     launch_blend_bwd_t<true>(ranges, xyab, cop, blue, cam, bg, final_T, n_contrib, dL_dimage, g2d, blended,
                              tile_blended, order, s, ev_start, ev_stop);
   else

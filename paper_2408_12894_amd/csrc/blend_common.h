@@ -48,6 +48,9 @@ __device__ __forceinline__ void stage_entry(const float4 *xyab, const float4 *co
 // octave), descending bucket offsets, then a scatter; the order inside a bucket is whatever
 // the LDS atomics give, which changes only the schedule, never a result. Consecutive
 // workgroups go to different XCDs (round-robin), so every XCD receives an even share.
+// With split_cap >= 0 it also writes, at order[n], how many tiles lead the order with a cost
+// in a bucket above that of split_factor times the mean cost (at most split_cap; none with
+// split_factor <= 0): the tiles the backward splits between two waves.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 256;
 
@@ -69,17 +72,29 @@ struct CountCost {        // backward: entries the forward blended somewhere in 
 };
 
 template <class Cost>
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, uint32_t *__restrict__ order) {
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, uint32_t *__restrict__ order,
+                                                              float split_factor, int split_cap) {
   constexpr int W = kOrderThreads / 64;
   // per-wave bucket counts (contention only inside a wave), then per (bucket, wave) offsets
   __shared__ uint32_t s_cnt[W][kOrderBuckets];
   __shared__ uint32_t s_wsum[kOrderBuckets / 64];
+  __shared__ unsigned long long s_csum[W];
+  __shared__ uint32_t s_split;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int k = tid; k < W * kOrderBuckets; k += kOrderThreads) (&s_cnt[0][0])[k] = 0u;
+  if (tid == 0) s_split = 0u;
   __syncthreads();
   const int chunk = (n + W - 1) / W;
   const int t0 = w * chunk, t1 = min(n, t0 + chunk);
-  for (int t = t0 + lane; t < t1; t += 64) atomicAdd(&s_cnt[w][cost_bucket(cost(t))], 1u);
+  unsigned long long csum = 0ull;
+  for (int t = t0 + lane; t < t1; t += 64) {
+    const uint32_t c = cost(t);
+    csum += c;
+    atomicAdd(&s_cnt[w][cost_bucket(c)], 1u);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) csum += __shfl_xor(csum, o, 64);
+  if (lane == 0) s_csum[w] = csum;
   __syncthreads();
   // thread d < 256 takes bucket b = 255 - d (descending cost): its count over the waves, with
   // each wave's count replaced by the running sum before it
@@ -108,9 +123,20 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, 
     const int b = kOrderBuckets - 1 - tid;
 #pragma unroll
     for (int k = 0; k < W; ++k) s_cnt[k][b] += base;
+    if (split_cap > 0 && split_factor > 0.0f) {
+      // tiles in the buckets above the threshold's lead the order: base + tot of the bucket
+      // just above it
+      unsigned long long total = 0ull;
+#pragma unroll
+      for (int k = 0; k < W; ++k) total += s_csum[k];
+      const double thr = (double)split_factor * (double)total / (double)max(n, 1);
+      const int bthr = cost_bucket((uint32_t)fmin(thr, 4.0e9)) + 1;
+      if (b == bthr) s_split = min(base + tot, (uint32_t)split_cap);
+    }
   }
   __syncthreads();
   for (int t = t0 + lane; t < t1; t += 64) order[atomicAdd(&s_cnt[w][cost_bucket(cost(t))], 1u)] = (uint32_t)t;
+  if (split_cap >= 0 && tid == 0) order[n] = s_split;
 }
 
 }  // namespace flod

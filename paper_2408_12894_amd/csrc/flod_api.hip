@@ -354,7 +354,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   need(B_TOT, 4 * (size_t)kRadix);
   need(B_RANGES, 8 * (size_t)n_tiles);
   need(B_TILE_BLENDED, 4 * (size_t)n_tiles);
-  need(B_TILE_ORDER, 4 * (size_t)n_tiles);
+  need(B_TILE_ORDER, 4 * ((size_t)n_tiles + 1));
   need(B_COUNTERS, 8 * (size_t)kCntSlots);
   if (st != FLOD_OK) {
     c->required = ws_bytes(c) + extra;
@@ -1037,7 +1037,7 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   size_t extra = 0;
   const int n_tiles = sv.cam.tiles_x * sv.cam.tiles_y;
   if (ensure(ctx, B_G2D, 9 * 4 * (size_t)N, s, &extra) != FLOD_OK ||
-      ensure(ctx, B_TILE_ORDER, 4 * (size_t)n_tiles, s, &extra) != FLOD_OK) {
+      ensure(ctx, B_TILE_ORDER, 4 * ((size_t)n_tiles + 1), s, &extra) != FLOD_OK) {
     ctx->required = ws_bytes(ctx) + extra;
     return FLOD_ERR_WORKSPACE;
   }
@@ -1046,8 +1046,7 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   uint32_t *order = P<uint32_t>(ctx, B_TILE_ORDER);
   hipEvent_t ev_a, ev_b;
   tm.dispatch(FLOD_STAGE_BLEND_BWD, &ev_a, &ev_b);
-  if (launch_tile_order_by_count(P<uint32_t>(ctx, B_TILE_BLENDED), n_tiles, order, s) != hipSuccess ||
-      launch_blend_bwd(P<uint2>(ctx, B_RANGES), P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
+  if (launch_blend_bwd(P<uint2>(ctx, B_RANGES), P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
                        P<float2>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d,
                        P<uint2>(ctx, B_BLENDED), P<uint32_t>(ctx, B_TILE_BLENDED), order, s, ev_a, ev_b) !=
           hipSuccess)
