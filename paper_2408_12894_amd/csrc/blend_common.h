@@ -53,6 +53,7 @@ __device__ __forceinline__ void stage_entry(const float4 *xyab, const float4 *co
 // split_factor <= 0): the tiles the backward splits between two waves.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 256;
+constexpr int kOrderLoads = 8;
 
 __device__ __forceinline__ int cost_bucket(uint32_t c) {
   if (c < 8u) return (int)c;
@@ -86,11 +87,21 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, 
   __syncthreads();
   const int chunk = (n + W - 1) / W;
   const int t0 = w * chunk, t1 = min(n, t0 + chunk);
+  // kOrderLoads costs per lane loaded before any is used (one loop trip at 1080p: each wave
+  // takes at most 512 tiles there), the indices clamped into the wave's range rather than
+  // guarded (a guard made each load a branch that waited for it); loaded one at a time, each
+  // trip waited for its load
   unsigned long long csum = 0ull;
-  for (int t = t0 + lane; t < t1; t += 64) {
-    const uint32_t c = cost(t);
-    csum += c;
-    atomicAdd(&s_cnt[w][cost_bucket(c)], 1u);
+  for (int base = t0 + lane; base < t1; base += 64 * kOrderLoads) {
+    uint32_t c[kOrderLoads];
+#pragma unroll
+    for (int u = 0; u < kOrderLoads; ++u) c[u] = cost(min(base + 64 * u, t1 - 1));   // in bounds: base < t1
+#pragma unroll
+    for (int u = 0; u < kOrderLoads; ++u)
+      if (base + 64 * u < t1) {
+        csum += c[u];
+        atomicAdd(&s_cnt[w][cost_bucket(c[u])], 1u);
+      }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) csum += __shfl_xor(csum, o, 64);
@@ -135,7 +146,14 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, 
     }
   }
   __syncthreads();
-  for (int t = t0 + lane; t < t1; t += 64) order[atomicAdd(&s_cnt[w][cost_bucket(cost(t))], 1u)] = (uint32_t)t;
+  for (int base = t0 + lane; base < t1; base += 64 * kOrderLoads) {
+    uint32_t c[kOrderLoads];
+#pragma unroll
+    for (int u = 0; u < kOrderLoads; ++u) c[u] = cost(min(base + 64 * u, t1 - 1));   // in bounds: base < t1
+#pragma unroll
+    for (int u = 0; u < kOrderLoads; ++u)
+      if (base + 64 * u < t1) order[atomicAdd(&s_cnt[w][cost_bucket(c[u])], 1u)] = (uint32_t)(base + 64 * u);
+  }
   if (split_cap >= 0 && tid == 0) order[n] = s_split;
 }
 
