@@ -106,11 +106,14 @@ __device__ __forceinline__ void set_priority_by_work(int work) {
 }
 
 // The LDS of one backward workgroup (one wave).
+// The reduction's buffer comes first: its nine components then lie within reach of three
+// base registers' 8-bit offsets (placed after the staged entries they took five, which the
+// compiler rebuilt with an add each per entry).
 struct __align__(16) BwdShared {
-  float4 a[kBwdBatch], b[kBwdBatch], c[kBwdBatch];   // the staged entries (see stage_entry)
-  uint32_t id[kBwdBatch];                             // their Gaussians
-  int pos[kBwdBatch];                                 // their positions in the tile's list
   float red[kG2d * kRedStride];                       // the per-entry reduction
+  float4 a[kBwdBatch], b[kBwdBatch], c[kBwdBatch];   // the staged entries (see stage_entry;
+                                                      // c.w holds the Gaussian's index)
+  int pos[kBwdBatch];                                 // their positions in the tile's list
   float red2[4 * kG2d];                               // its first round's partials (LDS form)
 };
 
@@ -132,7 +135,6 @@ __device__ __forceinline__ void bwd_part(
   constexpr int ROWS = NT / kTile;
   static_assert(kBwdBatch == NT, "one staged entry per lane");
   float4 *s_a = sh.a, *s_b = sh.b, *s_c = sh.c;
-  uint32_t *s_id = sh.id;
   int *s_pos = sh.pos;
   float *s_red = sh.red, *s_red2 = sh.red2;
   constexpr int RS = LDS_ROUND2 ? kRedStride : 64;   // component stride of the reduction
@@ -199,9 +201,13 @@ __device__ __forceinline__ void bwd_part(
     if (f) {
       const uint2 pe = blended[rg.x + start + tid];   // (list position, Gaussian)
       pos = (int)pe.x;
-      s_id[tid] = pe.y;
       s_pos[tid] = pos;
-      stage_entry(xyab, cop, blue, pe.y, x0, y0, s_a[tid], s_b[tid], s_c[tid]);
+      float4 a, b, c;
+      stage_entry(xyab, cop, blue, pe.y, x0, y0, a, b, c);
+      c.w = __uint_as_float(pe.y);   // read with the entry, for the gradient's row
+      s_a[tid] = a;
+      s_b[tid] = b;
+      s_c[tid] = c;
     }
     const int nlow = (int)__popcll(__ballot(f && pos < myfirst));
     __syncthreads();
@@ -217,7 +223,7 @@ __device__ __forceinline__ void bwd_part(
         const int jpos = CHECK ? s_pos[jl] : 0;
         const float4 A = s_a[jl];
         const float4 B = s_b[jl];
-        const float4 BL = s_c[jl];   // threshold on l, blue, clamp flag
+        const float4 BL = s_c[jl];   // threshold on l, blue, clamp flag, Gaussian
         const float dx = fx - A.x;
         const float t = conic_column(A.w, dx, B.y);
         // first only what decides whether a pixel takes part; the transmittance recovery and
@@ -286,7 +292,7 @@ __device__ __forceinline__ void bwd_part(
             for (int c = 0; c < kG2d; ++c) s_red[c * RS + lane] = gr[c];
             __syncthreads();
             const float4 *r4 = reinterpret_cast<const float4 *>(s_red);
-            const size_t row = (size_t)s_id[jl] * kG2d;
+            const size_t row = (size_t)__float_as_uint(BL.w) * kG2d;
             if (LDS_ROUND2) {
               // lane 4 c + h: 16 values of component c (lanes 4 h .. 4 h + 3 of each group of 16)
               const float4 q0 = r4[red_r1], q1 = r4[red_r1 + 4], q2 = r4[red_r1 + 8], q3 = r4[red_r1 + 12];
