@@ -31,7 +31,7 @@ namespace flod {
 
 constexpr int kG2d = 9;   // mu'x, mu'y, conic a, b, c, opacity, red, green, blue
 #ifndef FLOD_BWD_SPLIT
-#define FLOD_BWD_SPLIT 2.0f
+#define FLOD_BWD_SPLIT 1.75f
 #endif
 #ifndef FLOD_BWD_BATCH
 #define FLOD_BWD_BATCH 64
@@ -334,7 +334,8 @@ __device__ __forceinline__ void bwd_part(
 // quarter of the tiles. One wave per tile leaves the heaviest ones as the kernel's tail: five
 // waves share each SIMD, so a tile with twice the mean work runs about as long as a whole SIMD's
 // share of the frame (1080p / 1M: the last tiles, started at once, ended 70 us after the
-// last dispatch).
+// last dispatch). With the priority below, 1.75 measured best at 1080p / 1M (0.176 ms against
+// 0.181 at 2 and 0.189 at 1.65; 720p / 500k the same from 1.65 to 2).
 constexpr float kBwdSplitFactor = FLOD_BWD_SPLIT;
 
 // Workgroup b < 2 h (h = order[n_tiles], the split tiles leading the order) walks half b % 2
