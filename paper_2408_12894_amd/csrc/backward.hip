@@ -33,6 +33,9 @@ constexpr int kG2d = 9;   // mu'x, mu'y, conic a, b, c, opacity, red, green, blu
 #ifndef FLOD_BWD_SPLIT
 #define FLOD_BWD_SPLIT 1.75f
 #endif
+#ifndef FLOD_BWD_SPLIT4
+#define FLOD_BWD_SPLIT4 3.0f
+#endif
 #ifndef FLOD_BWD_BATCH
 #define FLOD_BWD_BATCH 64
 #endif
@@ -192,7 +195,7 @@ __device__ __forceinline__ void bwd_part(
   // positions are listed at 1080p / 1M (92 of 1040 per tile on average), so a tile took about
   // 16 batches, each two dependent global loads and two barriers for a handful of entries
   for (int end = n_bl; end > 0; end -= kBwdBatch) {
-    set_priority_by_work(end * (PPT == 4 ? 3 : 2));
+    set_priority_by_work(end * (PPT == 4 ? 3 : PPT == 2 ? 2 : 1));
     const int start = max(0, end - kBwdBatch);
     const int cnt = end - start;
     __syncthreads();
@@ -339,10 +342,15 @@ __device__ __forceinline__ void bwd_part(
 // last dispatch). With the priority below, 1.75 measured best at 1080p / 1M (0.176 ms against
 // 0.181 at 2 and 0.189 at 1.65; 720p / 500k the same from 1.65 to 2).
 constexpr float kBwdSplitFactor = FLOD_BWD_SPLIT;
+// Tiles above this many times the mean are split in four instead (quarters of 4 rows, one pixel
+// per lane): at 720p / 500k, with 3,600 tiles for 6,144 wave slots, the heaviest tiles' halves
+// still set the kernel's span.
+constexpr float kBwdSplit4Factor = FLOD_BWD_SPLIT4;
 
-// Workgroup b < 2 h (h = order[n_tiles], the split tiles leading the order) walks half b % 2
-// of tile order[b / 2], the others the whole tile order[b - h]; workgroups past n_tiles + h
-// have nothing to do.
+// The order leads with h4 = order[n_tiles + 1] tiles split in four (quarters of 4 rows, one
+// pixel per lane), then h2 - h4 (h2 = order[n_tiles]) split in two; workgroups 0 .. 4 h4 - 1
+// walk the quarters, the next 2 (h2 - h4) the halves, the next n_tiles - h2 whole tiles, and
+// any past those have nothing to do.
 template <bool LDS_ROUND2>
 __global__ __launch_bounds__(64) void k_blend_bwd(
     const uint2 *__restrict__ ranges, const float4 *__restrict__ xyab, const float4 *__restrict__ cop,
@@ -351,13 +359,17 @@ __global__ __launch_bounds__(64) void k_blend_bwd(
     float *__restrict__ g2d, const uint2 *__restrict__ blended, const uint32_t *__restrict__ tile_blended,
     const uint32_t *__restrict__ order) {
   __shared__ BwdShared sh;
-  const int h = (int)order[n_tiles];
+  const int h2 = (int)order[n_tiles], h4 = (int)order[n_tiles + 1];
   const int b = (int)blockIdx.x;
-  if (b < 2 * h)
-    bwd_part<2, LDS_ROUND2>(sh, (int)order[b >> 1], (b & 1) * (kTile / 2), ranges, xyab, cop, blue, W, H, tiles_x,
+  const int b2 = b - 4 * h4, b1 = b2 - 2 * (h2 - h4);
+  if (b < 4 * h4)
+    bwd_part<1, LDS_ROUND2>(sh, (int)order[b >> 2], (b & 3) * (kTile / 4), ranges, xyab, cop, blue, W, H, tiles_x,
                             bg0, bg1, bg2, final_T, n_contrib, dimg, g2d, blended, tile_blended);
-  else if (b - h < n_tiles)
-    bwd_part<4, LDS_ROUND2>(sh, (int)order[b - h], 0, ranges, xyab, cop, blue, W, H, tiles_x, bg0, bg1, bg2,
+  else if (b1 < 0)
+    bwd_part<2, LDS_ROUND2>(sh, (int)order[h4 + (b2 >> 1)], (b2 & 1) * (kTile / 2), ranges, xyab, cop, blue, W, H,
+                            tiles_x, bg0, bg1, bg2, final_T, n_contrib, dimg, g2d, blended, tile_blended);
+  else if (b1 < n_tiles - h2)
+    bwd_part<4, LDS_ROUND2>(sh, (int)order[h2 + b1], 0, ranges, xyab, cop, blue, W, H, tiles_x, bg0, bg1, bg2,
                             final_T, n_contrib, dimg, g2d, blended, tile_blended);
 }
 
@@ -367,7 +379,7 @@ static void launch_blend_bwd_t(const uint2 *ranges, const float4 *xyab, const fl
                                const float *dL_dimage, float *g2d, const uint2 *blended, const uint32_t *tile_blended,
                                const uint32_t *order, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
-  const int grid = n_tiles + bwd_split_cap(n_tiles);
+  const int grid = n_tiles + bwd_split_extra(n_tiles);
   auto kernel = k_blend_bwd<LDS_ROUND2>;
   if (ev_start || ev_stop) {
     // timed from the kernel's own dispatch: no event packets between it and its neighbours
@@ -381,7 +393,10 @@ static void launch_blend_bwd_t(const uint2 *ranges, const float4 *xyab, const fl
   }
 }
 
-int bwd_split_cap(int n_tiles) { return n_tiles / 4; }
+// at most a quarter of the tiles split in two or four, at most a sixteenth in four
+static int split_cap2(int n_tiles) { return n_tiles / 4; }
+static int split_cap4(int n_tiles) { return n_tiles / 16; }
+int bwd_split_extra(int n_tiles) { return split_cap2(n_tiles) + 2 * split_cap4(n_tiles); }
 
 hipError_t launch_blend_bwd(const uint2 *ranges, const float4 *xyab, const float4 *cop, const float2 *blue,
                             const DevCamera &cam, const float bg[3], const float *final_T, const int32_t *n_contrib,
@@ -391,7 +406,7 @@ hipError_t launch_blend_bwd(const uint2 *ranges, const float4 *xyab, const float
   if (n_tiles <= 0) return hipSuccess;
   // tiles in order of decreasing listed-entry count, the ones split in two first
   hipLaunchKernelGGL(k_tile_order<CountCost>, dim3(1), dim3(kOrderThreads), 0, s, CountCost{tile_blended}, n_tiles,
-                     order, kBwdSplitFactor, bwd_split_cap(n_tiles));
+                     order, TileSplit{kBwdSplitFactor, kBwdSplit4Factor, split_cap2(n_tiles), split_cap4(n_tiles)});
   if (n_tiles >= kLdsRound2MinTiles)
     launch_blend_bwd_t<true>(ranges, xyab, cop, blue, cam, bg, final_T, n_contrib, dL_dimage, g2d, blended,
                              tile_blended, order, s, ev_start, ev_stop);

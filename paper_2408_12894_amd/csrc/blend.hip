@@ -202,7 +202,7 @@ hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float
 hipError_t launch_tile_order_by_length(const uint2 *ranges, int n_tiles, uint32_t *order, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_order<ListLengthCost>, dim3(1), dim3(kOrderThreads), 0, s, ListLengthCost{ranges},
-                     n_tiles, order, 0.0f, -1);
+                     n_tiles, order, TileSplit{0.0f, 0.0f, -1, -1});
   return hipGetLastError();
 }
 

@@ -48,9 +48,14 @@ __device__ __forceinline__ void stage_entry(const float4 *xyab, const float4 *co
 // octave), descending bucket offsets, then a scatter; the order inside a bucket is whatever
 // the LDS atomics give, which changes only the schedule, never a result. Consecutive
 // workgroups go to different XCDs (round-robin), so every XCD receives an even share.
-// With split_cap >= 0 it also writes, at order[n], how many tiles lead the order with a cost
-// in a bucket above that of split_factor times the mean cost (at most split_cap; none with
-// split_factor <= 0): the tiles the backward splits between two waves.
+// For the backward (split.cap2 >= 0) it also writes, at order[n] and order[n + 1], how many tiles
+// lead the order with a cost in a bucket above that of split.f2 (respectively split.f4) times
+// the mean cost, at most split.cap2 (split.cap4 <= split.cap2); none for a factor <= 0: the
+// tiles the backward splits between two and between four waves.
+struct TileSplit {
+  float f2, f4;
+  int cap2, cap4;
+};
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 256;
 constexpr int kOrderLoads = 8;
@@ -74,16 +79,16 @@ struct CountCost {        // backward: entries the forward blended somewhere in 
 
 template <class Cost>
 __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, uint32_t *__restrict__ order,
-                                                              float split_factor, int split_cap) {
+                                                              TileSplit split) {
   constexpr int W = kOrderThreads / 64;
   // per-wave bucket counts (contention only inside a wave), then per (bucket, wave) offsets
   __shared__ uint32_t s_cnt[W][kOrderBuckets];
   __shared__ uint32_t s_wsum[kOrderBuckets / 64];
   __shared__ unsigned long long s_csum[W];
-  __shared__ uint32_t s_split;
+  __shared__ uint32_t s_split[2];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int k = tid; k < W * kOrderBuckets; k += kOrderThreads) (&s_cnt[0][0])[k] = 0u;
-  if (tid == 0) s_split = 0u;
+  if (tid < 2) s_split[tid] = 0u;
   __syncthreads();
   const int chunk = (n + W - 1) / W;
   const int t0 = w * chunk, t1 = min(n, t0 + chunk);
@@ -134,15 +139,21 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, 
     const int b = kOrderBuckets - 1 - tid;
 #pragma unroll
     for (int k = 0; k < W; ++k) s_cnt[k][b] += base;
-    if (split_cap > 0 && split_factor > 0.0f) {
-      // tiles in the buckets above the threshold's lead the order: base + tot of the bucket
+    if (split.cap2 > 0) {
+      // the tiles in the buckets above a threshold's lead the order: base + tot of the bucket
       // just above it
       unsigned long long total = 0ull;
 #pragma unroll
       for (int k = 0; k < W; ++k) total += s_csum[k];
-      const double thr = (double)split_factor * (double)total / (double)max(n, 1);
-      const int bthr = cost_bucket((uint32_t)fmin(thr, 4.0e9)) + 1;
-      if (b == bthr) s_split = min(base + tot, (uint32_t)split_cap);
+      const double mean = (double)total / (double)max(n, 1);
+      const float fs[2] = {split.f2, split.f4};
+      const int caps[2] = {split.cap2, split.cap4};
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        if (fs[i] > 0.0f && caps[i] > 0) {
+          const int bthr = cost_bucket((uint32_t)fmin((double)fs[i] * mean, 4.0e9)) + 1;
+          if (b == bthr) s_split[i] = min(base + tot, (uint32_t)caps[i]);
+        }
     }
   }
   __syncthreads();
@@ -154,7 +165,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, 
     for (int u = 0; u < kOrderLoads; ++u)
       if (base + 64 * u < t1) order[atomicAdd(&s_cnt[w][cost_bucket(c[u])], 1u)] = (uint32_t)(base + 64 * u);
   }
-  if (split_cap >= 0 && tid == 0) order[n] = s_split;
+  if (split.cap2 >= 0 && tid < 2) order[n + tid] = s_split[tid];
 }
 
 }  // namespace flod

@@ -354,7 +354,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   need(B_TOT, 4 * (size_t)kRadix);
   need(B_RANGES, 8 * (size_t)n_tiles);
   need(B_TILE_BLENDED, 4 * (size_t)n_tiles);
-  need(B_TILE_ORDER, 4 * ((size_t)n_tiles + 1));
+  need(B_TILE_ORDER, 4 * ((size_t)n_tiles + 2));
   need(B_COUNTERS, 8 * (size_t)kCntSlots);
   if (st != FLOD_OK) {
     c->required = ws_bytes(c) + extra;
@@ -1037,7 +1037,7 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   size_t extra = 0;
   const int n_tiles = sv.cam.tiles_x * sv.cam.tiles_y;
   if (ensure(ctx, B_G2D, 9 * 4 * (size_t)N, s, &extra) != FLOD_OK ||
-      ensure(ctx, B_TILE_ORDER, 4 * ((size_t)n_tiles + 1), s, &extra) != FLOD_OK) {
+      ensure(ctx, B_TILE_ORDER, 4 * ((size_t)n_tiles + 2), s, &extra) != FLOD_OK) {
     ctx->required = ws_bytes(ctx) + extra;
     return FLOD_ERR_WORKSPACE;
   }

@@ -137,15 +137,15 @@ hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float
                         const float bg[3], float *image, float *final_T, int32_t *n_contrib,
                         int32_t *n_blended, uint2 *blended, uint32_t *tile_blended, const uint32_t *order,
                         hipStream_t s);
-// order: n_tiles + 1 words of scratch (the backward's tile order and its count of split tiles);
+// order: n_tiles + 2 words of scratch (the backward's tile order and its counts of split tiles);
 // the kernel is timed by the events (if given), its tile order is not
 hipError_t launch_blend_bwd(const uint2 *ranges, const float4 *xyab, const float4 *cop, const float2 *blue,
                             const DevCamera &cam, const float bg[3], const float *final_T,
                             const int32_t *n_contrib, const float *dL_dimage, float *g2d,
                             const uint2 *blended, const uint32_t *tile_blended, uint32_t *order,
                             hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
-// the most tiles the backward splits between two waves
-int bwd_split_cap(int n_tiles);
+// the most blocks the backward's split tiles add beyond one per tile
+int bwd_split_extra(int n_tiles);
 hipError_t launch_tile_order_by_length(const uint2 *ranges, int n_tiles, uint32_t *order, hipStream_t s);
 // The blend backward's per-Gaussian moment sums into dL/d(mu', conic) in place (inspection).
 hipError_t launch_g2d_from_moments(int64_t n, const uint32_t *tiles, const float4 *xyab, const float4 *cop,
