@@ -294,7 +294,8 @@ flod_status flod_level_transition(flod_ctx *ctx, const flod_level *in, float s_m
    buffers). Besides them the backward reads the O(K) state the forward left in ctx: the
    tile ranges of the sorted list, per tile the list of the entries blended somewhere in the
    tile, and the per-tile counts of those entries (flod_view: blended, tile_blended). Returns
-   FLOD_ERR_UNSUPPORTED after a selective render or when no render preceded it. FP32
+   FLOD_ERR_UNSUPPORTED after a selective render, after a render that kept no backward state
+   (flod_ctx_keep_backward_state) or when no render preceded it. FP32
    atomic accumulation: results are deterministic up to summation order. */
 flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_grads *grads,
                                  void *stream);
@@ -359,6 +360,12 @@ enum {
   FLOD_STAGE_PREPROCESS_BWD,  /* chain rule to the 3D attributes                     */
   FLOD_NUM_STAGES
 };
+/* keep != 0 (the default): every render keeps the state flod_render_backward needs, per tile
+   the list of the entries blended into some pixel (8 bytes per instance slot of workspace).
+   keep == 0: renders keep none of it and take no workspace for it; a backward after such a
+   render returns FLOD_ERR_UNSUPPORTED. For callers that only render (a server), which then
+   need about a third less workspace per instance. Applies from the next render. */
+flod_status flod_ctx_keep_backward_state(flod_ctx *ctx, int keep);
 /* enable != 0 records every stage. */
 flod_status flod_ctx_set_timing(flod_ctx *ctx, int enable);
 /* Record only the stages whose bit (1 << FLOD_STAGE_...) is set; 0 turns timing off. Each

@@ -25,7 +25,7 @@ STAGES = ("preprocess", "depth_sort", "offsets", "emit", "tile_sort", "ranges", 
 
 EXPORTS = ("flod_ctx_create", "flod_ctx_destroy", "flod_ctx_workspace_bytes", "flod_ctx_required_bytes",
            "flod_ctx_trim", "flod_render_level", "flod_render_selective", "flod_render_backward",
-           "flod_ctx_stats", "flod_ctx_view", "flod_ctx_set_timing", "flod_ctx_set_timing_stages", "flod_ctx_stage_times",
+           "flod_ctx_stats", "flod_ctx_view", "flod_ctx_keep_backward_state", "flod_ctx_set_timing", "flod_ctx_set_timing_stages", "flod_ctx_stage_times",
            "flod_stage_name", "flod_smin", "flod_dproj", "flod_status_str", "flod_copy_to_host",
            "flod_render_merged", "flod_select_compact", "flod_overlap_prune", "flod_compact_level",
            "flod_level_transition", "flod_adam_step", "flod_l1_ssim_forward", "flod_l1_ssim_backward",
@@ -147,6 +147,8 @@ def load():
     L.flod_ctx_stats.restype = C.c_int
     L.flod_ctx_view.argtypes = [vp, C.POINTER(View)]
     L.flod_ctx_view.restype = C.c_int
+    L.flod_ctx_keep_backward_state.argtypes = [vp, C.c_int]
+    L.flod_ctx_keep_backward_state.restype = C.c_int
     L.flod_ctx_set_timing.argtypes = [vp, C.c_int]
     L.flod_ctx_set_timing.restype = C.c_int
     L.flod_ctx_set_timing_stages.argtypes = [vp, C.c_uint]

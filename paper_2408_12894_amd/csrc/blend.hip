@@ -112,7 +112,8 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
       if (__syncthreads_and(all_done)) break;
     }
     // the previous batch's blended entries join the list, this batch's flags start at zero
-    if (start > 0) append_blended<NT>(s_taken, s_id, s_wcnt, start - kBatch, n, blended + rg.x, n_bl, tid);
+    if (blended && start > 0)
+      append_blended<NT>(s_taken, s_id, s_wcnt, start - kBatch, n, blended + rg.x, n_bl, tid);
     for (int e = tid; e < kBatch; e += NT) {
       s_taken[e] = 0;
       if (start + e < n) {
@@ -169,8 +170,9 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
   }
   // the blended entries of the last batch walked (the walk blends nothing after it)
   __syncthreads();
-  if (last_start >= 0) append_blended<NT>(s_taken, s_id, s_wcnt, last_start, n, blended + rg.x, n_bl, tid);
-  if (tid == 0) tile_blended[tile] = n_bl;
+  if (blended && last_start >= 0)
+    append_blended<NT>(s_taken, s_id, s_wcnt, last_start, n, blended + rg.x, n_bl, tid);
+  if (tid == 0 && tile_blended) tile_blended[tile] = n_bl;
   const size_t plane = (size_t)W * H;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {

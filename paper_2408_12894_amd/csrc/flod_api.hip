@@ -74,6 +74,7 @@ struct Saved {
   int depth_buf = 0;
   bool has_grad2d = false;
   bool grad2d_moments = false;   // B_G2D still holds the backward's moment sums (see flod_ctx_view)
+  bool has_blended = false;      // the render listed its blended entries (the backward needs them)
 };
 
 }  // namespace
@@ -95,6 +96,7 @@ struct flod_ctx {
   unsigned long long *host_counts_dev = nullptr;
   uint32_t count_seq = 0;
   Saved saved;
+  bool keep_backward = true;          // renders list their blended entries (flod_ctx_keep_backward_state)
   flod_stats stats{};
   // timing
   bool timing = false;
@@ -298,8 +300,10 @@ int64_t instance_capacity(const flod_ctx *c) {
   size_t b = c->buf[B_TKEY0].cap;
   for (BufId id : {B_TKEY1, B_TVAL0, B_TVAL1}) b = b < c->buf[id].cap ? b : c->buf[id].cap;
   int64_t k = (int64_t)(b / 4);
-  const int64_t t = (int64_t)(c->buf[B_BLENDED].cap / 8);
-  if (t < k) k = t;
+  if (c->keep_backward) {
+    const int64_t t = (int64_t)(c->buf[B_BLENDED].cap / 8);
+    if (t < k) k = t;
+  }
   if (k > 0xFFFFFFFEll) k = 0xFFFFFFFEll;
   return k > 0 ? k : 0;
 }
@@ -443,7 +447,8 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     if (launch_tile_order_by_length(P<uint2>(c, B_RANGES), n_tiles, order, s) != hipSuccess ||
         launch_blend(P<uint2>(c, B_RANGES), tv[tres], P<float4>(c, B_XYAB), P<float4>(c, B_COP),
                      P<float2>(c, B_BLUE), cam, bg, out->image, out->final_T, out->n_contrib, out->n_blended,
-                     P<uint2>(c, B_BLENDED), P<uint32_t>(c, B_TILE_BLENDED), order, s) != hipSuccess)
+                     c->keep_backward ? P<uint2>(c, B_BLENDED) : nullptr,
+                     c->keep_backward ? P<uint32_t>(c, B_TILE_BLENDED) : nullptr, order, s) != hipSuccess)
       return FLOD_ERR_DEVICE;
     tm.end();
     return FLOD_OK;
@@ -478,7 +483,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
       need(B_TKEY1, 4 * (size_t)Kn);
       need(B_TVAL0, 4 * (size_t)Kn);
       need(B_TVAL1, 4 * (size_t)Kn);
-      need(B_BLENDED, 8 * (size_t)Kn);
+      if (c->keep_backward) need(B_BLENDED, 8 * (size_t)Kn);
       if (st == FLOD_OK) {
         cap = instance_capacity(c);
         need(B_HIST, hist_bytes(cap));
@@ -502,6 +507,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   sv.sorted_keys = tres;
   sv.depth_buf = dres;
   sv.sh_degree = p.sh_degree;
+  sv.has_blended = c->keep_backward;
   return FLOD_OK;
 }
 
@@ -1022,7 +1028,7 @@ flod_status flod_level_transition(flod_ctx *ctx, const flod_level *in, float s_m
 flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_grads *grads, void *stream) {
   if (!ctx || !dL_dimage || !grads) return FLOD_ERR_INVALID_ARG;
   const Saved &sv = ctx->saved;
-  if (!sv.valid || !sv.is_level) return FLOD_ERR_UNSUPPORTED;
+  if (!sv.valid || !sv.is_level || !sv.has_blended) return FLOD_ERR_UNSUPPORTED;
   const int64_t N = sv.level.n;
   if (N > 0 && (!grads->d_means || !grads->d_log_scales || !grads->d_quats || !grads->d_opacity_logits ||
                 !grads->d_sh || !aligned(grads->d_quats, 16) || !aligned(grads->d_sh, 16)))
@@ -1099,6 +1105,12 @@ flod_status flod_ctx_view(const flod_ctx *ctx, flod_view *out) {
   out->grad2d = sv.has_grad2d ? P<float>(c, B_G2D) : nullptr;
   out->blended = P<uint32_t>(c, B_BLENDED);
   out->tile_blended = P<uint32_t>(c, B_TILE_BLENDED);
+  return FLOD_OK;
+}
+
+flod_status flod_ctx_keep_backward_state(flod_ctx *ctx, int keep) {
+  if (!ctx) return FLOD_ERR_INVALID_ARG;
+  ctx->keep_backward = keep != 0;
   return FLOD_OK;
 }
 

@@ -132,6 +132,7 @@ hipError_t launch_ranges(const uint32_t *tile_ids, const uint32_t *k_ptr, int64_
                          uint2 *ranges, bool zeroed, hipStream_t s);
 // blended: per tile, the (list position, Gaussian) pairs of the entries the forward blended
 // into some pixel, in list order at the start of the tile's range; tile_blended: their count
+// (both may be null: the render keeps no backward state)
 hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float4 *xyab,
                         const float4 *cop, const float2 *blue, const DevCamera &cam,
                         const float bg[3], float *image, float *final_T, int32_t *n_contrib,

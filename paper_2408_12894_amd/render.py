@@ -296,6 +296,11 @@ class Renderer:
     def trim(self, stream=None):
         _lib.check(self.L.flod_ctx_trim(self.ctx, C.c_void_p(_stream_ptr(stream))), "flod_ctx_trim")
 
+    def keep_backward_state(self, keep: bool):
+        """Whether renders keep what backward() needs (default True; a renderer that only
+        renders saves 8 bytes of workspace per instance slot with False)."""
+        _lib.check(self.L.flod_ctx_keep_backward_state(self.ctx, int(bool(keep))), "flod_ctx_keep_backward_state")
+
     def set_timing(self, on: bool, stages=None):
         """Per-stage device timing; `stages` (names) restricts it to those stages."""
         if stages is None:

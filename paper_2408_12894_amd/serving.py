@@ -467,7 +467,9 @@ class GpuExecutor:
         self.renderers = []
         for s in range(n_slots):
             alloc, free = self._callbacks(s)
-            self.renderers.append(render.Renderer(self.device.index, alloc=alloc, release=free))
+            r = render.Renderer(self.device.index, alloc=alloc, release=free)
+            r.keep_backward_state(False)   # the server only renders: no backward state in its workspace
+            self.renderers.append(r)
         # device time reference for the requests' intervals
         self.t_ref = torch.cuda.Event(enable_timing=True)
         self.t_ref.record(torch.cuda.current_stream(self.device))

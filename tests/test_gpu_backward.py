@@ -288,3 +288,33 @@ def test_stage_timing_records_and_changes_nothing():
             np.testing.assert_array_equal(a, b)
         for a, b in zip(plain[1], other[1]):
             np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-6)
+
+
+def test_render_without_backward_state():
+    """A renderer told not to keep backward state (a server's) renders the same image in less
+    workspace, refuses a backward after such a render, and after it is told to keep the state
+    again backs the next render with the same gradient as a renderer that always kept it."""
+    from paper_2408_12894_amd import _lib, render
+    _say("128x128: render without backward state")
+    scene, cam, bg = synth.small_forward_case()
+    level = render.GaussianLevel.from_scene(scene)
+    keep, lean = render.Renderer(0), render.Renderer(0)
+    lean.keep_backward_state(False)
+    img_k = keep.render_level(level, cam, bg)[0].clone()
+    img_l = lean.render_level(level, cam, bg)[0].clone()
+    torch.cuda.synchronize()
+    assert torch.equal(img_k, img_l)
+    assert lean.workspace_bytes() < keep.workspace_bytes()
+    dimg = torch.ones((3, cam.height, cam.width), device="cuda") / (3 * cam.height * cam.width)
+    with pytest.raises(_lib.FlodError) as e:
+        lean.backward(level, dimg)
+    assert e.value.status == _lib.FLOD_ERR_UNSUPPORTED
+    lean.keep_backward_state(True)
+    lean.render_level(level, cam, bg)
+    g_l = {k: v.clone() for k, v in lean.backward(level, dimg).items()}
+    g_k = keep.backward(level, dimg)
+    torch.cuda.synchronize()
+    for name in NAMES:
+        a, b = g_l[name].cpu().numpy(), g_k[name].cpu().numpy()
+        # the same arithmetic; only the order of the FP32 atomic sums may differ
+        np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-5 * max(1e-30, float(np.abs(b).max())), err_msg=name)
