@@ -261,7 +261,8 @@ __device__ __forceinline__ void bwd_part(
             const float wT = alpha * Ti;
             const float dcc = d0[k] * B.z + d1[k] * B.w + d2[k] * BL.y;   // dL/dC . c
             const float diff = dcc - V[k];
-            const float e = (Ti * diff) * (CLAMP ? gmv[k] : alpha);     // dL/dalpha alpha
+            // dL/dalpha alpha (with alpha the weight, T_i alpha (c - Shat) is wT diff)
+            const float e = CLAMP ? (Ti * diff) * gmv[k] : wT * diff;
             gr[6] = fmaf(wT, d0[k], gr[6]);
             gr[7] = fmaf(wT, d1[k], gr[7]);
             gr[8] = fmaf(wT, d2[k], gr[8]);
