@@ -54,7 +54,9 @@ __device__ __forceinline__ void append_blended(const uint8_t *s_taken, const uin
   }
 }
 
-template <int PPT>
+// COUNT: the caller wants each pixel's count of blended entries (n_blended); without it the
+// walk does not count (one VALU fewer per blending wave and entry).
+template <int PPT, bool COUNT>
 __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__restrict__ ranges,
                                                               const uint32_t *__restrict__ values,
                                                               const float4 *__restrict__ xyab,
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
         C2[k] = fmaf(wgt, BL.y, C2[k]);
         T[k] = Tn;
         last[k] = start + j + 1;
-        ++nbl[k];
+        if (COUNT) ++nbl[k];
         s_taken[j] = 1;
       }
     }
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
     image[2 * plane + pix] = fmaf(Tf, bg2, C2[k]);
     final_T[pix] = Tf;
     n_contrib[pix] = last[k];
-    if (n_blended) n_blended[pix] = nbl[k];
+    if (COUNT) n_blended[pix] = nbl[k];
   }
 }
 
@@ -195,9 +197,10 @@ hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   // 1 pixel per thread (4 waves per tile) measured fastest at 1080p / 1M: 0.218 ms against
   // 0.242 ms with 2 and 0.353 ms with 4 (entry loop unrolled by two in that comparison).
-  hipLaunchKernelGGL(k_blend<kFwdPix>, dim3(n_tiles), dim3(kTile * kTile / kFwdPix), 0, s, ranges, values, xyab,
-                     cop, blue, cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], image, final_T, n_contrib,
-                     n_blended, blended, tile_blended, order);
+  auto kernel = n_blended ? k_blend<kFwdPix, true> : k_blend<kFwdPix, false>;
+  hipLaunchKernelGGL(kernel, dim3(n_tiles), dim3(kTile * kTile / kFwdPix), 0, s, ranges, values, xyab, cop, blue,
+                     cam.W, cam.H, cam.tiles_x, n_tiles, bg[0], bg[1], bg[2], image, final_T, n_contrib, n_blended,
+                     blended, tile_blended, order);
   return hipGetLastError();
 }
 
