@@ -153,12 +153,12 @@ __global__ __launch_bounds__(kTile * kTile / PPT) void k_blend(const uint2 *__re
         const float l = conic_kq(B.x, A.z, dx, fy[k] - A.y, t);   // k q + log2 o
         if (l < BL.x) continue;                                   // q > 9 or alpha < 1/255
         const float alpha = fminf(kAlphaMax, alpha_from_log2(l));
-        const float Tn = T[k] * (1.0f - alpha);
+        const float wgt = alpha * T[k];
+        const float Tn = fmaf(-alpha, T[k], T[k]);   // T (1 - alpha), one rounding
         if (Tn < kTMin) {
           done[k] = true;
           continue;
         }
-        const float wgt = alpha * T[k];
         C0[k] = fmaf(wgt, B.z, C0[k]);
         C1[k] = fmaf(wgt, B.w, C1[k]);
         C2[k] = fmaf(wgt, BL.y, C2[k]);
