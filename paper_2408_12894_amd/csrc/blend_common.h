@@ -77,9 +77,10 @@ struct CountCost {        // backward: entries the forward blended somewhere in 
   __device__ __forceinline__ uint32_t operator()(int t) const { return count[t]; }
 };
 
+// The tile order as one workgroup of kOrderThreads threads (the body of k_tile_order, which
+// the backward also runs beside other work in one launch).
 template <class Cost>
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, uint32_t *__restrict__ order,
-                                                              TileSplit split) {
+__device__ __forceinline__ void tile_order(Cost cost, int n, uint32_t *__restrict__ order, TileSplit split) {
   constexpr int W = kOrderThreads / 64;
   // per-wave bucket counts (contention only inside a wave), then per (bucket, wave) offsets
   __shared__ uint32_t s_cnt[W][kOrderBuckets];
@@ -166,6 +167,12 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, 
       if (base + 64 * u < t1) order[atomicAdd(&s_cnt[w][cost_bucket(c[u])], 1u)] = (uint32_t)(base + 64 * u);
   }
   if (split.cap2 >= 0 && tid < 2) order[n + tid] = s_split[tid];
+}
+
+template <class Cost>
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(Cost cost, int n, uint32_t *__restrict__ order,
+                                                              TileSplit split) {
+  tile_order(cost, n, order, split);
 }
 
 }  // namespace flod

@@ -1048,12 +1048,11 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
     return FLOD_ERR_WORKSPACE;
   }
   float *g2d = P<float>(ctx, B_G2D);
-  if (launch_fill_u32(reinterpret_cast<uint32_t *>(g2d), 0u, 9 * N, s) != hipSuccess) return FLOD_ERR_DEVICE;
   uint32_t *order = P<uint32_t>(ctx, B_TILE_ORDER);
   hipEvent_t ev_a, ev_b;
   tm.dispatch(FLOD_STAGE_BLEND_BWD, &ev_a, &ev_b);
   if (launch_blend_bwd(P<uint2>(ctx, B_RANGES), P<float4>(ctx, B_XYAB), P<float4>(ctx, B_COP),
-                       P<float2>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d,
+                       P<float2>(ctx, B_BLUE), sv.cam, sv.bg, sv.final_T, sv.n_contrib, dL_dimage, g2d, 9 * N,
                        P<uint2>(ctx, B_BLENDED), P<uint32_t>(ctx, B_TILE_BLENDED), order, s, ev_a, ev_b) !=
           hipSuccess)
     return FLOD_ERR_DEVICE;

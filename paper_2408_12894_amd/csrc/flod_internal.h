@@ -139,10 +139,11 @@ hipError_t launch_blend(const uint2 *ranges, const uint32_t *values, const float
                         int32_t *n_blended, uint2 *blended, uint32_t *tile_blended, const uint32_t *order,
                         hipStream_t s);
 // order: n_tiles + 2 words of scratch (the backward's tile order and its counts of split tiles);
-// the kernel is timed by the events (if given), its tile order is not
+// g2d: the n_g2d floats of gradient sums, zeroed here first; the kernel is timed by the events
+// (if given), its tile order and the zeroing are not
 hipError_t launch_blend_bwd(const uint2 *ranges, const float4 *xyab, const float4 *cop, const float2 *blue,
                             const DevCamera &cam, const float bg[3], const float *final_T,
-                            const int32_t *n_contrib, const float *dL_dimage, float *g2d,
+                            const int32_t *n_contrib, const float *dL_dimage, float *g2d, int64_t n_g2d,
                             const uint2 *blended, const uint32_t *tile_blended, uint32_t *order,
                             hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // the most blocks the backward's split tiles add beyond one per tile
