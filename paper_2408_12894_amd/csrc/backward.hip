@@ -449,21 +449,10 @@ hipError_t launch_blend_bwd(const uint2 *ranges, const float4 *xyab, const float
 
 // ---------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const uint32_t *__restrict__ tiles,
-                                                           const float *__restrict__ g2d,
-                                                           flod_grads out) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const DevLevel L = p.lv[0];
-  if (i >= L.n) return;
-  float *dsh = out.d_sh + i * (FLOD_SH_COEFFS * 3);
-  if (tiles[i] == 0u) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) { out.d_means[i * 3 + k] = 0.f; out.d_log_scales[i * 3 + k] = 0.f; }
-    reinterpret_cast<float4 *>(out.d_quats)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    out.d_opacity_logits[i] = 0.f;
-    for (int k = 0; k < 12; ++k) reinterpret_cast<float4 *>(dsh)[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    return;
-  }
+// The chain rule for one visible Gaussian i; its SH gradient row goes to dsh (LDS).
+__device__ __forceinline__ void preprocess_bwd_one(const PreParams &p, const DevLevel &L, int64_t i,
+                                                        const float *__restrict__ g2d, const flod_grads &out,
+                                                        float4 *dsh) {
   double g[kG2d];   // the blend backward's sums (moments of e, colour), turned into gradients below
 #pragma unroll
   for (int c = 0; c < kG2d; ++c) g[c] = (double)g2d[i * kG2d + c];
@@ -601,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
     gm[2] += (double)((gdz - z * dd) * inv);
 #pragma unroll
     for (int k = 0; k < 12; ++k)
-      reinterpret_cast<float4 *>(dsh)[k] = make_float4(gsh[4 * k], gsh[4 * k + 1], gsh[4 * k + 2], gsh[4 * k + 3]);
+      dsh[k] = make_float4(gsh[4 * k], gsh[4 * k + 1], gsh[4 * k + 2], gsh[4 * k + 3]);
   }
 
   // Sigma = M M^T, M = R diag(s): gM = Gs M
@@ -640,6 +629,34 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
 #pragma unroll
   for (int k = 0; k < 3; ++k) out.d_means[i * 3 + k] = (float)gm[k];
   out.d_opacity_logits[i] = d_logit;
+}
+
+// The SH gradients leave through LDS: each thread stages its 192-byte row, then the workgroup
+// writes its 256 consecutive rows with consecutive float4 stores (written row by row, every
+// lane of a store instruction hit a different cache line: 0.126 -> 0.097 ms at 1080p / 1M).
+constexpr int kShRow4 = FLOD_SH_COEFFS * 3 / 4;   // float4 per SH row
+
+__global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const uint32_t *__restrict__ tiles,
+                                                           const float *__restrict__ g2d,
+                                                           flod_grads out) {
+  __shared__ float4 s_sh[kBlock * kShRow4];   // 48 KB: the workgroup's SH gradient rows
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const DevLevel L = p.lv[0];
+  float4 *dsh = s_sh + threadIdx.x * kShRow4;
+  if (i < L.n && tiles[i] == 0u) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { out.d_means[i * 3 + k] = 0.f; out.d_log_scales[i * 3 + k] = 0.f; }
+    reinterpret_cast<float4 *>(out.d_quats)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    out.d_opacity_logits[i] = 0.f;
+    for (int k = 0; k < kShRow4; ++k) dsh[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+  } else if (i < L.n) {
+    preprocess_bwd_one(p, L, i, g2d, out, dsh);
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kBlock;
+  float4 *dst = reinterpret_cast<float4 *>(out.d_sh + base * (FLOD_SH_COEFFS * 3));
+  const int nf = (int)(min((int64_t)kBlock, L.n - base) * kShRow4);
+  for (int f = threadIdx.x; f < nf; f += kBlock) dst[f] = s_sh[f];
 }
 
 hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, const float *g2d,
