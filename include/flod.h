@@ -101,9 +101,9 @@ typedef struct {
 typedef struct {
   float *d_means;           /* [n,3]    */
   float *d_log_scales;      /* [n,3]    */
-  float *d_quats;           /* [n,4]    */
+  float *d_quats;           /* [n,4]    16-byte aligned */
   float *d_opacity_logits;  /* [n]      */
-  float *d_sh;              /* [n,16,3] */
+  float *d_sh;              /* [n,16,3] 16-byte aligned */
 } flod_grads;
 
 /* Workspace allocator. alloc returns a device pointer (256-byte aligned) or NULL to refuse;
@@ -295,7 +295,8 @@ flod_status flod_level_transition(flod_ctx *ctx, const flod_level *in, float s_m
    tile ranges of the sorted list, per tile the list of the entries blended somewhere in the
    tile, and the per-tile counts of those entries (flod_view: blended, tile_blended). Returns
    FLOD_ERR_UNSUPPORTED after a selective render, after a render that kept no backward state
-   (flod_ctx_keep_backward_state) or when no render preceded it. FP32
+   (flod_ctx_keep_backward_state) or when no render preceded it; FLOD_ERR_INVALID_ARG for
+   a NULL array or d_quats / d_sh not 16-byte aligned. FP32
    atomic accumulation: results are deterministic up to summation order. */
 flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_grads *grads,
                                  void *stream);
