@@ -169,7 +169,7 @@ static unsigned radix_grid(int nb_max) {
 // directly, and keys equal to kDepthNone (candidates not rendered) are not counted.
 template <int ITEMS, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const uint32_t *n_ptr, uint32_t n_all,
-                                                    int shift, uint32_t *hist, int stride) {
+                                                    int shift, uint32_t dmask, uint32_t *hist, int stride) {
   constexpr uint32_t TILE = kBlock * ITEMS;
   __shared__ uint32_t h[kRadix];
   const uint32_t n = FIRST ? n_all : *n_ptr;
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, const 
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r)
     if (base + r * kBlock + threadIdx.x < n && (!FIRST || kr[r] != kDepthNone))
-      atomicAdd(&h[(kr[r] >> shift) & (kRadix - 1)], 1u);
+      atomicAdd(&h[(kr[r] >> shift) & dmask], 1u);
   __syncthreads();
   hist[(size_t)threadIdx.x * stride + b] = h[threadIdx.x];
 }
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
                                                        const uint32_t *__restrict__ vals_in,
                                                        uint32_t *__restrict__ keys_out,
                                                        uint32_t *__restrict__ vals_out, const uint32_t *n_ptr,
-                                                       uint32_t n_all, uint32_t *n_out, int shift,
+                                                       uint32_t n_all, uint32_t *n_out, int shift, uint32_t dmask,
                                                        const uint32_t *hist, const uint32_t *scan,
                                                        const uint32_t *tot, int stride, TileTail tail) {
   constexpr uint32_t TILE = kBlock * ITEMS;
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
     const uint32_t li = (uint32_t)w * WTILE + (uint32_t)r * 64u + (uint32_t)lane;
     const bool valid = li < count && (!FIRST || kr[r] != kDepthNone);
     const uint32_t key = kr[r];
-    const uint32_t d = (key >> shift) & (kRadix - 1);
+    const uint32_t d = (key >> shift) & dmask;   // bits above the pass's digit are zero
     unsigned long long peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < kRadixBits; ++bit) {
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
   for (int r = 0; r < ITEMS; ++r) {
     const uint32_t li = (uint32_t)w * WTILE + (uint32_t)r * 64u + (uint32_t)lane;
     if (li < count && (!FIRST || kr[r] != kDepthNone)) {
-      const uint32_t pos = s_wcnt[w][(kr[r] >> shift) & (kRadix - 1)] + rr[r];
+      const uint32_t pos = s_wcnt[w][(kr[r] >> shift) & dmask] + rr[r];
       s_keys[pos] = kr[r];
       s_vals[pos] = vr[r];
     }
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
   if (!TILES) {
     for (uint32_t li = tid; li < kept; li += kBlock) {
       const uint32_t key = s_keys[li];
-      const uint32_t d = (key >> shift) & (kRadix - 1);
+      const uint32_t d = (key >> shift) & dmask;
       const uint32_t pos = s_goff[d] + li;
       keys_out[pos] = key;
       vals_out[pos] = s_vals[li];
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
       if (valid) {
         const uint32_t key = s_keys[li];
         const uint32_t v = s_vals[li];
-        const uint32_t pos = s_goff[(key >> shift) & (kRadix - 1)] + li;
+        const uint32_t pos = s_goff[(key >> shift) & dmask] + li;
         keys_out[pos] = key;
         vals_out[pos] = v;
         c = tail.tiles_of[v];
@@ -421,38 +421,44 @@ static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], uint32_t *n_ptr, 
   const TileTail none{nullptr, nullptr, nullptr};
   const unsigned grid = radix_grid(nb_max);
   int cur = 0;
-  for (int shift = 0; shift < bits; shift += kRadixBits) {
-    const bool first = shift == 0 && first_keys;
-    const bool last = shift + kRadixBits >= bits;
+  // the fewest passes of at most kRadixBits digit bits, the bits spread evenly over them (the
+  // 13-bit tile ids of a 1080p frame as 7 + 6 rather than 8 + 5 bits)
+  const int passes = (bits + kRadixBits - 1) / kRadixBits;
+  for (int pass = 0, shift = 0; pass < passes; ++pass) {
+    const int nbits = bits / passes + (pass < bits % passes ? 1 : 0);
+    const uint32_t dmask = (1u << nbits) - 1u;
+    const bool first = pass == 0 && first_keys;
+    const bool last = pass == passes - 1;
     const uint32_t *kin = first ? first_keys : keys[cur];
     if (first)
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_hist<ITEMS, true>), dim3(grid), dim3(kBlock), 0, s, kin, n_ptr, n_all,
-                         shift, hist, stride);
+                         shift, dmask, hist, stride);
     else
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_hist<ITEMS, false>), dim3(grid), dim3(kBlock), 0, s, kin, n_ptr, n_all,
-                         shift, hist, stride);
+                         shift, dmask, hist, stride);
     // the first pass's workgroups cover all candidates; the later passes' the count it kept
     hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, s, first ? nullptr : n_ptr, n_all, hist, scan, tot,
                        stride, TILE);
     const TileTail &tt = (last && tail) ? *tail : none;
     if (first && last && tail) {
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<ITEMS, true, true>), dim3(grid), dim3(kBlock), 0, s, kin,
-                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, n_all, n_ptr, shift, hist, scan, tot, stride,
+                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, n_all, n_ptr, shift, dmask, hist, scan, tot, stride,
                          tt);
     } else if (first) {
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<ITEMS, false, true>), dim3(grid), dim3(kBlock), 0, s, kin,
-                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, n_all, n_ptr, shift, hist, scan, tot, stride,
+                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, n_all, n_ptr, shift, dmask, hist, scan, tot, stride,
                          tt);
     } else if (last && tail) {
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<ITEMS, true, false>), dim3(grid), dim3(kBlock), 0, s, kin,
-                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, n_all, n_ptr, shift, hist, scan, tot, stride,
+                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, n_all, n_ptr, shift, dmask, hist, scan, tot, stride,
                          tt);
     } else {
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<ITEMS, false, false>), dim3(grid), dim3(kBlock), 0, s, kin,
-                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, n_all, n_ptr, shift, hist, scan, tot, stride,
+                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, n_all, n_ptr, shift, dmask, hist, scan, tot, stride,
                          tt);
     }
     cur ^= 1;
+    shift += nbits;
   }
   *cur_out = cur;
 }
