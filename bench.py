@@ -90,7 +90,7 @@ FLOPS_BLEND_BWD = 46
 # step_1080p_1M_hbm_counters.md). A figure holds only for the kernel sources it was taken
 # with: the sha256 over the listed files must match, else the traffic is reported as null.
 PROFILED_TRAFFIC = {
-    "blend_bwd": {"bytes": 368512989, "sha256": "c62fd8f87277ac9913c1becae44e4a290997063bacf8d43101826b95e169f6dd",
+    "blend_bwd": {"bytes": 368300182, "sha256": "c62fd8f87277ac9913c1becae44e4a290997063bacf8d43101826b95e169f6dd",
                   "sources": ['paper_2408_12894_amd/csrc/backward.hip', 'paper_2408_12894_amd/csrc/blend_common.h', 'paper_2408_12894_amd/csrc/project.h', 'paper_2408_12894_amd/csrc/flod_internal.h']},
 }
 
