@@ -451,7 +451,8 @@ hipError_t launch_blend_bwd(const uint2 *ranges, const float4 *xyab, const float
 
 // The chain rule for one visible Gaussian i; its SH gradient row goes to dsh (LDS).
 __device__ __forceinline__ void preprocess_bwd_one(const PreParams &p, const DevLevel &L, int64_t i,
-                                                        const float *__restrict__ g2d, const flod_grads &out,
+                                                        const float *__restrict__ g2d,
+                                                        const float4 *__restrict__ shjac, const flod_grads &out,
                                                         float4 *dsh) {
   double g[kG2d];   // the blend backward's sums (moments of e, colour), turned into gradients below
 #pragma unroll
@@ -546,7 +547,9 @@ __device__ __forceinline__ void preprocess_bwd_one(const PreParams &p, const Dev
 #pragma unroll
   for (int k = 0; k < 3; ++k) gm[k] = Rc[k] * gtx + Rc[3 + k] * gty + Rc[6 + k] * gtz;
 
-  // colour -> SH coefficients and view direction (FP32: colour is not on the key path)
+  // colour -> SH coefficients and view direction (FP32: colour is not on the key path), from
+  // the forward's Jacobian of the colour in the unit view direction and its colours before the
+  // clamp (the same values this recomputed from the SH coefficients)
   {
     const int deg = p.sh_degree;
     const int nk = (deg + 1) * (deg + 1);
@@ -554,35 +557,21 @@ __device__ __forceinline__ void preprocess_bwd_one(const PreParams &p, const Dev
     const float nv = sqrtf((vx * vx + vy * vy) + vz * vz);
     const float inv = 1.0f / nv;
     const float x = vx * inv, y = vy * inv, z = vz * inv;
-    float Y[16], Gx[16], Gy[16], Gz[16];
+    float Y[16];
     sh_basis(deg, x, y, z, Y);
-    sh_basis_grad(deg, x, y, z, Gx, Gy, Gz);
-    const float4 *shv = reinterpret_cast<const float4 *>(L.sh + i * (FLOD_SH_COEFFS * 3));
-    float sh[48];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      float4 v = shv[k];
-      sh[4 * k + 0] = v.x; sh[4 * k + 1] = v.y; sh[4 * k + 2] = v.z; sh[4 * k + 3] = v.w;
-    }
+    const float4 j0 = shjac[i], j1 = shjac[L.n + i], j2 = shjac[2 * L.n + i];   // three planes of n float4
+    const float J[9] = {j0.x, j0.y, j0.z, j0.w, j1.x, j1.y, j1.z, j1.w, j2.x};
+    const float pre[3] = {j2.y, j2.z, j2.w};
     float gsh[48];
     float gdx = 0.f, gdy = 0.f, gdz = 0.f;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-      float acc = 0.0f;
+      const float gcol = (pre[ch] < 0.0f) ? 0.0f : (float)g[6 + ch];
 #pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (k < nk) acc = fmaf(sh[k * 3 + ch], Y[k], acc);
-      const float gcol = (acc + 0.5f < 0.0f) ? 0.0f : (float)g[6 + ch];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const bool on = k < nk;
-        gsh[k * 3 + ch] = on ? gcol * Y[k] : 0.0f;
-        if (on) {
-          gdx += gcol * sh[k * 3 + ch] * Gx[k];
-          gdy += gcol * sh[k * 3 + ch] * Gy[k];
-          gdz += gcol * sh[k * 3 + ch] * Gz[k];
-        }
-      }
+      for (int k = 0; k < 16; ++k) gsh[k * 3 + ch] = k < nk ? gcol * Y[k] : 0.0f;
+      gdx = fmaf(gcol, J[ch * 3 + 0], gdx);
+      gdy = fmaf(gcol, J[ch * 3 + 1], gdy);
+      gdz = fmaf(gcol, J[ch * 3 + 2], gdz);
     }
     const float dd = x * gdx + y * gdy + z * gdz;
     gm[0] += (double)((gdx - x * dd) * inv);
@@ -638,7 +627,7 @@ constexpr int kShRow4 = FLOD_SH_COEFFS * 3 / 4;   // float4 per SH row
 
 __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const uint32_t *__restrict__ tiles,
                                                            const float *__restrict__ g2d,
-                                                           flod_grads out) {
+                                                           const float4 *__restrict__ shjac, flod_grads out) {
   __shared__ float4 s_sh[kBlock * kShRow4];   // 48 KB: the workgroup's SH gradient rows
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const DevLevel L = p.lv[0];
@@ -650,7 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
     out.d_opacity_logits[i] = 0.f;
     for (int k = 0; k < kShRow4; ++k) dsh[k] = make_float4(0.f, 0.f, 0.f, 0.f);
   } else if (i < L.n) {
-    preprocess_bwd_one(p, L, i, g2d, out, dsh);
+    preprocess_bwd_one(p, L, i, g2d, shjac, out, dsh);
   }
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kBlock;
@@ -660,11 +649,11 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(PreParams p, const ui
 }
 
 hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, const float *g2d,
-                                 const flod_grads &g, hipStream_t s) {
+                                 const float4 *shjac, const flod_grads &g, hipStream_t s) {
   const int64_t n = p.lv[0].n;
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, tiles,
-                     g2d, g);
+                     g2d, shjac, g);
   return hipGetLastError();
 }
 

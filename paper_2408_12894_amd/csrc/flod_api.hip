@@ -57,7 +57,7 @@ enum BufId {
   B_XYAB, B_COP, B_BLUE, B_DEPTH, B_BIN, B_TILES, B_BLOCKVIS, B_PREFIX,
   B_DKEY0, B_DKEY1, B_DVAL0, B_DVAL1, B_TBSUM, B_TPREFIX,
   B_TKEY0, B_TKEY1, B_TVAL0, B_TVAL1, B_HIST, B_SCAN, B_TOT, B_RANGES, B_COUNTERS,
-  B_G2D, B_SSIM, B_BLENDED, B_TILE_BLENDED, B_TILE_ORDER, B_STILES, B_COUNT
+  B_G2D, B_SSIM, B_BLENDED, B_TILE_BLENDED, B_TILE_ORDER, B_STILES, B_SHJAC, B_COUNT
 };
 
 struct Saved {
@@ -318,8 +318,10 @@ size_t hist_bytes(int64_t n_max) { return radix_hist_bytes(n_max); }
 // case they do nothing. Meanwhile the host reads K back (stream-ordered, 16 bytes) for the
 // statistics and the capacity check: when K > cap it grows the buffers and enqueues the scan's
 // count and the tail again. A context's first render (cap = 0) waits for K before enqueuing.
+// level: a single-level render, which keeps what its backward needs (when the context keeps
+// backward state)
 flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const float bg[3],
-                          flod_frame *out, hipStream_t s) {
+                          flod_frame *out, hipStream_t s, bool level = false) {
   c->required = 0;
   if (use_stream(c, s) != hipSuccess) return FLOD_ERR_DEVICE;
   c->saved.valid = false;
@@ -360,6 +362,8 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
   need(B_TILE_BLENDED, 4 * (size_t)n_tiles);
   need(B_TILE_ORDER, 4 * ((size_t)n_tiles + 2));
   need(B_COUNTERS, 8 * (size_t)kCntSlots);
+  const bool jac = level && c->keep_backward;   // the colour Jacobians for the backward
+  if (jac) need(B_SHJAC, 48 * (size_t)N);
   if (st != FLOD_OK) {
     c->required = ws_bytes(c) + extra;
     return st;
@@ -390,6 +394,7 @@ flod_status render_common(flod_ctx *c, PreParams &p, int64_t *n_selected, const 
     o.block_vis = P<uint32_t>(c, B_BLOCKVIS);
     o.zero_sums = P<uint32_t>(c, B_TBSUM);
     o.n_selected = reinterpret_cast<unsigned long long *>(n_selected);
+    o.shjac = jac ? P<float4>(c, B_SHJAC) : nullptr;
     tm.begin(FLOD_STAGE_PREPROCESS);
     if (launch_preprocess(p, o, s) != hipSuccess) return FLOD_ERR_DEVICE;
     tm.end();
@@ -615,7 +620,7 @@ flod_status flod_render_level(flod_ctx *ctx, const flod_level *level, int sh_deg
   L.offset = 0; L.n = level->n; L.s_min = level->s_min;
   L.lo2 = 0.0f; L.hi2 = INFINITY;
   p.n_total = level->n;
-  st = render_common(ctx, p, nullptr, bg, out, (hipStream_t)stream);
+  st = render_common(ctx, p, nullptr, bg, out, (hipStream_t)stream, true);
   if (st == FLOD_OK) {
     ctx->saved.is_level = true;
     ctx->saved.level = *level;
@@ -1064,7 +1069,8 @@ flod_status flod_render_backward(flod_ctx *ctx, const float *dL_dimage, flod_gra
   L.logits = sv.level.opacity_logits; L.sh = sv.level.sh;
   L.offset = 0; L.n = N; L.s_min = sv.level.s_min;
   p.n_total = N;
-  if (launch_preprocess_bwd(p, P<uint32_t>(ctx, B_TILES), g2d, *grads, s) != hipSuccess) return FLOD_ERR_DEVICE;
+  if (launch_preprocess_bwd(p, P<uint32_t>(ctx, B_TILES), g2d, P<float4>(ctx, B_SHJAC), *grads, s) != hipSuccess)
+    return FLOD_ERR_DEVICE;
   tm.end();
   ctx->saved.has_grad2d = true;
   ctx->saved.grad2d_moments = true;

@@ -73,6 +73,9 @@ struct PreOut {
   uint32_t *block_vis;  // per-workgroup count of visible candidates
   uint32_t *zero_sums;  // one word per workgroup, zeroed (the depth sort's tile-count sums; may be null)
   unsigned long long *n_selected;   // per-level selected counts (may be null)
+  float4 *shjac;      // three planes of n_total float4, per visible candidate the colour's Jacobian in
+                      // the unit view direction, J[ch][a] row-major, then the three colours before the
+                      // clamp (J00 J01 J02 J10 | J11 J12 J20 J21 | J22 c0 c1 c2); may be null
 };
 
 // One attribute array of a level in an Adam step: parameter, gradient and the two moment
@@ -152,8 +155,9 @@ hipError_t launch_tile_order_by_length(const uint2 *ranges, int n_tiles, uint32_
 // The blend backward's per-Gaussian moment sums into dL/d(mu', conic) in place (inspection).
 hipError_t launch_g2d_from_moments(int64_t n, const uint32_t *tiles, const float4 *xyab, const float4 *cop,
                                    float *g2d, hipStream_t s);
+// shjac: the forward preprocess's Jacobians and pre-clamp colours (PreOut::shjac)
 hipError_t launch_preprocess_bwd(const PreParams &p, const uint32_t *tiles, const float *g2d,
-                                 const flod_grads &g, hipStream_t s);
+                                 const float4 *shjac, const flod_grads &g, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_select_count(const float *means, int64_t n, const float centre[3], float lo2, float hi2,
                                uint32_t *block_cnt, hipStream_t s);

@@ -3,7 +3,8 @@
 // thread per candidate Gaussian.
 //
 // Memory: one pass over the attributes (12 + 12 + 16 + 4 + 192 bytes per Gaussian, the SH
-// row read as 12 dwordx4 loads), 56 bytes written per Gaussian. The projection runs in FP64
+// row read as 12 dwordx4 loads), 80 bytes written per visible Gaussian (128 when the render
+// keeps the backward's state: the colour Jacobian below). The projection runs in FP64
 // (see project.h); mu' is stored as its FP32 rounding plus a bf16 residual so that the blend
 // kernels can form pixel offsets to better than 1e-6 px. Rejected candidates stop
 // after reading the mean (selection) or the mean and logit (near-plane / opacity culls).
@@ -11,6 +12,10 @@
 
 namespace flod {
 
+// JAC (renders that keep the backward's state): also the colour's Jacobian in the view
+// direction and the colours before the clamp, so that the preprocess backward needs no SH
+// coefficients (reading 48 bytes per Gaussian instead of 192).
+template <bool JAC>
 __global__ __launch_bounds__(kBlock) void k_preprocess(PreParams p, PreOut o) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   bool vis = false;
@@ -57,8 +62,10 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreParams p, PreOut o) {
             // colour from SH (not on the key path: contraction allowed via fmaf)
             float dx = m0 - p.cam.campos[0], dy = m1 - p.cam.campos[1], dz = m2 - p.cam.campos[2];
             float inv = 1.0f / sqrtf((dx * dx + dy * dy) + dz * dz);
+            // the basis before the SH loads for the colour alone, after them with the Jacobian
+            // (formed before them, the Jacobian variant measured 3 us slower at 1080p / 1M)
             float Y[16];
-            sh_basis(p.sh_degree, dx * inv, dy * inv, dz * inv, Y);
+            if (!JAC) sh_basis(p.sh_degree, dx * inv, dy * inv, dz * inv, Y);
             const float4 *shv = reinterpret_cast<const float4 *>(L.sh + j * (FLOD_SH_COEFFS * 3));
             const int nk = (p.sh_degree + 1) * (p.sh_degree + 1);
             const int nv4 = (nk * 3 + 3) / 4;
@@ -71,13 +78,41 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreParams p, PreOut o) {
               }
             }
             float col[3];
+            if (JAC) {
+              // the same colours, with J[ch][a] = sum_k sh[k][ch] dY_k / dd_a (d the unit view
+              // direction) and the colours before the clamp stored for the backward
+              float Gx[16], Gy[16], Gz[16];
+              sh_basis(p.sh_degree, dx * inv, dy * inv, dz * inv, Y);
+              sh_basis_grad(p.sh_degree, dx * inv, dy * inv, dz * inv, Gx, Gy, Gz);
+              float pre[3], J[9];
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-              float acc = 0.0f;
+              for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
-              for (int k = 0; k < 16; ++k)
-                if (k < nk) acc = fmaf(sh[k * 3 + ch], Y[k], acc);
-              col[ch] = fmaxf(acc + 0.5f, 0.0f);
+                for (int k = 0; k < 16; ++k)
+                  if (k < nk) {
+                    acc = fmaf(sh[k * 3 + ch], Y[k], acc);
+                    jx = fmaf(sh[k * 3 + ch], Gx[k], jx);
+                    jy = fmaf(sh[k * 3 + ch], Gy[k], jy);
+                    jz = fmaf(sh[k * 3 + ch], Gz[k], jz);
+                  }
+                pre[ch] = acc + 0.5f;
+                col[ch] = fmaxf(pre[ch], 0.0f);
+                J[ch * 3 + 0] = jx; J[ch * 3 + 1] = jy; J[ch * 3 + 2] = jz;
+              }
+              // three planes of n_total float4 (each store instruction writes consecutive float4)
+              o.shjac[i] = make_float4(J[0], J[1], J[2], J[3]);
+              o.shjac[p.n_total + i] = make_float4(J[4], J[5], J[6], J[7]);
+              o.shjac[2 * p.n_total + i] = make_float4(J[8], pre[0], pre[1], pre[2]);
+            } else {
+#pragma unroll
+              for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                  if (k < nk) acc = fmaf(sh[k * 3 + ch], Y[k], acc);
+                col[ch] = fmaxf(acc + 0.5f, 0.0f);
+              }
             }
             const float opac = 1.0f / (1.0f + __expf(-logit));
             o.xyab[i] = make_float4(hx, hy, ca, cb);
@@ -110,7 +145,10 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreParams p, PreOut o) {
 hipError_t launch_preprocess(const PreParams &p, const PreOut &o, hipStream_t s) {
   if (p.n_total <= 0) return hipSuccess;
   const unsigned grid = (unsigned)((p.n_total + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_preprocess, dim3(grid), dim3(kBlock), 0, s, p, o);
+  if (o.shjac)
+    hipLaunchKernelGGL(k_preprocess<true>, dim3(grid), dim3(kBlock), 0, s, p, o);
+  else
+    hipLaunchKernelGGL(k_preprocess<false>, dim3(grid), dim3(kBlock), 0, s, p, o);
   return hipGetLastError();
 }
 
