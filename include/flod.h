@@ -291,9 +291,11 @@ flod_status flod_level_transition(flod_ctx *ctx, const flod_level *in, float s_m
    and n_contrib (no per-pixel contributor lists are stored): the forward's output buffers,
    which must still hold its values (the walk of each pixel is clamped to its tile's list, so
    changed n_contrib values give wrong gradients but no access outside the context's
-   buffers). Besides them the backward reads the O(K) state the forward left in ctx: the
-   tile ranges of the sorted list, per tile the list of the entries blended somewhere in the
-   tile, and the per-tile counts of those entries (flod_view: blended, tile_blended). Returns
+   buffers). Besides them the backward reads the state the forward left in ctx: the tile
+   ranges of the sorted list, per tile the list of the entries blended somewhere in the tile,
+   the per-tile counts of those entries (flod_view: blended, tile_blended), and per visible
+   Gaussian the Jacobian of its SH colour in the unit view direction with its colours before
+   the clamp (48 bytes; the backward reads no SH coefficients). Returns
    FLOD_ERR_UNSUPPORTED after a selective render, after a render that kept no backward state
    (flod_ctx_keep_backward_state) or when no render preceded it; FLOD_ERR_INVALID_ARG for
    a NULL array or d_quats / d_sh not 16-byte aligned. FP32
@@ -362,7 +364,8 @@ enum {
   FLOD_NUM_STAGES
 };
 /* keep != 0 (the default): every render keeps the state flod_render_backward needs, per tile
-   the list of the entries blended into some pixel (8 bytes per instance slot of workspace).
+   the list of the entries blended into some pixel (8 bytes per instance slot of workspace)
+   and, for single-level renders, each Gaussian's colour Jacobian (48 bytes per Gaussian).
    keep == 0: renders keep none of it and take no workspace for it; a backward after such a
    render returns FLOD_ERR_UNSUPPORTED. For callers that only render (a server), which then
    need about a third less workspace per instance. Applies from the next render. */
