@@ -107,7 +107,7 @@ def test_fd_instance(renderer):
     print(worst)
 
 
-@pytest.mark.parametrize("deg", [0, 3])
+@pytest.mark.parametrize("deg", [0, 1, 2, 3])
 def test_small_scene(renderer, deg):
     _say(f"2k Gaussians, 128x128, sh degree {deg}")
     scene, cam, _ = synth.small_forward_case()
